@@ -1,0 +1,244 @@
+"""Seeded synthetic inputs: problem descriptions, interface nodes and grids.
+
+Both the GPU library's binding and the CPU oracle's wrapper take these plain
+dicts and arrays and convert them into their own structures. Nothing here runs
+the Monte Carlo method; the module only states problems (coefficients, the
+manufactured solution U from which f and g follow, the domain) and where the
+interfacial nodes sit.
+
+Problem dict fields::
+
+    dim            2 or 3
+    domain         "box" (lo, hi) or "ball" (center, radius)
+    sigma          isotropic diffusion, a_ij = sigma^2 delta_ij
+    b0, B          drift b(x) = b0 + B x
+    c_a, c_b       killing rate c(x) = c_a + c_b |x|^2
+    trig           [{amp, k[dim], phase[dim]}]  amp * prod sin(k_d x_d + phase_d)
+    mono           [{coef, e[dim]}]             coef * prod x_d^e_d
+    fx, gx         monomials added to f and to g
+    seed           64-bit key of the path generator
+
+For (1/2) sigma^2 Lap u + b.grad u + c u = f (the paper's eq. F:EllipticBVP
+with A = sigma^2 I), the source is f = (1/2) sigma^2 Lap U + b.grad U + c U +
+sum(fx) and the Dirichlet data is g = U + sum(gx); when fx = gx = 0 the exact
+solution is U.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PI = math.pi
+
+
+# --------------------------------------------------------------------------- problems
+def operator_problem(lo, hi, seed=0):
+    """The unit-square workload operator on the box [lo, hi]^2:
+    b = (0.5 x, -0.3 y), c = -(1 + x^2 + y^2), sigma = 1 (generator 1/2 Lap),
+    manufactured solution u = sin(pi x) cos(pi y) + x^2 y."""
+    return {
+        "dim": 2, "domain": "box", "lo": [float(lo)] * 2, "hi": [float(hi)] * 2,
+        "sigma": 1.0, "b0": [0.0, 0.0], "B": [[0.5, 0.0], [0.0, -0.3]],
+        "c_a": -1.0, "c_b": -1.0,
+        "trig": [{"amp": 1.0, "k": [PI, PI], "phase": [0.0, PI / 2]}],
+        "mono": [{"coef": 1.0, "e": [2, 1]}],
+        "fx": [], "gx": [], "seed": int(seed),
+    }
+
+
+def unit_square_problem(seed=0):
+    """Plain first-stage workload: unit square, 18 interface nodes."""
+    return operator_problem(0.0, 1.0, seed)
+
+
+def unit_square_nodes():
+    """4 subdomains cut by the interfaces x = 1/4, 1/2, 3/4, six equispaced
+    nodes each at y = j/7, j = 1..6 (end points on the boundary excluded),
+    interface-major. 18 x 2 array."""
+    pts = [(xi, j / 7.0) for xi in (0.25, 0.5, 0.75) for j in range(1, 7)]
+    return np.array(pts, dtype=np.float64)
+
+
+def big_square_problem(seed=0):
+    """Throughput workload: the same operator on [0, 4]^2."""
+    return operator_problem(0.0, 4.0, seed)
+
+
+def big_square_nodes(side=4.0, cells=8, per_segment=16):
+    """[0, side]^2 cut into cells x cells subdomains. Every interior grid line
+    is split into `cells` segments by the crossing lines; each segment carries
+    `per_segment` equispaced nodes at offsets (len * j / (per_segment + 1)),
+    j = 1..per_segment (crossing points excluded). Vertical segments first
+    (line by line, bottom to top), then horizontal ones. For the defaults,
+    7 * 8 * 2 = 112 segments, 1,792 nodes."""
+    step = side / cells
+    pts = []
+    for a in range(1, cells):
+        x = a * step
+        for s in range(cells):
+            for j in range(1, per_segment + 1):
+                pts.append((x, s * step + step * j / (per_segment + 1)))
+    for a in range(1, cells):
+        y = a * step
+        for s in range(cells):
+            for j in range(1, per_segment + 1):
+                pts.append((s * step + step * j / (per_segment + 1), y))
+    return np.array(pts, dtype=np.float64)
+
+
+def ball_exit_time_problem(dim=2, radius=1.0, center=None, sigma=1.0, seed=0):
+    """E[tau] from x for (1/2) sigma^2 Lap: u = (R^2 - |x - c|^2) / (dim sigma^2),
+    b = c = 0, so f = -1, g = 0 on the sphere. Centered at the origin unless
+    center is given (then U is written about the origin through monomials)."""
+    cen = [0.0] * dim if center is None else [float(v) for v in center]
+    s2 = sigma * sigma
+    mono = [{"coef": (radius * radius - sum(v * v for v in cen)) / (dim * s2), "e": [0] * dim}]
+    for d in range(dim):
+        e2 = [0] * dim
+        e2[d] = 2
+        mono.append({"coef": -1.0 / (dim * s2), "e": e2})
+        if cen[d] != 0.0:
+            e1 = [0] * dim
+            e1[d] = 1
+            mono.append({"coef": 2.0 * cen[d] / (dim * s2), "e": e1})
+    return {"dim": dim, "domain": "ball", "center": cen, "radius": float(radius),
+            "sigma": float(sigma), "b0": [0.0] * dim, "B": [[0.0] * dim for _ in range(dim)],
+            "c_a": 0.0, "c_b": 0.0, "trig": [], "mono": mono, "fx": [], "gx": [],
+            "seed": int(seed)}
+
+
+def ball_killing_problem(dim=2, radius=1.0, c=-1.0, sigma=1.0, seed=0):
+    """u(x) = E[exp(c tau)] in a ball: f = 0, g = 1, constant c < 0. With
+    kappa = sqrt(2|c|)/sigma: 2D u = I0(kappa r)/I0(kappa R); 3D
+    u = [sinh(kappa r)/(kappa r)] / [sinh(kappa R)/(kappa R)]."""
+    return {"dim": dim, "domain": "ball", "center": [0.0] * dim, "radius": float(radius),
+            "sigma": float(sigma), "b0": [0.0] * dim, "B": [[0.0] * dim for _ in range(dim)],
+            "c_a": float(c), "c_b": 0.0, "trig": [], "mono": [], "fx": [],
+            "gx": [{"coef": 1.0, "e": [0] * dim}], "seed": int(seed)}
+
+
+def box_exit_time_problem(lo=(0.0, 0.0), hi=(1.0, 1.0), sigma=1.0, seed=0):
+    """E[tau] in a box: U = 0, f = -1 (fx), g = 0, b = c = 0."""
+    dim = len(lo)
+    return {"dim": dim, "domain": "box", "lo": [float(v) for v in lo],
+            "hi": [float(v) for v in hi], "sigma": float(sigma), "b0": [0.0] * dim,
+            "B": [[0.0] * dim for _ in range(dim)], "c_a": 0.0, "c_b": 0.0,
+            "trig": [], "mono": [], "fx": [{"coef": -1.0, "e": [0] * dim}], "gx": [],
+            "seed": int(seed)}
+
+
+def harmonic_problem(kind="saddle", domain="box", seed=0):
+    """b = c = f = 0 and harmonic g, so u = g: 'saddle' x^2 - y^2, 'xy' x y,
+    'linear' x."""
+    mono = {"saddle": [{"coef": 1.0, "e": [2, 0]}, {"coef": -1.0, "e": [0, 2]}],
+            "xy": [{"coef": 1.0, "e": [1, 1]}],
+            "linear": [{"coef": 1.0, "e": [1, 0]}]}[kind]
+    pd = {"dim": 2, "domain": domain, "sigma": 1.0, "b0": [0.0, 0.0],
+          "B": [[0.0, 0.0], [0.0, 0.0]], "c_a": 0.0, "c_b": 0.0, "trig": [], "mono": mono,
+          "fx": [], "gx": [], "seed": int(seed)}
+    if domain == "box":
+        pd.update(lo=[0.0, 0.0], hi=[1.0, 1.0])
+    else:
+        pd.update(center=[0.0, 0.0], radius=1.0)
+    return pd
+
+
+def bilinear_problem(coef=(0.3, 1.0, -0.5, 2.0), lo=0.0, hi=1.0, seed=0):
+    """u = a + b x + c y + d x y with the unit-square drift and killing.
+    Lap u = 0, so f = b.grad u + c u. A grid reproduces u exactly under
+    bilinear interpolation, which makes u a zero-variance control variate."""
+    a, bx, cy, dxy = coef
+    pd = operator_problem(lo, hi, seed)
+    pd["trig"] = []
+    pd["mono"] = [{"coef": a, "e": [0, 0]}, {"coef": bx, "e": [1, 0]},
+                  {"coef": cy, "e": [0, 1]}, {"coef": dxy, "e": [1, 1]}]
+    return pd
+
+
+# --------------------------------------------------------------------------- exact values
+def manufactured_u(pd: dict, pts) -> np.ndarray:
+    """U at the points (the exact solution when fx = gx = 0)."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    dim = pd["dim"]
+    out = np.zeros(len(pts))
+    for t in pd.get("trig", []):
+        v = np.full(len(pts), float(t["amp"]))
+        for d in range(dim):
+            v = v * np.sin(t["k"][d] * pts[:, d] + t["phase"][d])
+        out += v
+    for m in pd.get("mono", []):
+        v = np.full(len(pts), float(m["coef"]))
+        for d in range(dim):
+            v = v * pts[:, d] ** int(m["e"][d])
+        out += v
+    return out
+
+
+# --------------------------------------------------------------------------- grids
+def grid_points(n, lo, hi):
+    """Coordinates of an n[0] x n[1] uniform grid, x fastest, shape (ny*nx, 2)."""
+    xs = np.linspace(lo[0], hi[0], n[0])
+    ys = np.linspace(lo[1], hi[1], n[1])
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def fourier_perturbation(seed=1, n_modes=32, amp=1e-2, kmax=16, dim=2):
+    """p(x) = sum_m A_m prod_d sin(pi k_{m,d} xhat_d), xhat = (x - lo)/(hi - lo):
+    k_{m,d} uniform on 1..kmax, random sign, A_m = amp * sign * dim / |k_m|^2
+    (so the lowest mode has amplitude amp and the modes decay as k^-2).
+    p vanishes on the boundary of the box."""
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(1, kmax + 1, size=(n_modes, dim))
+    sg = rng.choice([-1.0, 1.0], size=n_modes)
+    A = amp * sg * dim / np.sum(ks.astype(np.float64) ** 2, axis=1)
+    return {"k": ks, "A": A}
+
+
+def _pert_eval(pert, pts, lo, hi):
+    """p, grad p and Lap p at the points (box [lo, hi]^dim)."""
+    dim = pts.shape[1]
+    L = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+    xh = (pts - np.asarray(lo)) / L
+    val = np.zeros(len(pts))
+    grad = np.zeros_like(pts)
+    lap = np.zeros(len(pts))
+    for m in range(len(pert["A"])):
+        w = PI * pert["k"][m] / L           # angular wavenumber per coordinate
+        s = np.sin(PI * pert["k"][m] * xh)
+        c = np.cos(PI * pert["k"][m] * xh)
+        term = pert["A"][m] * np.prod(s, axis=1)
+        val += term
+        lap += -np.sum(w ** 2) * term
+        for d in range(dim):
+            others = np.prod(np.delete(s, d, axis=1), axis=1)
+            grad[:, d] += pert["A"][m] * w[d] * c[:, d] * others
+    return val, grad, lap
+
+
+def correction_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=1e-2):
+    """u_prev = U + p on an n x n grid over the box, and the residual
+    r = f - (L + c) u_prev = -(1/2 sigma^2 Lap p + b.grad p + c p), both
+    evaluated exactly at the grid points in float64 and stored in `dtype`.
+    Returns (u_prev_grid, resid_grid, perturbation)."""
+    lo, hi = pd["lo"], pd["hi"]
+    pts = grid_points((n, n), lo, hi)
+    pert = fourier_perturbation(seed, n_modes=n_modes, amp=amp)
+    p, gp, lp = _pert_eval(pert, pts, lo, hi)
+    b = np.asarray(pd["b0"])[None, :] + pts @ np.asarray(pd["B"]).T
+    c = pd["c_a"] + pd["c_b"] * np.sum(pts ** 2, axis=1)
+    s2 = pd["sigma"] ** 2
+    resid = -(0.5 * s2 * lp + np.sum(b * gp, axis=1) + c * p)
+    u_prev = manufactured_u(pd, pts) + p
+    mk = lambda v: {"dim": 2, "n": [n, n], "lo": list(lo), "hi": list(hi),  # noqa: E731
+                    "data": v.astype(dtype).reshape(n, n)}
+    return mk(u_prev), mk(resid), pert
+
+
+def sampled_grid(pd: dict, fn, n=257, dtype=np.float64):
+    """fn sampled on an n x n grid over the box of pd."""
+    lo, hi = pd["lo"], pd["hi"]
+    pts = grid_points((n, n), lo, hi)
+    return {"dim": 2, "n": [n, n], "lo": list(lo), "hi": list(hi),
+            "data": np.asarray(fn(pts), dtype=dtype).reshape(n, n)}
