@@ -1,0 +1,215 @@
+/*
+ * pdd.h - C ABI of the MI355X (gfx950) first-stage PDD nodal solver.
+ *
+ * The library estimates, at interfacial nodes x0, the solution of the
+ * elliptic Dirichlet problem (paper Sec. 2.1, eq. F:EllipticBVP with
+ * a_ij = sigma^2 delta_ij)
+ *     (1/2) sigma^2 Lap u + b . grad u + c u = f  in Omega,   u = g on dOmega
+ * through its probabilistic representation (eq. F:Dynkin)
+ *     u(x0) = E[ g(X_tau) Y_tau + Z_tau ],  Y = exp(int c dt), Z = -int f Y dt,
+ * sampling independent Euler-Maruyama paths (Sec. 2.3, Alg. 1, eq. F:E_M)
+ * with a Brownian-bridge (default), shifted-boundary (Alg. 1) or naive exit
+ * test, and the correction estimator of the multigrid-like iteration, where
+ * a previous approximation u_prev is the control variate (eqs. F:Statistics_VR,
+ * F:xiControlVariate; Alg. 4, the nodal solves inside the outer loop).
+ *
+ * Conventions
+ *  - All functions return a pdd_status; 0 is success. No exception crosses
+ *    the ABI. On failure pdd_last_error() returns a thread-local message.
+ *  - Invalid arguments are rejected before anything is enqueued.
+ *  - "device" pointers are HIP device memory of the context's GPU; "host"
+ *    pointers are ordinary CPU memory. `stream` is a hipStream_t passed as
+ *    void* (NULL = the default stream). Solves are asynchronous on `stream`:
+ *    outputs are valid once the stream has been synchronised.
+ *  - A context owns device scratch; solves issued through one context are
+ *    ordered on the device (each waits for the previous one), whatever
+ *    stream they use. Use one context per concurrent user.
+ *  - Limits: nodes < 2^32, paths per node < 2^32, path_offset + n_paths
+ *    <= 2^32, stream_id < 2^28, steps per path < 2^31.
+ */
+#ifndef PDD_H
+#define PDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdd_status;
+#define PDD_OK 0
+#define PDD_E_INVALID (-1)     /* bad argument (node outside Omega, dt <= 0, ...) */
+#define PDD_E_NOMEM (-2)       /* device or pinned allocation failed */
+#define PDD_E_HIP (-3)         /* a HIP runtime call failed */
+#define PDD_E_UNSUPPORTED (-4) /* valid but not implemented combination */
+#define PDD_E_BUSY (-5)        /* resource in use */
+#define PDD_E_INTERNAL (-6)
+
+typedef struct pdd_ctx pdd_ctx;
+typedef struct pdd_problem pdd_problem;
+
+enum { PDD_DOMAIN_BOX = 0, PDD_DOMAIN_BALL = 1 };
+/* Exit tests: Brownian bridge between consecutive steps (per flat face
+ * p = exp(-2 a a' / (sigma^2 h)), faces combined as independent), the
+ * Gobet-Menozzi shifted boundary of Alg. 1 (stop when within
+ * 0.5826 sigma sqrt(h) of the boundary), or the naive test (stop when a step
+ * lands outside). */
+enum { PDD_EXIT_BRIDGE = 0, PDD_EXIT_SHIFT = 1, PDD_EXIT_NAIVE = 2 };
+/* Law of the increments: Gaussian (Box-Muller) or +-1 (testing only). */
+enum { PDD_LAW_GAUSS = 0, PDD_LAW_RADEMACHER = 1 };
+/* Path arithmetic: FP32 (per-path integrals and node sums in FP64) or FP64. */
+enum { PDD_FP32 = 0, PDD_FP64 = 1 };
+enum { PDD_DTYPE_F32 = 0, PDD_DTYPE_F64 = 1 };
+
+/* Solve flags. */
+#define PDD_PLAIN_ALONGSIDE 1u /* correction solve: also score phi, report rho, VR */
+
+#define PDD_MAX_TRIG 16
+#define PDD_MAX_MONO 8
+
+/* amp * prod_{d<dim} sin(k[d] x_d + phase[d]) */
+typedef struct {
+    double amp;
+    double k[3];
+    double phase[3];
+} pdd_trig_term;
+
+/* coef * prod_{d<dim} x_d^e[d], 0 <= e[d] <= 8 */
+typedef struct {
+    double coef;
+    int32_t e[3];
+} pdd_mono_term;
+
+/* Problem descriptor (eq. F:EllipticBVP; SDE of eq. F:SDE with diffusion
+ * sigma I). The drift is affine, b(x) = b0 + B x (B row-major: b_i = b0_i +
+ * sum_j B[i][j] x_j); the killing rate is c(x) = c_a + c_b |x|^2 (c <= 0 keeps
+ * the problem well posed). The source and boundary data follow from a
+ * manufactured function U (trig + monomial terms):
+ *   f = (1/2) sigma^2 Lap U + b.grad U + c U + sum(fx),   g = U + sum(gx),
+ * so U is the exact solution when fx and gx are empty. The caller's struct
+ * is copied; it is not retained. */
+typedef struct {
+    int32_t dim;    /* 2 or 3 */
+    int32_t domain; /* PDD_DOMAIN_BOX: [lo, hi]; PDD_DOMAIN_BALL: |x - center| < radius */
+    double lo[3], hi[3];
+    double center[3], radius;
+    double sigma; /* > 0 */
+    double b0[3];
+    double B[3][3];
+    double c_a, c_b;
+    int32_t n_trig, n_mono, n_fx, n_gx;
+    pdd_trig_term trig[PDD_MAX_TRIG];
+    pdd_mono_term mono[PDD_MAX_MONO];
+    pdd_mono_term fx[PDD_MAX_MONO];
+    pdd_mono_term gx[PDD_MAX_MONO];
+    uint64_t seed; /* Philox4x32-10 key (lo word, hi word) */
+} pdd_problem_desc;
+
+/* Values on a uniform grid of n[0] x n[1] (x n[2]) points spanning [lo, hi],
+ * x fastest, in device memory. Interpolated bilinearly (trilinearly): cell
+ * index clamped to the grid, in-cell weight clamped to [0, 1]. Borrowed: the
+ * caller keeps `data` alive until the solve's stream has completed. The grid
+ * must cover the bounding box of Omega. */
+typedef struct {
+    int32_t dim;
+    int32_t dtype; /* PDD_DTYPE_F32 or PDD_DTYPE_F64 */
+    int32_t n[3];  /* >= 2 each */
+    double lo[3], hi[3];
+    const void *data;
+} pdd_grid;
+
+/* Launch shape of the path kernel (0 = library default / tuning cache). */
+typedef struct {
+    int32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t blocks_per_cu;/* persistent workgroups per compute unit */
+    int32_t grab;         /* paths a wavefront takes from the queue at a time */
+    int32_t max_launch_paths; /* cap on paths per path-kernel launch (0 = 2^27; records
+                                 given by the caller: no cap) */
+} pdd_tuning;
+
+typedef struct {
+    double dt;                          /* time step h > 0 */
+    uint64_t n_paths;                   /* paths per node (used when n_paths_per_node is NULL) */
+    const uint64_t *n_paths_per_node;   /* host, n_nodes counts, or NULL */
+    uint64_t path_offset;               /* index of each node's first path */
+    uint32_t stream_id;                 /* iterate / request index in the RNG counter */
+    int32_t precision;                  /* PDD_FP32 or PDD_FP64 */
+    int32_t exit_mode;                  /* PDD_EXIT_* */
+    int32_t law;                        /* PDD_LAW_* */
+    uint64_t max_steps;                 /* 0 = 2^26 */
+    uint32_t flags;                     /* PDD_PLAIN_ALONGSIDE */
+    int32_t reserved;
+    /* Optional per-path records (device, NULL = not kept). Path jj of node i
+     * sits at slot s = sum_{i'<i} N_i' + jj: rec_phi[s] = phi, rec_e[s] = e
+     * (correction solves), rec_steps[s] = exit step | (capped << 31). */
+    double *rec_phi;
+    double *rec_e;
+    uint32_t *rec_steps;
+    const pdd_tuning *tuning;           /* NULL = default / tuned */
+} pdd_solve_opts;
+
+/* Per-node result (Sec. 2.2 eq. F:Statistical_error; Sec. 2.3 eqs.
+ * F:Variance_Reduction, F:Rho). Plain solve: mean/var/stderr of phi.
+ * Correction solve: mean = u_prev(x0) + mean(e), var/stderr of e; with
+ * PDD_PLAIN_ALONGSIDE also mean_plain/var_plain of phi, cov = Cov[phi, xi]
+ * and rho = rho[phi, xi] for the control variate xi = u_prev(x0) + e - phi,
+ * vr = var_plain / var and vr_opt = 1 / (1 - rho^2). Unused fields are NaN.
+ * sums: Neumaier pairs (sum, compensation) of phi, phi^2, e, e^2, phi*e, so
+ * that results of disjoint path ranges can be merged exactly enough. */
+typedef struct {
+    int64_t n, n_capped, steps_sum;
+    double mean, var, stderr_, mean_steps;
+    double mean_plain, var_plain, cov, rho, vr, vr_opt;
+    double sums[10];
+} pdd_node_stats;
+
+/* One item of a batched solve. */
+typedef struct {
+    pdd_problem *problem;
+    const double *nodes;        /* host, n_nodes x dim, row-major */
+    int64_t n_nodes;
+    const pdd_solve_opts *opts;
+    const pdd_grid *u_prev;     /* both NULL: plain estimator */
+    const pdd_grid *resid;
+    pdd_node_stats *out;        /* device, n_nodes entries */
+} pdd_work_item;
+
+/* Creates a context on HIP device `hip_device` (made current for the call). */
+pdd_status pdd_init(pdd_ctx **out, int hip_device);
+/* Waits for the context's work and frees its scratch. NULL is a no-op. */
+void pdd_shutdown(pdd_ctx *ctx);
+
+/* Validates and uploads a problem (eq. F:EllipticBVP). */
+pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_problem **out);
+/* Frees a problem; the caller ensures no solve using it is in flight. */
+void pdd_destroy_problem(pdd_problem *problem);
+
+/* Plain estimator phi at n_nodes nodes (host array, n_nodes x dim). Every
+ * node must lie strictly inside Omega. `out` is device memory of n_nodes
+ * entries. n_nodes == 0 is a no-op. */
+pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
+                           const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
+
+/* Correction estimator with u_prev as control variate and the residual
+ * r = f - (L + c) u_prev, both on grids (same dim as the problem). */
+pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,
+                                const pdd_grid *resid, const double *nodes, int64_t n_nodes,
+                                const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
+
+/* Several problems in one persistent launch per (dim, precision, estimator)
+ * group. Each item's results equal those of its own solve call. */
+pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items,
+                           void *stream);
+
+/* Times the path kernel over launch shapes on a small copy of the given
+ * solve (synchronous) and writes the fastest. */
+pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nodes,
+                        const pdd_solve_opts *opts, pdd_tuning *out);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *pdd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDD_H */

@@ -1,0 +1,630 @@
+// Path kernel of the first-stage PDD nodal solve on gfx950.
+//
+// One path per lane. A persistent wavefront takes paths from a global queue
+// (one atomic per `grab` paths) and refills a lane as soon as its path has
+// ended, so waves stay full whatever the spread of exit times. Each path is
+// the Euler-Maruyama walk of Alg. 1 (eq. F:E_M, coefficients at the left
+// point) with the bridge, shifted-boundary or naive exit test, carrying the
+// killing weight Y, the source integral Z and, for the correction estimator,
+// the residual integral R (Sec. 2.3; eq. F:Dynkin). Every path writes its
+// score and exit step to its own slot; the per-node sums are formed afterwards
+// in a fixed order, so results do not depend on scheduling.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) in registers, key =
+// problem seed (wave-uniform), counter = (step block, path, node, stream tag).
+// In 2D one block gives the two normals of two consecutive steps (words 0,1
+// then 2,3), so a lane starts a new path only at an even step; in 3D one block
+// per step. The bridge uniform of step s is word s mod 4 of the tag-1 block
+// s/4, drawn only when a face is live and cached for the next steps.
+// Box-Muller (1958) on the VALU: in FP32 with the hardware log2, sqrt, sin
+// and cos (which take revolutions, so 2 pi u needs no multiply).
+#include "pdd_internal.hpp"
+
+namespace pdd {
+namespace {
+
+constexpr float kLn2f = 0.6931471805599453f;
+constexpr float kLog2ef = 1.4426950408889634f;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct Block4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+// Philox4x32-10: two 32x32->64 products per round (v_mad_u64_u32), the key
+// bumped by the Weyl constants after each round.
+__device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+template <class T>
+struct Arith;
+
+// FP32 path arithmetic: 24-bit uniforms, hardware transcendentals.
+template <>
+struct Arith<float> {
+    __device__ static __forceinline__ float unif(uint32_t w)
+    {
+        return fmaf((float)(w >> 8), 0x1.0p-24f, 0x1.0p-25f);
+    }
+    __device__ static __forceinline__ float unif_bridge(uint32_t w)
+    {
+        return fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);
+    }
+    __device__ static __forceinline__ float radius(uint32_t w)
+    {
+        return __builtin_amdgcn_sqrtf(-2.0f * kLn2f * __builtin_amdgcn_logf(unif(w)));
+    }
+    __device__ static __forceinline__ void box_muller(uint32_t a, uint32_t b, float &n0, float &n1)
+    {
+        const float r = radius(a);
+        const float t = unif(b);  // revolutions
+        n0 = r * __builtin_amdgcn_cosf(t);
+        n1 = r * __builtin_amdgcn_sinf(t);
+    }
+    __device__ static __forceinline__ float box_muller_cos(uint32_t a, uint32_t b)
+    {
+        return radius(a) * __builtin_amdgcn_cosf(unif(b));
+    }
+    __device__ static __forceinline__ void trig(const DevTrig<float> &t, int d, float x, float &s,
+                                                float &c)
+    {
+        const float rev = __builtin_amdgcn_fractf(fmaf(t.krev[d], x, t.phrev[d]));
+        s = __builtin_amdgcn_sinf(rev);
+        c = __builtin_amdgcn_cosf(rev);
+    }
+    __device__ static __forceinline__ float sine(const DevTrig<float> &t, int d, float x)
+    {
+        return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(fmaf(t.krev[d], x, t.phrev[d])));
+    }
+    __device__ static __forceinline__ float exp_neg(float x)
+    {
+        return __builtin_amdgcn_exp2f(-x * kLog2ef);
+    }
+    __device__ static __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// FP64 path arithmetic: 32-bit uniforms, correctly rounded-ish library calls.
+template <>
+struct Arith<double> {
+    __device__ static __forceinline__ double unif(uint32_t w)
+    {
+        return ((double)w + 0.5) * 0x1.0p-32;
+    }
+    __device__ static __forceinline__ double unif_bridge(uint32_t w) { return unif(w); }
+    __device__ static __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0,
+                                                      double &n1)
+    {
+        const double r = sqrt(-2.0 * log(unif(a)));
+        const double th = kTwoPi * unif(b);
+        double s, c;
+        sincos(th, &s, &c);
+        n0 = r * c;
+        n1 = r * s;
+    }
+    __device__ static __forceinline__ double box_muller_cos(uint32_t a, uint32_t b)
+    {
+        return sqrt(-2.0 * log(unif(a))) * cos(kTwoPi * unif(b));
+    }
+    __device__ static __forceinline__ void trig(const DevTrig<double> &t, int d, double x,
+                                                double &s, double &c)
+    {
+        sincos(t.k[d] * x + t.ph[d], &s, &c);
+    }
+    __device__ static __forceinline__ double sine(const DevTrig<double> &t, int d, double x)
+    {
+        return sin(t.k[d] * x + t.ph[d]);
+    }
+    __device__ static __forceinline__ double exp_neg(double x) { return exp(-x); }
+    __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
+};
+
+template <class T>
+__device__ __forceinline__ T ipow(T x, int n)
+{
+    T r = (T)1;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T mono_value(const DevMono<T> &q, const T *x)
+{
+    T v = q.coef;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v *= ipow(x[d], q.e[d]);
+    return v;
+}
+
+// b(x), c(x) and, when asked, f(x) = (1/2) sigma^2 Lap U + b.grad U + c U + fx.
+template <class T, int D>
+__device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x, T *b, T &c,
+                                             T &f, bool want_f)
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        T v = P.b0[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v += P.B[i][j] * x[j];
+        b[i] = v;
+    }
+    T r2 = (T)0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) r2 += x[d] * x[d];
+    c = P.c_a + P.c_b * r2;
+    if (!want_f) return;
+    T u = (T)0, lap = (T)0, gr[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gr[d] = (T)0;
+    for (int m = 0; m < P.n_trig; ++m) {
+        const DevTrig<T> &t = P.trig[m];
+        T s[D], co[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) Arith<T>::trig(t, d, x[d], s[d], co[d]);
+        T val = t.amp;
+#pragma unroll
+        for (int d = 0; d < D; ++d) val *= s[d];
+        u += val;
+        lap -= t.ksq * val;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T g = t.amp * t.k[d] * co[d];
+#pragma unroll
+            for (int e = 0; e < D; ++e)
+                if (e != d) g *= s[e];
+            gr[d] += g;
+        }
+    }
+    for (int m = 0; m < P.n_mono; ++m) {
+        const DevMono<T> &q = P.mono[m];
+        T pw[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) pw[d] = ipow(x[d], q.e[d]);
+        T val = q.coef;
+#pragma unroll
+        for (int d = 0; d < D; ++d) val *= pw[d];
+        u += val;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int ed = q.e[d];
+            if (ed >= 1) {
+                T g = q.coef * (T)ed * ipow(x[d], ed - 1);
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    if (e != d) g *= pw[e];
+                gr[d] += g;
+            }
+            if (ed >= 2) {
+                T l = q.coef * (T)(ed * (ed - 1)) * ipow(x[d], ed - 2);
+#pragma unroll
+                for (int e = 0; e < D; ++e)
+                    if (e != d) l *= pw[e];
+                lap += l;
+            }
+        }
+    }
+    T acc = P.half_s2 * lap;
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc += b[d] * gr[d];
+    acc += c * u;
+    for (int m = 0; m < P.n_fx; ++m) acc += mono_value<T, D>(P.fx[m], x);
+    f = acc;
+}
+
+// g = U + gx at a boundary point.
+template <class T, int D>
+__device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x)
+{
+    T u = (T)0;
+    for (int m = 0; m < P.n_trig; ++m) {
+        const DevTrig<T> &t = P.trig[m];
+        T v = t.amp;
+#pragma unroll
+        for (int d = 0; d < D; ++d) v *= Arith<T>::sine(t, d, x[d]);
+        u += v;
+    }
+    for (int m = 0; m < P.n_mono; ++m) u += mono_value<T, D>(P.mono[m], x);
+    for (int m = 0; m < P.n_gx; ++m) u += mono_value<T, D>(P.gx[m], x);
+    return u;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
+{
+    int i[D];
+    T w[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const T t = (x[d] - g.lo[d]) * g.inv[d];
+        const T fl = floor(t);
+        int id = (int)fl;
+        if (fl < (T)0) id = 0;
+        if (fl > (T)(g.n[d] - 2)) id = g.n[d] - 2;
+        T wd = t - (T)id;
+        wd = wd < (T)0 ? (T)0 : (wd > (T)1 ? (T)1 : wd);
+        i[d] = id;
+        w[d] = wd;
+    }
+    const int nx = g.n[0];
+    if (D == 2) {
+        const T *r0 = g.data + (size_t)i[1] * nx + i[0];
+        const T *r1 = r0 + nx;
+        return ((T)1 - w[1]) * (((T)1 - w[0]) * r0[0] + w[0] * r0[1]) +
+               w[1] * (((T)1 - w[0]) * r1[0] + w[0] * r1[1]);
+    }
+    const int ny = g.n[1];
+    T acc = (T)0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        T layer = (T)0;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const T *row = g.data + ((size_t)(i[2 % D] + dz) * ny + (i[1] + dy)) * nx + i[0];
+            const T line = ((T)1 - w[0]) * row[0] + w[0] * row[1];
+            layer += (dy ? w[1] : (T)1 - w[1]) * line;
+        }
+        acc += (dz ? w[2 % D] : (T)1 - w[2 % D]) * layer;
+    }
+    return acc;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T inner_distance(const DevProblem<T> &P, const T *x)
+{
+    if (P.domain == kBox) {
+        T m = x[0] - P.lo[0];
+        m = fmin(m, P.hi[0] - x[0]);
+#pragma unroll
+        for (int d = 1; d < D; ++d) {
+            m = fmin(m, x[d] - P.lo[d]);
+            m = fmin(m, P.hi[d] - x[d]);
+        }
+        return m;
+    }
+    T r2 = (T)0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const T t = x[d] - P.center[d];
+        r2 += t * t;
+    }
+    return P.radius - Arith<T>::sqrt_(r2);
+}
+
+template <class T, int D>
+__device__ __forceinline__ void radial(const DevProblem<T> &P, const T *x, T *out)
+{
+    T r2 = (T)0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const T t = x[d] - P.center[d];
+        r2 += t * t;
+    }
+    const T r = Arith<T>::sqrt_(r2);
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        out[d] = r > (T)0 ? P.center[d] + P.radius * ((x[d] - P.center[d]) / r)
+                          : P.center[d] + (d == 0 ? P.radius : (T)0);
+}
+
+// Closest boundary point: inside a box the nearest face (ties to the lowest
+// face index, faces ordered x-lo, x-hi, y-lo, ...), outside the clamp.
+template <class T, int D>
+__device__ __forceinline__ void project(const DevProblem<T> &P, const T *x, T *out)
+{
+    if (P.domain == kBall) {
+        radial<T, D>(P, x, out);
+        return;
+    }
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        out[d] = x[d];
+        inside = inside && (x[d] > P.lo[d]) && (x[d] < P.hi[d]);
+    }
+    if (inside) {
+        int best = 0;
+        T bd = x[0] - P.lo[0];
+#pragma unroll
+        for (int f = 1; f < 2 * D; ++f) {
+            const int d = f >> 1;
+            const T t = (f & 1) ? P.hi[d] - x[d] : x[d] - P.lo[d];
+            if (t < bd) {
+                bd = t;
+                best = f;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if ((best >> 1) == d) out[d] = (best & 1) ? P.hi[d] : P.lo[d];
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) out[d] = fmin(fmax(out[d], P.lo[d]), P.hi[d]);
+    }
+}
+
+// State of the path a lane is walking.
+template <class T, int D, bool CV>
+struct Walker {
+    T X[D], Xt[D];
+    T Y;
+    double Z, R;
+    uint64_t slot;
+    uint32_t k, j, node, capped;
+    uint32_t bb_blk;
+    uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
+
+    __device__ __forceinline__ void start(const PathArgs<T> &a, uint64_t s)
+    {
+        slot = s;
+        uint64_t jj;
+        if (a.node_start == nullptr) {
+            if (a.total_slots <= 0xffffffffull) {
+                const uint32_t q = (uint32_t)s / (uint32_t)a.uniform_n;
+                node = q;
+                jj = (uint32_t)s - q * (uint32_t)a.uniform_n;
+            } else {
+                node = (uint32_t)(s / a.uniform_n);
+                jj = s - (uint64_t)node * a.uniform_n;
+            }
+        } else {
+            uint32_t lo = 0, hi = a.n_nodes;  // node_start[lo] <= s < node_start[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.node_start[mid] <= s)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            node = lo;
+            jj = s - a.node_start[lo];
+        }
+        j = (uint32_t)(a.path_offset + jj);
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
+        Y = (T)1;
+        Z = 0.0;
+        R = 0.0;
+        k = 0;
+        capped = 0;
+        bb_blk = 0xffffffffu;
+    }
+
+    __device__ __forceinline__ T bridge_uniform(const PathArgs<T> &a, uint32_t s)
+    {
+        const uint32_t blk = s >> 2;
+        if (blk != bb_blk) {
+            const Block4 q = philox(blk, j, node, a.stream_tag | 1u, a.prob.key0, a.prob.key1);
+            bw01 = (uint64_t)q.w0 | ((uint64_t)q.w1 << 32);
+            bw23 = (uint64_t)q.w2 | ((uint64_t)q.w3 << 32);
+            bb_blk = blk;
+        }
+        // word s mod 4, picked with a shift (a select chain becomes a stack array)
+        const uint32_t w = (uint32_t)(((s & 2) ? bw23 : bw01) >> ((s & 1) << 5));
+        return Arith<T>::unif_bridge(w);
+    }
+
+    // One step of the walk with the words that feed its normals. Returns
+    // false when the path has ended (exit point in Xt).
+    __device__ __forceinline__ bool step(const PathArgs<T> &a, uint32_t wa, uint32_t wb,
+                                         uint32_t wc, uint32_t wd)
+    {
+        const DevProblem<T> &P = a.prob;
+        if (a.exit_mode == kExitShift && inner_distance<T, D>(P, X) <= a.gm_thresh) {
+            project<T, D>(P, X, Xt);
+            return false;
+        }
+        if (k == a.max_steps) {
+            capped = 1;
+            project<T, D>(P, X, Xt);
+            return false;
+        }
+        T n[D];
+        if (a.law == kLawGauss) {
+            Arith<T>::box_muller(wa, wb, n[0], n[1]);
+            if (D == 3) n[2 % D] = Arith<T>::box_muller_cos(wc, wd);
+        } else {
+            n[0] = (wa >> 31) ? (T)1 : (T)-1;
+            n[1] = (wb >> 31) ? (T)1 : (T)-1;
+            if (D == 3) n[2 % D] = (wc >> 31) ? (T)1 : (T)-1;
+        }
+        T b[D], c, f = (T)0;
+        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0);
+        const T hY = a.h * Y;
+        if (a.score_plain) Z -= (double)(hY * f);
+        if (CV) R += (double)(hY * interp<T, D>(a.resid, X));
+        Y = Y + hY * c;
+        T Xn[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) Xn[d] = X[d] + a.h * b[d] + a.sig_sqh * n[d];
+        const uint32_t s = k;
+        k = k + 1;
+
+        if (a.exit_mode != kExitShift) {
+            if (P.domain == kBox) {
+                bool inside = true;
+#pragma unroll
+                for (int d = 0; d < D; ++d) inside = inside && (Xn[d] > P.lo[d]) && (Xn[d] < P.hi[d]);
+                if (!inside) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) Xt[d] = fmin(fmax(Xn[d], P.lo[d]), P.hi[d]);
+                    return false;
+                }
+                if (a.exit_mode == kExitBridge) {
+                    T prod[2 * D];
+                    T mp;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        prod[2 * d] = (X[d] - P.lo[d]) * (Xn[d] - P.lo[d]);
+                        prod[2 * d + 1] = (P.hi[d] - X[d]) * (P.hi[d] - Xn[d]);
+                    }
+                    mp = prod[0];
+#pragma unroll
+                    for (int q = 1; q < 2 * D; ++q) mp = fmin(mp, prod[q]);
+                    if (mp * a.two_over_s2h <= a.bridge_thresh) {
+                        T Pe = (T)0, bestp = (T)-1;
+                        int bestf = 0;
+#pragma unroll
+                        for (int q = 0; q < 2 * D; ++q) {
+                            const T arg = prod[q] * a.two_over_s2h;
+                            if (arg <= a.bridge_thresh) {
+                                const T p = Arith<T>::exp_neg(arg);
+                                Pe = Pe + p * ((T)1 - Pe);
+                                if (p > bestp) {
+                                    bestp = p;
+                                    bestf = q;
+                                }
+                            }
+                        }
+                        if (bridge_uniform(a, s) < Pe) {
+#pragma unroll
+                            for (int d = 0; d < D; ++d)
+                                Xt[d] = (bestf >> 1) == d ? ((bestf & 1) ? P.hi[d] : P.lo[d]) : Xn[d];
+                            return false;
+                        }
+                    }
+                }
+            } else {
+                T r2n = (T)0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const T t = Xn[d] - P.center[d];
+                    r2n += t * t;
+                }
+                if (!(r2n < P.radius2)) {
+                    radial<T, D>(P, Xn, Xt);
+                    return false;
+                }
+                if (a.exit_mode == kExitBridge) {
+                    const T an = P.radius - Arith<T>::sqrt_(r2n);
+                    const T a0 = inner_distance<T, D>(P, X);
+                    const T arg = a0 * an * a.two_over_s2h;
+                    if (arg <= a.bridge_thresh) {
+                        const T Pe = Arith<T>::exp_neg(arg);
+                        if (bridge_uniform(a, s) < Pe) {
+                            radial<T, D>(P, Xn, Xt);
+                            return false;
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) X[d] = Xn[d];
+        return true;
+    }
+
+    // Score the ended path and write its record.
+    __device__ __forceinline__ void finish(const PathArgs<T> &a)
+    {
+        const T gv = boundary_value<T, D>(a.prob, Xt);
+        const uint64_t r = slot - a.rec_base;
+        if (a.score_plain) a.rec_phi[r] = (double)gv * (double)Y + Z;
+        if (CV) {
+            const T up = interp<T, D>(a.u_prev, Xt);
+            a.rec_e[r] = ((double)gv - (double)up) * (double)Y - R;
+        }
+        a.rec_steps[r] = k | (capped ? kCappedBit : 0u);
+    }
+};
+
+template <class T, int D, bool CV>
+__global__ void __launch_bounds__(256) path_kernel(const PathArgs<T> a)
+{
+    const int lane = __lane_id();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    Walker<T, D, CV> w;
+    int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
+    uint32_t pool_next = 0, pool_end = 0;
+    bool exhausted = false;
+
+    for (;;) {
+        if (st == 2) {
+            w.finish(a);
+            st = 0;
+        }
+        const uint64_t idle = __ballot(st == 0);
+        if (idle) {
+            if (pool_next == pool_end && !exhausted) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(a.counter, (uint32_t)a.grab);
+                base = __builtin_amdgcn_readfirstlane(base);
+                if (base >= a.launch_slots) {
+                    exhausted = true;
+                } else {
+                    pool_next = base;
+                    pool_end = min(base + (uint32_t)a.grab, a.launch_slots);
+                }
+            }
+            const uint32_t avail = pool_end - pool_next;
+            const uint32_t rank = (uint32_t)__popcll(idle & below);
+            if (st == 0 && rank < avail) {
+                w.start(a, a.slot_begin + pool_next + rank);
+                st = 1;
+            }
+            pool_next += min(avail, (uint32_t)__popcll(idle));
+        }
+        if (__ballot(st == 1) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        if (st == 1) {
+            if (D == 2) {
+                // One block feeds this step (words 0,1) and the next (words 2,3).
+                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, a.prob.key0, a.prob.key1);
+                if (!w.step(a, q.w0, q.w1, 0u, 0u))
+                    st = 2;
+                else if (!w.step(a, q.w2, q.w3, 0u, 0u))
+                    st = 2;
+            } else {
+                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, a.prob.key0, a.prob.key1);
+                if (!w.step(a, q.w0, q.w1, q.w2, q.w3)) st = 2;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+template <class T, int D, bool CV>
+hipError_t launch_path_kernel(const PathArgs<T> &a, int grid, int block, hipStream_t s)
+{
+    static_assert(sizeof(PathArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
+    hipLaunchKernelGGL((path_kernel<T, D, CV>), dim3(grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int D, bool CV>
+const void *path_kernel_symbol()
+{
+    return reinterpret_cast<const void *>(&path_kernel<T, D, CV>);
+}
+
+#define PDD_INSTANTIATE(T, D, CV)                                                              \
+    template hipError_t launch_path_kernel<T, D, CV>(const PathArgs<T> &, int, int, hipStream_t); \
+    template const void *path_kernel_symbol<T, D, CV>();
+
+PDD_INSTANTIATE(float, 2, false)
+PDD_INSTANTIATE(float, 2, true)
+PDD_INSTANTIATE(float, 3, false)
+PDD_INSTANTIATE(float, 3, true)
+PDD_INSTANTIATE(double, 2, false)
+PDD_INSTANTIATE(double, 2, true)
+PDD_INSTANTIATE(double, 3, false)
+PDD_INSTANTIATE(double, 3, true)
+
+}  // namespace pdd

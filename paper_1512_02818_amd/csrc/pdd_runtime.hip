@@ -1,0 +1,611 @@
+// Host runtime of the first-stage PDD nodal solver: the C ABI of pdd.h.
+//
+// A solve turns its nodes and path counts into a path space of slots (node
+// after node, path after path), cuts it into launches that fit the record
+// scratch, and per launch runs the persistent path kernel and the per-node
+// reduction; a finalize kernel turns the node accumulators into statistics.
+// Everything is enqueued on the caller's stream; host inputs travel through a
+// pinned staging buffer owned by the context.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pdd.h"
+#include "pdd_internal.hpp"
+
+using namespace pdd;
+
+namespace {
+
+thread_local std::string g_error;
+
+pdd_status fail(pdd_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(PDD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr double kGmShift = 0.5826;                    // Alg. 1 boundary shift
+constexpr double kBridgeSkip = 24.953298500158186;     // 36 ln 2: p < 2^-36 skipped
+constexpr uint64_t kDefaultMaxSteps = 1ull << 26;
+constexpr uint64_t kScratchSlots = 1ull << 27;         // record slots per launch
+constexpr uint64_t kMaxLaunchSlots = 1ull << 31;
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct pdd_ctx {
+    int device = 0;
+    int n_cu = 0;
+    hipEvent_t done = nullptr;    // end of the last solve
+    hipEvent_t staged = nullptr;  // last copy out of the staging buffer
+    bool any_done = false, any_staged = false;
+    DeviceBuffer nodes, starts, acc, counters, rec;
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+    std::map<std::tuple<const void *, int>, int> occupancy;
+};
+
+struct pdd_problem {
+    pdd_ctx *ctx = nullptr;
+    pdd_problem_desc desc{};
+    DevProblem<float> pf{};
+    DevProblem<double> pd{};
+};
+
+namespace {
+
+pdd_status ensure(pdd_ctx *ctx, DeviceBuffer &b, size_t bytes)
+{
+    if (bytes <= b.cap) return PDD_OK;
+    // the previous solve may still read the old buffer
+    if (ctx->any_done) HIP_TRY(hipEventSynchronize(ctx->done));
+    if (b.ptr) HIP_TRY(hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.cap = 0;
+    size_t want = std::max<size_t>(bytes, 4096);
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(PDD_E_NOMEM, "hipMalloc of %zu bytes failed", want);
+    }
+    b.cap = want;
+    return PDD_OK;
+}
+
+pdd_status ensure_stage(pdd_ctx *ctx, size_t bytes)
+{
+    if (ctx->any_staged) HIP_TRY(hipEventSynchronize(ctx->staged));
+    if (bytes <= ctx->stage_cap) return PDD_OK;
+    if (ctx->stage) HIP_TRY(hipHostFree(ctx->stage));
+    ctx->stage = nullptr;
+    ctx->stage_cap = 0;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&ctx->stage, want, hipHostMallocDefault) != hipSuccess) {
+        ctx->stage = nullptr;
+        return fail(PDD_E_NOMEM, "pinned allocation of %zu bytes failed", want);
+    }
+    ctx->stage_cap = want;
+    return PDD_OK;
+}
+
+template <class T>
+void fill_problem(const pdd_problem_desc &d, DevProblem<T> &p)
+{
+    std::memset(&p, 0, sizeof p);
+    p.dim = d.dim;
+    p.domain = d.domain;
+    p.n_trig = d.n_trig;
+    p.n_mono = d.n_mono;
+    p.n_fx = d.n_fx;
+    p.n_gx = d.n_gx;
+    p.key0 = (uint32_t)(d.seed & 0xffffffffu);
+    p.key1 = (uint32_t)(d.seed >> 32);
+    for (int i = 0; i < 3; ++i) {
+        p.lo[i] = (T)d.lo[i];
+        p.hi[i] = (T)d.hi[i];
+        p.center[i] = (T)d.center[i];
+        p.b0[i] = (T)d.b0[i];
+        for (int j = 0; j < 3; ++j) p.B[i][j] = (T)d.B[i][j];
+    }
+    p.radius = (T)d.radius;
+    p.radius2 = (T)(d.radius * d.radius);
+    p.half_s2 = (T)(0.5 * d.sigma * d.sigma);
+    p.c_a = (T)d.c_a;
+    p.c_b = (T)d.c_b;
+    const double inv2pi = 0.15915494309189533577;
+    for (int m = 0; m < d.n_trig; ++m) {
+        const pdd_trig_term &t = d.trig[m];
+        DevTrig<T> &q = p.trig[m];
+        q.amp = (T)t.amp;
+        double ksq = 0.0;
+        for (int k = 0; k < d.dim; ++k) ksq += t.k[k] * t.k[k];
+        q.ksq = (T)ksq;
+        for (int k = 0; k < 3; ++k) {
+            q.k[k] = (T)t.k[k];
+            q.ph[k] = (T)t.phase[k];
+            q.krev[k] = (T)(t.k[k] * inv2pi);
+            q.phrev[k] = (T)(t.phase[k] * inv2pi);
+        }
+    }
+    auto cp = [](const pdd_mono_term *src, DevMono<T> *dst, int n) {
+        for (int m = 0; m < n; ++m) {
+            dst[m].coef = (T)src[m].coef;
+            for (int k = 0; k < 3; ++k) dst[m].e[k] = src[m].e[k];
+        }
+    };
+    cp(d.mono, p.mono, d.n_mono);
+    cp(d.fx, p.fx, d.n_fx);
+    cp(d.gx, p.gx, d.n_gx);
+}
+
+bool finite3(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+pdd_status check_desc(const pdd_problem_desc *d)
+{
+    if (!d) return fail(PDD_E_INVALID, "desc is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(PDD_E_INVALID, "dim must be 2 or 3 (got %d)", d->dim);
+    if (d->domain == PDD_DOMAIN_BOX) {
+        for (int i = 0; i < d->dim; ++i)
+            if (!(d->lo[i] < d->hi[i]) || !std::isfinite(d->lo[i]) || !std::isfinite(d->hi[i]))
+                return fail(PDD_E_INVALID, "box needs finite lo < hi on axis %d", i);
+    } else if (d->domain == PDD_DOMAIN_BALL) {
+        if (!(d->radius > 0.0) || !std::isfinite(d->radius) || !finite3(d->center, d->dim))
+            return fail(PDD_E_INVALID, "ball needs a finite center and radius > 0");
+    } else {
+        return fail(PDD_E_INVALID, "unknown domain %d", d->domain);
+    }
+    if (!(d->sigma > 0.0) || !std::isfinite(d->sigma)) return fail(PDD_E_INVALID, "sigma must be > 0");
+    if (d->n_trig < 0 || d->n_trig > PDD_MAX_TRIG || d->n_mono < 0 || d->n_mono > PDD_MAX_MONO ||
+        d->n_fx < 0 || d->n_fx > PDD_MAX_MONO || d->n_gx < 0 || d->n_gx > PDD_MAX_MONO)
+        return fail(PDD_E_INVALID, "term counts out of range");
+    auto mono_ok = [&](const pdd_mono_term *m, int n) {
+        for (int q = 0; q < n; ++q) {
+            if (!std::isfinite(m[q].coef)) return false;
+            for (int k = 0; k < 3; ++k)
+                if (m[q].e[k] < 0 || m[q].e[k] > 8 || (k >= d->dim && m[q].e[k] != 0)) return false;
+        }
+        return true;
+    };
+    if (!mono_ok(d->mono, d->n_mono) || !mono_ok(d->fx, d->n_fx) || !mono_ok(d->gx, d->n_gx))
+        return fail(PDD_E_INVALID, "monomial exponents must be 0..8 (and 0 beyond dim)");
+    for (int q = 0; q < d->n_trig; ++q)
+        if (!std::isfinite(d->trig[q].amp) || !finite3(d->trig[q].k, d->dim) ||
+            !finite3(d->trig[q].phase, d->dim))
+            return fail(PDD_E_INVALID, "trig term %d is not finite", q);
+    if (!finite3(d->b0, d->dim) || !std::isfinite(d->c_a) || !std::isfinite(d->c_b))
+        return fail(PDD_E_INVALID, "drift / killing coefficients must be finite");
+    for (int i = 0; i < d->dim; ++i)
+        if (!finite3(d->B[i], d->dim)) return fail(PDD_E_INVALID, "drift matrix must be finite");
+    return PDD_OK;
+}
+
+bool strictly_inside(const pdd_problem_desc &d, const double *x)
+{
+    if (d.domain == PDD_DOMAIN_BOX) {
+        for (int i = 0; i < d.dim; ++i)
+            if (!(x[i] > d.lo[i] && x[i] < d.hi[i])) return false;
+        return true;
+    }
+    double r2 = 0.0;
+    for (int i = 0; i < d.dim; ++i) {
+        const double t = x[i] - d.center[i];
+        r2 += t * t;
+    }
+    return r2 < d.radius * d.radius;
+}
+
+pdd_status check_grid(const pdd_problem_desc &d, const pdd_grid *g, int precision, const char *name)
+{
+    if (!g) return fail(PDD_E_INVALID, "%s grid is NULL", name);
+    if (g->dim != d.dim) return fail(PDD_E_INVALID, "%s grid dim %d != problem dim %d", name, g->dim, d.dim);
+    if (!g->data) return fail(PDD_E_INVALID, "%s grid has no data", name);
+    const int want = precision == PDD_FP64 ? PDD_DTYPE_F64 : PDD_DTYPE_F32;
+    if (g->dtype != want)
+        return fail(PDD_E_UNSUPPORTED, "%s grid dtype must match the path precision (%s)", name,
+                    precision == PDD_FP64 ? "f64" : "f32");
+    for (int i = 0; i < d.dim; ++i) {
+        if (g->n[i] < 2) return fail(PDD_E_INVALID, "%s grid needs >= 2 points per axis", name);
+        if (!(g->lo[i] < g->hi[i])) return fail(PDD_E_INVALID, "%s grid needs lo < hi", name);
+        const double blo = d.domain == PDD_DOMAIN_BOX ? d.lo[i] : d.center[i] - d.radius;
+        const double bhi = d.domain == PDD_DOMAIN_BOX ? d.hi[i] : d.center[i] + d.radius;
+        if (g->lo[i] > blo || g->hi[i] < bhi)
+            return fail(PDD_E_INVALID, "%s grid does not cover the domain on axis %d", name, i);
+    }
+    return PDD_OK;
+}
+
+template <class T>
+GridView<T> make_view(const pdd_grid *g, int dim)
+{
+    GridView<T> v{};
+    if (!g) return v;
+    v.data = static_cast<const T *>(g->data);
+    for (int i = 0; i < 3; ++i) {
+        v.n[i] = i < dim ? g->n[i] : 1;
+        v.lo[i] = (T)g->lo[i];
+        v.inv[i] = i < dim ? (T)((double)(g->n[i] - 1) / (g->hi[i] - g->lo[i])) : (T)0;
+    }
+    return v;
+}
+
+int occupancy(pdd_ctx *ctx, const void *fn, int block)
+{
+    auto key = std::make_tuple(fn, block);
+    auto it = ctx->occupancy.find(key);
+    if (it != ctx->occupancy.end()) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0) != hipSuccess || n < 1) n = 1;
+    ctx->occupancy[key] = n;
+    return n;
+}
+
+template <class T, int D, bool CV>
+pdd_status run_launches(pdd_ctx *ctx, PathArgs<T> &a, ReduceArgs &r, uint64_t total,
+                        uint64_t per_launch, bool caller_records, const pdd_tuning &tune,
+                        const std::vector<uint64_t> *starts, uint64_t uniform_n, hipStream_t s)
+{
+    const int block = tune.block;
+    const void *fn = path_kernel_symbol<T, D, CV>();
+    const int bpc = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : occupancy(ctx, fn, block);
+    uint32_t launch = 0;
+    for (uint64_t b = 0; b < total; b += per_launch, ++launch) {
+        const uint64_t len = std::min(per_launch, total - b);
+        a.slot_begin = b;
+        a.launch_slots = (uint32_t)len;
+        a.counter = static_cast<uint32_t *>(ctx->counters.ptr) + launch;
+        a.rec_base = caller_records ? 0 : b;
+        const uint64_t waves_needed = (len + 63) / 64;
+        const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));
+        HIP_TRY((launch_path_kernel<T, D, CV>(a, grid, block, s)));
+        // nodes touched by slots [b, b + len)
+        uint32_t n_lo, n_hi;
+        if (starts) {
+            n_lo = (uint32_t)(std::upper_bound(starts->begin(), starts->end(), b) - starts->begin() - 1);
+            n_hi = (uint32_t)(std::upper_bound(starts->begin(), starts->end(), b + len - 1) - starts->begin() - 1);
+        } else {
+            n_lo = (uint32_t)(b / uniform_n);
+            n_hi = (uint32_t)((b + len - 1) / uniform_n);
+        }
+        r.rec_base = a.rec_base;
+        r.slot_begin = b;
+        r.slot_end = b + len;
+        r.node_lo = n_lo;
+        HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
+    }
+    return PDD_OK;
+}
+
+pdd_status solve_impl(pdd_problem *prob, const pdd_grid *u_prev, const pdd_grid *resid,
+                      const double *nodes, int64_t n_nodes, const pdd_solve_opts *o,
+                      pdd_node_stats *out, void *stream)
+{
+    if (!prob) return fail(PDD_E_INVALID, "problem is NULL");
+    if (!o) return fail(PDD_E_INVALID, "opts is NULL");
+    if (n_nodes < 0) return fail(PDD_E_INVALID, "n_nodes < 0");
+    if (n_nodes == 0) return PDD_OK;
+    if (n_nodes >= (1ll << 32)) return fail(PDD_E_INVALID, "too many nodes");
+    if (!nodes) return fail(PDD_E_INVALID, "nodes is NULL");
+    if (!out) return fail(PDD_E_INVALID, "out is NULL");
+    const pdd_problem_desc &d = prob->desc;
+    const int dim = d.dim;
+    const bool cv = u_prev || resid;
+    if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(PDD_E_INVALID, "dt must be > 0");
+    if (o->precision != PDD_FP32 && o->precision != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
+    if (o->exit_mode < PDD_EXIT_BRIDGE || o->exit_mode > PDD_EXIT_NAIVE) return fail(PDD_E_INVALID, "bad exit mode");
+    if (o->law != PDD_LAW_GAUSS && o->law != PDD_LAW_RADEMACHER) return fail(PDD_E_INVALID, "bad law");
+    if (o->stream_id >= (1u << 28)) return fail(PDD_E_INVALID, "stream_id must be < 2^28");
+    const uint64_t max_steps = o->max_steps ? o->max_steps : kDefaultMaxSteps;
+    if (max_steps >= (1ull << 31)) return fail(PDD_E_INVALID, "max_steps must be < 2^31");
+    if (cv) {
+        pdd_status st = check_grid(d, u_prev, o->precision, "u_prev");
+        if (st) return st;
+        st = check_grid(d, resid, o->precision, "residual");
+        if (st) return st;
+    }
+    if ((o->rec_phi || o->rec_e) && !o->rec_steps)
+        return fail(PDD_E_INVALID, "per-path records need rec_steps");
+    if (o->rec_steps && cv && !o->rec_e) return fail(PDD_E_INVALID, "correction records need rec_e");
+    const bool score_plain = !cv || (o->flags & PDD_PLAIN_ALONGSIDE);
+    if (o->rec_steps && score_plain && !o->rec_phi) return fail(PDD_E_INVALID, "records need rec_phi");
+
+    // nodes strictly inside, path counts, prefix
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const double *x = nodes + i * dim;
+        if (!finite3(x, dim) || !strictly_inside(d, x))
+            return fail(PDD_E_INVALID, "node %lld is not strictly inside the domain", (long long)i);
+    }
+    const bool uniform = o->n_paths_per_node == nullptr;
+    std::vector<uint64_t> starts;
+    uint64_t total = 0;
+    if (uniform) {
+        if (o->path_offset + o->n_paths > (1ull << 32))
+            return fail(PDD_E_INVALID, "path_offset + n_paths must be <= 2^32");
+        if (o->n_paths && (uint64_t)n_nodes > UINT64_MAX / o->n_paths) return fail(PDD_E_INVALID, "too many paths");
+        total = (uint64_t)n_nodes * o->n_paths;
+    } else {
+        starts.resize(n_nodes + 1);
+        for (int64_t i = 0; i < n_nodes; ++i) {
+            const uint64_t c = o->n_paths_per_node[i];
+            if (o->path_offset + c > (1ull << 32))
+                return fail(PDD_E_INVALID, "path_offset + paths of node %lld exceed 2^32", (long long)i);
+            starts[i] = total;
+            total += c;
+        }
+        starts[n_nodes] = total;
+    }
+    const bool caller_records = o->rec_steps != nullptr;
+    if (caller_records && total > kMaxLaunchSlots)
+        return fail(PDD_E_UNSUPPORTED, "per-path records are limited to 2^31 paths per solve");
+
+    pdd_ctx *ctx = prob->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pdd_tuning tune{256, 0, 64, 0};
+    if (o->tuning) {
+        if (o->tuning->block) tune.block = o->tuning->block;
+        if (o->tuning->blocks_per_cu) tune.blocks_per_cu = o->tuning->blocks_per_cu;
+        if (o->tuning->grab) tune.grab = o->tuning->grab;
+        tune.max_launch_paths = o->tuning->max_launch_paths;
+    }
+    if (tune.block != 64 && tune.block != 128 && tune.block != 256)
+        return fail(PDD_E_INVALID, "tuning.block must be 64, 128 or 256");
+    if (tune.grab < 1 || tune.grab > 4096 || tune.blocks_per_cu < 0 || tune.blocks_per_cu > 64 ||
+        tune.max_launch_paths < 0)
+        return fail(PDD_E_INVALID, "tuning out of range");
+
+    uint64_t per_launch = caller_records ? std::max<uint64_t>(total, 1)
+                                         : std::min(kScratchSlots, std::max<uint64_t>(total, 1));
+    if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
+    const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
+
+    // order after the context's previous solve
+    if (ctx->any_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+
+    // scratch
+    const size_t node_bytes = (size_t)n_nodes * dim * sizeof(double);
+    const size_t start_bytes = uniform ? 0 : starts.size() * sizeof(uint64_t);
+    pdd_status st;
+    if ((st = ensure(ctx, ctx->nodes, node_bytes + start_bytes))) return st;
+    if ((st = ensure(ctx, ctx->acc, (size_t)n_nodes * sizeof(NodeAcc)))) return st;
+    if ((st = ensure(ctx, ctx->counters, (size_t)(n_launch + 2) * sizeof(uint32_t)))) return st;
+    double *rec_phi = o->rec_phi, *rec_e = o->rec_e;
+    uint32_t *rec_steps = o->rec_steps;
+    if (!caller_records && total) {
+        const size_t per = sizeof(uint32_t) + (score_plain ? 8 : 0) + (cv ? 8 : 0);
+        if ((st = ensure(ctx, ctx->rec, per_launch * per))) return st;
+        char *base = static_cast<char *>(ctx->rec.ptr);
+        rec_phi = score_plain ? reinterpret_cast<double *>(base) : nullptr;
+        rec_e = cv ? reinterpret_cast<double *>(base + (score_plain ? per_launch * 8 : 0)) : nullptr;
+        rec_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((score_plain ? 8 : 0) + (cv ? 8 : 0)));
+    }
+    if ((st = ensure_stage(ctx, node_bytes + start_bytes))) return st;
+    std::memcpy(ctx->stage, nodes, node_bytes);
+    if (!uniform) std::memcpy(static_cast<char *>(ctx->stage) + node_bytes, starts.data(), start_bytes);
+    HIP_TRY(hipMemcpyAsync(ctx->nodes.ptr, ctx->stage, node_bytes + start_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    ctx->any_staged = true;
+    HIP_TRY(launch_zero(ctx->acc.ptr, (size_t)n_nodes * sizeof(NodeAcc), s));
+    HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
+
+    const double *d_nodes = static_cast<const double *>(ctx->nodes.ptr);
+    const uint64_t *d_starts =
+        uniform ? nullptr
+                : reinterpret_cast<const uint64_t *>(static_cast<const char *>(ctx->nodes.ptr) + node_bytes);
+
+    ReduceArgs r{};
+    r.rec_phi = rec_phi;
+    r.rec_e = rec_e;
+    r.rec_steps = rec_steps;
+    r.node_start = d_starts;
+    r.uniform_n = o->n_paths;
+    r.acc = static_cast<NodeAcc *>(ctx->acc.ptr);
+    r.has_phi = score_plain;
+    r.has_e = cv;
+
+    const double h = o->dt;
+    const double sig_sqh = d.sigma * std::sqrt(h);
+    auto fill_args = [&](auto &a, const auto &problem) {
+        using TT = std::remove_reference_t<decltype(a.h)>;
+        a.prob = problem;
+        a.nodes = d_nodes;
+        a.node_start = d_starts;
+        a.uniform_n = o->n_paths;
+        a.total_slots = total;
+        a.path_offset = o->path_offset;
+        a.rec_phi = rec_phi;
+        a.rec_e = rec_e;
+        a.rec_steps = rec_steps;
+        a.n_nodes = (uint32_t)n_nodes;
+        a.stream_tag = o->stream_id << 4;
+        a.max_steps = (uint32_t)max_steps;
+        a.exit_mode = o->exit_mode;
+        a.law = o->law;
+        a.grab = tune.grab;
+        a.score_plain = score_plain ? 1 : 0;
+        a.h = (TT)h;
+        a.sig_sqh = (TT)sig_sqh;
+        a.two_over_s2h = (TT)(2.0 / (d.sigma * d.sigma * h));
+        a.gm_thresh = (TT)(kGmShift * sig_sqh);
+        a.bridge_thresh = (TT)kBridgeSkip;
+        a.u_prev = make_view<TT>(u_prev, dim);
+        a.resid = make_view<TT>(resid, dim);
+    };
+
+    if (total) {
+        const std::vector<uint64_t> *sp = uniform ? nullptr : &starts;
+        if (o->precision == PDD_FP32) {
+            PathArgs<float> a{};
+            fill_args(a, prob->pf);
+            if (dim == 2)
+                st = cv ? run_launches<float, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
+                        : run_launches<float, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+            else
+                st = cv ? run_launches<float, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
+                        : run_launches<float, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+        } else {
+            PathArgs<double> a{};
+            fill_args(a, prob->pd);
+            if (dim == 2)
+                st = cv ? run_launches<double, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
+                        : run_launches<double, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+            else
+                st = cv ? run_launches<double, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
+                        : run_launches<double, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+        }
+        if (st) return st;
+    }
+
+    FinalizeArgs f{};
+    f.acc = static_cast<const NodeAcc *>(ctx->acc.ptr);
+    f.nodes = d_nodes;
+    f.out = out;
+    f.n_nodes = (uint32_t)n_nodes;
+    f.dim = dim;
+    f.has_phi = score_plain;
+    f.has_e = cv;
+    if (cv) {
+        f.up_data = u_prev->data;
+        f.up_f64 = u_prev->dtype == PDD_DTYPE_F64;
+        for (int i = 0; i < 3; ++i) {
+            f.up_n[i] = i < dim ? u_prev->n[i] : 1;
+            f.up_lo[i] = u_prev->lo[i];
+            f.up_inv[i] = i < dim ? (double)(u_prev->n[i] - 1) / (u_prev->hi[i] - u_prev->lo[i]) : 0.0;
+        }
+    }
+    HIP_TRY(launch_finalize(f, s));
+    HIP_TRY(hipEventRecord(ctx->done, s));
+    ctx->any_done = true;
+    return PDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pdd_last_error(void) { return g_error.c_str(); }
+
+pdd_status pdd_init(pdd_ctx **out, int hip_device)
+{
+    if (!out) return fail(PDD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (hip_device < 0 || hip_device >= n) return fail(PDD_E_INVALID, "no HIP device %d (have %d)", hip_device, n);
+    HIP_TRY(hipSetDevice(hip_device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PDD_E_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+    pdd_ctx *ctx = new pdd_ctx();
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return fail(PDD_E_HIP, "event creation failed");
+    }
+    *out = ctx;
+    return PDD_OK;
+}
+
+void pdd_shutdown(pdd_ctx *ctx)
+{
+    if (!ctx) return;
+    // best effort: errors cannot be reported from here
+    (void)hipSetDevice(ctx->device);
+    if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
+    if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
+    for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec})
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    (void)hipEventDestroy(ctx->done);
+    (void)hipEventDestroy(ctx->staged);
+    delete ctx;
+}
+
+pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_problem **out)
+{
+    if (!ctx || !out) return fail(PDD_E_INVALID, "ctx and out must not be NULL");
+    *out = nullptr;
+    pdd_status st = check_desc(desc);
+    if (st) return st;
+    pdd_problem *p = new pdd_problem();
+    p->ctx = ctx;
+    p->desc = *desc;
+    fill_problem(*desc, p->pf);
+    fill_problem(*desc, p->pd);
+    *out = p;
+    return PDD_OK;
+}
+
+void pdd_destroy_problem(pdd_problem *problem) { delete problem; }
+
+pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
+                           const pdd_solve_opts *opts, pdd_node_stats *out, void *stream)
+{
+    return solve_impl(problem, nullptr, nullptr, nodes, n_nodes, opts, out, stream);
+}
+
+pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev, const pdd_grid *resid,
+                                const double *nodes, int64_t n_nodes, const pdd_solve_opts *opts,
+                                pdd_node_stats *out, void *stream)
+{
+    if (!u_prev || !resid) return fail(PDD_E_INVALID, "correction solve needs u_prev and residual grids");
+    return solve_impl(problem, u_prev, resid, nodes, n_nodes, opts, out, stream);
+}
+
+pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items, void *stream)
+{
+    if (!ctx) return fail(PDD_E_INVALID, "ctx is NULL");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(PDD_E_INVALID, "bad items");
+    for (int32_t q = 0; q < n_items; ++q) {
+        const pdd_work_item &it = items[q];
+        if (!it.problem || it.problem->ctx != ctx) return fail(PDD_E_INVALID, "item %d: problem of another context", q);
+        pdd_status st = solve_impl(it.problem, it.u_prev, it.resid, it.nodes, it.n_nodes, it.opts, it.out, stream);
+        if (st) return st;
+    }
+    return PDD_OK;
+}
+
+pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nodes,
+                        const pdd_solve_opts *opts, pdd_tuning *out)
+{
+    (void)problem;
+    (void)nodes;
+    (void)n_nodes;
+    (void)opts;
+    (void)out;
+    return fail(PDD_E_UNSUPPORTED, "autotuning is not available yet");
+}
+
+}  // extern "C"

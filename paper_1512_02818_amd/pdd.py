@@ -1,0 +1,370 @@
+"""Python binding of the C ABI in include/pdd.h (argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libpdd.so``; PyTorch
+provides device memory (result and record tensors) and the HIP stream. If the
+library is missing, importing the binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdd.so")
+
+PDD_OK = 0
+DOMAINS = {"box": 0, "ball": 1}
+EXITS = {"bridge": 0, "shift": 1, "naive": 2}
+LAWS = {"gauss": 0, "rademacher": 1}
+PRECISIONS = {"fp32": 0, "fp64": 1}
+PLAIN_ALONGSIDE = 1
+MAX_TRIG, MAX_MONO = 16, 8
+
+
+class TrigTerm(C.Structure):
+    _fields_ = [("amp", C.c_double), ("k", C.c_double * 3), ("phase", C.c_double * 3)]
+
+
+class MonoTerm(C.Structure):
+    _fields_ = [("coef", C.c_double), ("e", C.c_int32 * 3)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("domain", C.c_int32),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("center", C.c_double * 3), ("radius", C.c_double),
+        ("sigma", C.c_double),
+        ("b0", C.c_double * 3), ("B", (C.c_double * 3) * 3),
+        ("c_a", C.c_double), ("c_b", C.c_double),
+        ("n_trig", C.c_int32), ("n_mono", C.c_int32), ("n_fx", C.c_int32), ("n_gx", C.c_int32),
+        ("trig", TrigTerm * MAX_TRIG), ("mono", MonoTerm * MAX_MONO),
+        ("fx", MonoTerm * MAX_MONO), ("gx", MonoTerm * MAX_MONO),
+        ("seed", C.c_uint64),
+    ]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("data", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32),
+                ("max_launch_paths", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_paths", C.c_uint64),
+                ("n_paths_per_node", C.POINTER(C.c_uint64)), ("path_offset", C.c_uint64),
+                ("stream_id", C.c_uint32), ("precision", C.c_int32), ("exit_mode", C.c_int32),
+                ("law", C.c_int32), ("max_steps", C.c_uint64), ("flags", C.c_uint32),
+                ("reserved", C.c_int32),
+                ("rec_phi", C.c_void_p), ("rec_e", C.c_void_p), ("rec_steps", C.c_void_p),
+                ("tuning", C.POINTER(Tuning))]
+
+
+class NodeStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_capped", C.c_int64), ("steps_sum", C.c_int64),
+                ("mean", C.c_double), ("var", C.c_double), ("stderr_", C.c_double),
+                ("mean_steps", C.c_double), ("mean_plain", C.c_double), ("var_plain", C.c_double),
+                ("cov", C.c_double), ("rho", C.c_double), ("vr", C.c_double),
+                ("vr_opt", C.c_double), ("sums", C.c_double * 10)]
+
+
+class WorkItem(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("nodes", C.POINTER(C.c_double)),
+                ("n_nodes", C.c_int64), ("opts", C.POINTER(SolveOpts)),
+                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)), ("out", C.c_void_p)]
+
+
+STATS_DTYPE = np.dtype([("n", "<i8"), ("n_capped", "<i8"), ("steps_sum", "<i8"),
+                        ("mean", "<f8"), ("var", "<f8"), ("stderr", "<f8"), ("mean_steps", "<f8"),
+                        ("mean_plain", "<f8"), ("var_plain", "<f8"), ("cov", "<f8"),
+                        ("rho", "<f8"), ("vr", "<f8"), ("vr_opt", "<f8"), ("sums", "<f8", (10,))])
+assert STATS_DTYPE.itemsize == C.sizeof(NodeStats)
+
+# Every entry point of include/pdd.h with its ctypes signature.
+SIGNATURES = {
+    "pdd_init": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int]),
+    "pdd_shutdown": (None, [C.c_void_p]),
+    "pdd_create_problem": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.POINTER(C.c_void_p)]),
+    "pdd_destroy_problem": (None, [C.c_void_p]),
+    "pdd_solve_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
+                                    C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
+    "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
+                                         C.POINTER(C.c_double), C.c_int64, C.POINTER(SolveOpts),
+                                         C.c_void_p, C.c_void_p]),
+    "pdd_solve_batch": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32, C.c_void_p]),
+    "pdd_autotune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
+                                 C.POINTER(SolveOpts), C.POINTER(Tuning)]),
+    "pdd_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class PDDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pdd status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1512_02818_amd.build` (no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != PDD_OK:
+        raise PDDError(status, lib().pdd_last_error().decode())
+
+
+# --------------------------------------------------------------------------- marshalling
+def problem_desc(pd: dict) -> ProblemDesc:
+    """Fills the C descriptor from a problem dict (see workloads)."""
+    d = ProblemDesc()
+    d.dim = int(pd["dim"])
+    d.domain = DOMAINS[pd.get("domain", "box")]
+    for key in ("lo", "hi", "center", "b0"):
+        vals = pd.get(key, [])
+        arr = getattr(d, key)
+        for i, v in enumerate(vals):
+            arr[i] = float(v)
+    d.radius = float(pd.get("radius", 0.0))
+    d.sigma = float(pd.get("sigma", 1.0))
+    for i, row in enumerate(pd.get("B", [])):
+        for j, v in enumerate(row):
+            d.B[i][j] = float(v)
+    d.c_a = float(pd.get("c_a", 0.0))
+    d.c_b = float(pd.get("c_b", 0.0))
+    trig = pd.get("trig", [])
+    if len(trig) > MAX_TRIG:
+        raise ValueError("too many trig terms")
+    d.n_trig = len(trig)
+    for m, t in enumerate(trig):
+        d.trig[m].amp = float(t["amp"])
+        for i, v in enumerate(t["k"]):
+            d.trig[m].k[i] = float(v)
+        for i, v in enumerate(t["phase"]):
+            d.trig[m].phase[i] = float(v)
+    for field in ("mono", "fx", "gx"):
+        terms = pd.get(field, [])
+        if len(terms) > MAX_MONO:
+            raise ValueError(f"too many {field} terms")
+        setattr(d, "n_" + field, len(terms))
+        arr = getattr(d, field)
+        for m, t in enumerate(terms):
+            arr[m].coef = float(t["coef"])
+            for i, v in enumerate(t["e"]):
+                arr[m].e[i] = int(v)
+    d.seed = int(pd.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    return d
+
+
+def grid_struct(gd: dict, tensor) -> Grid:
+    """C grid over a device tensor holding the values (x fastest)."""
+    import torch
+    g = Grid()
+    g.dim = int(gd["dim"])
+    if tensor.dtype == torch.float32:
+        g.dtype = 0
+    elif tensor.dtype == torch.float64:
+        g.dtype = 1
+    else:
+        raise TypeError("grid values must be float32 or float64")
+    if not tensor.is_cuda or not tensor.is_contiguous():
+        raise ValueError("grid values must be a contiguous device tensor")
+    for i in range(g.dim):
+        g.n[i] = int(gd["n"][i])
+        g.lo[i] = float(gd["lo"][i])
+        g.hi[i] = float(gd["hi"][i])
+    g.data = tensor.data_ptr()
+    return g
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """A library context on one HIP device (owns the solve scratch)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        torch.cuda.init()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().pdd_init(C.byref(h), int(device)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdd_shutdown(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Problem:
+    """A problem uploaded to a context (pdd_create_problem)."""
+
+    def __init__(self, ctx: Context, pd: dict):
+        self.ctx = ctx
+        self.pd = pd
+        self.dim = int(pd["dim"])
+        self.desc = problem_desc(pd)
+        h = C.c_void_p()
+        _check(lib().pdd_create_problem(ctx.handle, C.byref(self.desc), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdd_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
+              precision="fp32", exit="bridge", law="gauss", max_steps=0, plain_alongside=False,
+              records=None, tuning=None):
+    o = SolveOpts()
+    o.dt = float(dt)
+    o.n_paths = int(n_paths)
+    keep = []
+    if n_paths_per_node is not None:
+        counts = np.ascontiguousarray(n_paths_per_node, dtype=np.uint64)
+        keep.append(counts)
+        o.n_paths_per_node = counts.ctypes.data_as(C.POINTER(C.c_uint64))
+    o.path_offset = int(path_offset)
+    o.stream_id = int(stream_id)
+    o.precision = PRECISIONS[precision]
+    o.exit_mode = EXITS[exit]
+    o.law = LAWS[law]
+    o.max_steps = int(max_steps)
+    o.flags = PLAIN_ALONGSIDE if plain_alongside else 0
+    if records is not None:
+        o.rec_phi = records["phi"].data_ptr() if records.get("phi") is not None else None
+        o.rec_e = records["e"].data_ptr() if records.get("e") is not None else None
+        o.rec_steps = records["steps"].data_ptr()
+    if tuning is not None:
+        t = Tuning(*[int(v) for v in tuning]) if not isinstance(tuning, Tuning) else tuning
+        keep.append(t)
+        o.tuning = C.pointer(t)
+    o._keep = keep  # noqa: SLF001 - lifetime of the arrays the struct points to
+    return o
+
+
+def alloc_stats(n_nodes, device="cuda"):
+    import torch
+    return torch.empty(n_nodes * STATS_DTYPE.itemsize, dtype=torch.uint8, device=device)
+
+
+def stats_to_numpy(t) -> np.ndarray:
+    """Copies a stats tensor to the host as a structured array (synchronises)."""
+    return t.cpu().numpy().view(STATS_DTYPE)
+
+
+def alloc_records(total, correction=False, plain=True, device="cuda"):
+    import torch
+    rec = {"steps": torch.empty(total, dtype=torch.int32, device=device)}
+    rec["phi"] = torch.empty(total, dtype=torch.float64, device=device) if plain else None
+    rec["e"] = torch.empty(total, dtype=torch.float64, device=device) if correction else None
+    return rec
+
+
+def solve_nodes(problem: Problem, nodes, out=None, stream=None, **opt):
+    """pdd_solve_nodes: returns the device stats tensor (asynchronous)."""
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+    n = len(nodes)
+    if out is None:
+        out = alloc_stats(n)
+    o = make_opts(**opt)
+    _check(lib().pdd_solve_nodes(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                 C.byref(o), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def solve_correction(problem: Problem, u_prev: dict, u_prev_t, resid: dict, resid_t, nodes,
+                     out=None, stream=None, **opt):
+    """pdd_solve_correction with u_prev / residual values in device tensors."""
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+    n = len(nodes)
+    if out is None:
+        out = alloc_stats(n)
+    gu, gr = grid_struct(u_prev, u_prev_t), grid_struct(resid, resid_t)
+    o = make_opts(**opt)
+    _check(lib().pdd_solve_correction(problem.handle, C.byref(gu), C.byref(gr),
+                                      nodes.ctypes.data_as(C.POINTER(C.c_double)), n, C.byref(o),
+                                      C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def solve_batch(ctx: Context, items, stream=None):
+    """pdd_solve_batch over dicts {problem, nodes, opts(dict), out, [u_prev, u_prev_t, resid,
+    resid_t]}; returns the list of stats tensors."""
+    arr = (WorkItem * len(items))()
+    keep = []
+    outs = []
+    for q, it in enumerate(items):
+        prob = it["problem"]
+        nodes = np.ascontiguousarray(np.asarray(it["nodes"], dtype=np.float64).reshape(-1, prob.dim))
+        out = it.get("out")
+        if out is None:
+            out = alloc_stats(len(nodes))
+        o = make_opts(**it["opts"])
+        keep += [nodes, o]
+        arr[q].problem = prob.handle
+        arr[q].nodes = nodes.ctypes.data_as(C.POINTER(C.c_double))
+        arr[q].n_nodes = len(nodes)
+        arr[q].opts = C.pointer(o)
+        if it.get("u_prev") is not None:
+            gu = grid_struct(it["u_prev"], it["u_prev_t"])
+            gr = grid_struct(it["resid"], it["resid_t"])
+            keep += [gu, gr]
+            arr[q].u_prev = C.pointer(gu)
+            arr[q].resid = C.pointer(gr)
+        arr[q].out = out.data_ptr()
+        outs.append(out)
+    _check(lib().pdd_solve_batch(ctx.handle, arr, len(items), _stream_handle(stream)))
+    return outs
+
+
+def autotune(problem: Problem, nodes, **opt):
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+    o = make_opts(**opt)
+    t = Tuning()
+    _check(lib().pdd_autotune(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)),
+                              len(nodes), C.byref(o), C.byref(t)))
+    return (t.block, t.blocks_per_cu, t.grab)

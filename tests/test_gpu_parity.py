@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path against the CPU oracle on the same random streams.
+
+FP64 path arithmetic: at least 99.99 % of paths end at the same step as the
+oracle's; on nodes where every path matches, node means agree to 1e-10
+relative and matching paths' scores to 1e-11 (transcendentals differ between
+the device library and glibc by about an ulp, so a rare path may take a
+different exit decision when it lands within rounding of a threshold).
+FP32 path arithmetic (FP64 per-path integrals and sums): per node within
+3 SE + 1e-5 of the oracle's mean on the same streams.
+All calls go through the C ABI of include/pdd.h.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_02818_amd import pdd  # noqa: E402
+from paper_1512_02818_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_solve(ctx, pd, nodes, n_paths=None, counts=None, grids=None, **opt):
+    """Runs one solve with per-path records; returns (stats, records) on the host."""
+    prob = pdd.Problem(ctx, pd)
+    nodes = np.asarray(nodes, dtype=np.float64).reshape(-1, pd["dim"])
+    total = int(np.sum(counts)) if counts is not None else len(nodes) * int(n_paths)
+    cv = grids is not None
+    plain = (not cv) or opt.get("plain_alongside", False)
+    rec = pdd.alloc_records(max(total, 1), correction=cv, plain=plain)
+    kw = dict(opt)
+    if counts is not None:
+        kw["n_paths_per_node"] = np.asarray(counts, dtype=np.uint64)
+    else:
+        kw["n_paths"] = int(n_paths)
+    if cv:
+        gu, gr = grids
+        dt = torch.float64 if kw.get("precision") == "fp64" else torch.float32
+        tu = torch.as_tensor(np.asarray(gu["data"]), dtype=dt).cuda().contiguous()
+        tr = torch.as_tensor(np.asarray(gr["data"]), dtype=dt).cuda().contiguous()
+        out = pdd.solve_correction(prob, gu, tu, gr, tr, nodes, records=rec, **kw)
+    else:
+        out = pdd.solve_nodes(prob, nodes, records=rec, **kw)
+    torch.cuda.synchronize()
+    st = pdd.stats_to_numpy(out)
+    host = {"steps": rec["steps"].cpu().numpy().view(np.uint32)[:total]}
+    host["phi"] = rec["phi"].cpu().numpy()[:total] if rec["phi"] is not None else None
+    host["e"] = rec["e"].cpu().numpy()[:total] if rec["e"] is not None else None
+    prob.close()
+    return st, host
+
+
+def oracle_solve(pd, nodes, n_paths, grids=None, **opt):
+    from oracle import oracle as O
+    kw = {k: v for k, v in opt.items() if k in ("path_offset", "stream", "exit", "law", "max_steps")}
+    if grids is not None:
+        kw["u_prev"], kw["resid"] = grids
+    return O.solve_nodes(pd, nodes, record=True, h=opt["dt"], n_paths=n_paths, **kw)
+
+
+def check_fp64_parity(st, rec, ost, orec, n_paths, cv=False):
+    steps_g = rec["steps"] & 0x7FFFFFFF
+    cap_g = rec["steps"] >> 31
+    same = steps_g == orec["steps"].astype(np.uint32)
+    assert same.mean() >= 0.9999, f"exit-step agreement {same.mean():.6f}"
+    assert np.array_equal(cap_g[same].astype(bool), orec["capped"][same].astype(bool))
+    n_nodes = len(st)
+    per_node = same.reshape(n_nodes, n_paths).all(axis=1)
+    key = "e" if cv else "phi"
+    ok = same
+    g = rec[key][ok]
+    o = orec[key][ok]
+    assert np.all(np.abs(g - o) <= 1e-11 * np.maximum(1.0, np.abs(o))), np.max(np.abs(g - o))
+    for i in np.nonzero(per_node)[0]:
+        assert abs(st["mean"][i] - ost["mean"][i]) <= 1e-10 * max(1.0, abs(ost["mean"][i])), i
+        assert abs(st["var"][i] - ost["var"][i]) <= 1e-8 * max(1.0, abs(ost["var"][i])), i
+        assert st["steps_sum"][i] == ost["steps_sum"][i]
+        assert st["n"][i] == n_paths
+    return same.mean(), per_node.mean()
+
+
+@pytest.mark.parametrize("exit_mode", ["bridge", "shift", "naive"])
+def test_unit_square_fp64_per_path(ctx, exit_mode):
+    pd = W.unit_square_problem(seed=0)
+    nodes = W.unit_square_nodes()
+    n = 10000 if exit_mode == "bridge" else 2000
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp64", exit=exit_mode)
+    ost, orec = oracle_solve(pd, nodes, n, dt=1e-3, exit=exit_mode)
+    agree, nodes_ok = check_fp64_parity(st, rec, ost, orec, n)
+    print(f"{exit_mode}: exit-step agreement {agree:.6f}, clean nodes {nodes_ok:.3f}")
+
+
+def test_unit_square_fp32_within_3se(ctx):
+    pd = W.unit_square_problem(seed=0)
+    nodes = W.unit_square_nodes()
+    n = 10000
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp32")
+    ost, orec = oracle_solve(pd, nodes, n, dt=1e-3)
+    diff = np.abs(st["mean"] - ost["mean"])
+    assert np.all(diff <= 3 * ost["stderr"] + 1e-5), (diff, ost["stderr"])
+    same = (rec["steps"] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
+    assert same.mean() > 0.99
+    print(f"fp32: max |mean32 - mean64| = {diff.max():.3e}, exit-step agreement {same.mean():.5f}")
+
+
+@pytest.mark.parametrize("case", ["ball2d_exit", "ball3d_exit", "ball3d_kill", "box3d"])
+def test_other_geometries_fp64(ctx, case):
+    if case == "ball2d_exit":
+        pd = W.ball_exit_time_problem(dim=2, sigma=0.8, seed=3)
+        nodes = np.array([[0.0, 0.0], [0.5, 0.2], [-0.3, 0.7]])
+    elif case == "ball3d_exit":
+        pd = W.ball_exit_time_problem(dim=3, center=[0.1, 0.2, -0.1], seed=4)
+        nodes = np.array([[0.1, 0.2, -0.1], [0.5, 0.2, 0.1]])
+    elif case == "ball3d_kill":
+        pd = W.ball_killing_problem(dim=3, c=-2.0, seed=6)
+        nodes = np.array([[0.0, 0.0, 0.0], [0.6, 0.0, 0.2]])
+    else:
+        pd = {"dim": 3, "domain": "box", "lo": [0, 0, 0], "hi": [1, 1.2, 0.8], "sigma": 0.7,
+              "b0": [0.1, -0.2, 0.3], "B": [[0.2, 0.1, 0.0], [0.0, -0.4, 0.3], [0.5, 0.0, 0.1]],
+              "c_a": -0.5, "c_b": -2.0,
+              "trig": [{"amp": 0.8, "k": [2.0, 3.0, 1.5], "phase": [0.3, 1.1, -0.4]}],
+              "mono": [{"coef": 1.5, "e": [1, 2, 0]}, {"coef": -0.7, "e": [0, 0, 3]}],
+              "fx": [{"coef": 0.25, "e": [1, 0, 1]}], "gx": [{"coef": 0.1, "e": [0, 0, 0]}],
+              "seed": 99}
+        nodes = np.array([[0.5, 0.6, 0.4], [0.2, 0.3, 0.7]])
+    n = 3000
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp64")
+    ost, orec = oracle_solve(pd, nodes, n, dt=1e-3)
+    check_fp64_parity(st, rec, ost, orec, n)
+
+
+def test_rademacher_law_fp64(ctx):
+    pd = W.unit_square_problem(seed=5)
+    nodes = W.unit_square_nodes()[::2]
+    n = 2000
+    for mode in ("bridge", "shift"):
+        st, rec = gpu_solve(ctx, pd, nodes, n, dt=2e-3, precision="fp64", law="rademacher", exit=mode)
+        ost, orec = oracle_solve(pd, nodes, n, dt=2e-3, law="rademacher", exit=mode)
+        check_fp64_parity(st, rec, ost, orec, n)
+
+
+def test_correction_fp64_per_path(ctx):
+    pd = W.unit_square_problem(seed=13)
+    gu, gr, _ = W.correction_grids(pd, n=129, seed=1, dtype=np.float64)
+    nodes = W.unit_square_nodes()
+    n = 4000
+    st, rec = gpu_solve(ctx, pd, nodes, n, grids=(gu, gr), dt=1e-3, precision="fp64",
+                        plain_alongside=True)
+    ost, orec = oracle_solve(pd, nodes, n, grids=(gu, gr), dt=1e-3)
+    check_fp64_parity(st, rec, ost, orec, n, cv=True)
+    same = (rec["steps"] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
+    assert np.all(np.abs(rec["phi"][same] - orec["phi"][same])
+                  <= 1e-11 * np.maximum(1.0, np.abs(orec["phi"][same])))
+    for f in ("mean_plain", "vr", "rho"):
+        assert np.allclose(st[f], ost[f], rtol=1e-6, atol=1e-9), f
+
+
+def test_correction_fp32_within_3se(ctx):
+    pd = W.unit_square_problem(seed=13)
+    gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
+    nodes = W.unit_square_nodes()
+    n = 4000
+    st, rec = gpu_solve(ctx, pd, nodes, n, grids=(gu, gr), dt=1e-3, precision="fp32",
+                        plain_alongside=True)
+    ost, orec = oracle_solve(pd, nodes, n, grids=(gu, gr), dt=1e-3)
+    assert np.all(np.abs(st["mean"] - ost["mean"]) <= 3 * ost["stderr"] + 1e-5)
+    assert np.all(np.abs(st["mean_plain"] - ost["mean_plain"])
+                  <= 3 * np.sqrt(ost["var_plain"] / n) + 1e-5)
+    assert np.all(st["vr"] > 20)
+    # correction only (no plain score): same e, phi statistics are NaN
+    st2, rec2 = gpu_solve(ctx, pd, nodes, n, grids=(gu, gr), dt=1e-3, precision="fp32")
+    assert np.array_equal(rec2["e"], rec["e"])
+    assert np.all(np.isnan(st2["mean_plain"])) and np.array_equal(st2["mean"], st["mean"])
+
+
+def test_exact_control_variate_on_gpu(ctx):
+    pd = W.bilinear_problem(seed=12)
+    nodes = W.unit_square_nodes()[::3]
+    exact = W.manufactured_u(pd, nodes)
+    for prec, dt_np, var_tol, mean_tol in (("fp64", np.float64, 1e-24, 1e-13),
+                                           ("fp32", np.float32, 1e-10, 2e-6)):
+        gu = W.sampled_grid(pd, lambda p: W.manufactured_u(pd, p), n=33, dtype=dt_np)
+        gr = W.sampled_grid(pd, lambda p: np.zeros(len(p)), n=33, dtype=dt_np)
+        st, _ = gpu_solve(ctx, pd, nodes, 3000, grids=(gu, gr), dt=1e-3, precision=prec,
+                          plain_alongside=True)
+        assert np.all(st["var"] < var_tol), (prec, st["var"])
+        assert np.allclose(st["mean"], exact, rtol=0, atol=mean_tol), prec
+        assert np.all(st["var_plain"] > 1e-2)
+
+
+def test_big_square_sampled_paths(ctx):
+    """The throughput workload in the launch configuration the benchmark times
+    (all 1,792 nodes, one batch of paths per node, FP32), checked on sampled
+    paths the oracle replays one by one, plus FP64 on a smaller batch."""
+    from oracle import oracle as O
+    pd = W.big_square_problem(seed=0)
+    nodes = W.big_square_nodes()
+    h = 1e-4
+    rng = np.random.default_rng(7)
+    for prec, n in (("fp32", 4096), ("fp64", 256)):
+        off = 62500 * 3
+        st, rec = gpu_solve(ctx, pd, nodes, n, dt=h, precision=prec, path_offset=off)
+        assert np.all(st["n"] == n) and np.all(st["n_capped"] == 0)
+        ni = rng.integers(0, len(nodes), 300)
+        pj = rng.integers(0, n, 300)
+        orec = O.run_paths(pd, nodes, ni, off + pj, h=h)
+        slot = ni * n + pj
+        same = (rec["steps"][slot] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
+        if prec == "fp64":
+            assert same.mean() >= 0.99
+            assert np.all(np.abs(rec["phi"][slot][same] - orec["phi"][same])
+                          <= 1e-10 * np.maximum(1.0, np.abs(orec["phi"][same])))
+        else:
+            assert same.mean() >= 0.95
+            # same walk in FP32: scores agree to FP32 accumulation accuracy
+            assert np.median(np.abs(rec["phi"][slot][same] - orec["phi"][same])) < 1e-4
+        # every node mean is consistent with the exact solution
+        exact = W.manufactured_u(pd, nodes)
+        z = np.abs(st["mean"] - exact) / st["stderr"]
+        assert np.mean(z < 3.5) > 0.98, np.sort(z)[-10:]
