@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput of the first-stage PDD nodal solve on one MI355X.
+
+Workload: (1/2) Lap u + b.grad u + c u = f on [0, 4]^2 with b = (0.5 x, -0.3 y),
+c = -(1 + x^2 + y^2), u = sin(pi x) cos(pi y) + x^2 y; 1,792 interface nodes
+of an 8 x 8 partition; h = 1e-4; bridge exit test; FP32 path arithmetic with
+FP64 integrals and sums; 10^6 paths per node in total. One benchmark step is
+one solve call over every node with the next block of `--paths-per-step` paths
+(path_offset = step * paths), so 16 steps of 62,500 paths are the whole job.
+
+Prints one JSON line: path-steps/s over the timed steps (inputs resident on
+the device, timed with HIP events on the solve's stream), the roofline of the
+path kernel (VALU-issue bound; see the design doc for the per-step operation
+count), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+H = 1e-4
+SEED = 0
+
+# Algorithmic VALU cost of one 2D path step of this workload, in full-rate
+# lane-instruction slots (a quarter-rate instruction counts 4). Derived from
+# the operations the step must perform ("Roofline of the path
+# kernel"); independent of how the kernel happens to be compiled.
+STEP_COST = {
+    "philox_half_block": 10 * (2 * 4 + 4) // 2,  # 10 rounds x (2 wide mul + 4 xor), 2 steps/block
+    "uniforms": 2 * 3,                           # shift, convert, fma per word
+    "box_muller": 4 * 4 + 3,                     # log2, sqrt, sin, cos + 3 mul
+    "drift_killing": 4 + 3,                      # b = b0 + B x, c = c_a + c_b |x|^2
+    "source_f": 4 * 4 + 10 + 6 + 4,              # sin/cos x 2 + trig term + monomial + assembly
+    "euler_step": 9,                             # hY, Z (f64), Y, X
+    "exit_test": 17,                             # inside test + bridge live check
+}
+OPS_PER_STEP = sum(STEP_COST.values())
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane slots per second
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--paths-per-step", type=int, default=62500)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--cpu-paths", type=int, default=4,
+                    help="oracle sample: paths 0..n-1 of every node (0 = skip)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="HBM bytes per launch measured with rocprofv3 counters")
+    return ap.parse_args()
+
+
+def cpu_baseline(pd, nodes, n_paths):
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    _, rec = O.solve_nodes(pd, nodes, record=True, h=H, n_paths=n_paths)
+    dt = time.perf_counter() - t0
+    steps = int(rec["steps"].sum())
+    return {"value": steps / dt, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(nodes)} nodes x paths 0..{n_paths - 1} of the same workload, "
+                      f"FP64, single thread: {steps} path-steps in {dt:.1f} s",
+            "host": platform.processor() or platform.machine()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the nodal solve is sharded by node across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+
+    pd = W.big_square_problem(seed=SEED)
+    nodes = W.big_square_nodes()
+    P = args.paths_per_step
+    ctx = pdd.Context(0)
+    prob = pdd.Problem(ctx, pd)
+    outs = [pdd.alloc_stats(len(nodes)) for _ in range(args.warmup + args.steps)]
+
+    def step(s):
+        pdd.solve_nodes(prob, nodes, out=outs[s], dt=H, n_paths=P, path_offset=s * P,
+                        precision=args.precision, time_kernel=True)
+
+    for s in range(args.warmup):
+        step(s)
+    torch.cuda.synchronize()
+    pdd.kernel_times(ctx)  # drop warmup timings
+    print(f"warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for s in range(args.warmup, args.warmup + args.steps):
+        step(s)
+    end.record()
+    torch.cuda.synchronize()
+    elapsed_ms = start.elapsed_time(end)
+    kern_ms = pdd.kernel_times(ctx)
+
+    timed = [pdd.stats_to_numpy(outs[s]) for s in range(args.warmup, args.warmup + args.steps)]
+    steps_per_launch = [int(t["steps_sum"].sum()) for t in timed]
+    total_steps = sum(steps_per_launch)
+    value = total_steps / (elapsed_ms / 1e3)
+    avg_kern_s = float(np.mean(kern_ms)) / 1e3
+    achieved = OPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("precision") == args.precision and tj.get("paths_per_step") == P:
+                traffic = tj.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    exact = W.manufactured_u(pd, nodes)
+    z = np.abs(timed[-1]["mean"] - exact) / timed[-1]["stderr"]
+    print(f"timed {args.steps} steps: {elapsed_ms:.1f} ms, path kernel {np.mean(kern_ms):.1f} ms/launch, "
+          f"{total_steps:.3e} path-steps, node z-scores median {np.median(z):.2f}",
+          file=sys.stderr, flush=True)
+
+    result = {
+        "metric": "path-steps/s",
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "[0,4]^2 first-stage nodal solve: 1,792 interface nodes, "
+                               f"{P} paths per node per step (10^6 per node over "
+                               f"{1_000_000 // P} steps), h=1e-4, bridge exit, "
+                               f"{args.precision} paths, fp64 sums",
+                   "nodes": int(len(nodes)), "paths_per_step": P, "dt": H,
+                   "mean_steps_per_path": total_steps / (args.steps * len(nodes) * P)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "Top/s (full-rate VALU lane slots)",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                     "ops_per_step": OPS_PER_STEP,
+                     "kernel_ms_per_launch": float(np.mean(kern_ms))},
+    }
+    if args.cpu_paths > 0:
+        print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(pd, nodes, args.cpu_paths)
+    print(json.dumps(result), flush=True)
+    prob.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -63,6 +63,7 @@ enum { PDD_DTYPE_F32 = 0, PDD_DTYPE_F64 = 1 };
 
 /* Solve flags. */
 #define PDD_PLAIN_ALONGSIDE 1u /* correction solve: also score phi, report rho, VR */
+#define PDD_TIME_KERNEL 2u     /* record HIP events around the solve's path-kernel launches */
 
 #define PDD_MAX_TRIG 16
 #define PDD_MAX_MONO 8
@@ -205,6 +206,12 @@ pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_i
  * solve (synchronous) and writes the fastest. */
 pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                         const pdd_solve_opts *opts, pdd_tuning *out);
+
+/* GPU milliseconds between the first path-kernel launch and the end of the
+ * last one, for each solve issued with PDD_TIME_KERNEL since the previous
+ * call, oldest first. Waits for those solves. Writes at most `cap` values to
+ * `ms` (host) and their count to `n`; the rest are dropped. */
+pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *pdd_last_error(void);

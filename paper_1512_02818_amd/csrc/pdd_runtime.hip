@@ -68,6 +68,8 @@ struct pdd_ctx {
     void *stage = nullptr;
     size_t stage_cap = 0;
     std::map<std::tuple<const void *, int>, int> occupancy;
+    // timing of path-kernel launches (PDD_TIME_KERNEL)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;
 };
 
 struct pdd_problem {
@@ -271,9 +273,20 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
 template <class T, int D, bool CV>
 pdd_status run_launches(pdd_ctx *ctx, PathArgs<T> &a, ReduceArgs &r, uint64_t total,
                         uint64_t per_launch, bool caller_records, const pdd_tuning &tune,
-                        const std::vector<uint64_t> *starts, uint64_t uniform_n, hipStream_t s)
+                        const std::vector<uint64_t> *starts, uint64_t uniform_n, bool timed,
+                        hipStream_t s)
 {
     const int block = tune.block;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (timed) {
+        if (!ctx->spare.empty()) {
+            ev = ctx->spare.back();
+            ctx->spare.pop_back();
+        } else {
+            HIP_TRY(hipEventCreate(&ev.first));
+            HIP_TRY(hipEventCreate(&ev.second));
+        }
+    }
     const void *fn = path_kernel_symbol<T, D, CV>();
     const int bpc = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : occupancy(ctx, fn, block);
     uint32_t launch = 0;
@@ -286,7 +299,9 @@ pdd_status run_launches(pdd_ctx *ctx, PathArgs<T> &a, ReduceArgs &r, uint64_t to
         const uint64_t waves_needed = (len + 63) / 64;
         const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));
+        if (timed && b == 0) HIP_TRY(hipEventRecord(ev.first, s));
         HIP_TRY((launch_path_kernel<T, D, CV>(a, grid, block, s)));
+        if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
         // nodes touched by slots [b, b + len)
         uint32_t n_lo, n_hi;
         if (starts) {
@@ -302,6 +317,7 @@ pdd_status run_launches(pdd_ctx *ctx, PathArgs<T> &a, ReduceArgs &r, uint64_t to
         r.node_lo = n_lo;
         HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
     }
+    if (timed) ctx->timed.push_back(ev);
     return PDD_OK;
 }
 
@@ -463,24 +479,25 @@ pdd_status solve_impl(pdd_problem *prob, const pdd_grid *u_prev, const pdd_grid 
 
     if (total) {
         const std::vector<uint64_t> *sp = uniform ? nullptr : &starts;
+        const bool timed = (o->flags & PDD_TIME_KERNEL) != 0;
         if (o->precision == PDD_FP32) {
             PathArgs<float> a{};
             fill_args(a, prob->pf);
             if (dim == 2)
-                st = cv ? run_launches<float, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
-                        : run_launches<float, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+                st = cv ? run_launches<float, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
+                        : run_launches<float, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
             else
-                st = cv ? run_launches<float, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
-                        : run_launches<float, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+                st = cv ? run_launches<float, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
+                        : run_launches<float, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
         } else {
             PathArgs<double> a{};
             fill_args(a, prob->pd);
             if (dim == 2)
-                st = cv ? run_launches<double, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
-                        : run_launches<double, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+                st = cv ? run_launches<double, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
+                        : run_launches<double, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
             else
-                st = cv ? run_launches<double, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s)
-                        : run_launches<double, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, s);
+                st = cv ? run_launches<double, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
+                        : run_launches<double, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
         }
         if (st) return st;
     }
@@ -550,6 +567,12 @@ void pdd_shutdown(pdd_ctx *ctx)
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     (void)hipEventDestroy(ctx->done);
     (void)hipEventDestroy(ctx->staged);
+    for (auto *v : {&ctx->timed, &ctx->spare})
+        for (auto &e : *v) {
+            (void)hipEventSynchronize(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
     delete ctx;
 }
 
@@ -594,6 +617,23 @@ pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_i
         pdd_status st = solve_impl(it.problem, it.u_prev, it.resid, it.nodes, it.n_nodes, it.opts, it.out, stream);
         if (st) return st;
     }
+    return PDD_OK;
+}
+
+pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !ms)) return fail(PDD_E_INVALID, "bad arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    int32_t k = 0;
+    for (auto &e : ctx->timed) {
+        HIP_TRY(hipEventSynchronize(e.second));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+        if (k < cap) ms[k++] = (double)t;
+        ctx->spare.push_back(e);
+    }
+    ctx->timed.clear();
+    *n = k;
     return PDD_OK;
 }
 

@@ -20,6 +20,7 @@ EXITS = {"bridge": 0, "shift": 1, "naive": 2}
 LAWS = {"gauss": 0, "rademacher": 1}
 PRECISIONS = {"fp32": 0, "fp64": 1}
 PLAIN_ALONGSIDE = 1
+TIME_KERNEL = 2
 MAX_TRIG, MAX_MONO = 16, 8
 
 
@@ -100,6 +101,8 @@ SIGNATURES = {
     "pdd_solve_batch": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32, C.c_void_p]),
     "pdd_autotune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
                                  C.POINTER(SolveOpts), C.POINTER(Tuning)]),
+    "pdd_kernel_times": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                     C.POINTER(C.c_int32)]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -258,7 +261,7 @@ class Problem:
 
 def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
               precision="fp32", exit="bridge", law="gauss", max_steps=0, plain_alongside=False,
-              records=None, tuning=None):
+              records=None, tuning=None, time_kernel=False):
     o = SolveOpts()
     o.dt = float(dt)
     o.n_paths = int(n_paths)
@@ -273,7 +276,7 @@ def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
     o.exit_mode = EXITS[exit]
     o.law = LAWS[law]
     o.max_steps = int(max_steps)
-    o.flags = PLAIN_ALONGSIDE if plain_alongside else 0
+    o.flags = (PLAIN_ALONGSIDE if plain_alongside else 0) | (TIME_KERNEL if time_kernel else 0)
     if records is not None:
         o.rec_phi = records["phi"].data_ptr() if records.get("phi") is not None else None
         o.rec_e = records["e"].data_ptr() if records.get("e") is not None else None
@@ -359,6 +362,14 @@ def solve_batch(ctx: Context, items, stream=None):
         outs.append(out)
     _check(lib().pdd_solve_batch(ctx.handle, arr, len(items), _stream_handle(stream)))
     return outs
+
+
+def kernel_times(ctx: Context, cap=4096):
+    """Path-kernel GPU milliseconds of the solves issued with time_kernel=True."""
+    buf = (C.c_double * cap)()
+    n = C.c_int32()
+    _check(lib().pdd_kernel_times(ctx.handle, buf, cap, C.byref(n)))
+    return [buf[i] for i in range(n.value)]
 
 
 def autotune(problem: Problem, nodes, **opt):
