@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-paths", type=int, default=4,
                     help="oracle sample: paths 0..n-1 of every node (0 = skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before warmup, one plain device copy of this many MiB (scales the "
+                         "HBM byte counters of a profiler run)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -90,6 +93,13 @@ def main():
     ctx = pdd.Context(0)
     prob = pdd.Problem(ctx, pd)
     outs = [pdd.alloc_stats(len(nodes)) for _ in range(args.warmup + args.steps)]
+
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(s):
         pdd.solve_nodes(prob, nodes, out=outs[s], dt=H, n_paths=P, path_offset=s * P,

@@ -31,23 +31,51 @@ struct Block4 {
     uint32_t w0, w1, w2, w3;
 };
 
-// Philox4x32-10: two 32x32->64 products per round (v_mad_u64_u32), the key
-// bumped by the Weyl constants after each round.
+// Philox4x32-10: two 32x32->64 products per round (v_mad_u64_u32) and two
+// three-way XORs (v_bitop3_b32 with the XOR3 truth table 0x96), the key bumped
+// by the Weyl constants after each round.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// The ten round keys of a (wave-uniform) Philox key.
+struct KeySchedule {
+    uint32_t k0[10], k1[10];
+};
+
+// Builds the round keys in vector registers: the XOR3 takes three vector
+// operands at no extra cost, and keeping twenty uniform values out of the
+// scalar register file leaves it to the problem constants (no spills).
+__device__ __forceinline__ KeySchedule key_schedule(uint32_t k0, uint32_t k1)
+{
+    KeySchedule ks;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t v0, v1;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(v0) : "s"(k0));
+        asm volatile("v_mov_b32 %0, %1" : "=v"(v1) : "s"(k1));
+        ks.k0[r] = v0;
+        ks.k1[r] = v1;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return ks;
+}
+
 __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                         uint32_t k0, uint32_t k1)
+                                         const KeySchedule &ks)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, ks.k0[r]);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, ks.k1[r]);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
         c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
     }
     return {c0, c1, c2, c3};
 }
@@ -58,14 +86,13 @@ struct Arith;
 // FP32 path arithmetic: 24-bit uniforms, hardware transcendentals.
 template <>
 struct Arith<float> {
+    // (w + 1/2) 2^-32 with w rounded to 24 significant bits: within 2^-24
+    // (relative) of the FP64 uniform of the same word, never 0.
     __device__ static __forceinline__ float unif(uint32_t w)
-    {
-        return fmaf((float)(w >> 8), 0x1.0p-24f, 0x1.0p-25f);
-    }
-    __device__ static __forceinline__ float unif_bridge(uint32_t w)
     {
         return fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);
     }
+    __device__ static __forceinline__ float unif_bridge(uint32_t w) { return unif(w); }
     __device__ static __forceinline__ float radius(uint32_t w)
     {
         return __builtin_amdgcn_sqrtf(-2.0f * kLn2f * __builtin_amdgcn_logf(unif(w)));
@@ -81,16 +108,18 @@ struct Arith<float> {
     {
         return radius(a) * __builtin_amdgcn_cosf(unif(b));
     }
+    // k and ph are in revolutions; the hardware sine and cosine reduce any
+    // argument within +-256 revolutions themselves.
     __device__ static __forceinline__ void trig(const DevTrig<float> &t, int d, float x, float &s,
                                                 float &c)
     {
-        const float rev = __builtin_amdgcn_fractf(fmaf(t.krev[d], x, t.phrev[d]));
+        const float rev = fmaf(t.k[d], x, t.ph[d]);
         s = __builtin_amdgcn_sinf(rev);
         c = __builtin_amdgcn_cosf(rev);
     }
     __device__ static __forceinline__ float sine(const DevTrig<float> &t, int d, float x)
     {
-        return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(fmaf(t.krev[d], x, t.phrev[d])));
+        return __builtin_amdgcn_sinf(fmaf(t.k[d], x, t.ph[d]));
     }
     __device__ static __forceinline__ float exp_neg(float x)
     {
@@ -134,24 +163,67 @@ struct Arith<double> {
     __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
 };
 
-template <class T>
-__device__ __forceinline__ T ipow(T x, int n)
-{
-    T r = (T)1;
-    for (int i = 0; i < n; ++i) r *= x;
-    return r;
-}
-
+// Sum of monomials coef * x^e0 y^e1 z^e2 (exponents read from a wave-uniform
+// packed word, so the power loops are scalar-controlled).
 template <class T, int D>
-__device__ __forceinline__ T mono_value(const DevMono<T> &q, const T *x)
+__device__ __forceinline__ T poly_value(const DevPoly<T> *terms, int n, const T *x)
 {
-    T v = q.coef;
+    T acc = (T)0;
+    for (int m = 0; m < n; ++m) {
+        const uint32_t e = terms[m].e;
+        T v = terms[m].coef;
 #pragma unroll
-    for (int d = 0; d < D; ++d) v *= ipow(x[d], q.e[d]);
-    return v;
+        for (int d = 0; d < D; ++d) {
+            const int ed = (int)((e >> (8 * d)) & 0xffu);
+            for (int i = 0; i < ed; ++i) v *= x[d];
+        }
+        acc += v;
+    }
+    return acc;
 }
 
-// b(x), c(x) and, when asked, f(x) = (1/2) sigma^2 Lap U + b.grad U + c U + fx.
+// Dense polynomial in nested Horner form (no loops at run time): in 2D
+// sum_j y^j sum_{i <= 5 - j} c_ij x^i, coefficients ordered by j then i;
+// in 3D sum_k z^k sum_j y^j sum_{i <= 4 - j - k} c_ijk x^i, ordered by k, j, i.
+template <class T, int D>
+__device__ __forceinline__ T dense_poly(const T *c, const T *x)
+{
+    if (D == 2) {
+        constexpr int deg = kDenseDeg2;
+        T acc = (T)0;
+        int off = (deg + 1) * (deg + 2) / 2;
+#pragma unroll
+        for (int j = deg; j >= 0; --j) {
+            off -= deg - j + 1;  // first coefficient of row j
+            T p = c[off + deg - j];
+#pragma unroll
+            for (int i = deg - j - 1; i >= 0; --i) p = p * x[0] + c[off + i];
+            acc = (j == deg) ? p : acc * x[1] + p;
+        }
+        return acc;
+    }
+    constexpr int deg = kDenseDeg3;
+    T accz = (T)0;
+    int off = kMaxDense;
+#pragma unroll
+    for (int k = deg; k >= 0; --k) {
+        T accy = (T)0;
+#pragma unroll
+        for (int j = deg - k; j >= 0; --j) {
+            off -= deg - j - k + 1;  // row (j, k)
+            T p = c[off + deg - j - k];
+#pragma unroll
+            for (int i = deg - j - k - 1; i >= 0; --i) p = p * x[0] + c[off + i];
+            accy = (j == deg - k) ? p : accy * x[1] + p;
+        }
+        accz = (k == deg) ? accy : accz * x[2 % D] + accy;
+    }
+    return accz;
+}
+
+// b(x), c(x) and, when asked, f(x) = F(x) + sum over trig terms T of
+// (1/2) sigma^2 Lap T + b.grad T + c T, where Lap T = -|k|^2 T and
+// d_d T = amp k_d cos(k_d x_d + ph_d) prod_{e != d} sin(k_e x_e + ph_e).
 template <class T, int D>
 __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x, T *b, T &c,
                                              T &f, bool want_f)
@@ -168,69 +240,37 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
     for (int d = 0; d < D; ++d) r2 += x[d] * x[d];
     c = P.c_a + P.c_b * r2;
     if (!want_f) return;
-    T u = (T)0, lap = (T)0, gr[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) gr[d] = (T)0;
+    T acc = (T)0;
+    if (P.f_mode == kPolyDense)
+        acc = dense_poly<T, D>(P.fdense, x);
+    else if (P.f_mode == kPolySparse)
+        acc = poly_value<T, D>(P.fpoly, P.n_f, x);
     for (int m = 0; m < P.n_trig; ++m) {
         const DevTrig<T> &t = P.trig[m];
         T s[D], co[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) Arith<T>::trig(t, d, x[d], s[d], co[d]);
-        T val = t.amp;
+        T prod = s[0];
 #pragma unroll
-        for (int d = 0; d < D; ++d) val *= s[d];
-        u += val;
-        lap -= t.ksq * val;
+        for (int d = 1; d < D; ++d) prod *= s[d];
+        acc += (c * t.amp + t.nhk2a) * prod;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            T g = t.amp * t.k[d] * co[d];
+            T g = b[d] * t.ak[d] * co[d];
 #pragma unroll
             for (int e = 0; e < D; ++e)
                 if (e != d) g *= s[e];
-            gr[d] += g;
+            acc += g;
         }
     }
-    for (int m = 0; m < P.n_mono; ++m) {
-        const DevMono<T> &q = P.mono[m];
-        T pw[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) pw[d] = ipow(x[d], q.e[d]);
-        T val = q.coef;
-#pragma unroll
-        for (int d = 0; d < D; ++d) val *= pw[d];
-        u += val;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int ed = q.e[d];
-            if (ed >= 1) {
-                T g = q.coef * (T)ed * ipow(x[d], ed - 1);
-#pragma unroll
-                for (int e = 0; e < D; ++e)
-                    if (e != d) g *= pw[e];
-                gr[d] += g;
-            }
-            if (ed >= 2) {
-                T l = q.coef * (T)(ed * (ed - 1)) * ipow(x[d], ed - 2);
-#pragma unroll
-                for (int e = 0; e < D; ++e)
-                    if (e != d) l *= pw[e];
-                lap += l;
-            }
-        }
-    }
-    T acc = P.half_s2 * lap;
-#pragma unroll
-    for (int d = 0; d < D; ++d) acc += b[d] * gr[d];
-    acc += c * u;
-    for (int m = 0; m < P.n_fx; ++m) acc += mono_value<T, D>(P.fx[m], x);
     f = acc;
 }
 
-// g = U + gx at a boundary point.
+// g = G + sum(trig) at a boundary point.
 template <class T, int D>
 __device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x)
 {
-    T u = (T)0;
+    T u = poly_value<T, D>(P.gpoly, P.n_g, x);
     for (int m = 0; m < P.n_trig; ++m) {
         const DevTrig<T> &t = P.trig[m];
         T v = t.amp;
@@ -238,8 +278,6 @@ __device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x)
         for (int d = 0; d < D; ++d) v *= Arith<T>::sine(t, d, x[d]);
         u += v;
     }
-    for (int m = 0; m < P.n_mono; ++m) u += mono_value<T, D>(P.mono[m], x);
-    for (int m = 0; m < P.n_gx; ++m) u += mono_value<T, D>(P.gx[m], x);
     return u;
 }
 
@@ -362,13 +400,17 @@ template <class T, int D, bool CV>
 struct Walker {
     T X[D], Xt[D];
     T Y;
+    T m;  // distance from X to the boundary (inside; cached between steps)
     double Z, R;
     uint64_t slot;
     uint32_t k, j, node, capped;
     uint32_t bb_blk;
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
+    KeySchedule ks;
 
-    __device__ __forceinline__ void start(const PathArgs<T> &a, uint64_t s)
+    // Starts the path in slot s. Returns false when it ends before any step
+    // (a node inside the shift band of the shifted-boundary test).
+    __device__ __forceinline__ bool start(const PathArgs<T> &a, uint64_t s)
     {
         slot = s;
         uint64_t jj;
@@ -396,19 +438,25 @@ struct Walker {
         j = (uint32_t)(a.path_offset + jj);
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
+        m = inner_distance<T, D>(a.prob, X);
         Y = (T)1;
         Z = 0.0;
         R = 0.0;
         k = 0;
         capped = 0;
         bb_blk = 0xffffffffu;
+        if (a.exit_mode == kExitShift && m <= a.gm_thresh) {
+            project<T, D>(a.prob, X, Xt);
+            return false;
+        }
+        return true;
     }
 
     __device__ __forceinline__ T bridge_uniform(const PathArgs<T> &a, uint32_t s)
     {
         const uint32_t blk = s >> 2;
         if (blk != bb_blk) {
-            const Block4 q = philox(blk, j, node, a.stream_tag | 1u, a.prob.key0, a.prob.key1);
+            const Block4 q = philox(blk, j, node, a.stream_tag | 1u, ks);
             bw01 = (uint64_t)q.w0 | ((uint64_t)q.w1 << 32);
             bw23 = (uint64_t)q.w2 | ((uint64_t)q.w3 << 32);
             bb_blk = blk;
@@ -419,20 +467,13 @@ struct Walker {
     }
 
     // One step of the walk with the words that feed its normals. Returns
-    // false when the path has ended (exit point in Xt).
+    // false when the path has ended (exit point in Xt). Everything that ends a
+    // path (leaving the domain, a live bridge face, the shift band of the next
+    // step, the step cap) goes through one rarely taken branch.
     __device__ __forceinline__ bool step(const PathArgs<T> &a, uint32_t wa, uint32_t wb,
                                          uint32_t wc, uint32_t wd)
     {
         const DevProblem<T> &P = a.prob;
-        if (a.exit_mode == kExitShift && inner_distance<T, D>(P, X) <= a.gm_thresh) {
-            project<T, D>(P, X, Xt);
-            return false;
-        }
-        if (k == a.max_steps) {
-            capped = 1;
-            project<T, D>(P, X, Xt);
-            return false;
-        }
         T n[D];
         if (a.law == kLawGauss) {
             Arith<T>::box_muller(wa, wb, n[0], n[1]);
@@ -454,78 +495,91 @@ struct Walker {
         const uint32_t s = k;
         k = k + 1;
 
-        if (a.exit_mode != kExitShift) {
-            if (P.domain == kBox) {
-                bool inside = true;
+        // distance of the new point to the boundary (negative outside)
+        T mn;
+        if (P.domain == kBox) {
+            mn = Xn[0] - P.lo[0];
+            mn = fmin(mn, P.hi[0] - Xn[0]);
 #pragma unroll
-                for (int d = 0; d < D; ++d) inside = inside && (Xn[d] > P.lo[d]) && (Xn[d] < P.hi[d]);
-                if (!inside) {
+            for (int d = 1; d < D; ++d) {
+                mn = fmin(mn, Xn[d] - P.lo[d]);
+                mn = fmin(mn, P.hi[d] - Xn[d]);
+            }
+        } else {
+            T r2n = (T)0;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) Xt[d] = fmin(fmax(Xn[d], P.lo[d]), P.hi[d]);
-                    return false;
-                }
-                if (a.exit_mode == kExitBridge) {
-                    T prod[2 * D];
-                    T mp;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        prod[2 * d] = (X[d] - P.lo[d]) * (Xn[d] - P.lo[d]);
-                        prod[2 * d + 1] = (P.hi[d] - X[d]) * (P.hi[d] - Xn[d]);
-                    }
-                    mp = prod[0];
-#pragma unroll
-                    for (int q = 1; q < 2 * D; ++q) mp = fmin(mp, prod[q]);
-                    if (mp * a.two_over_s2h <= a.bridge_thresh) {
-                        T Pe = (T)0, bestp = (T)-1;
-                        int bestf = 0;
-#pragma unroll
-                        for (int q = 0; q < 2 * D; ++q) {
-                            const T arg = prod[q] * a.two_over_s2h;
-                            if (arg <= a.bridge_thresh) {
-                                const T p = Arith<T>::exp_neg(arg);
-                                Pe = Pe + p * ((T)1 - Pe);
-                                if (p > bestp) {
-                                    bestp = p;
-                                    bestf = q;
-                                }
-                            }
-                        }
-                        if (bridge_uniform(a, s) < Pe) {
-#pragma unroll
-                            for (int d = 0; d < D; ++d)
-                                Xt[d] = (bestf >> 1) == d ? ((bestf & 1) ? P.hi[d] : P.lo[d]) : Xn[d];
-                            return false;
-                        }
-                    }
-                }
-            } else {
-                T r2n = (T)0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const T t = Xn[d] - P.center[d];
-                    r2n += t * t;
-                }
-                if (!(r2n < P.radius2)) {
-                    radial<T, D>(P, Xn, Xt);
-                    return false;
-                }
-                if (a.exit_mode == kExitBridge) {
-                    const T an = P.radius - Arith<T>::sqrt_(r2n);
-                    const T a0 = inner_distance<T, D>(P, X);
-                    const T arg = a0 * an * a.two_over_s2h;
-                    if (arg <= a.bridge_thresh) {
-                        const T Pe = Arith<T>::exp_neg(arg);
-                        if (bridge_uniform(a, s) < Pe) {
-                            radial<T, D>(P, Xn, Xt);
-                            return false;
-                        }
-                    }
-                }
+            for (int d = 0; d < D; ++d) {
+                const T t = Xn[d] - P.center[d];
+                r2n += t * t;
+            }
+            mn = r2n < P.radius2 ? P.radius - Arith<T>::sqrt_(r2n) : (T)-1;
+        }
+        const bool shift = a.exit_mode == kExitShift;
+        // Bridge: a face f is live when a_f a'_f 2/(sigma^2 h) <= 36 ln 2; since
+        // a_f >= m and a'_f >= mn, no face is live unless m mn passes that test.
+        const bool out = !shift && !(mn > (T)0);
+        const bool maybe = a.exit_mode == kExitBridge && m * mn * a.two_over_s2h <= a.bridge_thresh;
+        const bool next_stop = k == a.max_steps || (shift && mn <= a.gm_thresh);
+        if (out || maybe || next_stop) {
+            if (out) {
+                project<T, D>(P, Xn, Xt);
+                return false;
+            }
+            if (maybe && bridge_exit(a, Xn, mn, s)) return false;
+            if (shift && mn <= a.gm_thresh) {  // stops before the next step
+                project<T, D>(P, Xn, Xt);
+                return false;
+            }
+            if (k == a.max_steps) {
+                capped = 1;
+                project<T, D>(P, Xn, Xt);
+                return false;
             }
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = Xn[d];
+        m = mn;
         return true;
+    }
+
+    // Brownian-bridge exit between X and Xn (both inside, Xn at distance mn).
+    // Per flat face P(cross) = exp(-2 a a' / (sigma^2 h)), faces combined as
+    // independent; exit onto the live face with the largest probability.
+    __device__ __forceinline__ bool bridge_exit(const PathArgs<T> &a, const T *Xn, T mn, uint32_t s)
+    {
+        const DevProblem<T> &P = a.prob;
+        if (P.domain == kBox) {
+            T Pe = (T)0, bestp = (T)-1;
+            int bestf = 0;
+#pragma unroll
+            for (int q = 0; q < 2 * D; ++q) {
+                const int d = q >> 1;
+                const T prod = (q & 1) ? (P.hi[d] - X[d]) * (P.hi[d] - Xn[d])
+                                       : (X[d] - P.lo[d]) * (Xn[d] - P.lo[d]);
+                const T arg = prod * a.two_over_s2h;
+                if (arg <= a.bridge_thresh) {
+                    const T p = Arith<T>::exp_neg(arg);
+                    Pe = Pe + p * ((T)1 - Pe);
+                    if (p > bestp) {
+                        bestp = p;
+                        bestf = q;
+                    }
+                }
+            }
+            if (bestp >= (T)0 && bridge_uniform(a, s) < Pe) {
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    Xt[d] = (bestf >> 1) == d ? ((bestf & 1) ? P.hi[d] : P.lo[d]) : Xn[d];
+                return true;
+            }
+            return false;
+        }
+        const T Pe = Arith<T>::exp_neg(m * mn * a.two_over_s2h);
+        if (bridge_uniform(a, s) < Pe) {
+            radial<T, D>(P, Xn, Xt);
+            return true;
+        }
+        return false;
     }
 
     // Score the ended path and write its record.
@@ -548,6 +602,7 @@ __global__ void __launch_bounds__(256) path_kernel(const PathArgs<T> a)
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     Walker<T, D, CV> w;
+    w.ks = key_schedule(a.prob.key0, a.prob.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     uint32_t pool_next = 0, pool_end = 0;
     bool exhausted = false;
@@ -572,26 +627,23 @@ __global__ void __launch_bounds__(256) path_kernel(const PathArgs<T> a)
             }
             const uint32_t avail = pool_end - pool_next;
             const uint32_t rank = (uint32_t)__popcll(idle & below);
-            if (st == 0 && rank < avail) {
-                w.start(a, a.slot_begin + pool_next + rank);
-                st = 1;
-            }
+            if (st == 0 && rank < avail) st = w.start(a, a.slot_begin + pool_next + rank) ? 1 : 2;
             pool_next += min(avail, (uint32_t)__popcll(idle));
         }
-        if (__ballot(st == 1) == 0) {
+        if (__ballot(st != 0) == 0) {
             if (exhausted) break;
             continue;
         }
         if (st == 1) {
             if (D == 2) {
                 // One block feeds this step (words 0,1) and the next (words 2,3).
-                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, a.prob.key0, a.prob.key1);
+                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
                 if (!w.step(a, q.w0, q.w1, 0u, 0u))
                     st = 2;
                 else if (!w.step(a, q.w2, q.w3, 0u, 0u))
                     st = 2;
             } else {
-                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, a.prob.key0, a.prob.key1);
+                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
                 if (!w.step(a, q.w0, q.w1, q.w2, q.w3)) st = 2;
             }
         }

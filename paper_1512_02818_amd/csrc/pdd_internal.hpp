@@ -14,38 +14,52 @@ constexpr int kLawGauss = 0, kLawRademacher = 1;
 constexpr int kBox = 0, kBall = 1;
 constexpr uint32_t kCappedBit = 0x80000000u;
 
-// One trig term amp * prod_d sin(k_d x_d + ph_d). krev / phrev are k / 2pi and
-// ph / 2pi (the hardware sine takes revolutions); ksq = |k|^2.
+// One trig term amp * prod_d sin(k_d x_d + ph_d). In FP32, k and ph are in
+// revolutions (k / 2 pi, ph / 2 pi: the hardware sine takes revolutions); in
+// FP64 in radians. ak_d = amp * k_d (radians), nhk2a = -(1/2) sigma^2 |k|^2 amp.
 template <class T>
 struct DevTrig {
-    T amp, ksq;
-    T k[3], ph[3];
-    T krev[3], phrev[3];
+    T amp, nhk2a;
+    T k[3], ph[3], ak[3];
 };
 
+// coef * x^e0 y^e1 z^e2, exponents packed e0 | e1 << 8 | e2 << 16.
 template <class T>
-struct DevMono {
+struct DevPoly {
     T coef;
-    int32_t e[3];
+    uint32_t e;
 };
 
-// Problem in the precision of the path arithmetic. Read by every lane with the
-// same address, so the compiler serves it from the scalar cache.
+constexpr int kMaxF = 64;  // terms of the expanded polynomial part of f
+constexpr int kMaxG = 16;  // terms of the polynomial part of g
+// Dense form of the polynomial part of f, evaluated without loops: total
+// degree <= 5 in 2D (21 coefficients), <= 4 in 3D (35 coefficients).
+constexpr int kDenseDeg2 = 5, kDenseDeg3 = 4, kMaxDense = 35;
+constexpr int kPolyNone = 0, kPolyDense = 1, kPolySparse = 2;
+
+// Problem in the precision of the path arithmetic; passed by value as a kernel
+// argument, so every lane reads it through the scalar unit. The manufactured
+// function is U = sum(trig) + P with P a sum of monomials; the host expands
+// F = (1/2) sigma^2 Lap P + b.grad P + c P + fx and G = P + gx into monomials,
+// so that f = F + sum over trig terms of ((1/2) sigma^2 Lap + b.grad + c) T and
+// g = G + sum(trig).
 template <class T>
 struct DevProblem {
     int32_t dim, domain;
-    int32_t n_trig, n_mono, n_fx, n_gx;
+    int32_t n_trig, n_f, n_g;
+    int32_t f_mode;  // kPolyNone, kPolyDense or kPolySparse
     uint32_t key0, key1;
     T lo[3], hi[3], center[3];
     T radius, radius2;
-    T half_s2;  // sigma^2 / 2
     T b0[3];
     T B[3][3];
     T c_a, c_b;
     DevTrig<T> trig[kMaxTrig];
-    DevMono<T> mono[kMaxMono];
-    DevMono<T> fx[kMaxMono];
-    DevMono<T> gx[kMaxMono];
+    DevPoly<T> fpoly[kMaxF];
+    DevPoly<T> gpoly[kMaxG];
+    // dense coefficients of F, ordered for nested Horner evaluation: 2D by
+    // j (power of y) then i (power of x), i + j <= 5; 3D by k, j, i
+    T fdense[kMaxDense];
 };
 
 // A grid as the kernels read it: value(x) = bilinear / trilinear interpolation.

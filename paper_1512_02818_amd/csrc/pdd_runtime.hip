@@ -114,16 +114,105 @@ pdd_status ensure_stage(pdd_ctx *ctx, size_t bytes)
     return PDD_OK;
 }
 
+// Monomials keyed by packed exponents (e0 | e1 << 8 | e2 << 16).
+using PolyMap = std::map<uint32_t, double>;
+
+uint32_t pack_exp(const int e[3]) { return (uint32_t)e[0] | ((uint32_t)e[1] << 8) | ((uint32_t)e[2] << 16); }
+
+void poly_add(PolyMap &p, const int e[3], double coef)
+{
+    if (coef != 0.0) p[pack_exp(e)] += coef;
+}
+
+// F = (1/2) sigma^2 Lap P + b.grad P + c P + fx for P = sum of the monomials,
+// b = b0 + B x, c = c_a + c_b |x|^2, expanded into monomials.
+PolyMap expand_source(const pdd_problem_desc &d)
+{
+    PolyMap F;
+    const double hs2 = 0.5 * d.sigma * d.sigma;
+    for (int m = 0; m < d.n_mono; ++m) {
+        const pdd_mono_term &q = d.mono[m];
+        int e[3] = {q.e[0], q.e[1], q.e[2]};
+        for (int i = 0; i < d.dim; ++i) {
+            if (e[i] >= 2) {  // (1/2) sigma^2 d_ii
+                int t[3] = {e[0], e[1], e[2]};
+                t[i] -= 2;
+                poly_add(F, t, hs2 * q.coef * e[i] * (e[i] - 1));
+            }
+            if (e[i] >= 1) {  // b_i d_i = (b0_i + sum_j B_ij x_j) d_i
+                int t[3] = {e[0], e[1], e[2]};
+                t[i] -= 1;
+                const double g = q.coef * e[i];
+                poly_add(F, t, d.b0[i] * g);
+                for (int j = 0; j < d.dim; ++j) {
+                    int u[3] = {t[0], t[1], t[2]};
+                    u[j] += 1;
+                    poly_add(F, u, d.B[i][j] * g);
+                }
+            }
+        }
+        poly_add(F, e, d.c_a * q.coef);  // c P
+        for (int j = 0; j < d.dim; ++j) {
+            int u[3] = {e[0], e[1], e[2]};
+            u[j] += 2;
+            poly_add(F, u, d.c_b * q.coef);
+        }
+    }
+    for (int m = 0; m < d.n_fx; ++m) poly_add(F, d.fx[m].e, d.fx[m].coef);
+    return F;
+}
+
+PolyMap expand_boundary(const pdd_problem_desc &d)
+{
+    PolyMap G;
+    for (int m = 0; m < d.n_mono; ++m) poly_add(G, d.mono[m].e, d.mono[m].coef);
+    for (int m = 0; m < d.n_gx; ++m) poly_add(G, d.gx[m].e, d.gx[m].coef);
+    return G;
+}
+
 template <class T>
-void fill_problem(const pdd_problem_desc &d, DevProblem<T> &p)
+int fill_poly(const PolyMap &src, DevPoly<T> *dst, int cap)
+{
+    int n = 0;
+    for (const auto &kv : src) {
+        if (kv.second == 0.0) continue;
+        if (n == cap) return -1;
+        dst[n].coef = (T)kv.second;
+        dst[n].e = kv.first;
+        ++n;
+    }
+    return n;
+}
+
+// Dense Horner table of F when every monomial fits (2D: total degree <= 5,
+// 3D: <= 4), in the order the kernel reads it (3D: k, then j, then i).
+template <class T>
+bool fill_dense(const PolyMap &F, int dim, T *c)
+{
+    const int deg = dim == 2 ? kDenseDeg2 : kDenseDeg3;
+    for (int q = 0; q < kMaxDense; ++q) c[q] = (T)0;
+    for (const auto &kv : F) {
+        const int e0 = kv.first & 0xff, e1 = (kv.first >> 8) & 0xff, e2 = (kv.first >> 16) & 0xff;
+        if (e0 + e1 + e2 > deg) return false;
+    }
+    int off = 0;
+    for (int k = 0; k <= (dim == 3 ? deg : 0); ++k)
+        for (int j = 0; j <= deg - k; ++j)
+            for (int i = 0; i <= deg - j - k; ++i, ++off) {
+                const int e[3] = {i, j, k};
+                auto it = F.find(pack_exp(e));
+                if (it != F.end()) c[off] = (T)it->second;
+            }
+    return true;
+}
+
+template <class T>
+pdd_status fill_problem(const pdd_problem_desc &d, DevProblem<T> &p, bool revolutions)
 {
     std::memset(&p, 0, sizeof p);
     p.dim = d.dim;
     p.domain = d.domain;
     p.n_trig = d.n_trig;
-    p.n_mono = d.n_mono;
-    p.n_fx = d.n_fx;
-    p.n_gx = d.n_gx;
     p.key0 = (uint32_t)(d.seed & 0xffffffffu);
     p.key1 = (uint32_t)(d.seed >> 32);
     for (int i = 0; i < 3; ++i) {
@@ -135,33 +224,33 @@ void fill_problem(const pdd_problem_desc &d, DevProblem<T> &p)
     }
     p.radius = (T)d.radius;
     p.radius2 = (T)(d.radius * d.radius);
-    p.half_s2 = (T)(0.5 * d.sigma * d.sigma);
     p.c_a = (T)d.c_a;
     p.c_b = (T)d.c_b;
     const double inv2pi = 0.15915494309189533577;
+    const double hs2 = 0.5 * d.sigma * d.sigma;
     for (int m = 0; m < d.n_trig; ++m) {
         const pdd_trig_term &t = d.trig[m];
         DevTrig<T> &q = p.trig[m];
-        q.amp = (T)t.amp;
         double ksq = 0.0;
         for (int k = 0; k < d.dim; ++k) ksq += t.k[k] * t.k[k];
-        q.ksq = (T)ksq;
+        q.amp = (T)t.amp;
+        q.nhk2a = (T)(-hs2 * ksq * t.amp);
         for (int k = 0; k < 3; ++k) {
-            q.k[k] = (T)t.k[k];
-            q.ph[k] = (T)t.phase[k];
-            q.krev[k] = (T)(t.k[k] * inv2pi);
-            q.phrev[k] = (T)(t.phase[k] * inv2pi);
+            q.k[k] = (T)(revolutions ? t.k[k] * inv2pi : t.k[k]);
+            q.ph[k] = (T)(revolutions ? t.phase[k] * inv2pi : t.phase[k]);
+            q.ak[k] = (T)(t.amp * t.k[k]);
         }
     }
-    auto cp = [](const pdd_mono_term *src, DevMono<T> *dst, int n) {
-        for (int m = 0; m < n; ++m) {
-            dst[m].coef = (T)src[m].coef;
-            for (int k = 0; k < 3; ++k) dst[m].e[k] = src[m].e[k];
-        }
-    };
-    cp(d.mono, p.mono, d.n_mono);
-    cp(d.fx, p.fx, d.n_fx);
-    cp(d.gx, p.gx, d.n_gx);
+    const PolyMap F = expand_source(d);
+    const int nf = fill_poly(F, p.fpoly, kMaxF);
+    const int ng = fill_poly(expand_boundary(d), p.gpoly, kMaxG);
+    if (nf < 0 || ng < 0)
+        return fail(PDD_E_UNSUPPORTED, "polynomial part too large: f needs <= %d and g <= %d monomials",
+                    kMaxF, kMaxG);
+    p.n_f = nf;
+    p.n_g = ng;
+    p.f_mode = nf == 0 ? kPolyNone : (fill_dense(F, d.dim, p.fdense) ? kPolyDense : kPolySparse);
+    return PDD_OK;
 }
 
 bool finite3(const double *v, int n)
@@ -585,8 +674,10 @@ pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_pr
     pdd_problem *p = new pdd_problem();
     p->ctx = ctx;
     p->desc = *desc;
-    fill_problem(*desc, p->pf);
-    fill_problem(*desc, p->pd);
+    if ((st = fill_problem(*desc, p->pf, true)) || (st = fill_problem(*desc, p->pd, false))) {
+        delete p;
+        return st;
+    }
     *out = p;
     return PDD_OK;
 }

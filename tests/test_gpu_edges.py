@@ -1,0 +1,181 @@
+"""GPU edge cases through the C ABI: empty and ragged inputs, single paths,
+the step cap, invalid arguments, resume by path offset, independence of the
+launch shape (block size, persistent grid, queue grab, launch chunking) and
+run-to-run determinism."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_02818_amd import pdd  # noqa: E402
+from paper_1512_02818_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def prob(ctx):
+    p = pdd.Problem(ctx, W.unit_square_problem(seed=3))
+    yield p
+    p.close()
+
+
+def run(prob, nodes, total, **kw):
+    rec = pdd.alloc_records(max(total, 1))
+    out = pdd.solve_nodes(prob, nodes, records=rec, **kw)
+    torch.cuda.synchronize()
+    st = pdd.stats_to_numpy(out)
+    return st, {k: (v.cpu().numpy()[:total] if v is not None else None) for k, v in rec.items()}
+
+
+def test_zero_nodes_is_a_noop(prob):
+    out = torch.full((pdd.STATS_DTYPE.itemsize,), 7, dtype=torch.uint8, device="cuda")
+    pdd.solve_nodes(prob, np.zeros((0, 2)), out=out, dt=1e-3, n_paths=10)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7)
+
+
+def test_ragged_counts_match_oracle_paths(prob):
+    from oracle import oracle as O
+    nodes = W.unit_square_nodes()[:7]
+    counts = np.array([0, 1, 63, 64, 65, 0, 300], dtype=np.uint64)
+    total = int(counts.sum())
+    for prec in ("fp64", "fp32"):
+        st, rec = run(prob, nodes, total, dt=1e-3, n_paths_per_node=counts, precision=prec,
+                      path_offset=11)
+        assert list(st["n"]) == list(counts)
+        assert np.isnan(st["mean"][0]) and np.isnan(st["mean"][5])
+        assert np.isnan(st["var"][1]) and not np.isnan(st["mean"][1])
+        node_idx = np.repeat(np.arange(len(nodes)), counts.astype(np.int64))
+        path_idx = np.concatenate([np.arange(c) for c in counts.astype(np.int64)]) + 11
+        orec = O.run_paths(prob.pd, nodes, node_idx, path_idx, h=1e-3)
+        same = (rec["steps"].view(np.uint32) & 0x7FFFFFFF) == orec["steps"]
+        assert same.mean() > (0.999 if prec == "fp64" else 0.98)
+        if prec == "fp64":
+            assert np.allclose(rec["phi"][same], orec["phi"][same], rtol=1e-11, atol=1e-12)
+        for i in np.nonzero(counts > 1)[0]:
+            seg = slice(int(counts[:i].sum()), int(counts[:i + 1].sum()))
+            assert st["steps_sum"][i] == int((rec["steps"][seg].view(np.uint32) & 0x7FFFFFFF).sum())
+
+
+def test_step_cap(prob):
+    nodes = W.unit_square_nodes()[:3]
+    st, rec = run(prob, nodes, 3 * 500, dt=1e-3, n_paths=500, max_steps=9, precision="fp64")
+    steps = rec["steps"].view(np.uint32)
+    capped = steps >> 31
+    assert np.all((steps & 0x7FFFFFFF) <= 9)
+    assert np.all((steps[capped == 1] & 0x7FFFFFFF) == 9)
+    assert st["n_capped"].sum() == capped.sum() > 0
+    # odd cap lands between the two steps that share a Philox block; same as the oracle
+    from oracle import oracle as O
+    ost, orec = O.solve_nodes(prob.pd, nodes, record=True, h=1e-3, n_paths=500, max_steps=9)
+    assert np.array_equal(steps & 0x7FFFFFFF, orec["steps"].astype(np.uint32))
+    assert np.array_equal(capped, orec["capped"].astype(np.uint32))
+
+
+@pytest.mark.parametrize("bad", ["outside", "on_boundary", "dt", "nan", "grid_dtype", "grid_cover",
+                                 "stream", "offset", "tuning"])
+def test_invalid_arguments_are_rejected(ctx, prob, bad):
+    nodes = W.unit_square_nodes()[:2].copy()
+    kw = dict(dt=1e-3, n_paths=10)
+    if bad == "outside":
+        nodes[1] = [1.2, 0.5]
+    elif bad == "on_boundary":
+        nodes[0] = [0.0, 0.5]
+    elif bad == "dt":
+        kw["dt"] = 0.0
+    elif bad == "nan":
+        nodes[0, 0] = np.nan
+    elif bad == "stream":
+        kw["stream_id"] = 1 << 28
+    elif bad == "offset":
+        kw["path_offset"] = (1 << 32) - 5
+    elif bad == "tuning":
+        kw["tuning"] = (96, 0, 64, 0)
+    if bad in ("grid_dtype", "grid_cover"):
+        g = W.sampled_grid(prob.pd, lambda p: np.zeros(len(p)), n=9, dtype=np.float64)
+        if bad == "grid_cover":
+            g["lo"] = [0.1, 0.0]
+        t = torch.zeros(81, dtype=torch.float64, device="cuda")
+        prec = "fp32" if bad == "grid_dtype" else "fp64"
+        with pytest.raises(pdd.PDDError) as ei:
+            pdd.solve_correction(prob, g, t, g, t, nodes, precision=prec, **kw)
+        assert ei.value.status == (-4 if bad == "grid_dtype" else -1)
+        return
+    with pytest.raises(pdd.PDDError) as ei:
+        pdd.solve_nodes(prob, nodes, **kw)
+    assert ei.value.status == -1
+    assert pdd.lib().pdd_last_error()
+
+
+def test_invalid_problems_are_rejected(ctx):
+    for mutate in (lambda p: p.update(dim=4), lambda p: p.update(sigma=0.0),
+                   lambda p: p.update(lo=[1.0, 0.0], hi=[0.0, 1.0]),
+                   lambda p: p["mono"].append({"coef": 1.0, "e": [9, 0]})):
+        pd = W.unit_square_problem()
+        mutate(pd)
+        with pytest.raises(pdd.PDDError):
+            pdd.Problem(ctx, pd)
+
+
+def test_resume_by_path_offset_is_the_same_paths(prob):
+    nodes = W.unit_square_nodes()[4:9]
+    n, a = 700, 333
+    _, full = run(prob, nodes, 5 * n, dt=1e-3, n_paths=n)
+    _, r1 = run(prob, nodes, 5 * a, dt=1e-3, n_paths=a)
+    _, r2 = run(prob, nodes, 5 * (n - a), dt=1e-3, n_paths=n - a, path_offset=a)
+    for i in range(5):
+        joined = np.concatenate([r1["phi"][i * a:(i + 1) * a], r2["phi"][i * (n - a):(i + 1) * (n - a)]])
+        assert joined.tobytes() == full["phi"][i * n:(i + 1) * n].tobytes()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_launch_shape_does_not_change_results(prob, prec):
+    nodes = W.unit_square_nodes()
+    n = 3000
+    ref_st, ref = run(prob, nodes, 18 * n, dt=1e-3, n_paths=n, precision=prec)
+    for tune in ((64, 1, 1, 0), (128, 3, 7, 0), (256, 0, 1024, 0), (256, 2, 64, 0)):
+        st, rec = run(prob, nodes, 18 * n, dt=1e-3, n_paths=n, precision=prec, tuning=tune)
+        assert rec["phi"].tobytes() == ref["phi"].tobytes(), tune
+        assert rec["steps"].tobytes() == ref["steps"].tobytes(), tune
+        assert st.tobytes() == ref_st.tobytes(), tune
+
+
+def test_chunked_launches_and_scratch_records(prob):
+    """Without caller records the library keeps records in scratch and may
+    cut the solve into several launches; statistics agree with one launch."""
+    nodes = W.unit_square_nodes()
+    n = 2500
+    one = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=n))
+    for cap in (4096, 10007, 1 << 20):
+        st = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=n,
+                                                tuning=(256, 0, 64, cap)))
+        assert np.array_equal(st["n"], one["n"]) and np.array_equal(st["steps_sum"], one["steps_sum"])
+        assert np.allclose(st["mean"], one["mean"], rtol=1e-14, atol=1e-15)
+        assert np.allclose(st["var"], one["var"], rtol=1e-12)
+
+
+def test_repeat_runs_are_bitwise_identical(prob):
+    nodes = W.unit_square_nodes()
+    a = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=4000))
+    b = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=4000))
+    assert a.tobytes() == b.tobytes()
+
+
+def test_kernel_times_reported(ctx, prob):
+    pdd.kernel_times(ctx)
+    for _ in range(3):
+        pdd.solve_nodes(prob, W.unit_square_nodes(), dt=1e-3, n_paths=500, time_kernel=True)
+    pdd.solve_nodes(prob, W.unit_square_nodes(), dt=1e-3, n_paths=500)
+    ms = pdd.kernel_times(ctx)
+    assert len(ms) == 3 and all(t > 0 for t in ms)
+    assert pdd.kernel_times(ctx) == []
