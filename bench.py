@@ -29,21 +29,26 @@ H = 1e-4
 SEED = 0
 
 # Algorithmic VALU cost of one 2D path step of this workload, in full-rate
-# lane-instruction slots (a quarter-rate instruction counts 4). Derived from
-# the operations the step must perform ("Roofline of the path
-# kernel"); independent of how the kernel happens to be compiled.
+# FP32 lane slots; transcendentals (log2, sqrt, sin, cos, exp2) and 32x32-bit
+# multiplies issue at a quarter of the FP32 rate and count 4, an FP64 add 2.
+# Derived from the operations the step must perform ("Roofline of
+# the path kernel"), not from the compiled code.
 STEP_COST = {
-    "philox_half_block": 10 * (2 * 4 + 4) // 2,  # 10 rounds x (2 wide mul + 4 xor), 2 steps/block
-    "uniforms": 2 * 3,                           # shift, convert, fma per word
-    "box_muller": 4 * 4 + 3,                     # log2, sqrt, sin, cos + 3 mul
-    "drift_killing": 4 + 3,                      # b = b0 + B x, c = c_a + c_b |x|^2
-    "source_f": 4 * 4 + 10 + 6 + 4,              # sin/cos x 2 + trig term + monomial + assembly
-    "euler_step": 9,                             # hY, Z (f64), Y, X
-    "exit_test": 17,                             # inside test + bridge live check
+    "philox_half_block": (10 * 2 * 4 + 10 * 2) // 2,  # 10 rounds x (2 wide mul + 2 xor3); 2 steps/block
+    "uniforms": 2 * 2,                                # convert + fma per word
+    "box_muller": 4 * 4 + 5,                          # log2, sqrt, sin, cos; scale, 2 mul
+    "drift_killing": 4 + 3,                           # b = b0 + B x; c = c_a + c_b |x|^2
+    "poly_source": 20,                                # degree-5 Horner form of the polynomial part of f
+    "trig_source": 2 + 4 * 4 + 8,                     # 2 arguments, sin/cos x 2, combination
+    "euler_step": 9 + 2,                              # hY, Z (FP64 add), Y, X
+    "exit_test": 12,                                  # distance to the box, exit, bridge bound
 }
 OPS_PER_STEP = sum(STEP_COST.values())
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane slots per second
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# FP32 FLOPs of the same step (FMA = 2; transcendentals not counted)
+FLOPS_PER_STEP = 4 + 3 + 8 + 5 + 40 + 16 + 12 + 7
+# 256 CUs x 128 FP32 lanes x 2.4 GHz: the 157.3 TFLOP/s FP32 vector peak / 2
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -161,10 +166,12 @@ def main():
                    "nodes": int(len(nodes)), "paths_per_step": P, "dt": H,
                    "mean_steps_per_path": total_steps / (args.steps * len(nodes) * P)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "Top/s (full-rate VALU lane slots)",
+                     "unit": "Top/s (FP32 VALU lane slots)",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                      "ops_per_step": OPS_PER_STEP,
-                     "kernel_ms_per_launch": float(np.mean(kern_ms))},
+                     "kernel_ms_per_launch": float(np.mean(kern_ms)),
+                     "fp32_tflops": FLOPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12,
+                     "fp32_peak_tflops": FP32_PEAK_TFLOPS},
     }
     if args.cpu_paths > 0:
         print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)

@@ -13,9 +13,11 @@ SOURCES = ["path_kernel.hip", "reduce_kernel.hip", "pdd_runtime.hip"]
 HEADERS = ["pdd_internal.hpp"]
 
 # Packed FP32 instructions are switched off: hipcc -O3 would otherwise form
-# them from plain float code.
+# them from plain float code. Contraction is off so that every fused
+# multiply-add is written in the source and all kernels round alike.
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-parameter", "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"),

@@ -80,6 +80,12 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
     return {c0, c1, c2, c3};
 }
 
+// Multiply-add with one rounding. The library is built without automatic
+// contraction, so every fused operation is written out and all kernels that
+// walk the same path round identically.
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class T>
 struct Arith;
 
@@ -153,11 +159,11 @@ struct Arith<double> {
     __device__ static __forceinline__ void trig(const DevTrig<double> &t, int d, double x,
                                                 double &s, double &c)
     {
-        sincos(t.k[d] * x + t.ph[d], &s, &c);
+        sincos(madd(t.k[d], x, t.ph[d]), &s, &c);
     }
     __device__ static __forceinline__ double sine(const DevTrig<double> &t, int d, double x)
     {
-        return sin(t.k[d] * x + t.ph[d]);
+        return sin(madd(t.k[d], x, t.ph[d]));
     }
     __device__ static __forceinline__ double exp_neg(double x) { return exp(-x); }
     __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
@@ -197,8 +203,8 @@ __device__ __forceinline__ T dense_poly(const T *c, const T *x)
             off -= deg - j + 1;  // first coefficient of row j
             T p = c[off + deg - j];
 #pragma unroll
-            for (int i = deg - j - 1; i >= 0; --i) p = p * x[0] + c[off + i];
-            acc = (j == deg) ? p : acc * x[1] + p;
+            for (int i = deg - j - 1; i >= 0; --i) p = madd(p, x[0], c[off + i]);
+            acc = (j == deg) ? p : madd(acc, x[1], p);
         }
         return acc;
     }
@@ -213,10 +219,10 @@ __device__ __forceinline__ T dense_poly(const T *c, const T *x)
             off -= deg - j - k + 1;  // row (j, k)
             T p = c[off + deg - j - k];
 #pragma unroll
-            for (int i = deg - j - k - 1; i >= 0; --i) p = p * x[0] + c[off + i];
-            accy = (j == deg - k) ? p : accy * x[1] + p;
+            for (int i = deg - j - k - 1; i >= 0; --i) p = madd(p, x[0], c[off + i]);
+            accy = (j == deg - k) ? p : madd(accy, x[1], p);
         }
-        accz = (k == deg) ? accy : accz * x[2 % D] + accy;
+        accz = (k == deg) ? accy : madd(accz, x[2 % D], accy);
     }
     return accz;
 }
@@ -232,13 +238,13 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
     for (int i = 0; i < D; ++i) {
         T v = P.b0[i];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v += P.B[i][j] * x[j];
+        for (int j = 0; j < D; ++j) v = madd(P.B[i][j], x[j], v);
         b[i] = v;
     }
     T r2 = (T)0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) r2 += x[d] * x[d];
-    c = P.c_a + P.c_b * r2;
+    for (int d = 0; d < D; ++d) r2 = madd(x[d], x[d], r2);
+    c = madd(P.c_b, r2, P.c_a);
     if (!want_f) return;
     T acc = (T)0;
     if (P.f_mode == kPolyDense)
@@ -253,14 +259,15 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
         T prod = s[0];
 #pragma unroll
         for (int d = 1; d < D; ++d) prod *= s[d];
-        acc += (c * t.amp + t.nhk2a) * prod;
+        acc = madd(madd(c, t.amp, t.nhk2a), prod, acc);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
+            const int last = d == D - 1 ? D - 2 : D - 1;  // factor taken by the fused add
             T g = b[d] * t.ak[d] * co[d];
 #pragma unroll
             for (int e = 0; e < D; ++e)
-                if (e != d) g *= s[e];
-            acc += g;
+                if (e != d && e != last) g *= s[e];
+            acc = madd(g, s[last], acc);
         }
     }
     f = acc;
@@ -302,8 +309,9 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
     if (D == 2) {
         const T *r0 = g.data + (size_t)i[1] * nx + i[0];
         const T *r1 = r0 + nx;
-        return ((T)1 - w[1]) * (((T)1 - w[0]) * r0[0] + w[0] * r0[1]) +
-               w[1] * (((T)1 - w[0]) * r1[0] + w[0] * r1[1]);
+        const T l0 = madd(w[0], r0[1], ((T)1 - w[0]) * r0[0]);
+        const T l1 = madd(w[0], r1[1], ((T)1 - w[0]) * r1[0]);
+        return madd(w[1], l1, ((T)1 - w[1]) * l0);
     }
     const int ny = g.n[1];
     T acc = (T)0;
@@ -313,10 +321,10 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
             const T *row = g.data + ((size_t)(i[2 % D] + dz) * ny + (i[1] + dy)) * nx + i[0];
-            const T line = ((T)1 - w[0]) * row[0] + w[0] * row[1];
-            layer += (dy ? w[1] : (T)1 - w[1]) * line;
+            const T line = madd(w[0], row[1], ((T)1 - w[0]) * row[0]);
+            layer = madd(dy ? w[1] : (T)1 - w[1], line, layer);
         }
-        acc += (dz ? w[2 % D] : (T)1 - w[2 % D]) * layer;
+        acc = madd(dz ? w[2 % D] : (T)1 - w[2 % D], layer, acc);
     }
     return acc;
 }
@@ -338,7 +346,7 @@ __device__ __forceinline__ T inner_distance(const DevProblem<T> &P, const T *x)
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const T t = x[d] - P.center[d];
-        r2 += t * t;
+        r2 = madd(t, t, r2);
     }
     return P.radius - Arith<T>::sqrt_(r2);
 }
@@ -350,12 +358,12 @@ __device__ __forceinline__ void radial(const DevProblem<T> &P, const T *x, T *ou
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const T t = x[d] - P.center[d];
-        r2 += t * t;
+        r2 = madd(t, t, r2);
     }
     const T r = Arith<T>::sqrt_(r2);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        out[d] = r > (T)0 ? P.center[d] + P.radius * ((x[d] - P.center[d]) / r)
+        out[d] = r > (T)0 ? madd(P.radius, (x[d] - P.center[d]) / r, P.center[d])
                           : P.center[d] + (d == 0 ? P.radius : (T)0);
 }
 
@@ -408,37 +416,37 @@ struct Walker {
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
     KeySchedule ks;
 
-    // Starts the path in slot s. Returns false when it ends before any step
-    // (a node inside the shift band of the shifted-boundary test).
-    __device__ __forceinline__ bool start(const PathArgs<T> &a, uint64_t s)
+    // Starts path r (slot within the item) of item a. Returns false when it
+    // ends before any step (a node inside the shift band of the shifted test).
+    __device__ __forceinline__ bool start(const ItemDesc<T> &a, const DevProblem<T> &P, uint64_t r)
     {
-        slot = s;
+        slot = r;
         uint64_t jj;
         if (a.node_start == nullptr) {
-            if (a.total_slots <= 0xffffffffull) {
-                const uint32_t q = (uint32_t)s / (uint32_t)a.uniform_n;
+            if (a.n_slots <= 0xffffffffull) {
+                const uint32_t q = (uint32_t)r / (uint32_t)a.uniform_n;
                 node = q;
-                jj = (uint32_t)s - q * (uint32_t)a.uniform_n;
+                jj = (uint32_t)r - q * (uint32_t)a.uniform_n;
             } else {
-                node = (uint32_t)(s / a.uniform_n);
-                jj = s - (uint64_t)node * a.uniform_n;
+                node = (uint32_t)(r / a.uniform_n);
+                jj = r - (uint64_t)node * a.uniform_n;
             }
         } else {
-            uint32_t lo = 0, hi = a.n_nodes;  // node_start[lo] <= s < node_start[hi]
+            uint32_t lo = 0, hi = a.n_nodes;  // node_start[lo] <= r < node_start[hi]
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (a.node_start[mid] <= s)
+                if (a.node_start[mid] <= r)
                     lo = mid;
                 else
                     hi = mid;
             }
             node = lo;
-            jj = s - a.node_start[lo];
+            jj = r - a.node_start[lo];
         }
         j = (uint32_t)(a.path_offset + jj);
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
-        m = inner_distance<T, D>(a.prob, X);
+        m = inner_distance<T, D>(P, X);
         Y = (T)1;
         Z = 0.0;
         R = 0.0;
@@ -446,13 +454,13 @@ struct Walker {
         capped = 0;
         bb_blk = 0xffffffffu;
         if (a.exit_mode == kExitShift && m <= a.gm_thresh) {
-            project<T, D>(a.prob, X, Xt);
+            project<T, D>(P, X, Xt);
             return false;
         }
         return true;
     }
 
-    __device__ __forceinline__ T bridge_uniform(const PathArgs<T> &a, uint32_t s)
+    __device__ __forceinline__ T bridge_uniform(const ItemDesc<T> &a, uint32_t s)
     {
         const uint32_t blk = s >> 2;
         if (blk != bb_blk) {
@@ -470,10 +478,9 @@ struct Walker {
     // false when the path has ended (exit point in Xt). Everything that ends a
     // path (leaving the domain, a live bridge face, the shift band of the next
     // step, the step cap) goes through one rarely taken branch.
-    __device__ __forceinline__ bool step(const PathArgs<T> &a, uint32_t wa, uint32_t wb,
-                                         uint32_t wc, uint32_t wd)
+    __device__ __forceinline__ bool step(const ItemDesc<T> &a, const DevProblem<T> &P, uint32_t wa,
+                                         uint32_t wb, uint32_t wc, uint32_t wd)
     {
-        const DevProblem<T> &P = a.prob;
         T n[D];
         if (a.law == kLawGauss) {
             Arith<T>::box_muller(wa, wb, n[0], n[1]);
@@ -488,10 +495,10 @@ struct Walker {
         const T hY = a.h * Y;
         if (a.score_plain) Z -= (double)(hY * f);
         if (CV) R += (double)(hY * interp<T, D>(a.resid, X));
-        Y = Y + hY * c;
+        Y = madd(hY, c, Y);
         T Xn[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) Xn[d] = X[d] + a.h * b[d] + a.sig_sqh * n[d];
+        for (int d = 0; d < D; ++d) Xn[d] = madd(a.sig_sqh, n[d], madd(a.h, b[d], X[d]));
         const uint32_t s = k;
         k = k + 1;
 
@@ -510,7 +517,7 @@ struct Walker {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const T t = Xn[d] - P.center[d];
-                r2n += t * t;
+                r2n = madd(t, t, r2n);
             }
             mn = r2n < P.radius2 ? P.radius - Arith<T>::sqrt_(r2n) : (T)-1;
         }
@@ -525,7 +532,7 @@ struct Walker {
                 project<T, D>(P, Xn, Xt);
                 return false;
             }
-            if (maybe && bridge_exit(a, Xn, mn, s)) return false;
+            if (maybe && bridge_exit(a, P, Xn, mn, s)) return false;
             if (shift && mn <= a.gm_thresh) {  // stops before the next step
                 project<T, D>(P, Xn, Xt);
                 return false;
@@ -545,9 +552,9 @@ struct Walker {
     // Brownian-bridge exit between X and Xn (both inside, Xn at distance mn).
     // Per flat face P(cross) = exp(-2 a a' / (sigma^2 h)), faces combined as
     // independent; exit onto the live face with the largest probability.
-    __device__ __forceinline__ bool bridge_exit(const PathArgs<T> &a, const T *Xn, T mn, uint32_t s)
+    __device__ __forceinline__ bool bridge_exit(const ItemDesc<T> &a, const DevProblem<T> &P,
+                                                const T *Xn, T mn, uint32_t s)
     {
-        const DevProblem<T> &P = a.prob;
         if (P.domain == kBox) {
             T Pe = (T)0, bestp = (T)-1;
             int bestf = 0;
@@ -559,7 +566,7 @@ struct Walker {
                 const T arg = prod * a.two_over_s2h;
                 if (arg <= a.bridge_thresh) {
                     const T p = Arith<T>::exp_neg(arg);
-                    Pe = Pe + p * ((T)1 - Pe);
+                    Pe = madd(p, (T)1 - Pe, Pe);
                     if (p > bestp) {
                         bestp = p;
                         bestf = q;
@@ -582,69 +589,168 @@ struct Walker {
         return false;
     }
 
-    // Score the ended path and write its record.
-    __device__ __forceinline__ void finish(const PathArgs<T> &a)
+    // Score the ended path and write its record at slot - rec_base.
+    __device__ __forceinline__ void finish(const ItemDesc<T> &a, const DevProblem<T> &P,
+                                           uint64_t rec_base)
     {
-        const T gv = boundary_value<T, D>(a.prob, Xt);
-        const uint64_t r = slot - a.rec_base;
-        if (a.score_plain) a.rec_phi[r] = (double)gv * (double)Y + Z;
+        const T gv = boundary_value<T, D>(P, Xt);
+        const uint64_t r = slot - rec_base;
+        if (a.score_plain) a.rec_phi[r] = madd((double)gv, (double)Y, Z);
         if (CV) {
             const T up = interp<T, D>(a.u_prev, Xt);
-            a.rec_e[r] = ((double)gv - (double)up) * (double)Y - R;
+            a.rec_e[r] = madd((double)gv - (double)up, (double)Y, -R);
         }
         a.rec_steps[r] = k | (capped ? kCappedBit : 0u);
     }
 };
 
-template <class T, int D, bool CV>
-__global__ void __launch_bounds__(256) path_kernel(const PathArgs<T> a)
+// Item whose slot range holds group slot s (items are sorted, non-empty
+// ranges never overlap). Wave-uniform: a scalar binary search.
+template <class T>
+__device__ __forceinline__ int find_item(const ItemDesc<T> *__restrict__ items, int n, uint64_t s)
 {
+    int lo = 0, hi = n;  // items[lo].slot_begin <= s < items[hi].slot_begin
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (items[mid].slot_begin <= s)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Queue refill shared by both loops: takes `grab` slots at a time from the
+// launch counter and hands the wave's idle lanes consecutive slots below
+// `limit` (launch-relative). Returns the number handed out.
+struct Pool {
+    uint32_t next = 0, end = 0;
+    bool exhausted = false;
+
+    __device__ __forceinline__ void refill(const LaunchArgs &L, int lane)
+    {
+        if (next == end && !exhausted) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(L.counter, (uint32_t)L.grab);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= L.launch_slots) {
+                exhausted = true;
+            } else {
+                next = base;
+                end = min(base + (uint32_t)L.grab, L.launch_slots);
+            }
+        }
+    }
+};
+
+// One item, passed by value (FP32 2D plain solves): asked to fit seven waves
+// per SIMD, which it does in 72 registers.
+template <class T, int D, bool CV>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
+    path_kernel_one(const OneItemArgs<T> A)
+{
+    static_assert(kOneItemKernel<T, D, CV>, "single-item kernel is for FP32 2D plain solves");
+    const LaunchArgs &L = A.launch;
+    const ItemDesc<T> &a = A.item;
+    const DevProblem<T> &P = A.prob;
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     Walker<T, D, CV> w;
-    w.ks = key_schedule(a.prob.key0, a.prob.key1);
+    w.ks = key_schedule(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
-    uint32_t pool_next = 0, pool_end = 0;
-    bool exhausted = false;
+    Pool pool;
 
     for (;;) {
         if (st == 2) {
-            w.finish(a);
+            w.finish(a, P, a.rec_base);  // set per launch by the host
             st = 0;
         }
         const uint64_t idle = __ballot(st == 0);
         if (idle) {
-            if (pool_next == pool_end && !exhausted) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(a.counter, (uint32_t)a.grab);
-                base = __builtin_amdgcn_readfirstlane(base);
-                if (base >= a.launch_slots) {
-                    exhausted = true;
-                } else {
-                    pool_next = base;
-                    pool_end = min(base + (uint32_t)a.grab, a.launch_slots);
-                }
-            }
-            const uint32_t avail = pool_end - pool_next;
+            pool.refill(L, lane);
+            const uint32_t avail = pool.end - pool.next;
             const uint32_t rank = (uint32_t)__popcll(idle & below);
-            if (st == 0 && rank < avail) st = w.start(a, a.slot_begin + pool_next + rank) ? 1 : 2;
-            pool_next += min(avail, (uint32_t)__popcll(idle));
+            if (st == 0 && rank < avail) st = w.start(a, P, L.slot_begin + pool.next + rank) ? 1 : 2;  // the one item starts at slot 0
+            pool.next += min(avail, (uint32_t)__popcll(idle));
         }
         if (__ballot(st != 0) == 0) {
-            if (exhausted) break;
+            if (pool.exhausted) break;
             continue;
         }
         if (st == 1) {
+            // One Philox block feeds two steps in 2D (words 0,1 then 2,3), one in 3D.
             if (D == 2) {
-                // One block feeds this step (words 0,1) and the next (words 2,3).
                 const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
-                if (!w.step(a, q.w0, q.w1, 0u, 0u))
+                if (!w.step(a, P, q.w0, q.w1, 0u, 0u))
                     st = 2;
-                else if (!w.step(a, q.w2, q.w3, 0u, 0u))
+                else if (!w.step(a, P, q.w2, q.w3, 0u, 0u))
                     st = 2;
             } else {
                 const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
-                if (!w.step(a, q.w0, q.w1, q.w2, q.w3)) st = 2;
+                if (!w.step(a, P, q.w0, q.w1, q.w2, q.w3)) st = 2;
+            }
+        }
+    }
+}
+
+// A batch: items and problems in device tables read at wave-uniform indices.
+// A wave walks the paths of one item at a time and moves to the next item
+// only once all its lanes are idle.
+template <class T, int D, bool CV>
+__global__ void __launch_bounds__(256)
+    path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
+                     const DevProblem<T> *__restrict__ probs)
+{
+    const int lane = __lane_id();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    Walker<T, D, CV> w;
+    int st = 0;
+    Pool pool;
+    int cur = -1;          // item of the wave (wave-uniform)
+    uint32_t cur_end = 0;  // launch-relative end of its slots
+
+    for (;;) {
+        if (st == 2) {
+            const ItemDesc<T> &it = items[cur];
+            // scratch records sit at group slot - launch start (modular arithmetic)
+            w.finish(it, probs[it.prob], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
+            st = 0;
+        }
+        const uint64_t idle = __ballot(st == 0);
+        if (idle) {
+            pool.refill(L, lane);
+            if (pool.next < pool.end && (cur < 0 || pool.next >= cur_end) && idle == ~0ull) {
+                cur = __builtin_amdgcn_readfirstlane(find_item(items, L.n_items, L.slot_begin + pool.next));
+                const ItemDesc<T> &it = items[cur];
+                const uint64_t e = it.slot_begin + it.n_slots - L.slot_begin;
+                cur_end = e < (uint64_t)L.launch_slots ? (uint32_t)e : L.launch_slots;
+                w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
+            }
+            if (cur >= 0 && pool.next < cur_end) {
+                const uint32_t avail = min(pool.end, cur_end) - pool.next;
+                const uint32_t rank = (uint32_t)__popcll(idle & below);
+                if (st == 0 && rank < avail)
+                    st = w.start(items[cur], probs[items[cur].prob],
+                                 L.slot_begin + pool.next + rank - items[cur].slot_begin) ? 1 : 2;
+                pool.next += min(avail, (uint32_t)__popcll(idle));
+            }
+        }
+        if (__ballot(st != 0) == 0) {
+            if (pool.exhausted && pool.next == pool.end) break;
+            continue;
+        }
+        if (st == 1) {
+            const ItemDesc<T> &a = items[cur];
+            const DevProblem<T> &P = probs[a.prob];
+            if (D == 2) {
+                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
+                if (!w.step(a, P, q.w0, q.w1, 0u, 0u))
+                    st = 2;
+                else if (!w.step(a, P, q.w2, q.w3, 0u, 0u))
+                    st = 2;
+            } else {
+                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
+                if (!w.step(a, P, q.w0, q.w1, q.w2, q.w3)) st = 2;
             }
         }
     }
@@ -653,22 +759,38 @@ __global__ void __launch_bounds__(256) path_kernel(const PathArgs<T> a)
 }  // namespace
 
 template <class T, int D, bool CV>
-hipError_t launch_path_kernel(const PathArgs<T> &a, int grid, int block, hipStream_t s)
+hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
+                              const DevProblem<T> *probs, int grid, int block, hipStream_t s)
 {
-    static_assert(sizeof(PathArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
-    hipLaunchKernelGGL((path_kernel<T, D, CV>), dim3(grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((path_kernel_many<T, D, CV>), dim3(grid), dim3(block), 0, s, l, items, probs);
     return hipGetLastError();
 }
 
 template <class T, int D, bool CV>
-const void *path_kernel_symbol()
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, hipStream_t s)
 {
-    return reinterpret_cast<const void *>(&path_kernel<T, D, CV>);
+    static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
+    if constexpr (kOneItemKernel<T, D, CV>) {
+        hipLaunchKernelGGL((path_kernel_one<T, D, CV>), dim3(grid), dim3(block), 0, s, a);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidDeviceFunction;
+    }
+}
+
+template <class T, int D, bool CV>
+const void *path_kernel_symbol(bool one)
+{
+    if constexpr (kOneItemKernel<T, D, CV>)
+        if (one) return reinterpret_cast<const void *>(&path_kernel_one<T, D, CV>);
+    return reinterpret_cast<const void *>(&path_kernel_many<T, D, CV>);
 }
 
 #define PDD_INSTANTIATE(T, D, CV)                                                              \
-    template hipError_t launch_path_kernel<T, D, CV>(const PathArgs<T> &, int, int, hipStream_t); \
-    template const void *path_kernel_symbol<T, D, CV>();
+    template hipError_t launch_path_kernel<T, D, CV>(const LaunchArgs &, const ItemDesc<T> *, \
+                                                     const DevProblem<T> *, int, int, hipStream_t); \
+    template hipError_t launch_path_kernel_one<T, D, CV>(const OneItemArgs<T> &, int, int, hipStream_t); \
+    template const void *path_kernel_symbol<T, D, CV>(bool);
 
 PDD_INSTANTIATE(float, 2, false)
 PDD_INSTANTIATE(float, 2, true)

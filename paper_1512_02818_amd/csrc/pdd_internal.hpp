@@ -73,32 +73,44 @@ struct GridView {
     T inv[3];  // (n - 1) / (hi - lo)
 };
 
-// Arguments of one launch of the path kernel: the slots [slot_begin,
-// slot_begin + launch_slots) of the solve's path space. Slot s belongs to the
-// node i with node_start[i] <= s < node_start[i + 1] (or i = s / uniform_n).
+// One work item: the paths of one solve (one problem, its nodes, its
+// estimator and options). Items occupy consecutive ranges of a launch group's
+// slot space; slot s of the item belongs to its node i with
+// node_start[i] <= s - slot_begin < node_start[i + 1] (or i = (s - slot_begin)
+// / uniform_n). Every lane of a wave reads it at the same address, so the
+// kernels serve it from the scalar cache.
 template <class T>
-struct PathArgs {
-    DevProblem<T> prob;         // by value: kernel arguments are read with scalar loads
-    const double *nodes;        // n_nodes x dim
-    const uint64_t *node_start; // n_nodes + 1 prefix, or null (uniform)
-    uint64_t uniform_n;
-    uint64_t total_slots;
-    uint64_t slot_begin;
+struct ItemDesc {
+    int32_t prob;               // index into the problem table (batches)
+    int32_t exit_mode, law;
+    int32_t score_plain;        // 1: evaluate f and score phi
+    uint32_t stream_tag;        // stream_id << 4
+    uint32_t max_steps;
+    uint32_t n_nodes;
+    uint32_t rec_launch;        // 1: scratch records, at group slot - launch start
+    uint64_t slot_begin;        // first slot of the item in the group's slot space
+    uint64_t n_slots;
+    uint64_t uniform_n;         // paths per node when node_start is null
     uint64_t path_offset;
-    uint64_t rec_base;          // records are indexed by slot - rec_base
+    uint64_t rec_base;          // record of item slot r at r - rec_base (caller records: 0)
+    const double *nodes;        // n_nodes x dim
+    const uint64_t *node_start; // n_nodes + 1 item-relative prefix, or null
     double *rec_phi;
     double *rec_e;
     uint32_t *rec_steps;
-    uint32_t *counter;          // queue head of this launch
-    uint32_t n_nodes;
-    uint32_t launch_slots;
-    uint32_t stream_tag;        // stream_id << 4
-    uint32_t max_steps;
-    int32_t exit_mode, law;
-    int32_t grab;
-    int32_t score_plain;        // 1: evaluate f and score phi
     T h, sig_sqh, two_over_s2h, gm_thresh, bridge_thresh;
     GridView<T> u_prev, resid;
+};
+
+// One launch of the path kernel: slots [slot_begin, slot_begin + launch_slots)
+// of the group's slot space, handed out through *counter.
+struct LaunchArgs {
+    uint64_t slot_begin;
+    uint32_t launch_slots;
+    int32_t n_items;
+    int32_t grab;
+    int32_t pad;
+    uint32_t *counter;
 };
 
 // Compensated (Neumaier) per-node accumulators: phi, phi^2, e, e^2, phi*e.
@@ -135,11 +147,30 @@ struct FinalizeArgs {
     double up_lo[3], up_inv[3];
 };
 
+// Kernel arguments of a launch that holds a single item: the item and its
+// problem travel by value (scalar loads from the argument segment).
+template <class T>
+struct OneItemArgs {
+    LaunchArgs launch;
+    ItemDesc<T> item;
+    DevProblem<T> prob;
+};
+
+// The by-value single-item kernel exists for the FP32 2D plain solve only: it
+// fits seven waves per SIMD there without spilling, while with FP64 or the
+// correction terms the larger argument block spills and the table kernel is
+// as fast. Both kernels give bitwise identical results.
+template <class T, int D, bool CV>
+constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && !CV;
+
 // Launchers (defined in the .hip files).
 template <class T, int D, bool CV>
-hipError_t launch_path_kernel(const PathArgs<T> &a, int grid, int block, hipStream_t s);
+hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
+                              const DevProblem<T> *probs, int grid, int block, hipStream_t s);
 template <class T, int D, bool CV>
-const void *path_kernel_symbol();
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, hipStream_t s);
+template <class T, int D, bool CV>
+const void *path_kernel_symbol(bool one);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);

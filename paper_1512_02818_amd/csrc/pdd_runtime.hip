@@ -359,123 +359,81 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
     return n;
 }
 
-template <class T, int D, bool CV>
-pdd_status run_launches(pdd_ctx *ctx, PathArgs<T> &a, ReduceArgs &r, uint64_t total,
-                        uint64_t per_launch, bool caller_records, const pdd_tuning &tune,
-                        const std::vector<uint64_t> *starts, uint64_t uniform_n, bool timed,
-                        hipStream_t s)
-{
-    const int block = tune.block;
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (timed) {
-        if (!ctx->spare.empty()) {
-            ev = ctx->spare.back();
-            ctx->spare.pop_back();
-        } else {
-            HIP_TRY(hipEventCreate(&ev.first));
-            HIP_TRY(hipEventCreate(&ev.second));
-        }
-    }
-    const void *fn = path_kernel_symbol<T, D, CV>();
-    const int bpc = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : occupancy(ctx, fn, block);
-    uint32_t launch = 0;
-    for (uint64_t b = 0; b < total; b += per_launch, ++launch) {
-        const uint64_t len = std::min(per_launch, total - b);
-        a.slot_begin = b;
-        a.launch_slots = (uint32_t)len;
-        a.counter = static_cast<uint32_t *>(ctx->counters.ptr) + launch;
-        a.rec_base = caller_records ? 0 : b;
-        const uint64_t waves_needed = (len + 63) / 64;
-        const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
-        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));
-        if (timed && b == 0) HIP_TRY(hipEventRecord(ev.first, s));
-        HIP_TRY((launch_path_kernel<T, D, CV>(a, grid, block, s)));
-        if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
-        // nodes touched by slots [b, b + len)
-        uint32_t n_lo, n_hi;
-        if (starts) {
-            n_lo = (uint32_t)(std::upper_bound(starts->begin(), starts->end(), b) - starts->begin() - 1);
-            n_hi = (uint32_t)(std::upper_bound(starts->begin(), starts->end(), b + len - 1) - starts->begin() - 1);
-        } else {
-            n_lo = (uint32_t)(b / uniform_n);
-            n_hi = (uint32_t)((b + len - 1) / uniform_n);
-        }
-        r.rec_base = a.rec_base;
-        r.slot_begin = b;
-        r.slot_end = b + len;
-        r.node_lo = n_lo;
-        HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
-    }
-    if (timed) ctx->timed.push_back(ev);
-    return PDD_OK;
-}
+// One solve (or batch item) after validation.
+struct HostItem {
+    pdd_problem *prob = nullptr;
+    const pdd_grid *u_prev = nullptr, *resid = nullptr;
+    const double *nodes = nullptr;
+    int64_t n_nodes = 0;
+    const pdd_solve_opts *o = nullptr;
+    pdd_node_stats *out = nullptr;
+    bool cv = false, score_plain = true, uniform = true, caller_records = false;
+    uint64_t total = 0, max_steps = 0;
+    std::vector<uint64_t> starts;  // item-relative prefix (non-uniform counts)
+};
 
-pdd_status solve_impl(pdd_problem *prob, const pdd_grid *u_prev, const pdd_grid *resid,
-                      const double *nodes, int64_t n_nodes, const pdd_solve_opts *o,
-                      pdd_node_stats *out, void *stream)
+pdd_status validate_item(HostItem &it)
 {
-    if (!prob) return fail(PDD_E_INVALID, "problem is NULL");
+    const pdd_solve_opts *o = it.o;
+    if (!it.prob) return fail(PDD_E_INVALID, "problem is NULL");
     if (!o) return fail(PDD_E_INVALID, "opts is NULL");
-    if (n_nodes < 0) return fail(PDD_E_INVALID, "n_nodes < 0");
-    if (n_nodes == 0) return PDD_OK;
-    if (n_nodes >= (1ll << 32)) return fail(PDD_E_INVALID, "too many nodes");
-    if (!nodes) return fail(PDD_E_INVALID, "nodes is NULL");
-    if (!out) return fail(PDD_E_INVALID, "out is NULL");
-    const pdd_problem_desc &d = prob->desc;
+    if (it.n_nodes < 0) return fail(PDD_E_INVALID, "n_nodes < 0");
+    if (it.n_nodes >= (1ll << 32)) return fail(PDD_E_INVALID, "too many nodes");
+    if (it.n_nodes > 0 && !it.nodes) return fail(PDD_E_INVALID, "nodes is NULL");
+    if (it.n_nodes > 0 && !it.out) return fail(PDD_E_INVALID, "out is NULL");
+    const pdd_problem_desc &d = it.prob->desc;
     const int dim = d.dim;
-    const bool cv = u_prev || resid;
+    it.cv = it.u_prev || it.resid;
+    if (it.cv && (!it.u_prev || !it.resid)) return fail(PDD_E_INVALID, "correction needs u_prev and residual grids");
     if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(PDD_E_INVALID, "dt must be > 0");
     if (o->precision != PDD_FP32 && o->precision != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
     if (o->exit_mode < PDD_EXIT_BRIDGE || o->exit_mode > PDD_EXIT_NAIVE) return fail(PDD_E_INVALID, "bad exit mode");
     if (o->law != PDD_LAW_GAUSS && o->law != PDD_LAW_RADEMACHER) return fail(PDD_E_INVALID, "bad law");
     if (o->stream_id >= (1u << 28)) return fail(PDD_E_INVALID, "stream_id must be < 2^28");
-    const uint64_t max_steps = o->max_steps ? o->max_steps : kDefaultMaxSteps;
-    if (max_steps >= (1ull << 31)) return fail(PDD_E_INVALID, "max_steps must be < 2^31");
-    if (cv) {
-        pdd_status st = check_grid(d, u_prev, o->precision, "u_prev");
+    it.max_steps = o->max_steps ? o->max_steps : kDefaultMaxSteps;
+    if (it.max_steps >= (1ull << 31)) return fail(PDD_E_INVALID, "max_steps must be < 2^31");
+    if (it.cv) {
+        pdd_status st = check_grid(d, it.u_prev, o->precision, "u_prev");
         if (st) return st;
-        st = check_grid(d, resid, o->precision, "residual");
+        st = check_grid(d, it.resid, o->precision, "residual");
         if (st) return st;
     }
-    if ((o->rec_phi || o->rec_e) && !o->rec_steps)
-        return fail(PDD_E_INVALID, "per-path records need rec_steps");
-    if (o->rec_steps && cv && !o->rec_e) return fail(PDD_E_INVALID, "correction records need rec_e");
-    const bool score_plain = !cv || (o->flags & PDD_PLAIN_ALONGSIDE);
-    if (o->rec_steps && score_plain && !o->rec_phi) return fail(PDD_E_INVALID, "records need rec_phi");
-
-    // nodes strictly inside, path counts, prefix
-    for (int64_t i = 0; i < n_nodes; ++i) {
-        const double *x = nodes + i * dim;
+    if ((o->rec_phi || o->rec_e) && !o->rec_steps) return fail(PDD_E_INVALID, "per-path records need rec_steps");
+    if (o->rec_steps && it.cv && !o->rec_e) return fail(PDD_E_INVALID, "correction records need rec_e");
+    it.score_plain = !it.cv || (o->flags & PDD_PLAIN_ALONGSIDE);
+    if (o->rec_steps && it.score_plain && !o->rec_phi) return fail(PDD_E_INVALID, "records need rec_phi");
+    it.caller_records = o->rec_steps != nullptr;
+    for (int64_t i = 0; i < it.n_nodes; ++i) {
+        const double *x = it.nodes + i * dim;
         if (!finite3(x, dim) || !strictly_inside(d, x))
             return fail(PDD_E_INVALID, "node %lld is not strictly inside the domain", (long long)i);
     }
-    const bool uniform = o->n_paths_per_node == nullptr;
-    std::vector<uint64_t> starts;
-    uint64_t total = 0;
-    if (uniform) {
+    it.uniform = o->n_paths_per_node == nullptr;
+    it.total = 0;
+    if (it.uniform) {
         if (o->path_offset + o->n_paths > (1ull << 32))
             return fail(PDD_E_INVALID, "path_offset + n_paths must be <= 2^32");
-        if (o->n_paths && (uint64_t)n_nodes > UINT64_MAX / o->n_paths) return fail(PDD_E_INVALID, "too many paths");
-        total = (uint64_t)n_nodes * o->n_paths;
+        if (o->n_paths && (uint64_t)it.n_nodes > UINT64_MAX / o->n_paths) return fail(PDD_E_INVALID, "too many paths");
+        it.total = (uint64_t)it.n_nodes * o->n_paths;
     } else {
-        starts.resize(n_nodes + 1);
-        for (int64_t i = 0; i < n_nodes; ++i) {
+        it.starts.resize(it.n_nodes + 1);
+        for (int64_t i = 0; i < it.n_nodes; ++i) {
             const uint64_t c = o->n_paths_per_node[i];
             if (o->path_offset + c > (1ull << 32))
                 return fail(PDD_E_INVALID, "path_offset + paths of node %lld exceed 2^32", (long long)i);
-            starts[i] = total;
-            total += c;
+            it.starts[i] = it.total;
+            it.total += c;
         }
-        starts[n_nodes] = total;
+        it.starts[it.n_nodes] = it.total;
     }
-    const bool caller_records = o->rec_steps != nullptr;
-    if (caller_records && total > kMaxLaunchSlots)
+    if (it.caller_records && it.total > kMaxLaunchSlots)
         return fail(PDD_E_UNSUPPORTED, "per-path records are limited to 2^31 paths per solve");
+    return PDD_OK;
+}
 
-    pdd_ctx *ctx = prob->ctx;
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    pdd_tuning tune{256, 0, 64, 0};
+pdd_status read_tuning(const pdd_solve_opts *o, pdd_tuning &tune)
+{
+    tune = pdd_tuning{256, 0, 64, 0};
     if (o->tuning) {
         if (o->tuning->block) tune.block = o->tuning->block;
         if (o->tuning->blocks_per_cu) tune.blocks_per_cu = o->tuning->blocks_per_cu;
@@ -487,130 +445,267 @@ pdd_status solve_impl(pdd_problem *prob, const pdd_grid *u_prev, const pdd_grid 
     if (tune.grab < 1 || tune.grab > 4096 || tune.blocks_per_cu < 0 || tune.blocks_per_cu > 64 ||
         tune.max_launch_paths < 0)
         return fail(PDD_E_INVALID, "tuning out of range");
+    return PDD_OK;
+}
 
-    uint64_t per_launch = caller_records ? std::max<uint64_t>(total, 1)
-                                         : std::min(kScratchSlots, std::max<uint64_t>(total, 1));
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Runs a group of items that share precision, dimension and estimator: one
+// slot space, launches of the persistent path kernel over it, per-item
+// reductions and statistics.
+template <class T, int D, bool CV>
+pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tuning &tune,
+                     bool timed, hipStream_t s)
+{
+    const int n_items = (int)items.size();
+    // problems used by the group
+    std::vector<pdd_problem *> probs;
+    std::vector<int> prob_of(n_items);
+    for (int q = 0; q < n_items; ++q) {
+        auto f = std::find(probs.begin(), probs.end(), items[q]->prob);
+        prob_of[q] = (int)(f - probs.begin());
+        if (f == probs.end()) probs.push_back(items[q]->prob);
+    }
+    // slot space and node tables
+    std::vector<uint64_t> slot_begin(n_items), gnode(n_items + 1);
+    uint64_t total = 0, n_nodes_all = 0, n_starts = 0;
+    for (int q = 0; q < n_items; ++q) {
+        slot_begin[q] = total;
+        total += items[q]->total;
+        gnode[q] = n_nodes_all;
+        n_nodes_all += items[q]->n_nodes;
+        if (!items[q]->uniform) n_starts += items[q]->n_nodes + 1;
+    }
+    gnode[n_items] = n_nodes_all;
+    if (n_nodes_all == 0) return PDD_OK;
+    bool any_scratch = false;
+    for (auto *it : items) any_scratch |= !it->caller_records;
+
+    uint64_t per_launch = std::min(kScratchSlots, std::max<uint64_t>(total, 1));
     if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
     const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
 
-    // order after the context's previous solve
-    if (ctx->any_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+    // staged upload: nodes | global node starts | item node starts | items | problems
+    const size_t off_nodes = 0;
+    const size_t off_gstart = align_up(off_nodes + n_nodes_all * D * sizeof(double), 256);
+    const size_t off_istart = align_up(off_gstart + (n_nodes_all + 1) * sizeof(uint64_t), 256);
+    const size_t off_items = align_up(off_istart + n_starts * sizeof(uint64_t), 256);
+    const size_t off_probs = align_up(off_items + n_items * sizeof(ItemDesc<T>), 256);
+    const size_t bytes = align_up(off_probs + probs.size() * sizeof(DevProblem<T>), 256);
 
-    // scratch
-    const size_t node_bytes = (size_t)n_nodes * dim * sizeof(double);
-    const size_t start_bytes = uniform ? 0 : starts.size() * sizeof(uint64_t);
     pdd_status st;
-    if ((st = ensure(ctx, ctx->nodes, node_bytes + start_bytes))) return st;
-    if ((st = ensure(ctx, ctx->acc, (size_t)n_nodes * sizeof(NodeAcc)))) return st;
+    if ((st = ensure(ctx, ctx->nodes, bytes))) return st;
+    if ((st = ensure(ctx, ctx->acc, n_nodes_all * sizeof(NodeAcc)))) return st;
     if ((st = ensure(ctx, ctx->counters, (size_t)(n_launch + 2) * sizeof(uint32_t)))) return st;
-    double *rec_phi = o->rec_phi, *rec_e = o->rec_e;
-    uint32_t *rec_steps = o->rec_steps;
-    if (!caller_records && total) {
-        const size_t per = sizeof(uint32_t) + (score_plain ? 8 : 0) + (cv ? 8 : 0);
-        if ((st = ensure(ctx, ctx->rec, per_launch * per))) return st;
+    const bool need_phi = std::any_of(items.begin(), items.end(), [](HostItem *i) { return i->score_plain && !i->caller_records; });
+    const size_t per_slot = sizeof(uint32_t) + (need_phi ? 8 : 0) + (CV ? 8 : 0);
+    double *sc_phi = nullptr, *sc_e = nullptr;
+    uint32_t *sc_steps = nullptr;
+    if (any_scratch && total) {
+        if ((st = ensure(ctx, ctx->rec, per_launch * per_slot))) return st;
         char *base = static_cast<char *>(ctx->rec.ptr);
-        rec_phi = score_plain ? reinterpret_cast<double *>(base) : nullptr;
-        rec_e = cv ? reinterpret_cast<double *>(base + (score_plain ? per_launch * 8 : 0)) : nullptr;
-        rec_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((score_plain ? 8 : 0) + (cv ? 8 : 0)));
+        sc_phi = need_phi ? reinterpret_cast<double *>(base) : nullptr;
+        sc_e = CV ? reinterpret_cast<double *>(base + (need_phi ? per_launch * 8 : 0)) : nullptr;
+        sc_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((need_phi ? 8 : 0) + (CV ? 8 : 0)));
     }
-    if ((st = ensure_stage(ctx, node_bytes + start_bytes))) return st;
-    std::memcpy(ctx->stage, nodes, node_bytes);
-    if (!uniform) std::memcpy(static_cast<char *>(ctx->stage) + node_bytes, starts.data(), start_bytes);
-    HIP_TRY(hipMemcpyAsync(ctx->nodes.ptr, ctx->stage, node_bytes + start_bytes, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(ctx->staged, s));
-    ctx->any_staged = true;
-    HIP_TRY(launch_zero(ctx->acc.ptr, (size_t)n_nodes * sizeof(NodeAcc), s));
-    HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
-
-    const double *d_nodes = static_cast<const double *>(ctx->nodes.ptr);
-    const uint64_t *d_starts =
-        uniform ? nullptr
-                : reinterpret_cast<const uint64_t *>(static_cast<const char *>(ctx->nodes.ptr) + node_bytes);
-
-    ReduceArgs r{};
-    r.rec_phi = rec_phi;
-    r.rec_e = rec_e;
-    r.rec_steps = rec_steps;
-    r.node_start = d_starts;
-    r.uniform_n = o->n_paths;
-    r.acc = static_cast<NodeAcc *>(ctx->acc.ptr);
-    r.has_phi = score_plain;
-    r.has_e = cv;
-
-    const double h = o->dt;
-    const double sig_sqh = d.sigma * std::sqrt(h);
-    auto fill_args = [&](auto &a, const auto &problem) {
-        using TT = std::remove_reference_t<decltype(a.h)>;
-        a.prob = problem;
-        a.nodes = d_nodes;
-        a.node_start = d_starts;
-        a.uniform_n = o->n_paths;
-        a.total_slots = total;
-        a.path_offset = o->path_offset;
-        a.rec_phi = rec_phi;
-        a.rec_e = rec_e;
-        a.rec_steps = rec_steps;
-        a.n_nodes = (uint32_t)n_nodes;
-        a.stream_tag = o->stream_id << 4;
-        a.max_steps = (uint32_t)max_steps;
+    if ((st = ensure_stage(ctx, bytes))) return st;
+    char *h = static_cast<char *>(ctx->stage);
+    char *dv = static_cast<char *>(ctx->nodes.ptr);
+    uint64_t *h_gstart = reinterpret_cast<uint64_t *>(h + off_gstart);
+    uint64_t *h_istart = reinterpret_cast<uint64_t *>(h + off_istart);
+    ItemDesc<T> *h_items = reinterpret_cast<ItemDesc<T> *>(h + off_items);
+    DevProblem<T> *h_probs = reinterpret_cast<DevProblem<T> *>(h + off_probs);
+    std::memset(h_items, 0, n_items * sizeof(ItemDesc<T>));
+    size_t istart_used = 0;
+    for (int q = 0; q < n_items; ++q) {
+        HostItem &it = *items[q];
+        const pdd_solve_opts *o = it.o;
+        std::memcpy(h + off_nodes + gnode[q] * D * sizeof(double), it.nodes, it.n_nodes * D * sizeof(double));
+        for (int64_t i = 0; i < it.n_nodes; ++i)
+            h_gstart[gnode[q] + i] = slot_begin[q] + (it.uniform ? (uint64_t)i * o->n_paths : it.starts[i]);
+        ItemDesc<T> &a = h_items[q];
+        a.prob = prob_of[q];
         a.exit_mode = o->exit_mode;
         a.law = o->law;
-        a.grab = tune.grab;
-        a.score_plain = score_plain ? 1 : 0;
-        a.h = (TT)h;
-        a.sig_sqh = (TT)sig_sqh;
-        a.two_over_s2h = (TT)(2.0 / (d.sigma * d.sigma * h));
-        a.gm_thresh = (TT)(kGmShift * sig_sqh);
-        a.bridge_thresh = (TT)kBridgeSkip;
-        a.u_prev = make_view<TT>(u_prev, dim);
-        a.resid = make_view<TT>(resid, dim);
-    };
-
-    if (total) {
-        const std::vector<uint64_t> *sp = uniform ? nullptr : &starts;
-        const bool timed = (o->flags & PDD_TIME_KERNEL) != 0;
-        if (o->precision == PDD_FP32) {
-            PathArgs<float> a{};
-            fill_args(a, prob->pf);
-            if (dim == 2)
-                st = cv ? run_launches<float, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
-                        : run_launches<float, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
-            else
-                st = cv ? run_launches<float, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
-                        : run_launches<float, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
+        a.score_plain = it.score_plain ? 1 : 0;
+        a.stream_tag = o->stream_id << 4;
+        a.max_steps = (uint32_t)it.max_steps;
+        a.n_nodes = (uint32_t)it.n_nodes;
+        a.slot_begin = slot_begin[q];
+        a.n_slots = it.total;
+        a.uniform_n = o->n_paths;
+        a.path_offset = o->path_offset;
+        a.nodes = reinterpret_cast<const double *>(dv + off_nodes + gnode[q] * D * sizeof(double));
+        if (!it.uniform) {
+            std::memcpy(h_istart + istart_used, it.starts.data(), it.starts.size() * sizeof(uint64_t));
+            a.node_start = reinterpret_cast<const uint64_t *>(dv + off_istart) + istart_used;
+            istart_used += it.starts.size();
+        }
+        if (it.caller_records) {  // records of item slot r at r
+            a.rec_phi = o->rec_phi;
+            a.rec_e = o->rec_e;
+            a.rec_steps = o->rec_steps;
+            a.rec_base = 0;
         } else {
-            PathArgs<double> a{};
-            fill_args(a, prob->pd);
-            if (dim == 2)
-                st = cv ? run_launches<double, 2, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
-                        : run_launches<double, 2, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
-            else
-                st = cv ? run_launches<double, 3, true>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s)
-                        : run_launches<double, 3, false>(ctx, a, r, total, per_launch, caller_records, tune, sp, o->n_paths, timed, s);
+            a.rec_phi = sc_phi;
+            a.rec_e = sc_e;
+            a.rec_steps = sc_steps;
+            a.rec_launch = 1;
         }
-        if (st) return st;
+        const pdd_problem_desc &d = it.prob->desc;
+        const double hh = o->dt;
+        const double sig_sqh = d.sigma * std::sqrt(hh);
+        a.h = (T)hh;
+        a.sig_sqh = (T)sig_sqh;
+        a.two_over_s2h = (T)(2.0 / (d.sigma * d.sigma * hh));
+        a.gm_thresh = (T)(kGmShift * sig_sqh);
+        a.bridge_thresh = (T)kBridgeSkip;
+        a.u_prev = make_view<T>(it.u_prev, D);
+        a.resid = make_view<T>(it.resid, D);
     }
+    h_gstart[n_nodes_all] = total;
+    for (size_t p = 0; p < probs.size(); ++p)
+        std::memcpy(&h_probs[p], sizeof(T) == 4 ? (const void *)&probs[p]->pf : (const void *)&probs[p]->pd,
+                    sizeof(DevProblem<T>));
 
-    FinalizeArgs f{};
-    f.acc = static_cast<const NodeAcc *>(ctx->acc.ptr);
-    f.nodes = d_nodes;
-    f.out = out;
-    f.n_nodes = (uint32_t)n_nodes;
-    f.dim = dim;
-    f.has_phi = score_plain;
-    f.has_e = cv;
-    if (cv) {
-        f.up_data = u_prev->data;
-        f.up_f64 = u_prev->dtype == PDD_DTYPE_F64;
-        for (int i = 0; i < 3; ++i) {
-            f.up_n[i] = i < dim ? u_prev->n[i] : 1;
-            f.up_lo[i] = u_prev->lo[i];
-            f.up_inv[i] = i < dim ? (double)(u_prev->n[i] - 1) / (u_prev->hi[i] - u_prev->lo[i]) : 0.0;
+    HIP_TRY(hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    ctx->any_staged = true;
+    HIP_TRY(launch_zero(ctx->acc.ptr, n_nodes_all * sizeof(NodeAcc), s));
+    HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
+
+    const int block = tune.block;
+    const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
+    const void *fn = path_kernel_symbol<T, D, CV>(one);
+    const int bpc = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : occupancy(ctx, fn, block);
+    const ItemDesc<T> *d_items = reinterpret_cast<const ItemDesc<T> *>(dv + off_items);
+    const DevProblem<T> *d_probs = reinterpret_cast<const DevProblem<T> *>(dv + off_probs);
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (timed && total) {
+        if (!ctx->spare.empty()) {
+            ev = ctx->spare.back();
+            ctx->spare.pop_back();
+        } else {
+            HIP_TRY(hipEventCreate(&ev.first));
+            HIP_TRY(hipEventCreate(&ev.second));
         }
     }
-    HIP_TRY(launch_finalize(f, s));
-    HIP_TRY(hipEventRecord(ctx->done, s));
-    ctx->any_done = true;
+    uint32_t launch = 0;
+    for (uint64_t b = 0; b < total; b += per_launch, ++launch) {
+        const uint64_t len = std::min(per_launch, total - b);
+        LaunchArgs L{};
+        L.slot_begin = b;
+        L.launch_slots = (uint32_t)len;
+        L.n_items = n_items;
+        L.grab = tune.grab;
+        L.counter = static_cast<uint32_t *>(ctx->counters.ptr) + launch;
+        const uint64_t waves_needed = (len + 63) / 64;
+        const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
+        const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));
+        if (timed && b == 0) HIP_TRY(hipEventRecord(ev.first, s));
+        if (one) {  // the item and its problem travel as kernel arguments
+            OneItemArgs<T> A;
+            A.launch = L;
+            A.item = h_items[0];
+            A.prob = h_probs[0];
+            // the single item starts at slot 0; scratch records of this launch
+            // start at slot b
+            if (!items[0]->caller_records) A.item.rec_base = b;
+            HIP_TRY((launch_path_kernel_one<T, D, CV>(A, grid, block, s)));
+        } else {
+            HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, s)));
+        }
+        if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
+        // per-item reduction of the nodes this launch touched
+        for (int q = 0; q < n_items; ++q) {
+            HostItem &it = *items[q];
+            const uint64_t lo = std::max(b, slot_begin[q]);
+            const uint64_t hi = std::min(b + len, slot_begin[q] + it.total);
+            if (lo >= hi) continue;
+            const uint64_t *gs = h_gstart + gnode[q];
+            const uint32_t n_lo = (uint32_t)(std::upper_bound(gs, gs + it.n_nodes + 1, lo) - gs - 1);
+            const uint32_t n_hi = (uint32_t)(std::upper_bound(gs, gs + it.n_nodes + 1, hi - 1) - gs - 1);
+            ReduceArgs r{};
+            r.rec_phi = it.caller_records ? it.o->rec_phi : sc_phi;
+            r.rec_e = it.caller_records ? it.o->rec_e : sc_e;
+            r.rec_steps = it.caller_records ? it.o->rec_steps : sc_steps;
+            r.rec_base = it.caller_records ? slot_begin[q] : b;
+            r.node_start = reinterpret_cast<const uint64_t *>(dv + off_gstart) + gnode[q];
+            r.slot_begin = lo;
+            r.slot_end = hi;
+            r.acc = static_cast<NodeAcc *>(ctx->acc.ptr) + gnode[q];
+            r.node_lo = n_lo;
+            r.has_phi = it.score_plain;
+            r.has_e = CV;
+            HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
+        }
+    }
+    if (timed && total) ctx->timed.push_back(ev);
+    for (int q = 0; q < n_items; ++q) {
+        HostItem &it = *items[q];
+        if (it.n_nodes == 0) continue;
+        FinalizeArgs f{};
+        f.acc = static_cast<const NodeAcc *>(ctx->acc.ptr) + gnode[q];
+        f.nodes = reinterpret_cast<const double *>(dv + off_nodes + gnode[q] * D * sizeof(double));
+        f.out = it.out;
+        f.n_nodes = (uint32_t)it.n_nodes;
+        f.dim = D;
+        f.has_phi = it.score_plain;
+        f.has_e = CV;
+        if (CV) {
+            f.up_data = it.u_prev->data;
+            f.up_f64 = it.u_prev->dtype == PDD_DTYPE_F64;
+            for (int i = 0; i < 3; ++i) {
+                f.up_n[i] = i < D ? it.u_prev->n[i] : 1;
+                f.up_lo[i] = it.u_prev->lo[i];
+                f.up_inv[i] = i < D ? (double)(it.u_prev->n[i] - 1) / (it.u_prev->hi[i] - it.u_prev->lo[i]) : 0.0;
+            }
+        }
+        HIP_TRY(launch_finalize(f, s));
+    }
+    return PDD_OK;
+}
+
+// Validates items, then runs them grouped by (precision, dim, estimator).
+pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s)
+{
+    for (auto &it : items) {
+        pdd_status st = validate_item(it);
+        if (st) return st;
+        if (it.prob->ctx != ctx) return fail(PDD_E_INVALID, "problem belongs to another context");
+    }
+    if (items.empty()) return PDD_OK;
+    pdd_tuning tune;
+    pdd_status st = read_tuning(items[0].o, tune);
+    if (st) return st;
+    bool timed = false;
+    for (auto &it : items) timed |= (it.o->flags & PDD_TIME_KERNEL) != 0;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (ctx->any_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+    for (int prec = 0; prec < 2; ++prec)
+        for (int dim = 2; dim <= 3; ++dim)
+            for (int cv = 0; cv < 2; ++cv) {
+                std::vector<HostItem *> g;
+                for (auto &it : items)
+                    if (it.o->precision == prec && it.prob->desc.dim == dim && (int)it.cv == cv && it.n_nodes > 0)
+                        g.push_back(&it);
+                if (g.empty()) continue;
+                if (prec == PDD_FP32) {
+                    if (dim == 2)
+                        st = cv ? run_group<float, 2, true>(ctx, g, tune, timed, s) : run_group<float, 2, false>(ctx, g, tune, timed, s);
+                    else
+                        st = cv ? run_group<float, 3, true>(ctx, g, tune, timed, s) : run_group<float, 3, false>(ctx, g, tune, timed, s);
+                } else {
+                    if (dim == 2)
+                        st = cv ? run_group<double, 2, true>(ctx, g, tune, timed, s) : run_group<double, 2, false>(ctx, g, tune, timed, s);
+                    else
+                        st = cv ? run_group<double, 3, true>(ctx, g, tune, timed, s) : run_group<double, 3, false>(ctx, g, tune, timed, s);
+                }
+                if (st) return st;
+                // the next group reuses the staging buffer and the scratch
+                HIP_TRY(hipEventRecord(ctx->done, s));
+                ctx->any_done = true;
+            }
     return PDD_OK;
 }
 
@@ -687,28 +782,52 @@ void pdd_destroy_problem(pdd_problem *problem) { delete problem; }
 pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                            const pdd_solve_opts *opts, pdd_node_stats *out, void *stream)
 {
-    return solve_impl(problem, nullptr, nullptr, nodes, n_nodes, opts, out, stream);
+    if (!problem) return fail(PDD_E_INVALID, "problem is NULL");
+    std::vector<HostItem> items(1);
+    items[0].prob = problem;
+    items[0].nodes = nodes;
+    items[0].n_nodes = n_nodes;
+    items[0].o = opts;
+    items[0].out = out;
+    return run_items(problem->ctx, items, static_cast<hipStream_t>(stream));
 }
 
 pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev, const pdd_grid *resid,
                                 const double *nodes, int64_t n_nodes, const pdd_solve_opts *opts,
                                 pdd_node_stats *out, void *stream)
 {
+    if (!problem) return fail(PDD_E_INVALID, "problem is NULL");
     if (!u_prev || !resid) return fail(PDD_E_INVALID, "correction solve needs u_prev and residual grids");
-    return solve_impl(problem, u_prev, resid, nodes, n_nodes, opts, out, stream);
+    std::vector<HostItem> items(1);
+    items[0].prob = problem;
+    items[0].u_prev = u_prev;
+    items[0].resid = resid;
+    items[0].nodes = nodes;
+    items[0].n_nodes = n_nodes;
+    items[0].o = opts;
+    items[0].out = out;
+    return run_items(problem->ctx, items, static_cast<hipStream_t>(stream));
 }
 
-pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items, void *stream)
+pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *witems, int32_t n_items, void *stream)
 {
     if (!ctx) return fail(PDD_E_INVALID, "ctx is NULL");
-    if (n_items < 0 || (n_items > 0 && !items)) return fail(PDD_E_INVALID, "bad items");
+    if (n_items < 0 || (n_items > 0 && !witems)) return fail(PDD_E_INVALID, "bad items");
+    std::vector<HostItem> items(n_items);
     for (int32_t q = 0; q < n_items; ++q) {
-        const pdd_work_item &it = items[q];
-        if (!it.problem || it.problem->ctx != ctx) return fail(PDD_E_INVALID, "item %d: problem of another context", q);
-        pdd_status st = solve_impl(it.problem, it.u_prev, it.resid, it.nodes, it.n_nodes, it.opts, it.out, stream);
-        if (st) return st;
+        const pdd_work_item &w = witems[q];
+        if (!w.problem) return fail(PDD_E_INVALID, "item %d: problem is NULL", q);
+        if ((w.u_prev == nullptr) != (w.resid == nullptr))
+            return fail(PDD_E_INVALID, "item %d: correction needs u_prev and residual grids", q);
+        items[q].prob = w.problem;
+        items[q].u_prev = w.u_prev;
+        items[q].resid = w.resid;
+        items[q].nodes = w.nodes;
+        items[q].n_nodes = w.n_nodes;
+        items[q].o = w.opts;
+        items[q].out = w.out;
     }
-    return PDD_OK;
+    return run_items(ctx, items, static_cast<hipStream_t>(stream));
 }
 
 pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n)

@@ -242,3 +242,58 @@ def sampled_grid(pd: dict, fn, n=257, dtype=np.float64):
     pts = grid_points((n, n), lo, hi)
     return {"dim": 2, "n": [n, n], "lo": list(lo), "hi": list(hi),
             "data": np.asarray(fn(pts), dtype=dtype).reshape(n, n)}
+
+
+# --------------------------------------------------------------------------- batches
+def random_problem(rng, dim=None):
+    """One random problem of the batched workload: the box [0, L]^D with
+    L ~ U[0.5, 4]; drift b_d = beta_d x_d, beta ~ U[-1, 1]; killing
+    c = c0 (1 + |x|^2), c0 ~ U[-3, -0.1]; manufactured U = sum of 8 separable
+    terms A prod_d sin(k_d x_d + phase_d), A ~ U[-1, 1], k ~ (pi/L) U[0.5, 3],
+    phase ~ U[0, 2 pi); sigma = 1."""
+    D = int(dim if dim is not None else rng.choice([2, 3]))
+    L = float(rng.uniform(0.5, 4.0))
+    beta = rng.uniform(-1.0, 1.0, size=D)
+    c0 = float(rng.uniform(-3.0, -0.1))
+    trig = []
+    for _ in range(8):
+        trig.append({"amp": float(rng.uniform(-1, 1)),
+                     "k": [float(v) for v in (PI / L) * rng.uniform(0.5, 3.0, size=D)],
+                     "phase": [float(v) for v in rng.uniform(0, 2 * PI, size=D)]})
+    return {"dim": D, "domain": "box", "lo": [0.0] * D, "hi": [L] * D, "sigma": 1.0,
+            "b0": [0.0] * D, "B": [[float(beta[i]) if i == j else 0.0 for j in range(D)] for i in range(D)],
+            "c_a": c0, "c_b": c0, "trig": trig, "mono": [], "fx": [], "gx": [],
+            "seed": int(rng.integers(0, 2**63))}
+
+
+def face_nodes(rng, pd, n):
+    """n nodes uniform on the internal faces of an m^D partition of the box,
+    m = max(2, round(L / 0.5)): pick one of the D (m - 1) interior hyperplanes
+    x_d = L a / m, then a uniform point of the box on it (strictly inside)."""
+    D = pd["dim"]
+    L = pd["hi"][0] - pd["lo"][0]
+    m = max(2, int(round(L / 0.5)))
+    pts = rng.uniform(0.0, 1.0, size=(n, D))
+    # keep strictly inside: the open unit interval, mapped to the box
+    pts = np.clip(pts, 1e-9, 1 - 1e-9) * L + pd["lo"][0]
+    d = rng.integers(0, D, size=n)
+    a = rng.integers(1, m, size=n)
+    pts[np.arange(n), d] = pd["lo"][0] + L * a / m
+    return pts
+
+
+def batch_workload(seed=4, n_problems=64, node_range=(10, 5000), path_range=(1e3, 1e6),
+                   dts=(1e-3, 1e-4), scale=1.0):
+    """The batched uneven workload: n_problems random problems (random_problem)
+    with log-uniform node counts and paths per node, h drawn from dts.
+    `scale` multiplies the path counts (for smaller test versions).
+    Returns a list of dicts {problem, nodes, n_paths, dt}."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_problems):
+        pd = random_problem(rng)
+        n = int(round(np.exp(rng.uniform(np.log(node_range[0]), np.log(node_range[1])))))
+        npath = int(round(np.exp(rng.uniform(np.log(path_range[0]), np.log(path_range[1]))) * scale))
+        out.append({"problem": pd, "nodes": face_nodes(rng, pd, n), "n_paths": max(npath, 1),
+                    "dt": float(rng.choice(dts))})
+    return out

@@ -1,0 +1,89 @@
+"""Batched solves: many problems (2D and 3D, plain and correction, FP32 and
+FP64, uneven node and path counts) in one pdd_solve_batch call. Every item
+must give exactly the statistics of its own solve call (same paths, same
+reduction order), and one item is checked against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_02818_amd import pdd  # noqa: E402
+from paper_1512_02818_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def _items(ctx):
+    wl = W.batch_workload(seed=4, n_problems=12, node_range=(3, 60), path_range=(50, 800))
+    items = []
+    for q, w in enumerate(wl):
+        prob = pdd.Problem(ctx, w["problem"])
+        items.append({"problem": prob, "nodes": w["nodes"],
+                      "opts": dict(dt=w["dt"] * 10, n_paths=w["n_paths"],
+                                   precision="fp64" if q % 3 == 0 else "fp32", stream_id=q)})
+    # a correction item and a ragged item on the unit-square problem
+    pd = W.unit_square_problem(seed=9)
+    prob = pdd.Problem(ctx, pd)
+    gu, gr, _ = W.correction_grids(pd, n=65, seed=3, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    items.append({"problem": prob, "nodes": W.unit_square_nodes(),
+                  "opts": dict(dt=1e-3, n_paths=700, precision="fp32", plain_alongside=True),
+                  "u_prev": gu, "u_prev_t": tu, "resid": gr, "resid_t": tr})
+    items.append({"problem": prob, "nodes": W.unit_square_nodes()[:5],
+                  "opts": dict(dt=1e-3, n_paths_per_node=np.array([0, 3, 500, 64, 1], dtype=np.uint64),
+                               precision="fp64")})
+    return items
+
+
+def test_batch_equals_solo(ctx):
+    items = _items(ctx)
+    outs = pdd.solve_batch(ctx, items)
+    torch.cuda.synchronize()
+    batch = [pdd.stats_to_numpy(o) for o in outs]
+    for it, b in zip(items, batch):
+        if it.get("u_prev") is not None:
+            solo = pdd.solve_correction(it["problem"], it["u_prev"], it["u_prev_t"], it["resid"],
+                                        it["resid_t"], it["nodes"], **it["opts"])
+        else:
+            solo = pdd.solve_nodes(it["problem"], it["nodes"], **it["opts"])
+        torch.cuda.synchronize()
+        s = pdd.stats_to_numpy(solo)
+        assert s.tobytes() == b.tobytes()
+        assert np.all(s["n_capped"] == 0)
+
+
+def test_batch_item_matches_oracle(ctx):
+    from oracle import oracle as O
+    items = _items(ctx)
+    outs = pdd.solve_batch(ctx, items)
+    torch.cuda.synchronize()
+    q = 3  # an FP64 item
+    it = items[q]
+    st = pdd.stats_to_numpy(outs[q])
+    ost = O.solve_nodes(it["problem"].pd, it["nodes"], h=it["opts"]["dt"],
+                        n_paths=it["opts"]["n_paths"], stream=it["opts"]["stream_id"])
+    assert np.allclose(st["mean"], ost["mean"], rtol=1e-9, atol=1e-10)
+    assert np.array_equal(st["steps_sum"], ost["steps_sum"])
+
+
+def test_batch_chunked_and_empty(ctx):
+    items = _items(ctx)[:6]
+    items.insert(2, {"problem": items[0]["problem"], "nodes": np.zeros((0, items[0]["problem"].dim)),
+                     "opts": dict(dt=1e-3, n_paths=10)})
+    ref = [pdd.stats_to_numpy(o) for o in pdd.solve_batch(ctx, items)]
+    for it in items:
+        it["opts"] = dict(it["opts"], tuning=(128, 2, 16, 3001))
+    got = [pdd.stats_to_numpy(o) for o in pdd.solve_batch(ctx, items)]
+    for a, b in zip(ref, got):
+        assert np.array_equal(a["n"], b["n"]) and np.array_equal(a["steps_sum"], b["steps_sum"])
+        assert np.allclose(a["mean"], b["mean"], rtol=1e-13, atol=1e-14, equal_nan=True)
