@@ -51,6 +51,19 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the path kernel's sources and build flags: HBM counters
+    taken for another version of the kernel are not reported."""
+    import hashlib
+    from paper_1512_02818_amd import build as B
+    h = hashlib.sha256()
+    for name in ("path_kernel.hip", "pdd_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1512_02818_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(B.FLAGS[:-1]).encode())  # the include path differs between machines
+    return h.hexdigest()
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,7 +149,8 @@ def main():
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("precision") == args.precision and tj.get("paths_per_step") == P:
+            if (tj.get("precision") == args.precision and tj.get("paths_per_step") == P
+                    and tj.get("source_sha256") == kernel_source_hash()):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
