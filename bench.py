@@ -76,6 +76,12 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before warmup, one plain device copy of this many MiB (scales the "
                          "HBM byte counters of a profiler run)")
+    ap.add_argument("--rms-tol", type=float, default=1e-3,
+                    help="RMS error target of the node-solve comparison (0 = skip it)")
+    ap.add_argument("--rms-replicas-plain", type=int, default=50,
+                    help="copies of the 18 unit-square nodes (distinct streams), plain FP64")
+    ap.add_argument("--rms-replicas-cv", type=int, default=2000,
+                    help="copies of the 18 unit-square nodes (distinct streams), CV + FP32")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -91,6 +97,103 @@ def cpu_baseline(pd, nodes, n_paths):
             "sample": f"{len(nodes)} nodes x paths 0..{n_paths - 1} of the same workload, "
                       f"FP64, single thread: {steps} path-steps in {dt:.1f} s",
             "host": platform.processor() or platform.machine()}
+
+
+DT_LADDER = (1e-3, 5e-4, 2.5e-4, 1e-4)
+N_PILOT = 1000
+
+
+def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
+    """Interface-node solves per second at an RMS error `tol` against the
+    manufactured solution, for the plain FP64 estimator and for the FP32
+    correction estimator with u_prev = U + p on a 257^2 grid (32 Fourier modes
+    of amplitude 1e-2) as control variate, on the 18 unit-square nodes
+    replicated with distinct RNG streams. The error budget is split evenly:
+    RMS bias <= tol/sqrt(2) picks dt from a ladder (largest first; bias
+    measured against U with many paths, untimed), SE <= tol/sqrt(2) per node
+    sets the paths through a 1,000-path pilot and the planner (timed, with the
+    pilot)."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+
+    pd = W.unit_square_problem(seed=SEED)
+    nodes = W.unit_square_nodes()
+    exact = W.manufactured_u(pd, nodes)
+    t0 = time.perf_counter()
+    prob = pdd.Problem(ctx, pd)
+    gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    budget = tol / np.sqrt(2.0)
+    nstat = pdd.STATS_DTYPE.itemsize
+
+    def items_for(kind, dt, replicas, stream0, out):
+        its = []
+        for r in range(replicas):
+            it = {"problem": prob, "nodes": nodes,
+                  "out": out[r * len(nodes) * nstat:(r + 1) * len(nodes) * nstat],
+                  "opts": dict(dt=dt, precision="fp64" if kind == "plain" else "fp32",
+                               stream_id=stream0 + r)}
+            if kind == "cv":
+                it.update(u_prev=gu, u_prev_t=tu, resid=gr, resid_t=tr)
+            its.append(it)
+        return its
+
+    res = {}
+    for kind, reps in (("plain", replicas_plain), ("cv", replicas_cv)):
+        # dt: the largest rung whose measured RMS bias fits half the budget
+        # (the bias estimate removes the sampling variance of the means)
+        ladder = []
+        chosen = DT_LADDER[-1]
+        cal_reps, cal_paths = (8, 1_000_000) if kind == "plain" else (8, 200_000)
+        cal_out = pdd.alloc_stats(cal_reps * len(nodes))
+        for dt in DT_LADDER:
+            its = items_for(kind, dt, cal_reps, 1 << 20, cal_out)
+            for it in its:
+                it["opts"]["n_paths"] = cal_paths
+                it["opts"]["plain_alongside"] = kind == "cv"  # variance reduction, reported
+            pdd.solve_batch(ctx, its)
+            st = pdd.stats_to_numpy(cal_out).reshape(cal_reps, len(nodes))
+            m = st["mean"].mean(axis=0)
+            se2 = (st["var"] / (cal_reps * cal_paths)).mean(axis=0)
+            bias = float(np.sqrt(max(0.0, np.mean((m - exact) ** 2 - se2))))
+            noise = float(np.sqrt(np.mean(se2)))
+            ladder.append({"dt": dt, "rms_bias": bias, "rms_se_of_estimate": noise,
+                           "mean_vr": float(np.mean(st["vr"])) if kind == "cv" else None,
+                           "mean_abs_rho": float(np.mean(np.abs(st["rho"]))) if kind == "cv" else None})
+            if bias + noise <= budget:
+                chosen = dt
+                break
+        out = pdd.alloc_stats(reps * len(nodes))
+        batch = pdd.Batch(items_for(kind, chosen, reps, 16, out))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pdd.solve_to_tolerance(ctx, batch, budget, N_PILOT, 1 << 31)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = pdd.stats_to_numpy(out).reshape(reps, len(nodes))
+        err = st["mean"] - exact[None, :]
+        res[kind] = {"node_solves": int(reps * len(nodes)), "wall_s": wall,
+                     "node_solves_per_s": reps * len(nodes) / wall,
+                     "rms_error": float(np.sqrt(np.mean(err ** 2))),
+                     "dt": chosen, "mean_paths_per_node": float(st["n"].mean()),
+                     "path_steps": int(st["steps_sum"].sum()),
+                     "precision": "fp64" if kind == "plain" else "fp32",
+                     "dt_ladder": ladder}
+        print(f"{kind}: dt={chosen} {reps * len(nodes)} node-solves in {wall:.3f} s, "
+              f"RMS err {res[kind]['rms_error']:.2e}, mean N {st['n'].mean():.0f}",
+              file=sys.stderr, flush=True)
+    prob.close()
+    return {"tol": tol, "setup_s": setup_s, "pilot_paths": N_PILOT,
+            "workload": "unit square, 18 interface nodes per replica, manufactured u; "
+                        "CV: u_prev = u + 32-mode Fourier perturbation (amplitude 1e-2) on 257^2, FP32 grids",
+            "plain_fp64": res["plain"], "cv_fp32": res["cv"],
+            "ratio_cv_fp32_over_plain_fp64": res["cv"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"]}
 
 
 def main():
@@ -187,6 +290,10 @@ def main():
                      "fp32_tflops": FLOPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12,
                      "fp32_peak_tflops": FP32_PEAK_TFLOPS},
     }
+    if args.rms_tol > 0:
+        print("node solves at fixed RMS error ...", file=sys.stderr, flush=True)
+        result["node_solves_at_rms"] = node_solves_at_rms(ctx, args.rms_tol, args.rms_replicas_plain,
+                                                          args.rms_replicas_cv)
     if args.cpu_paths > 0:
         print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(pd, nodes, args.cpu_paths)

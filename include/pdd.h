@@ -64,6 +64,13 @@ enum { PDD_DTYPE_F32 = 0, PDD_DTYPE_F64 = 1 };
 /* Solve flags. */
 #define PDD_PLAIN_ALONGSIDE 1u /* correction solve: also score phi, report rho, VR */
 #define PDD_TIME_KERNEL 2u     /* record HIP events around the solve's path-kernel launches */
+/* `out` (device) already holds this library's statistics of the same nodes,
+ * in the same order, from earlier paths of the same problem, estimator, dt,
+ * precision, exit test and stream_id (paths below path_offset); the new
+ * paths are merged into those sums, so `out` ends up describing all of them
+ * (the pilot-then-continue scheme of the balanced simulation, Sec. 3.1). The
+ * caller keeps the path ranges disjoint; nothing checks it. */
+#define PDD_ACCUMULATE 4u
 
 #define PDD_MAX_TRIG 16
 #define PDD_MAX_MONO 8
@@ -121,7 +128,7 @@ typedef struct {
 
 /* Launch shape of the path kernel (0 = library default / tuning cache). */
 typedef struct {
-    int32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t block;        /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;/* persistent workgroups per compute unit */
     int32_t grab;         /* paths a wavefront takes from the queue at a time */
     int32_t max_launch_paths; /* cap on paths per path-kernel launch (0 = 2^27; records
@@ -138,7 +145,7 @@ typedef struct {
     int32_t exit_mode;                  /* PDD_EXIT_* */
     int32_t law;                        /* PDD_LAW_* */
     uint64_t max_steps;                 /* 0 = 2^26 */
-    uint32_t flags;                     /* PDD_PLAIN_ALONGSIDE */
+    uint32_t flags;                     /* PDD_PLAIN_ALONGSIDE | PDD_TIME_KERNEL | PDD_ACCUMULATE */
     int32_t reserved;
     /* Optional per-path records (device, NULL = not kept). Path jj of node i
      * sits at slot s = sum_{i'<i} N_i' + jj: rec_phi[s] = phi, rec_e[s] = e
@@ -201,6 +208,31 @@ pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,
  * group. Each item's results equal those of its own solve call. */
 pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items,
                            void *stream);
+
+/* Path counts of a balanced simulation (Sec. 3.1, Def. D:Balanced_MC_simulation,
+ * eq. F:N_y_h): for accuracy a at confidence q the statistical error q SE
+ * must equal a/2, i.e. SE = a/(2q) and N = V[phi]/SE^2 = 4 q^2 V[phi]/a^2.
+ * Given pilot statistics (host, n_nodes entries, each with n >= 2), writes
+ *   n_total[i] = min(n_max, max(pilot[i].n, ceil(pilot[i].var / target_se^2)))
+ * to n_total (host). `var` is that of the estimator the pilot ran (phi for
+ * the plain solve, e for the correction). Host only; needs no GPU.
+ * Errors: NULL pointers, n_nodes < 0, target_se not finite and > 0, a pilot
+ * with n < 2 or a non-finite variance. */
+pdd_status pdd_plan_paths(const pdd_node_stats *pilot, int64_t n_nodes, double target_se,
+                          uint64_t n_max, uint64_t *n_total);
+
+/* Solves items to a standard error: a pilot of n_pilot paths per node (paths
+ * path_offset .. path_offset + n_pilot - 1 of each item's opts; the opts'
+ * n_paths and n_paths_per_node are ignored), then pdd_plan_paths per item with
+ * target_se[q] (host, n_items values), then the missing paths of every node
+ * from path_offset + n_pilot on, merged into the pilot's statistics
+ * (PDD_ACCUMULATE). Blocks until the pilot has finished; the continuation is
+ * asynchronous on `stream`. n_pilot >= 2, n_max >= n_pilot. Items' `out`
+ * receive the final statistics. Paths of a node are the same whichever
+ * items share the call. */
+pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items,
+                                  const double *target_se, uint64_t n_pilot, uint64_t n_max,
+                                  void *stream);
 
 /* Times the path kernel over launch shapes on a small copy of the given
  * solve (synchronous) and writes the fastest. */

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pdd.h"
+
 namespace pdd {
 
 constexpr int kMaxTrig = 16;
@@ -174,5 +176,6 @@ const void *path_kernel_symbol(bool one);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
+hipError_t launch_load_acc(const pdd_node_stats *in, NodeAcc *acc, uint32_t n, hipStream_t s);
 
 }  // namespace pdd

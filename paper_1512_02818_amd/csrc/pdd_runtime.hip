@@ -367,7 +367,7 @@ struct HostItem {
     int64_t n_nodes = 0;
     const pdd_solve_opts *o = nullptr;
     pdd_node_stats *out = nullptr;
-    bool cv = false, score_plain = true, uniform = true, caller_records = false;
+    bool cv = false, score_plain = true, uniform = true, caller_records = false, accumulate = false;
     uint64_t total = 0, max_steps = 0;
     std::vector<uint64_t> starts;  // item-relative prefix (non-uniform counts)
 };
@@ -403,6 +403,7 @@ pdd_status validate_item(HostItem &it)
     it.score_plain = !it.cv || (o->flags & PDD_PLAIN_ALONGSIDE);
     if (o->rec_steps && it.score_plain && !o->rec_phi) return fail(PDD_E_INVALID, "records need rec_phi");
     it.caller_records = o->rec_steps != nullptr;
+    it.accumulate = (o->flags & PDD_ACCUMULATE) != 0;
     for (int64_t i = 0; i < it.n_nodes; ++i) {
         const double *x = it.nodes + i * dim;
         if (!finite3(x, dim) || !strictly_inside(d, x))
@@ -572,6 +573,10 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     HIP_TRY(hipEventRecord(ctx->staged, s));
     ctx->any_staged = true;
     HIP_TRY(launch_zero(ctx->acc.ptr, n_nodes_all * sizeof(NodeAcc), s));
+    for (int q = 0; q < n_items; ++q)  // earlier paths' sums are the starting point
+        if (items[q]->accumulate)
+            HIP_TRY(launch_load_acc(items[q]->out, static_cast<NodeAcc *>(ctx->acc.ptr) + gnode[q],
+                                    (uint32_t)items[q]->n_nodes, s));
     HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
 
     const int block = tune.block;
@@ -828,6 +833,86 @@ pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *witems, int32_t n_
         items[q].out = w.out;
     }
     return run_items(ctx, items, static_cast<hipStream_t>(stream));
+}
+
+pdd_status pdd_plan_paths(const pdd_node_stats *pilot, int64_t n_nodes, double target_se,
+                          uint64_t n_max, uint64_t *n_total)
+{
+    if (n_nodes < 0 || (n_nodes > 0 && (!pilot || !n_total))) return fail(PDD_E_INVALID, "bad arguments");
+    if (!(target_se > 0.0) || !std::isfinite(target_se)) return fail(PDD_E_INVALID, "target_se must be finite and > 0");
+    const double inv2 = 1.0 / (target_se * target_se);
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const pdd_node_stats &p = pilot[i];
+        if (p.n < 2 || !std::isfinite(p.var) || p.var < 0.0)
+            return fail(PDD_E_INVALID, "pilot of node %lld has n < 2 or no finite variance", (long long)i);
+        const double want = std::ceil(p.var * inv2);  // N = V / SE^2
+        uint64_t n = want >= 1.8e19 ? UINT64_MAX : (uint64_t)want;
+        n = std::max<uint64_t>(n, (uint64_t)p.n);
+        n_total[i] = std::min(n, n_max);
+    }
+    return PDD_OK;
+}
+
+pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int32_t n_items,
+                                  const double *target_se, uint64_t n_pilot, uint64_t n_max,
+                                  void *stream)
+{
+    if (!ctx) return fail(PDD_E_INVALID, "ctx is NULL");
+    if (n_items < 0 || (n_items > 0 && (!witems || !target_se))) return fail(PDD_E_INVALID, "bad items");
+    if (n_pilot < 2 || n_max < n_pilot) return fail(PDD_E_INVALID, "need 2 <= n_pilot <= n_max");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<pdd_solve_opts> opts(n_items);
+    std::vector<HostItem> items(n_items);
+    for (int32_t q = 0; q < n_items; ++q) {
+        const pdd_work_item &w = witems[q];
+        if (!w.problem || !w.opts) return fail(PDD_E_INVALID, "item %d: problem or opts is NULL", q);
+        if ((w.u_prev == nullptr) != (w.resid == nullptr))
+            return fail(PDD_E_INVALID, "item %d: correction needs u_prev and residual grids", q);
+        if (w.opts->rec_steps || w.opts->rec_phi || w.opts->rec_e)
+            return fail(PDD_E_UNSUPPORTED, "item %d: per-path records are not kept by solves to a tolerance", q);
+        if (!(target_se[q] > 0.0) || !std::isfinite(target_se[q]))
+            return fail(PDD_E_INVALID, "item %d: target_se must be finite and > 0", q);
+        opts[q] = *w.opts;
+        opts[q].n_paths = n_pilot;
+        opts[q].n_paths_per_node = nullptr;
+        opts[q].flags &= ~PDD_ACCUMULATE;
+        HostItem &it = items[q];
+        it.prob = w.problem;
+        it.u_prev = w.u_prev;
+        it.resid = w.resid;
+        it.nodes = w.nodes;
+        it.n_nodes = w.n_nodes;
+        it.o = &opts[q];
+        it.out = w.out;
+    }
+    pdd_status st = run_items(ctx, items, s);  // pilot
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<std::vector<uint64_t>> counts(n_items);
+    std::vector<pdd_node_stats> pilot;
+    for (int32_t q = 0; q < n_items; ++q) {
+        const int64_t n = witems[q].n_nodes;
+        if (n <= 0) continue;
+        pilot.resize(n);
+        HIP_TRY(hipMemcpy(pilot.data(), witems[q].out, n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost));
+        counts[q].resize(n);
+        if ((st = pdd_plan_paths(pilot.data(), n, target_se[q], n_max, counts[q].data()))) return st;
+        for (auto &c : counts[q]) c -= n_pilot;
+        opts[q].n_paths_per_node = counts[q].data();
+        opts[q].path_offset += n_pilot;
+        opts[q].flags |= PDD_ACCUMULATE;
+    }
+    for (int32_t q = 0; q < n_items; ++q) {
+        items[q] = HostItem{};
+        items[q].prob = witems[q].problem;
+        items[q].u_prev = witems[q].u_prev;
+        items[q].resid = witems[q].resid;
+        items[q].nodes = witems[q].nodes;
+        items[q].n_nodes = witems[q].n_nodes;
+        items[q].o = &opts[q];
+        items[q].out = witems[q].out;
+    }
+    return run_items(ctx, items, s);  // continuation
 }
 
 pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n)

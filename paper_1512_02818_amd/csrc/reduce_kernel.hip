@@ -204,6 +204,24 @@ __global__ void finalize_kernel(const FinalizeArgs f)
     static_cast<pdd_node_stats *>(f.out)[i] = st;
 }
 
+// Starting sums of an accumulating solve: the statistics of earlier paths.
+__global__ void load_acc_kernel(const pdd_node_stats *in, NodeAcc *acc, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const pdd_node_stats &p = in[i];
+    NodeAcc a;
+    for (int q = 0; q < 5; ++q) {
+        a.s[q] = p.sums[2 * q];
+        a.c[q] = p.sums[2 * q + 1];
+    }
+    a.n = p.n;
+    a.steps = p.steps_sum;
+    a.capped = p.n_capped;
+    a.pad = 0;
+    acc[i] = a;
+}
+
 __global__ void zero_kernel(uint64_t *p, uint64_t n_words)
 {
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n_words;
@@ -224,6 +242,13 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
 {
     if (a.n_nodes == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3((a.n_nodes + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_acc(const pdd_node_stats *in, NodeAcc *acc, uint32_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(load_acc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, acc, n);
     return hipGetLastError();
 }
 

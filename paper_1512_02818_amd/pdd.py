@@ -21,6 +21,7 @@ LAWS = {"gauss": 0, "rademacher": 1}
 PRECISIONS = {"fp32": 0, "fp64": 1}
 PLAIN_ALONGSIDE = 1
 TIME_KERNEL = 2
+ACCUMULATE = 4
 MAX_TRIG, MAX_MONO = 16, 8
 
 
@@ -103,6 +104,11 @@ SIGNATURES = {
                                  C.POINTER(SolveOpts), C.POINTER(Tuning)]),
     "pdd_kernel_times": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                      C.POINTER(C.c_int32)]),
+    "pdd_plan_paths": (C.c_int32, [C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
+                                   C.POINTER(C.c_uint64)]),
+    "pdd_solve_to_tolerance": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32,
+                                           C.POINTER(C.c_double), C.c_uint64, C.c_uint64,
+                                           C.c_void_p]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -261,7 +267,7 @@ class Problem:
 
 def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
               precision="fp32", exit="bridge", law="gauss", max_steps=0, plain_alongside=False,
-              records=None, tuning=None, time_kernel=False):
+              records=None, tuning=None, time_kernel=False, accumulate=False):
     o = SolveOpts()
     o.dt = float(dt)
     o.n_paths = int(n_paths)
@@ -276,7 +282,8 @@ def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
     o.exit_mode = EXITS[exit]
     o.law = LAWS[law]
     o.max_steps = int(max_steps)
-    o.flags = (PLAIN_ALONGSIDE if plain_alongside else 0) | (TIME_KERNEL if time_kernel else 0)
+    o.flags = ((PLAIN_ALONGSIDE if plain_alongside else 0) | (TIME_KERNEL if time_kernel else 0)
+               | (ACCUMULATE if accumulate else 0))
     if records is not None:
         o.rec_phi = records["phi"].data_ptr() if records.get("phi") is not None else None
         o.rec_e = records["e"].data_ptr() if records.get("e") is not None else None
@@ -334,9 +341,20 @@ def solve_correction(problem: Problem, u_prev: dict, u_prev_t, resid: dict, resi
     return out
 
 
-def solve_batch(ctx: Context, items, stream=None):
-    """pdd_solve_batch over dicts {problem, nodes, opts(dict), out, [u_prev, u_prev_t, resid,
-    resid_t]}; returns the list of stats tensors."""
+class Batch:
+    """Marshalled pdd_work_item array (and what it points to) of batch-style
+    item dicts, reusable across calls."""
+
+    def __init__(self, items):
+        self.arr, self.outs, self._keep = _work_items(items)
+        self.n = len(items)
+
+
+def _as_batch(items):
+    return items if isinstance(items, Batch) else Batch(items)
+
+
+def _work_items(items):
     arr = (WorkItem * len(items))()
     keep = []
     outs = []
@@ -360,8 +378,35 @@ def solve_batch(ctx: Context, items, stream=None):
             arr[q].resid = C.pointer(gr)
         arr[q].out = out.data_ptr()
         outs.append(out)
-    _check(lib().pdd_solve_batch(ctx.handle, arr, len(items), _stream_handle(stream)))
-    return outs
+    return arr, outs, keep
+
+
+def solve_batch(ctx: Context, items, stream=None):
+    """pdd_solve_batch over dicts {problem, nodes, opts(dict), out, [u_prev, u_prev_t, resid,
+    resid_t]}; returns the list of stats tensors."""
+    b = _as_batch(items)
+    _check(lib().pdd_solve_batch(ctx.handle, b.arr, b.n, _stream_handle(stream)))
+    return b.outs
+
+
+def plan_paths(pilot: np.ndarray, target_se: float, n_max: int) -> np.ndarray:
+    """pdd_plan_paths on host pilot statistics (a STATS_DTYPE array)."""
+    pilot = np.ascontiguousarray(pilot, dtype=STATS_DTYPE)
+    out = np.zeros(len(pilot), dtype=np.uint64)
+    _check(lib().pdd_plan_paths(pilot.ctypes.data_as(C.c_void_p), len(pilot), float(target_se),
+                                int(n_max), out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out
+
+
+def solve_to_tolerance(ctx: Context, items, target_se, n_pilot, n_max, stream=None):
+    """pdd_solve_to_tolerance over batch-style item dicts (their n_paths is ignored);
+    target_se is one value or one per item. Returns the stats tensors."""
+    b = _as_batch(items)
+    se = np.ascontiguousarray(np.broadcast_to(np.asarray(target_se, dtype=np.float64), (b.n,)))
+    _check(lib().pdd_solve_to_tolerance(ctx.handle, b.arr, b.n,
+                                        se.ctypes.data_as(C.POINTER(C.c_double)), int(n_pilot),
+                                        int(n_max), _stream_handle(stream)))
+    return b.outs
 
 
 def kernel_times(ctx: Context, cap=4096):
