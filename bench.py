@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--paths-per-step", type=int, default=62500)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--cpu-paths", type=int, default=4,
+    ap.add_argument("--cpu-paths", type=int, default=10,
                     help="oracle sample: paths 0..n-1 of every node (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before warmup, one plain device copy of this many MiB (scales the "
@@ -82,6 +82,10 @@ def parse():
                     help="copies of the 18 unit-square nodes (distinct streams), plain FP64")
     ap.add_argument("--rms-replicas-cv", type=int, default=2000,
                     help="copies of the 18 unit-square nodes (distinct streams), CV + FP32")
+    ap.add_argument("--serve-duration", type=float, default=2.0,
+                    help="seconds of Poisson arrivals (200 requests/s) for the serving loop (0 = skip)")
+    ap.add_argument("--serve-drain", type=float, default=10.0,
+                    help="seconds to wait for completions after the last arrival")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -294,6 +298,17 @@ def main():
         print("node solves at fixed RMS error ...", file=sys.stderr, flush=True)
         result["node_solves_at_rms"] = node_solves_at_rms(ctx, args.rms_tol, args.rms_replicas_plain,
                                                           args.rms_replicas_cv)
+    if args.serve_duration > 0:
+        print("serving loop ...", file=sys.stderr, flush=True)
+        from paper_1512_02818_amd import serving
+        problems, reqs = W.serving_stream(seed=5, rate=200.0, duration=args.serve_duration)
+        rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=args.serve_drain,
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
+        rep["workload"] = ("Poisson 200 requests/s of 1-2,000 nodes (log-uniform) on 16 random 2D/3D "
+                           "box problems, RMS tolerance in {1e-2, 3e-3, 1e-3}, 30% with a u_prev grid "
+                           "(129^2-513^2 or 65^3), FP32, 64 GiB budget; requests still running after "
+                           "the drain are cancelled and reported")
+        result["serving"] = rep
     if args.cpu_paths > 0:
         print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(pd, nodes, args.cpu_paths)

@@ -245,6 +245,89 @@ pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nod
  * `ms` (host) and their count to `n`; the rest are dropped. */
 pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of node-solve requests, each to its own
+ * standard error (pilot, plan by pdd_plan_paths, continuation in chunks).
+ *
+ * A server owns a host thread and a HIP stream and is the only user of its
+ * context while it lives. The thread runs epochs: each epoch is one
+ * pdd_solve_batch-style launch per (precision, dim, estimator) group over the
+ * next chunk of admitted requests (a new request's pilot, or the next slice
+ * of its planned paths), pilots first, then the requests with the least
+ * remaining work (path-steps estimated from the pilot), up to epoch_paths. Requests submitted while an epoch runs wait in
+ * a FIFO queue and are admitted at the next epoch boundary when a slot is
+ * free and their device memory fits the budget; their chunks then share the
+ * launches with those already in flight. A request's chunks depend only on
+ * the request and the server options, and each group of an epoch is a single
+ * launch, so its results are bitwise the same alone or in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct pdd_server pdd_server;
+
+typedef struct {
+    uint64_t memory_budget; /* device bytes for admitted requests and the record scratch (0 = 64 GiB) */
+    int32_t max_inflight;   /* requests admitted at once (0 = 1024) */
+    int32_t max_queued;     /* submit sheds (PDD_E_BUSY) beyond this many waiting requests (0 = no limit) */
+    uint64_t n_pilot;       /* pilot paths per node (0 = 1000) */
+    uint64_t n_max;         /* paths per node at most (0 = 2^31) */
+    uint64_t chunk_paths;   /* paths of one request per epoch, cut per request (0 = 2^22) */
+    uint64_t epoch_paths;   /* paths per epoch launch, <= 2^27 (0 = 2^27) */
+} pdd_server_opts;
+
+typedef struct {
+    pdd_problem *problem;        /* kept alive by the caller until completion */
+    const double *nodes;         /* host, n_nodes x dim; copied by pdd_server_submit */
+    int64_t n_nodes;             /* >= 1 */
+    double dt;
+    double target_se;            /* per-node standard error to reach (> 0) */
+    int32_t precision;           /* PDD_FP32 or PDD_FP64 */
+    int32_t exit_mode;           /* PDD_EXIT_* */
+    uint32_t stream_id;          /* RNG stream of the request */
+    int32_t reserved;
+    const pdd_grid *u_prev;      /* both NULL: plain estimator; else the correction (structs */
+    const pdd_grid *resid;       /* copied, data borrowed until completion) */
+    pdd_node_stats *out;         /* host, n_nodes entries; final statistics, written before
+                                    the completion is reported */
+    uint64_t user_tag;           /* returned in the completion */
+} pdd_request;
+
+typedef struct {
+    uint64_t id, user_tag;
+    pdd_status status;           /* PDD_OK, or why the request failed (PDD_E_BUSY: cancelled) */
+    int32_t reserved;
+    double queued_ms;            /* submit to admission */
+    double latency_ms;           /* submit to completion */
+    uint64_t paths, path_steps;  /* over all nodes */
+    int64_t n_nodes;
+} pdd_completion;
+
+typedef struct {
+    uint64_t submitted, shed, admitted, completed, failed, queued, inflight, epochs;
+    uint64_t nodes_completed, path_steps;
+    uint64_t mem_in_use, mem_peak, mem_fixed; /* bytes: admitted requests; their peak; record scratch */
+    double p50_ms, p99_ms, mean_ms;           /* latency of completed requests */
+    double wall_s;                            /* first submit to last completion */
+    double node_solves_per_s;                 /* nodes_completed / wall_s */
+    double epoch_s;                           /* time spent running epochs (enqueue to device done) */
+} pdd_server_report;
+
+/* Starts a server on `ctx` (NULL opts = defaults). Errors: bad options, a
+ * budget smaller than the record scratch, thread or stream creation. */
+pdd_status pdd_server_create(pdd_ctx *ctx, const pdd_server_opts *opts, pdd_server **out);
+/* Validates and queues a request; writes its id. PDD_E_INVALID: bad request;
+ * PDD_E_NOMEM: it can never fit the budget; PDD_E_UNSUPPORTED: its pilot
+ * exceeds epoch_paths; PDD_E_BUSY: shed (queue full or server stopping). */
+pdd_status pdd_server_submit(pdd_server *server, const pdd_request *req, uint64_t *id);
+/* Moves up to `cap` completions (oldest first) to `out` (host) and writes
+ * their count to `n`, waiting up to wait_ms (0 = no wait) for the first. */
+pdd_status pdd_server_poll(pdd_server *server, pdd_completion *out, int32_t cap, int32_t *n,
+                           int32_t wait_ms);
+/* Counters and latency percentiles so far. */
+pdd_status pdd_server_report_get(pdd_server *server, pdd_server_report *out);
+/* Stops the server: the running epoch ends, requests still queued or in
+ * flight are cancelled (their `out` is not written), device memory is freed.
+ * NULL is a no-op. */
+void pdd_server_destroy(pdd_server *server);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *pdd_last_error(void);
 

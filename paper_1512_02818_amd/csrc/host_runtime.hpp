@@ -1,0 +1,82 @@
+// Host-side internals shared by the solver runtime and the serving loop
+// (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "pdd.h"
+#include "pdd_internal.hpp"
+
+namespace pdd {
+
+// Records a thread-local message for pdd_last_error() and returns `code`.
+pdd_status fail(pdd_status code, const char *fmt, ...);
+extern thread_local std::string g_error;
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::pdd::fail(PDD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr double kGmShift = 0.5826;                    // Alg. 1 boundary shift
+constexpr double kBridgeSkip = 24.953298500158186;     // 36 ln 2: p < 2^-36 skipped
+constexpr uint64_t kDefaultMaxSteps = 1ull << 26;
+constexpr uint64_t kScratchSlots = 1ull << 27;         // record slots per launch
+constexpr uint64_t kMaxLaunchSlots = 1ull << 31;
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+// One solve (or batch item) after validation.
+struct HostItem {
+    pdd_problem *prob = nullptr;
+    const pdd_grid *u_prev = nullptr, *resid = nullptr;
+    const double *nodes = nullptr;
+    int64_t n_nodes = 0;
+    const pdd_solve_opts *o = nullptr;
+    pdd_node_stats *out = nullptr;
+    bool cv = false, score_plain = true, uniform = true, caller_records = false, accumulate = false;
+    uint64_t total = 0, max_steps = 0;
+    std::vector<uint64_t> starts;  // item-relative prefix (non-uniform counts)
+};
+
+// Checks an item's arguments against its problem (nothing is enqueued).
+pdd_status validate_item(HostItem &it);
+// Validates items, then enqueues them on `s`, grouped by (precision,
+// dimension, estimator); a group of at most kScratchSlots paths without
+// caller records is one launch.
+pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s);
+
+}  // namespace pdd
+
+struct pdd_ctx {
+    int device = 0;
+    int n_cu = 0;
+    hipEvent_t done = nullptr;    // end of the last solve
+    hipEvent_t staged = nullptr;  // last copy out of the staging buffer
+    bool any_done = false, any_staged = false;
+    pdd::DeviceBuffer nodes, starts, acc, counters, rec;
+    void *stage = nullptr;
+    size_t stage_cap = 0;
+    std::map<std::tuple<const void *, int>, int> occupancy;
+    // timing of path-kernel launches (PDD_TIME_KERNEL)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;
+};
+
+struct pdd_problem {
+    pdd_ctx *ctx = nullptr;
+    pdd_problem_desc desc{};
+    pdd::DevProblem<float> pf{};
+    pdd::DevProblem<double> pd{};
+};

@@ -19,11 +19,11 @@
 #include <vector>
 
 #include "../../include/pdd.h"
-#include "pdd_internal.hpp"
+#include "host_runtime.hpp"
 
 using namespace pdd;
 
-namespace {
+namespace pdd {
 
 thread_local std::string g_error;
 
@@ -38,46 +38,7 @@ pdd_status fail(pdd_status code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(PDD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
-    } while (0)
-
-constexpr double kGmShift = 0.5826;                    // Alg. 1 boundary shift
-constexpr double kBridgeSkip = 24.953298500158186;     // 36 ln 2: p < 2^-36 skipped
-constexpr uint64_t kDefaultMaxSteps = 1ull << 26;
-constexpr uint64_t kScratchSlots = 1ull << 27;         // record slots per launch
-constexpr uint64_t kMaxLaunchSlots = 1ull << 31;
-
-struct DeviceBuffer {
-    void *ptr = nullptr;
-    size_t cap = 0;
-};
-
-}  // namespace
-
-struct pdd_ctx {
-    int device = 0;
-    int n_cu = 0;
-    hipEvent_t done = nullptr;    // end of the last solve
-    hipEvent_t staged = nullptr;  // last copy out of the staging buffer
-    bool any_done = false, any_staged = false;
-    DeviceBuffer nodes, starts, acc, counters, rec;
-    void *stage = nullptr;
-    size_t stage_cap = 0;
-    std::map<std::tuple<const void *, int>, int> occupancy;
-    // timing of path-kernel launches (PDD_TIME_KERNEL)
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;
-};
-
-struct pdd_problem {
-    pdd_ctx *ctx = nullptr;
-    pdd_problem_desc desc{};
-    DevProblem<float> pf{};
-    DevProblem<double> pd{};
-};
+}  // namespace pdd
 
 namespace {
 
@@ -359,20 +320,10 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
     return n;
 }
 
-// One solve (or batch item) after validation.
-struct HostItem {
-    pdd_problem *prob = nullptr;
-    const pdd_grid *u_prev = nullptr, *resid = nullptr;
-    const double *nodes = nullptr;
-    int64_t n_nodes = 0;
-    const pdd_solve_opts *o = nullptr;
-    pdd_node_stats *out = nullptr;
-    bool cv = false, score_plain = true, uniform = true, caller_records = false, accumulate = false;
-    uint64_t total = 0, max_steps = 0;
-    std::vector<uint64_t> starts;  // item-relative prefix (non-uniform counts)
-};
 
-pdd_status validate_item(HostItem &it)
+}  // namespace
+
+pdd_status pdd::validate_item(HostItem &it)
 {
     const pdd_solve_opts *o = it.o;
     if (!it.prob) return fail(PDD_E_INVALID, "problem is NULL");
@@ -431,6 +382,8 @@ pdd_status validate_item(HostItem &it)
         return fail(PDD_E_UNSUPPORTED, "per-path records are limited to 2^31 paths per solve");
     return PDD_OK;
 }
+
+namespace {
 
 pdd_status read_tuning(const pdd_solve_opts *o, pdd_tuning &tune)
 {
@@ -671,8 +624,10 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     return PDD_OK;
 }
 
+}  // namespace
+
 // Validates items, then runs them grouped by (precision, dim, estimator).
-pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s)
+pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s)
 {
     for (auto &it : items) {
         pdd_status st = validate_item(it);
@@ -713,8 +668,6 @@ pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s)
             }
     return PDD_OK;
 }
-
-}  // namespace
 
 extern "C" {
 

@@ -88,6 +88,34 @@ STATS_DTYPE = np.dtype([("n", "<i8"), ("n_capped", "<i8"), ("steps_sum", "<i8"),
                         ("rho", "<f8"), ("vr", "<f8"), ("vr_opt", "<f8"), ("sums", "<f8", (10,))])
 assert STATS_DTYPE.itemsize == C.sizeof(NodeStats)
 
+class ServerOpts(C.Structure):
+    _fields_ = [("memory_budget", C.c_uint64), ("max_inflight", C.c_int32), ("max_queued", C.c_int32),
+                ("n_pilot", C.c_uint64), ("n_max", C.c_uint64), ("chunk_paths", C.c_uint64),
+                ("epoch_paths", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("nodes", C.POINTER(C.c_double)), ("n_nodes", C.c_int64),
+                ("dt", C.c_double), ("target_se", C.c_double), ("precision", C.c_int32),
+                ("exit_mode", C.c_int32), ("stream_id", C.c_uint32), ("reserved", C.c_int32),
+                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)), ("out", C.c_void_p),
+                ("user_tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("user_tag", C.c_uint64), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("queued_ms", C.c_double), ("latency_ms", C.c_double),
+                ("paths", C.c_uint64), ("path_steps", C.c_uint64), ("n_nodes", C.c_int64)]
+
+
+class ServerReport(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "shed", "admitted", "completed", "failed",
+                                           "queued", "inflight", "epochs", "nodes_completed",
+                                           "path_steps", "mem_in_use", "mem_peak", "mem_fixed")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "wall_s", "node_solves_per_s",
+                                          "epoch_s")]
+
+
 # Every entry point of include/pdd.h with its ctypes signature.
 SIGNATURES = {
     "pdd_init": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int]),
@@ -109,6 +137,12 @@ SIGNATURES = {
     "pdd_solve_to_tolerance": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32,
                                            C.POINTER(C.c_double), C.c_uint64, C.c_uint64,
                                            C.c_void_p]),
+    "pdd_server_create": (C.c_int32, [C.c_void_p, C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
+    "pdd_server_submit": (C.c_int32, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "pdd_server_poll": (C.c_int32, [C.c_void_p, C.POINTER(Completion), C.c_int32,
+                                    C.POINTER(C.c_int32), C.c_int32]),
+    "pdd_server_report_get": (C.c_int32, [C.c_void_p, C.POINTER(ServerReport)]),
+    "pdd_server_destroy": (None, [C.c_void_p]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -424,3 +458,86 @@ def autotune(problem: Problem, nodes, **opt):
     _check(lib().pdd_autotune(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)),
                               len(nodes), C.byref(o), C.byref(t)))
     return (t.block, t.blocks_per_cu, t.grab)
+
+
+class Server:
+    """pdd_server_*: continuous batching of node-solve requests to a standard
+    error. Host result arrays and grid structs are kept here until their
+    request completes."""
+
+    def __init__(self, ctx: Context, memory_budget=0, max_inflight=0, max_queued=0, n_pilot=0,
+                 n_max=0, chunk_paths=0, epoch_paths=0):
+        self.ctx = ctx
+        o = ServerOpts(int(memory_budget), int(max_inflight), int(max_queued), int(n_pilot),
+                       int(n_max), int(chunk_paths), int(epoch_paths))
+        h = C.c_void_p()
+        _check(lib().pdd_server_create(ctx.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+        self.pending = {}  # id -> (stats array, kept objects)
+        self.results = {}  # id -> (Completion fields, stats array)
+
+    def submit(self, problem: Problem, nodes, dt, target_se, precision="fp32", exit="bridge",
+               stream_id=0, u_prev=None, u_prev_t=None, resid=None, resid_t=None, tag=0):
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+        out = np.zeros(len(nodes), dtype=STATS_DTYPE)
+        r = Request()
+        r.problem = problem.handle
+        r.nodes = nodes.ctypes.data_as(C.POINTER(C.c_double))
+        r.n_nodes = len(nodes)
+        r.dt = float(dt)
+        r.target_se = float(target_se)
+        r.precision = PRECISIONS[precision]
+        r.exit_mode = EXITS[exit]
+        r.stream_id = int(stream_id)
+        keep = [nodes, problem]
+        if u_prev is not None:
+            gu, gr = grid_struct(u_prev, u_prev_t), grid_struct(resid, resid_t)
+            keep += [gu, gr, u_prev_t, resid_t]
+            r.u_prev = C.pointer(gu)
+            r.resid = C.pointer(gr)
+        r.out = out.ctypes.data
+        r.user_tag = int(tag)
+        rid = C.c_uint64()
+        _check(lib().pdd_server_submit(self.handle, C.byref(r), C.byref(rid)))
+        self.pending[rid.value] = (out, keep)
+        return rid.value
+
+    def poll(self, wait_ms=0, cap=256):
+        """Completions since the last poll, as dicts (with 'stats' on success)."""
+        buf = (Completion * cap)()
+        n = C.c_int32()
+        _check(lib().pdd_server_poll(self.handle, buf, cap, C.byref(n), int(wait_ms)))
+        got = []
+        for i in range(n.value):
+            c = buf[i]
+            d = {f: getattr(c, f) for f, _ in Completion._fields_ if f != "reserved"}
+            out, _ = self.pending.pop(c.id)
+            d["stats"] = out if c.status == PDD_OK else None
+            self.results[c.id] = d
+            got.append(d)
+        return got
+
+    def wait_all(self, timeout_s=600.0):
+        """Polls until no submitted request is pending (or the timeout)."""
+        import time
+        t_end = time.time() + timeout_s
+        while self.pending and time.time() < t_end:
+            self.poll(wait_ms=50)
+        return not self.pending
+
+    def report(self) -> dict:
+        r = ServerReport()
+        _check(lib().pdd_server_report_get(self.handle, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in ServerReport._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdd_server_destroy(self.handle)
+            self.handle = None
+            self.pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -177,11 +177,11 @@ def manufactured_u(pd: dict, pts) -> np.ndarray:
 
 # --------------------------------------------------------------------------- grids
 def grid_points(n, lo, hi):
-    """Coordinates of an n[0] x n[1] uniform grid, x fastest, shape (ny*nx, 2)."""
-    xs = np.linspace(lo[0], hi[0], n[0])
-    ys = np.linspace(lo[1], hi[1], n[1])
-    X, Y = np.meshgrid(xs, ys, indexing="xy")
-    return np.stack([X.ravel(), Y.ravel()], axis=1)
+    """Coordinates of an n[0] x n[1] (x n[2]) uniform grid, x fastest, shape
+    (prod(n), len(n))."""
+    axes = [np.linspace(lo[d], hi[d], n[d]) for d in range(len(n))]
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")  # slowest axis first
+    return np.stack([m.ravel() for m in mesh[::-1]], axis=1)
 
 
 def fourier_perturbation(seed=1, n_modes=32, amp=1e-2, kmax=16, dim=2):
@@ -217,22 +217,46 @@ def _pert_eval(pert, pts, lo, hi):
     return val, grad, lap
 
 
+def _pert_grid(pert, shape, lo, hi):
+    """p, grad p and Lap p on the uniform grid of `shape` (x fastest), flat
+    like grid_points; the modes are products of 1D sines, so each factor is
+    evaluated per axis and the products are formed by einsum."""
+    D = len(shape)
+    L = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+    k = np.asarray(pert["k"], dtype=np.float64)  # (modes, D)
+    A = np.asarray(pert["A"], dtype=np.float64)
+    xs = [np.linspace(0.0, 1.0, shape[d]) for d in range(D)]
+    S = [np.sin(PI * k[:, d][:, None] * xs[d][None, :]) for d in range(D)]   # (modes, n_d)
+    Cd = [PI * k[:, d][:, None] / L[d] * np.cos(PI * k[:, d][:, None] * xs[d][None, :]) for d in range(D)]
+    w2 = np.sum((PI * k / L[None, :]) ** 2, axis=1)
+    axes = "xyz"[:D]
+    spec = ",".join("m" + a for a in axes)
+    out = "".join(reversed(axes))  # slowest axis first
+    val = np.einsum("m," + spec + "->" + out, A, *S).ravel()
+    lap = np.einsum("m," + spec + "->" + out, -A * w2, *S).ravel()
+    grad = np.stack([np.einsum("m," + spec + "->" + out, A, *[Cd[e] if e == d else S[e] for e in range(D)]).ravel()
+                     for d in range(D)], axis=1)
+    return val, grad, lap
+
+
 def correction_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=1e-2):
     """u_prev = U + p on an n x n grid over the box, and the residual
     r = f - (L + c) u_prev = -(1/2 sigma^2 Lap p + b.grad p + c p), both
     evaluated exactly at the grid points in float64 and stored in `dtype`.
     Returns (u_prev_grid, resid_grid, perturbation)."""
     lo, hi = pd["lo"], pd["hi"]
-    pts = grid_points((n, n), lo, hi)
-    pert = fourier_perturbation(seed, n_modes=n_modes, amp=amp)
-    p, gp, lp = _pert_eval(pert, pts, lo, hi)
+    D = pd["dim"]
+    shape = (n,) * D
+    pts = grid_points(shape, lo, hi)
+    pert = fourier_perturbation(seed, n_modes=n_modes, amp=amp, dim=D)
+    p, gp, lp = _pert_grid(pert, shape, lo, hi)
     b = np.asarray(pd["b0"])[None, :] + pts @ np.asarray(pd["B"]).T
     c = pd["c_a"] + pd["c_b"] * np.sum(pts ** 2, axis=1)
     s2 = pd["sigma"] ** 2
     resid = -(0.5 * s2 * lp + np.sum(b * gp, axis=1) + c * p)
     u_prev = manufactured_u(pd, pts) + p
-    mk = lambda v: {"dim": 2, "n": [n, n], "lo": list(lo), "hi": list(hi),  # noqa: E731
-                    "data": v.astype(dtype).reshape(n, n)}
+    mk = lambda v: {"dim": D, "n": [n] * D, "lo": list(lo), "hi": list(hi),  # noqa: E731
+                    "data": v.astype(dtype).reshape(shape)}
     return mk(u_prev), mk(resid), pert
 
 
@@ -297,3 +321,41 @@ def batch_workload(seed=4, n_problems=64, node_range=(10, 5000), path_range=(1e3
         out.append({"problem": pd, "nodes": face_nodes(rng, pd, n), "n_paths": max(npath, 1),
                     "dt": float(rng.choice(dts))})
     return out
+
+
+# --------------------------------------------------------------------------- serving
+# time step by tolerance for plain requests (the bias of the bridge scheme is
+# first order; these keep it below tol / sqrt(2) on the unit-square problem)
+PLAIN_DT = {1e-2: 1e-3, 3e-3: 5e-4, 1e-3: 2.5e-4}
+CV_DT = 1e-3
+
+
+def serving_stream(seed=5, rate=200.0, duration=5.0, n_problems=16, node_range=(1, 2000),
+                   tols=(1e-2, 3e-3, 1e-3), cv_frac=0.3, grid_sizes_2d=(129, 257, 513), grid_3d=65):
+    """Seeded Poisson stream of node-solve requests: problems from the batched
+    generator (random_problem), node counts log-uniform in node_range on the
+    internal faces, tolerance uniform on `tols` (RMS target; per-node SE =
+    tol / sqrt(2)), a fraction cv_frac carrying a u_prev grid (2D: n uniform
+    on grid_sizes_2d, 3D: grid_3d^3) built like correction_grids.
+    Returns (problems, requests); a request is a dict with arrival time `t`,
+    problem index, nodes, tol, target_se, dt, cv, grid_n and stream_id."""
+    rng = np.random.default_rng(seed)
+    problems = [random_problem(rng) for _ in range(n_problems)]
+    reqs = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration:
+            break
+        q = int(rng.integers(n_problems))
+        pd = problems[q]
+        n = int(round(np.exp(rng.uniform(np.log(node_range[0]), np.log(node_range[1])))))
+        nodes = face_nodes(rng, pd, max(n, 1))
+        tol = float(tols[int(rng.integers(len(tols)))])
+        cv = bool(rng.random() < cv_frac)
+        gn = (int(grid_sizes_2d[int(rng.integers(len(grid_sizes_2d)))]) if pd["dim"] == 2 else grid_3d) \
+            if cv else None
+        reqs.append({"t": t, "problem": q, "nodes": nodes, "tol": tol,
+                     "target_se": tol / np.sqrt(2.0), "dt": CV_DT if cv else PLAIN_DT[tol],
+                     "cv": cv, "grid_n": gn, "stream_id": len(reqs)})
+    return problems, reqs

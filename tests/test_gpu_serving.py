@@ -1,0 +1,131 @@
+"""Serving loop through the C ABI: continuous batching of requests to a
+standard error. A request's statistics are bitwise the same alone and in a
+mix of other requests; admission keeps the memory model within the budget;
+a full queue sheds; results agree with pdd_solve_to_tolerance."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_02818_amd import pdd  # noqa: E402
+from paper_1512_02818_amd import serving as S  # noqa: E402
+from paper_1512_02818_amd import workloads as W  # noqa: E402
+
+SMALL = dict(epoch_paths=1 << 22, chunk_paths=1 << 17)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def stream(ctx):
+    problems, reqs = W.serving_stream(seed=7, rate=300.0, duration=0.12, n_problems=6,
+                                      node_range=(1, 60), tols=(1e-2, 3e-3), cv_frac=0.4,
+                                      grid_sizes_2d=(65, 129), grid_3d=33)
+    fx = S.Fixtures(ctx, problems, reqs)
+    yield problems, reqs, fx
+    fx.close()
+
+
+def _alone(ctx, fx, r, opts):
+    sv = pdd.Server(ctx, **opts)
+    rid = fx.submit(sv, r)
+    assert sv.wait_all(120)
+    c = sv.results[rid]
+    sv.close()
+    assert c["status"] == 0
+    return c
+
+
+def test_alone_equals_mix(ctx, stream):
+    problems, reqs, fx = stream
+    assert len(reqs) >= 20 and any(r["cv"] for r in reqs) and not all(r["cv"] for r in reqs)
+    rep, done = S.run_stream(ctx, problems, reqs, drain_s=120, server_opts=SMALL, fixtures=fx)
+    assert rep["completed"] == len(reqs) and rep["failed"] == 0 and rep["cancelled"] == 0
+    assert rep["epochs"] > 3
+    picks = [i for i, r in enumerate(reqs) if r["cv"]][:2] + [i for i, r in enumerate(reqs) if not r["cv"]][:2]
+    for i in picks:
+        r = reqs[i]
+        alone = _alone(ctx, fx, r, SMALL)
+        mixed = done[r["stream_id"]]
+        assert alone["stats"].tobytes() == mixed["stats"].tobytes(), i
+        assert alone["path_steps"] == mixed["path_steps"]
+    # every request reached about its standard error (the variance is re-estimated
+    # from all paths, the plan used the pilot's)
+    ratio = np.concatenate([done[r["stream_id"]]["stats"]["stderr"] / r["target_se"] for r in reqs])
+    assert np.median(ratio) <= 1.1 and np.all(ratio <= 2.0)
+
+
+def test_matches_solve_to_tolerance(ctx, stream):
+    _, reqs, fx = stream
+    r = next(r for r in reqs if not r["cv"] and len(r["nodes"]) > 3)
+    c = _alone(ctx, fx, r, SMALL)
+    item = {"problem": fx.problems[r["problem"]], "nodes": r["nodes"],
+            "opts": dict(dt=r["dt"], precision="fp32", stream_id=r["stream_id"])}
+    (o,) = pdd.solve_to_tolerance(ctx, [item], r["target_se"], 1000, 1 << 31)
+    st = pdd.stats_to_numpy(o)
+    got = c["stats"]
+    assert np.array_equal(st["n"], got["n"]) and np.array_equal(st["steps_sum"], got["steps_sum"])
+    assert np.allclose(st["mean"], got["mean"], rtol=1e-12, atol=1e-14)
+
+
+def test_admission_respects_memory_budget(ctx, stream):
+    problems, reqs, fx = stream
+    sub = reqs[:12]
+    fixed = SMALL["epoch_paths"] * 20
+    # room for about two requests' device state at a time
+    per = [len(r["nodes"]) * (184 + 112 + 8 * 3 + 16) +
+           (2 * 4 * r["grid_n"] ** problems[r["problem"]]["dim"] if r["cv"] else 0) for r in sub]
+    budget = fixed + 2 * max(per)
+    rep, done = S.run_stream(ctx, problems, sub, drain_s=120, fixtures=fx,
+                             server_opts=dict(SMALL, memory_budget=budget))
+    assert rep["completed"] == len(sub)
+    assert rep["mem_fixed"] == fixed
+    assert 0 < rep["mem_peak"] <= budget - fixed
+    assert rep["mem_in_use"] == 0 and rep["inflight"] == 0
+    assert 0 < rep["p50_ms"] <= rep["p99_ms"]
+    assert rep["node_solves_per_s"] > 0
+    # a request that can never fit is refused at submit
+    sv = pdd.Server(ctx, **SMALL, memory_budget=fixed + 1000)
+    with pytest.raises(pdd.PDDError) as ei:
+        fx.submit(sv, sub[0])
+    assert ei.value.status == -2
+    sv.close()
+
+
+def test_full_queue_sheds_and_close_cancels(ctx, stream):
+    _, reqs, fx = stream
+    sv = pdd.Server(ctx, **SMALL, max_inflight=1, max_queued=2)
+    statuses = []
+    for r in reqs[:10]:
+        try:
+            fx.submit(sv, r)
+            statuses.append(0)
+        except pdd.PDDError as e:
+            statuses.append(e.status)
+    assert -5 in statuses and 0 in statuses
+    rep = sv.report()
+    assert rep["shed"] == statuses.count(-5)
+    sv.close()  # cancels what is still queued or running; must not hang
+
+
+def test_invalid_requests(ctx, stream):
+    _, reqs, fx = stream
+    sv = pdd.Server(ctx, **SMALL)
+    r = dict(reqs[0])
+    bad = [dict(r, target_se=0.0), dict(r, dt=-1.0), dict(r, nodes=np.full_like(r["nodes"], 1e3))]
+    for b in bad:
+        with pytest.raises(pdd.PDDError) as ei:
+            fx.submit(sv, b)
+        assert ei.value.status == -1
+    sv.close()
+    with pytest.raises(pdd.PDDError):
+        pdd.Server(ctx, epoch_paths=1 << 30)
