@@ -86,6 +86,9 @@ def parse():
                     help="seconds of Poisson arrivals (200 requests/s) for the serving loop (0 = skip)")
     ap.add_argument("--serve-drain", type=float, default=10.0,
                     help="seconds to wait for completions after the last arrival")
+    ap.add_argument("--tuning", default="cache",
+                    help="launch shape block,blocks_per_cu,grab of the path kernel, 'cache' (the "
+                         "autotuner's cached shape for this GPU, else the default) or 'default'")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -216,6 +219,12 @@ def main():
     nodes = W.big_square_nodes()
     P = args.paths_per_step
     ctx = pdd.Context(0)
+    from paper_1512_02818_amd import tuning
+    shape = None
+    if args.tuning == "cache":
+        tuning.load(ctx)
+    elif args.tuning != "default":
+        shape = tuple(int(v) for v in args.tuning.split(","))
     prob = pdd.Problem(ctx, pd)
     outs = [pdd.alloc_stats(len(nodes)) for _ in range(args.warmup + args.steps)]
 
@@ -228,7 +237,8 @@ def main():
 
     def step(s):
         pdd.solve_nodes(prob, nodes, out=outs[s], dt=H, n_paths=P, path_offset=s * P,
-                        precision=args.precision, time_kernel=True)
+                        precision=args.precision, time_kernel=True,
+                        tuning=None if shape is None else shape + (0,))
 
     for s in range(args.warmup):
         step(s)
@@ -284,7 +294,7 @@ def main():
                                f"{P} paths per node per step (10^6 per node over "
                                f"{1_000_000 // P} steps), h=1e-4, bridge exit, "
                                f"{args.precision} paths, fp64 sums",
-                   "nodes": int(len(nodes)), "paths_per_step": P, "dt": H,
+                   "nodes": int(len(nodes)), "paths_per_step": P, "dt": H, "tuning": args.tuning,
                    "mean_steps_per_path": total_steps / (args.steps * len(nodes) * P)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Top/s (FP32 VALU lane slots)",

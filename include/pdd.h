@@ -126,7 +126,11 @@ typedef struct {
     const void *data;
 } pdd_grid;
 
-/* Launch shape of the path kernel (0 = library default / tuning cache). */
+/* Launch shape of the path kernel. A solve whose opts give no tuning uses the
+ * context's entry for its (precision, dim, estimator) group, set by
+ * pdd_autotune or pdd_set_tuning, else the default {256, occupancy, 64, 0};
+ * fields left 0 in a given tuning take the default. Results never depend on
+ * the launch shape. */
 typedef struct {
     int32_t block;        /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;/* persistent workgroups per compute unit */
@@ -234,10 +238,30 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int3
                                   const double *target_se, uint64_t n_pilot, uint64_t n_max,
                                   void *stream);
 
-/* Times the path kernel over launch shapes on a small copy of the given
- * solve (synchronous) and writes the fastest. */
-pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nodes,
-                        const pdd_solve_opts *opts, pdd_tuning *out);
+/* Key of the context's launch-shape table. */
+typedef struct {
+    int32_t precision;  /* PDD_FP32 or PDD_FP64 */
+    int32_t dim;        /* 2 or 3 */
+    int32_t correction; /* 0 plain, 1 correction estimator */
+    int32_t reserved;
+} pdd_tuning_key;
+
+/* Times samples of `item` (up to 32 of its nodes, about 8 and 16 paths per
+ * resident lane in all, its dt, precision, exit test, law, stream and grids;
+ * its path counts, records and tuning are ignored) under the launch shapes
+ * block {64, 128, 256} x grab {16, 64, 256} at full occupancy, and block 256
+ * with 3/4 and 1/2 of the occupancy, twice each after a warm-up. A shape's
+ * cost is the time of the larger sample minus that of the smaller, which
+ * leaves out fixed costs and the exit-time tail. The default
+ * {256, occupancy, 64} is kept unless a shape is more than 2% faster. The
+ * winner is written to `out` (host) and stored in the context's table for
+ * the item's key. Synchronous; uses the context like a solve. Errors as for
+ * the solve. */
+pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out);
+
+/* Sets (t non-NULL) or removes (t NULL) the context's table entry for `key`,
+ * e.g. to restore shapes tuned earlier. PDD_E_INVALID for a bad key or shape. */
+pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tuning *t);
 
 /* GPU milliseconds between the first path-kernel launch and the end of the
  * last one, for each solve issued with PDD_TIME_KERNEL since the previous

@@ -53,6 +53,9 @@ struct HostItem {
 
 // Checks an item's arguments against its problem (nothing is enqueued).
 pdd_status validate_item(HostItem &it);
+// Key of the launch-shape table: precision, dimension and estimator.
+inline int tuning_key(int precision, int dim, bool cv) { return precision * 4 + (dim - 2) * 2 + (cv ? 1 : 0); }
+
 // Validates items, then enqueues them on `s`, grouped by (precision,
 // dimension, estimator); a group of at most kScratchSlots paths without
 // caller records is one launch.
@@ -72,6 +75,8 @@ struct pdd_ctx {
     std::map<std::tuple<const void *, int>, int> occupancy;
     // timing of path-kernel launches (PDD_TIME_KERNEL)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;
+    // launch shapes by (precision, dim, estimator), from pdd_autotune / pdd_set_tuning
+    std::map<int, pdd_tuning> tuned;
 };
 
 struct pdd_problem {

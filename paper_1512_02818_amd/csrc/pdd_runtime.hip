@@ -385,21 +385,32 @@ pdd_status pdd::validate_item(HostItem &it)
 
 namespace {
 
-pdd_status read_tuning(const pdd_solve_opts *o, pdd_tuning &tune)
+pdd_status check_tuning(const pdd_tuning &tune)
 {
-    tune = pdd_tuning{256, 0, 64, 0};
-    if (o->tuning) {
-        if (o->tuning->block) tune.block = o->tuning->block;
-        if (o->tuning->blocks_per_cu) tune.blocks_per_cu = o->tuning->blocks_per_cu;
-        if (o->tuning->grab) tune.grab = o->tuning->grab;
-        tune.max_launch_paths = o->tuning->max_launch_paths;
-    }
     if (tune.block != 64 && tune.block != 128 && tune.block != 256)
         return fail(PDD_E_INVALID, "tuning.block must be 64, 128 or 256");
     if (tune.grab < 1 || tune.grab > 4096 || tune.blocks_per_cu < 0 || tune.blocks_per_cu > 64 ||
         tune.max_launch_paths < 0)
         return fail(PDD_E_INVALID, "tuning out of range");
     return PDD_OK;
+}
+
+// Launch shape of a group: the caller's (fields left 0 take the default),
+// else the context's table entry for the group's key, else the default.
+pdd_status read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd_tuning &tune)
+{
+    tune = pdd_tuning{256, 0, 64, 0};
+    if (!o->tuning && key >= 0) {
+        auto f = ctx->tuned.find(key);
+        if (f != ctx->tuned.end()) tune = f->second;
+    }
+    if (o->tuning) {
+        if (o->tuning->block) tune.block = o->tuning->block;
+        if (o->tuning->blocks_per_cu) tune.blocks_per_cu = o->tuning->blocks_per_cu;
+        if (o->tuning->grab) tune.grab = o->tuning->grab;
+        tune.max_launch_paths = o->tuning->max_launch_paths;
+    }
+    return check_tuning(tune);
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -636,7 +647,7 @@ pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_
     }
     if (items.empty()) return PDD_OK;
     pdd_tuning tune;
-    pdd_status st = read_tuning(items[0].o, tune);
+    pdd_status st = read_tuning(ctx, items[0].o, -1, tune);  // the caller's shape, checked up front
     if (st) return st;
     bool timed = false;
     for (auto &it : items) timed |= (it.o->flags & PDD_TIME_KERNEL) != 0;
@@ -650,6 +661,7 @@ pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_
                     if (it.o->precision == prec && it.prob->desc.dim == dim && (int)it.cv == cv && it.n_nodes > 0)
                         g.push_back(&it);
                 if (g.empty()) continue;
+                if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, cv), tune))) return st;
                 if (prec == PDD_FP32) {
                     if (dim == 2)
                         st = cv ? run_group<float, 2, true>(ctx, g, tune, timed, s) : run_group<float, 2, false>(ctx, g, tune, timed, s);
@@ -885,15 +897,140 @@ pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n)
     return PDD_OK;
 }
 
-pdd_status pdd_autotune(pdd_problem *problem, const double *nodes, int64_t n_nodes,
-                        const pdd_solve_opts *opts, pdd_tuning *out)
+pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out)
 {
-    (void)problem;
-    (void)nodes;
-    (void)n_nodes;
-    (void)opts;
-    (void)out;
-    return fail(PDD_E_UNSUPPORTED, "autotuning is not available yet");
+    if (!ctx || !item || !out || !item->problem || !item->opts) return fail(PDD_E_INVALID, "NULL argument");
+    if (item->problem->ctx != ctx) return fail(PDD_E_INVALID, "problem belongs to another context");
+    if (item->n_nodes < 1 || !item->nodes) return fail(PDD_E_INVALID, "autotuning needs nodes");
+    if ((item->u_prev == nullptr) != (item->resid == nullptr))
+        return fail(PDD_E_INVALID, "correction needs u_prev and residual grids");
+    const int dim = item->problem->desc.dim;
+    const bool cv = item->u_prev != nullptr;
+    const int prec = item->opts->precision;
+    if (prec != PDD_FP32 && prec != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
+    HIP_TRY(hipSetDevice(ctx->device));
+    // the kernel this group launches for a single item, and its occupancy
+    const void *fn = nullptr;
+    if (prec == PDD_FP32)
+        fn = dim == 2 ? (cv ? path_kernel_symbol<float, 2, true>(true) : path_kernel_symbol<float, 2, false>(true))
+                      : (cv ? path_kernel_symbol<float, 3, true>(true) : path_kernel_symbol<float, 3, false>(true));
+    else
+        fn = dim == 2 ? (cv ? path_kernel_symbol<double, 2, true>(true) : path_kernel_symbol<double, 2, false>(true))
+                      : (cv ? path_kernel_symbol<double, 3, true>(true) : path_kernel_symbol<double, 3, false>(true));
+    const int occ256 = occupancy(ctx, fn, 256);
+    // sample: up to 32 nodes spread over the item's, about 8 (then 16) paths
+    // per resident lane of the default shape
+    const int64_t ns = std::min<int64_t>(32, item->n_nodes);
+    const uint64_t lanes = (uint64_t)ctx->n_cu * occ256 * 256;
+    std::vector<double> nodes((size_t)ns * dim);
+    for (int64_t i = 0; i < ns; ++i) {
+        const int64_t src = i * item->n_nodes / ns;
+        std::memcpy(&nodes[(size_t)i * dim], item->nodes + src * dim, dim * sizeof(double));
+    }
+    pdd_solve_opts o = *item->opts;
+    o.n_paths = std::max<uint64_t>(64, (8 * lanes + ns - 1) / ns);
+    o.n_paths_per_node = nullptr;
+    o.path_offset = 0;
+    o.flags &= PDD_PLAIN_ALONGSIDE;
+    o.rec_phi = o.rec_e = nullptr;
+    o.rec_steps = nullptr;
+    pdd_tuning cand{};
+    o.tuning = &cand;
+    pdd_node_stats *dev = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pdd_status st = PDD_OK;
+    auto cleanup = [&] {
+        if (s) (void)hipStreamSynchronize(s);
+        if (dev) (void)hipFree(dev);
+        if (s) (void)hipStreamDestroy(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&dev, (size_t)ns * sizeof(pdd_node_stats)) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(PDD_E_HIP, "autotune could not allocate its sample");
+    }
+    const uint64_t base_paths = o.n_paths;
+    auto time_one = [&](const pdd_tuning &t, uint64_t paths, float &ms) -> pdd_status {
+        cand = t;
+        o.n_paths = paths;
+        std::vector<HostItem> items(1);
+        items[0].prob = item->problem;
+        items[0].u_prev = item->u_prev;
+        items[0].resid = item->resid;
+        items[0].nodes = nodes.data();
+        items[0].n_nodes = ns;
+        items[0].o = &o;
+        items[0].out = dev;
+        HIP_TRY(hipEventRecord(e0, s));
+        pdd_status r = run_items(ctx, items, s);
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        return PDD_OK;
+    };
+    float ms = 0.f;
+    const pdd_tuning dflt{256, occ256, 64, 0};
+    st = time_one(dflt, 2 * base_paths, ms);  // warm-up (code load, scratch growth)
+    // candidates: every block size and grab at full occupancy, and the
+    // default block with fewer workgroups per CU
+    std::vector<pdd_tuning> cands{dflt};
+    for (int block : {64, 128, 256}) {
+        const int occ = occupancy(ctx, fn, block);
+        for (int grab : {16, 64, 256})
+            if (!(block == 256 && grab == 64)) cands.push_back(pdd_tuning{block, occ, grab, 0});
+    }
+    if (occ256 * 3 / 4 >= 1 && occ256 * 3 / 4 != occ256) cands.push_back(pdd_tuning{256, occ256 * 3 / 4, 64, 0});
+    if (occ256 / 2 >= 1 && occ256 / 2 != occ256 * 3 / 4) cands.push_back(pdd_tuning{256, occ256 / 2, 64, 0});
+    pdd_tuning best = dflt;
+    float best_ms = 1e30f;
+    // the cost of a shape is the marginal time of the second P paths, t(2P) -
+    // t(P): it cancels the fixed costs and the exit-time tail, which a whole
+    // short run would weigh far more than a real solve does
+    for (size_t c = 0; c < cands.size() && !st; ++c) {
+        float t1 = 1e30f, t2 = 1e30f;
+        for (int rep = 0; rep < 2 && !st; ++rep) {
+            st = time_one(cands[c], base_paths, ms);
+            t1 = std::min(t1, ms);
+            if (!st) st = time_one(cands[c], 2 * base_paths, ms);
+            t2 = std::min(t2, ms);
+        }
+        const float m = t2 - t1;
+        // the default stands unless a shape is more than 2% faster
+        if (!st && (c == 0 || m < 0.98f * best_ms)) {
+            best_ms = m;
+            best = cands[c];
+        }
+    }
+    cleanup();
+    if (st) return st;
+    ctx->tuned[tuning_key(prec, dim, cv)] = best;
+    *out = best;
+    return PDD_OK;
+}
+
+pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tuning *t)
+{
+    if (!ctx || !key) return fail(PDD_E_INVALID, "NULL argument");
+    if ((key->precision != PDD_FP32 && key->precision != PDD_FP64) || key->dim < 2 || key->dim > 3 ||
+        (key->correction != 0 && key->correction != 1))
+        return fail(PDD_E_INVALID, "bad tuning key");
+    const int k = tuning_key(key->precision, key->dim, key->correction != 0);
+    if (!t) {
+        ctx->tuned.erase(k);
+        return PDD_OK;
+    }
+    pdd_tuning v = *t;
+    if (!v.block) v.block = 256;
+    if (!v.grab) v.grab = 64;
+    pdd_status st = check_tuning(v);
+    if (st) return st;
+    ctx->tuned[k] = v;
+    return PDD_OK;
 }
 
 }  // extern "C"

@@ -88,6 +88,11 @@ STATS_DTYPE = np.dtype([("n", "<i8"), ("n_capped", "<i8"), ("steps_sum", "<i8"),
                         ("rho", "<f8"), ("vr", "<f8"), ("vr_opt", "<f8"), ("sums", "<f8", (10,))])
 assert STATS_DTYPE.itemsize == C.sizeof(NodeStats)
 
+class TuningKey(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("dim", C.c_int32), ("correction", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("memory_budget", C.c_uint64), ("max_inflight", C.c_int32), ("max_queued", C.c_int32),
                 ("n_pilot", C.c_uint64), ("n_max", C.c_uint64), ("chunk_paths", C.c_uint64),
@@ -128,8 +133,8 @@ SIGNATURES = {
                                          C.POINTER(C.c_double), C.c_int64, C.POINTER(SolveOpts),
                                          C.c_void_p, C.c_void_p]),
     "pdd_solve_batch": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32, C.c_void_p]),
-    "pdd_autotune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
-                                 C.POINTER(SolveOpts), C.POINTER(Tuning)]),
+    "pdd_autotune": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.POINTER(Tuning)]),
+    "pdd_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(TuningKey), C.POINTER(Tuning)]),
     "pdd_kernel_times": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                      C.POINTER(C.c_int32)]),
     "pdd_plan_paths": (C.c_int32, [C.c_void_p, C.c_int64, C.c_double, C.c_uint64,
@@ -451,13 +456,20 @@ def kernel_times(ctx: Context, cap=4096):
     return [buf[i] for i in range(n.value)]
 
 
-def autotune(problem: Problem, nodes, **opt):
-    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
-    o = make_opts(**opt)
+def autotune(ctx: Context, item: dict):
+    """pdd_autotune on a batch-style item dict; returns (block, blocks_per_cu, grab), which
+    the context also keeps for later solves of the same key."""
+    b = Batch([dict(item, out=item.get("out", alloc_stats(0)))])
     t = Tuning()
-    _check(lib().pdd_autotune(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)),
-                              len(nodes), C.byref(o), C.byref(t)))
+    _check(lib().pdd_autotune(ctx.handle, b.arr, C.byref(t)))
     return (t.block, t.blocks_per_cu, t.grab)
+
+
+def set_tuning(ctx: Context, precision: str, dim: int, correction: bool, tuning=None):
+    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key, or None to remove it."""
+    k = TuningKey(PRECISIONS[precision], int(dim), 1 if correction else 0, 0)
+    t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]), 0)
+    _check(lib().pdd_set_tuning(ctx.handle, C.byref(k), C.byref(t) if t is not None else None))
 
 
 class Server:

@@ -1,0 +1,123 @@
+"""Launch-shape cache of the autotuner (pdd_autotune).
+
+A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction>" to
+[block, blocks_per_cu, grab]. `load` installs the entries of the running
+GPU's architecture in a context (pdd_set_tuning), so solves without an
+explicit tuning use them; `tune` runs pdd_autotune on an item and records
+the winner. Shapes change only speed, never results.
+
+    python -m paper_1512_02818_amd.tuning   # tunes the standard workloads, writes the cache
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import pdd
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "tuning_cache.json")
+
+
+def key(arch: str, precision: str, dim: int, correction: bool) -> str:
+    return f"{arch}/{precision}/D{int(dim)}/{'correction' if correction else 'plain'}"
+
+
+def parse_key(k: str):
+    arch, prec, d, est = k.split("/")
+    if prec not in pdd.PRECISIONS or not d.startswith("D") or est not in ("plain", "correction"):
+        raise ValueError(f"bad tuning key {k!r}")
+    return arch, prec, int(d[1:]), est == "correction"
+
+
+def read(path: str = DEFAULT_PATH) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    for k, v in data.items():
+        parse_key(k)
+        if len(v) != 3:
+            raise ValueError(f"bad shape for {k}: {v}")
+    return data
+
+
+def save_entry(path: str, k: str, shape) -> dict:
+    """Adds or replaces one entry; writes the file atomically."""
+    parse_key(k)
+    data = read(path)
+    data[k] = [int(v) for v in shape]
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(dict(sorted(data.items())), f, indent=1)
+        f.write("\n")
+    os.replace(tmp, path)
+    return data
+
+
+def arch_name(device: int = 0) -> str:
+    import torch
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+
+
+def load(ctx: pdd.Context, path: str = DEFAULT_PATH, arch: str | None = None) -> int:
+    """Installs the cached shapes of this architecture; returns how many."""
+    arch = arch or arch_name()
+    n = 0
+    for k, shape in read(path).items():
+        a, prec, dim, cv = parse_key(k)
+        if a == arch:
+            pdd.set_tuning(ctx, prec, dim, cv, shape)
+            n += 1
+    return n
+
+
+def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: str | None = None):
+    """pdd_autotune on `item` (batch-style dict); records the winner under its key."""
+    shape = pdd.autotune(ctx, item)
+    if path:
+        prob = item["problem"]
+        prec = item["opts"].get("precision", "fp32")
+        save_entry(path, key(arch or arch_name(), prec, prob.dim, item.get("u_prev") is not None), shape)
+    return shape
+
+
+def main():
+    import argparse
+
+    import numpy as np
+    import torch
+
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description="tunes the standard workloads, writes the cache")
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    args = ap.parse_args()
+    ctx = pdd.Context(0)
+    sq = W.big_square_problem(seed=0)
+    unit = W.unit_square_problem(seed=0)
+    rng = np.random.default_rng(4)
+    cube = W.random_problem(rng, dim=3)
+    probs = {"sq": pdd.Problem(ctx, sq), "unit": pdd.Problem(ctx, unit), "cube": pdd.Problem(ctx, cube)}
+    cube_nodes = W.face_nodes(rng, cube, 64)
+    for prec in ("fp32", "fp64"):
+        dt = np.float32 if prec == "fp32" else np.float64
+        items = [{"problem": probs["sq"], "nodes": W.big_square_nodes(), "opts": dict(dt=1e-4, precision=prec)},
+                 {"problem": probs["cube"], "nodes": cube_nodes, "opts": dict(dt=1e-3, precision=prec)}]
+        gu, gr, _ = W.correction_grids(unit, n=257, seed=1, dtype=dt)
+        items.append({"problem": probs["unit"], "nodes": W.unit_square_nodes(), "opts": dict(dt=1e-3, precision=prec),
+                      "u_prev": gu, "u_prev_t": torch.as_tensor(gu["data"]).cuda().contiguous(),
+                      "resid": gr, "resid_t": torch.as_tensor(gr["data"]).cuda().contiguous()})
+        gu3, gr3, _ = W.correction_grids(cube, n=65, seed=1, dtype=dt)
+        items.append({"problem": probs["cube"], "nodes": cube_nodes, "opts": dict(dt=1e-3, precision=prec),
+                      "u_prev": gu3, "u_prev_t": torch.as_tensor(gu3["data"]).cuda().contiguous(),
+                      "resid": gr3, "resid_t": torch.as_tensor(gr3["data"]).cuda().contiguous()})
+        for it in items:
+            shape = tune(ctx, it, path=args.out)
+            print(prec, it["problem"].dim, "correction" if "u_prev" in it else "plain", shape, flush=True)
+    for p in probs.values():
+        p.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

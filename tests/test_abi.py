@@ -33,7 +33,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(built_lib):
     names = declared_functions()
-    assert len(names) == 17, names
+    assert len(names) == 18, names
     for n in names:
         assert hasattr(built_lib, n), n
     assert set(names) == set(pdd.SIGNATURES)
@@ -62,6 +62,8 @@ def test_null_arguments_are_rejected_without_gpu(built_lib):
     assert built_lib.pdd_server_poll(None, None, 0, None, 0) == -1
     assert built_lib.pdd_server_report_get(None, None) == -1
     built_lib.pdd_server_destroy(None)
+    assert built_lib.pdd_autotune(None, None, None) == -1
+    assert built_lib.pdd_set_tuning(None, None, None) == -1
 
 
 STRUCTS = {
@@ -73,6 +75,7 @@ STRUCTS = {
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),
     "pdd_node_stats": (pdd.NodeStats, ["mean", "stderr_", "vr_opt", "sums"]),
     "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out"]),
+    "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction"]),
     "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",
                                   "user_tag"]),
