@@ -89,6 +89,10 @@ def parse():
     ap.add_argument("--tuning", default="cache",
                     help="launch shape block,blocks_per_cu,grab of the path kernel, 'cache' (the "
                          "autotuner's cached shape for this GPU, else the default) or 'default'")
+    ap.add_argument("--cv-iterates", type=int, default=1,
+                    help="1: report the correction iterates 10^3 -> 10^5 (0 = skip)")
+    ap.add_argument("--batch-scale", type=float, default=0.1,
+                    help="path-count scale of the 64-problem batched solve (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -203,6 +207,79 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
             "ratio_cv_fp32_over_plain_fp64": res["cv"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"]}
 
 
+def cv_iteration(ctx):
+    """The correction estimator on the unit-square problem with u_prev = U + p
+    on a 257^2 FP32 grid and its residual: iterates of 10^3, 10^4 and 10^5
+    paths per node (RNG stream = iterate, u_prev fixed), FP32, with the plain
+    score alongside for the variance reduction V[phi]/V[e] and rho."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    pd = W.unit_square_problem(seed=SEED)
+    nodes = W.unit_square_nodes()
+    exact = W.manufactured_u(pd, nodes)
+    prob = pdd.Problem(ctx, pd)
+    gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    out = []
+    for it, n in enumerate((1_000, 10_000, 100_000)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = pdd.stats_to_numpy(pdd.solve_correction(prob, gu, tu, gr, tr, nodes, dt=1e-3, n_paths=n,
+                                                     stream_id=it, precision="fp32", plain_alongside=True))
+        wall = time.perf_counter() - t0
+        out.append({"iterate": it, "paths_per_node": n, "mean_vr": float(np.mean(st["vr"])),
+                    "min_vr": float(np.min(st["vr"])), "mean_abs_rho": float(np.mean(np.abs(st["rho"]))),
+                    "rms_error": float(np.sqrt(np.mean((st["mean"] - exact) ** 2))),
+                    "rms_error_plain": float(np.sqrt(np.mean((st["mean_plain"] - exact) ** 2))),
+                    "mean_stderr": float(np.mean(st["stderr"])), "wall_s": wall})
+    prob.close()
+    return {"workload": "unit square, 18 nodes, dt=1e-3, u_prev = u + 32-mode Fourier perturbation "
+                        "(amplitude 1e-2) on 257^2 with its residual, FP32", "iterates": out}
+
+
+def batch_solve(ctx, scale):
+    """64 random 2D/3D box problems (uneven node counts, paths per node and
+    exit times; dt 1e-3 or 1e-4) in one pdd_solve_batch, FP32."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    wl = W.batch_workload(seed=4, n_problems=64, scale=scale)
+    probs = [pdd.Problem(ctx, w["problem"]) for w in wl]
+    items = [{"problem": p, "nodes": w["nodes"], "opts": dict(dt=w["dt"], n_paths=w["n_paths"], precision="fp32",
+                                                               stream_id=q, time_kernel=True)}
+             for q, (p, w) in enumerate(zip(probs, wl))]
+    batch = pdd.Batch(items)
+    pdd.kernel_times(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pdd.solve_batch(ctx, batch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = pdd.kernel_times(ctx)
+    st = [pdd.stats_to_numpy(o) for o in batch.outs]
+    steps = int(sum(int(s["steps_sum"].sum()) for s in st))
+    paths = int(sum(int(s["n"].sum()) for s in st))
+    exact_err = []
+    for w, s in zip(wl, st):
+        exact_err.append(np.abs(s["mean"] - W.manufactured_u(w["problem"], w["nodes"])) / s["stderr"])
+    z = np.concatenate(exact_err)
+    for p in probs:
+        p.close()
+    return {"workload": f"64 random 2D/3D boxes (seed 4), log-uniform 10-5,000 nodes and 10^3-10^6 paths per "
+                        f"node x {scale}, dt in {{1e-3, 1e-4}}, FP32, one pdd_solve_batch",
+            "scale": scale, "problems": len(wl), "dims": [int(w["problem"]["dim"]) for w in wl],
+            "nodes": int(sum(len(w["nodes"]) for w in wl)), "paths": paths, "path_steps": steps,
+            "wall_s": wall, "path_steps_per_s": steps / wall,
+            "path_kernel_ms": [float(k) for k in kern],
+            "median_abs_z_vs_exact": float(np.median(z))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -308,6 +385,14 @@ def main():
         print("node solves at fixed RMS error ...", file=sys.stderr, flush=True)
         result["node_solves_at_rms"] = node_solves_at_rms(ctx, args.rms_tol, args.rms_replicas_plain,
                                                           args.rms_replicas_cv)
+    if args.cv_iterates:
+        print("correction iterates ...", file=sys.stderr, flush=True)
+        result["cv_iteration"] = cv_iteration(ctx)
+    if args.batch_scale > 0:
+        print("batched solve ...", file=sys.stderr, flush=True)
+        result["batch"] = batch_solve(ctx, args.batch_scale)
+        print(f"batch: {result['batch']['path_steps']:.3e} path-steps in {result['batch']['wall_s']:.2f} s",
+              file=sys.stderr, flush=True)
     if args.serve_duration > 0:
         print("serving loop ...", file=sys.stderr, flush=True)
         from paper_1512_02818_amd import serving

@@ -230,9 +230,10 @@ __device__ __forceinline__ T dense_poly(const T *c, const T *x)
 // b(x), c(x) and, when asked, f(x) = F(x) + sum over trig terms T of
 // (1/2) sigma^2 Lap T + b.grad T + c T, where Lap T = -|k|^2 T and
 // d_d T = amp k_d cos(k_d x_d + ph_d) prod_{e != d} sin(k_e x_e + ph_e).
+// The dense coefficients of F come from `cf` (a copy of P.fdense in LDS).
 template <class T, int D>
 __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x, T *b, T &c,
-                                             T &f, bool want_f)
+                                             T &f, bool want_f, const T *cf)
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -248,7 +249,7 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
     if (!want_f) return;
     T acc = (T)0;
     if (P.f_mode == kPolyDense)
-        acc = dense_poly<T, D>(P.fdense, x);
+        acc = dense_poly<T, D>(cf, x);
     else if (P.f_mode == kPolySparse)
         acc = poly_value<T, D>(P.fpoly, P.n_f, x);
     for (int m = 0; m < P.n_trig; ++m) {
@@ -415,6 +416,7 @@ struct Walker {
     uint32_t bb_blk;
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
     KeySchedule ks;
+    const T *cf;          // dense source coefficients of the problem, in LDS
 
     // Starts path r (slot within the item) of item a. Returns false when it
     // ends before any step (a node inside the shift band of the shifted test).
@@ -491,7 +493,7 @@ struct Walker {
             if (D == 3) n[2 % D] = (wc >> 31) ? (T)1 : (T)-1;
         }
         T b[D], c, f = (T)0;
-        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0);
+        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0, cf);
         const T hY = a.h * Y;
         if (a.score_plain) Z -= (double)(hY * f);
         if (CV) R += (double)(hY * interp<T, D>(a.resid, X));
@@ -643,11 +645,13 @@ struct Pool {
     }
 };
 
-// One item, passed by value (FP32 2D plain solves): asked to fit seven waves
-// per SIMD, which it does in 72 registers.
+// One item, passed by value (FP32 2D plain solves). The source polynomial's
+// coefficients are staged through LDS once per workgroup: read from there,
+// they stay in vector registers for the whole loop (about 96 registers, five
+// waves per SIMD) instead of being reloaded by scalar loads at every step,
+// which the scalar register file cannot hold next to the other constants.
 template <class T, int D, bool CV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
-    path_kernel_one(const OneItemArgs<T> A)
+__global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 {
     static_assert(kOneItemKernel<T, D, CV>, "single-item kernel is for FP32 2D plain solves");
     const LaunchArgs &L = A.launch;
@@ -655,7 +659,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))
     const DevProblem<T> &P = A.prob;
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    __shared__ T s_cf[kMaxDense];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
+    __syncthreads();
     Walker<T, D, CV> w;
+    w.cf = s_cf;
     w.ks = key_schedule(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     Pool pool;
@@ -695,7 +703,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))
 
 // A batch: items and problems in device tables read at wave-uniform indices.
 // A wave walks the paths of one item at a time and moves to the next item
-// only once all its lanes are idle.
+// only once all its lanes are idle. Each wave keeps the source coefficients
+// of its current problem in its own LDS slot (written when it changes item;
+// a wave's LDS accesses complete in order, so no barrier is needed).
 template <class T, int D, bool CV>
 __global__ void __launch_bounds__(256)
     path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
@@ -703,7 +713,10 @@ __global__ void __launch_bounds__(256)
 {
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    __shared__ T s_cf[256 / 64][kMaxDense];
+    T *my_cf = s_cf[threadIdx.x >> 6];
     Walker<T, D, CV> w;
+    w.cf = my_cf;
     int st = 0;
     Pool pool;
     int cur = -1;          // item of the wave (wave-uniform)
@@ -725,6 +738,7 @@ __global__ void __launch_bounds__(256)
                 const uint64_t e = it.slot_begin + it.n_slots - L.slot_begin;
                 cur_end = e < (uint64_t)L.launch_slots ? (uint32_t)e : L.launch_slots;
                 w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
+                if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
             }
             if (cur >= 0 && pool.next < cur_end) {
                 const uint32_t avail = min(pool.end, cur_end) - pool.next;

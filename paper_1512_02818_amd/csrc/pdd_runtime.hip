@@ -18,7 +18,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/pdd.h"
+#include "pdd.h"
 #include "host_runtime.hpp"
 
 using namespace pdd;
@@ -546,7 +546,9 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     const int block = tune.block;
     const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
     const void *fn = path_kernel_symbol<T, D, CV>(one);
-    const int bpc = tune.blocks_per_cu > 0 ? tune.blocks_per_cu : occupancy(ctx, fn, block);
+    // more workgroups than fit at once only queue behind the resident ones
+    const int occ = occupancy(ctx, fn, block);
+    const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
     const ItemDesc<T> *d_items = reinterpret_cast<const ItemDesc<T> *>(dv + off_items);
     const DevProblem<T> *d_probs = reinterpret_cast<const DevProblem<T> *>(dv + off_probs);
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};

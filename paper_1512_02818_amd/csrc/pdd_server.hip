@@ -23,7 +23,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/pdd.h"
+#include "pdd.h"
 #include "host_runtime.hpp"
 
 using namespace pdd;

@@ -8,7 +8,7 @@
 // LDS, always in the same order, and added to the node's accumulator, which
 // only this workgroup touches during the launch. The result is therefore the
 // same whichever lanes walked which paths.
-#include "../../include/pdd.h"
+#include "pdd.h"
 #include "pdd_internal.hpp"
 
 namespace pdd {
