@@ -72,6 +72,8 @@ struct pdd_ctx {
     pdd::DeviceBuffer nodes, starts, acc, counters, rec;
     void *stage = nullptr;
     size_t stage_cap = 0;
+    void *readback = nullptr;  // pinned host copy of pilot statistics
+    size_t readback_cap = 0;
     std::map<std::tuple<const void *, int>, int> occupancy;
     // timing of path-kernel launches (PDD_TIME_KERNEL)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;

@@ -122,6 +122,27 @@ struct NodeAcc {
     int64_t n, steps, capped, pad;
 };
 
+// Per-item entry of the post-processing kernels of a group (nodes are
+// numbered across the group's items; node_item maps a node to its item).
+struct FinalItem {
+    pdd_node_stats *out;  // the item's statistics (device)
+    uint64_t gnode;       // first group node of the item
+    int32_t has_phi;      // phi is scored (plain solve or PDD_PLAIN_ALONGSIDE)
+    int32_t accumulate;   // start from the statistics already in `out`
+    int32_t own_reduce;   // caller records: reduced by a launch of its own
+    int32_t up_f64;
+    // u_prev for the node value u_prev(x0) + mean(e), read in its own dtype
+    const void *up_data;
+    int32_t up_n[3];
+    int32_t pad;
+    double up_lo[3], up_inv[3];
+};
+
+// One workgroup per node from node_lo on; node i covers slots
+// [node_start[i], node_start[i+1]) (or uniform_n each) clipped to
+// [slot_begin, slot_end); records of slot q sit at q - rec_base. With
+// node_item set, has_phi comes from the node's item and nodes whose item
+// reduces on its own are skipped.
 struct ReduceArgs {
     const double *rec_phi;
     const double *rec_e;
@@ -133,20 +154,18 @@ struct ReduceArgs {
     NodeAcc *acc;
     uint32_t node_lo;
     int32_t has_phi, has_e;
+    const uint32_t *node_item;
+    const FinalItem *fitems;
 };
 
 struct FinalizeArgs {
     const NodeAcc *acc;
-    const double *nodes;
-    void *out;  // pdd_node_stats
-    uint32_t n_nodes;
+    const double *nodes;  // group nodes, dim doubles each
+    uint32_t n_nodes;     // group nodes
     int32_t dim;
-    int32_t has_phi, has_e;
-    // u_prev for the node value u_prev(x0) + mean(e), read in its own dtype
-    const void *up_data;
-    int32_t up_f64;
-    int32_t up_n[3];
-    double up_lo[3], up_inv[3];
+    int32_t has_e;
+    const uint32_t *node_item;
+    const FinalItem *fitems;
 };
 
 // Kernel arguments of a launch that holds a single item: the item and its
@@ -176,6 +195,9 @@ const void *path_kernel_symbol(bool one);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
-hipError_t launch_load_acc(const pdd_node_stats *in, NodeAcc *acc, uint32_t n, hipStream_t s);
+// Starting sums of every group node: zero, or the statistics already in the
+// item's output for an accumulating solve.
+hipError_t launch_init_acc(NodeAcc *acc, uint32_t n, const uint32_t *node_item, const FinalItem *fitems,
+                           hipStream_t s);
 
 }  // namespace pdd

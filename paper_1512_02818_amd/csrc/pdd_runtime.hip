@@ -450,13 +450,16 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
     const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
 
-    // staged upload: nodes | global node starts | item node starts | items | problems
+    // staged upload: nodes | global node starts | item node starts | items |
+    // problems | node -> item | per-item post-processing entries
     const size_t off_nodes = 0;
     const size_t off_gstart = align_up(off_nodes + n_nodes_all * D * sizeof(double), 256);
     const size_t off_istart = align_up(off_gstart + (n_nodes_all + 1) * sizeof(uint64_t), 256);
     const size_t off_items = align_up(off_istart + n_starts * sizeof(uint64_t), 256);
     const size_t off_probs = align_up(off_items + n_items * sizeof(ItemDesc<T>), 256);
-    const size_t bytes = align_up(off_probs + probs.size() * sizeof(DevProblem<T>), 256);
+    const size_t off_nitem = align_up(off_probs + probs.size() * sizeof(DevProblem<T>), 256);
+    const size_t off_fitems = align_up(off_nitem + n_nodes_all * sizeof(uint32_t), 256);
+    const size_t bytes = align_up(off_fitems + n_items * sizeof(FinalItem), 256);
 
     pdd_status st;
     if ((st = ensure(ctx, ctx->nodes, bytes))) return st;
@@ -480,14 +483,34 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     uint64_t *h_istart = reinterpret_cast<uint64_t *>(h + off_istart);
     ItemDesc<T> *h_items = reinterpret_cast<ItemDesc<T> *>(h + off_items);
     DevProblem<T> *h_probs = reinterpret_cast<DevProblem<T> *>(h + off_probs);
+    uint32_t *h_nitem = reinterpret_cast<uint32_t *>(h + off_nitem);
+    FinalItem *h_fitems = reinterpret_cast<FinalItem *>(h + off_fitems);
     std::memset(h_items, 0, n_items * sizeof(ItemDesc<T>));
+    std::memset(h_fitems, 0, n_items * sizeof(FinalItem));
     size_t istart_used = 0;
     for (int q = 0; q < n_items; ++q) {
         HostItem &it = *items[q];
         const pdd_solve_opts *o = it.o;
         std::memcpy(h + off_nodes + gnode[q] * D * sizeof(double), it.nodes, it.n_nodes * D * sizeof(double));
-        for (int64_t i = 0; i < it.n_nodes; ++i)
+        for (int64_t i = 0; i < it.n_nodes; ++i) {
             h_gstart[gnode[q] + i] = slot_begin[q] + (it.uniform ? (uint64_t)i * o->n_paths : it.starts[i]);
+            h_nitem[gnode[q] + i] = (uint32_t)q;
+        }
+        FinalItem &fi = h_fitems[q];
+        fi.out = it.out;
+        fi.gnode = gnode[q];
+        fi.has_phi = it.score_plain ? 1 : 0;
+        fi.accumulate = it.accumulate ? 1 : 0;
+        fi.own_reduce = it.caller_records ? 1 : 0;
+        if (CV) {
+            fi.up_data = it.u_prev->data;
+            fi.up_f64 = it.u_prev->dtype == PDD_DTYPE_F64;
+            for (int i = 0; i < 3; ++i) {
+                fi.up_n[i] = i < D ? it.u_prev->n[i] : 1;
+                fi.up_lo[i] = it.u_prev->lo[i];
+                fi.up_inv[i] = i < D ? (double)(it.u_prev->n[i] - 1) / (it.u_prev->hi[i] - it.u_prev->lo[i]) : 0.0;
+            }
+        }
         ItemDesc<T> &a = h_items[q];
         a.prob = prob_of[q];
         a.exit_mode = o->exit_mode;
@@ -536,11 +559,11 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     HIP_TRY(hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->staged, s));
     ctx->any_staged = true;
-    HIP_TRY(launch_zero(ctx->acc.ptr, n_nodes_all * sizeof(NodeAcc), s));
-    for (int q = 0; q < n_items; ++q)  // earlier paths' sums are the starting point
-        if (items[q]->accumulate)
-            HIP_TRY(launch_load_acc(items[q]->out, static_cast<NodeAcc *>(ctx->acc.ptr) + gnode[q],
-                                    (uint32_t)items[q]->n_nodes, s));
+    const uint32_t *d_nitem = reinterpret_cast<const uint32_t *>(dv + off_nitem);
+    const FinalItem *d_fitems = reinterpret_cast<const FinalItem *>(dv + off_fitems);
+    NodeAcc *d_acc = static_cast<NodeAcc *>(ctx->acc.ptr);
+    // zero sums, or the earlier paths' sums of accumulating items
+    HIP_TRY(launch_init_acc(d_acc, (uint32_t)n_nodes_all, d_nitem, d_fitems, s));
     HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
 
     const int block = tune.block;
@@ -587,9 +610,31 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, s)));
         }
         if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
-        // per-item reduction of the nodes this launch touched
+        // reduction of the nodes this launch touched: one launch for the items
+        // whose records are in the scratch, one per item with caller records
+        const uint64_t *d_gstart = reinterpret_cast<const uint64_t *>(dv + off_gstart);
+        if (any_scratch) {
+            const uint32_t n_lo = (uint32_t)(std::upper_bound(h_gstart, h_gstart + n_nodes_all + 1, b) - h_gstart - 1);
+            const uint32_t n_hi =
+                (uint32_t)(std::upper_bound(h_gstart, h_gstart + n_nodes_all + 1, b + len - 1) - h_gstart - 1);
+            ReduceArgs r{};
+            r.rec_phi = sc_phi;
+            r.rec_e = sc_e;
+            r.rec_steps = sc_steps;
+            r.rec_base = b;
+            r.node_start = d_gstart;
+            r.slot_begin = b;
+            r.slot_end = b + len;
+            r.acc = d_acc;
+            r.node_lo = n_lo;
+            r.has_e = CV;
+            r.node_item = d_nitem;
+            r.fitems = d_fitems;
+            HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
+        }
         for (int q = 0; q < n_items; ++q) {
             HostItem &it = *items[q];
+            if (!it.caller_records) continue;
             const uint64_t lo = std::max(b, slot_begin[q]);
             const uint64_t hi = std::min(b + len, slot_begin[q] + it.total);
             if (lo >= hi) continue;
@@ -597,14 +642,14 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             const uint32_t n_lo = (uint32_t)(std::upper_bound(gs, gs + it.n_nodes + 1, lo) - gs - 1);
             const uint32_t n_hi = (uint32_t)(std::upper_bound(gs, gs + it.n_nodes + 1, hi - 1) - gs - 1);
             ReduceArgs r{};
-            r.rec_phi = it.caller_records ? it.o->rec_phi : sc_phi;
-            r.rec_e = it.caller_records ? it.o->rec_e : sc_e;
-            r.rec_steps = it.caller_records ? it.o->rec_steps : sc_steps;
-            r.rec_base = it.caller_records ? slot_begin[q] : b;
-            r.node_start = reinterpret_cast<const uint64_t *>(dv + off_gstart) + gnode[q];
+            r.rec_phi = it.o->rec_phi;
+            r.rec_e = it.o->rec_e;
+            r.rec_steps = it.o->rec_steps;
+            r.rec_base = slot_begin[q];
+            r.node_start = d_gstart + gnode[q];
             r.slot_begin = lo;
             r.slot_end = hi;
-            r.acc = static_cast<NodeAcc *>(ctx->acc.ptr) + gnode[q];
+            r.acc = d_acc + gnode[q];
             r.node_lo = n_lo;
             r.has_phi = it.score_plain;
             r.has_e = CV;
@@ -612,28 +657,15 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         }
     }
     if (timed && total) ctx->timed.push_back(ev);
-    for (int q = 0; q < n_items; ++q) {
-        HostItem &it = *items[q];
-        if (it.n_nodes == 0) continue;
-        FinalizeArgs f{};
-        f.acc = static_cast<const NodeAcc *>(ctx->acc.ptr) + gnode[q];
-        f.nodes = reinterpret_cast<const double *>(dv + off_nodes + gnode[q] * D * sizeof(double));
-        f.out = it.out;
-        f.n_nodes = (uint32_t)it.n_nodes;
-        f.dim = D;
-        f.has_phi = it.score_plain;
-        f.has_e = CV;
-        if (CV) {
-            f.up_data = it.u_prev->data;
-            f.up_f64 = it.u_prev->dtype == PDD_DTYPE_F64;
-            for (int i = 0; i < 3; ++i) {
-                f.up_n[i] = i < D ? it.u_prev->n[i] : 1;
-                f.up_lo[i] = it.u_prev->lo[i];
-                f.up_inv[i] = i < D ? (double)(it.u_prev->n[i] - 1) / (it.u_prev->hi[i] - it.u_prev->lo[i]) : 0.0;
-            }
-        }
-        HIP_TRY(launch_finalize(f, s));
-    }
+    FinalizeArgs f{};
+    f.acc = d_acc;
+    f.nodes = reinterpret_cast<const double *>(dv + off_nodes);
+    f.n_nodes = (uint32_t)n_nodes_all;
+    f.dim = D;
+    f.has_e = CV;
+    f.node_item = d_nitem;
+    f.fitems = d_fitems;
+    HIP_TRY(launch_finalize(f, s));
     return PDD_OK;
 }
 
@@ -721,6 +753,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->readback) (void)hipHostFree(ctx->readback);
     (void)hipEventDestroy(ctx->done);
     (void)hipEventDestroy(ctx->staged);
     for (auto *v : {&ctx->timed, &ctx->spare})
@@ -854,32 +887,61 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int
     }
     pdd_status st = run_items(ctx, items, s);  // pilot
     if (st) return st;
+    // all pilot statistics back in one batch of copies into pinned memory
+    size_t total_nodes = 0;
+    for (int32_t q = 0; q < n_items; ++q) total_nodes += (size_t)std::max<int64_t>(0, witems[q].n_nodes);
+    const size_t rb_bytes = std::max<size_t>(total_nodes, 1) * sizeof(pdd_node_stats);
+    if (rb_bytes > ctx->readback_cap) {
+        if (ctx->readback) HIP_TRY(hipHostFree(ctx->readback));
+        ctx->readback = nullptr;
+        ctx->readback_cap = 0;
+        if (hipHostMalloc(&ctx->readback, rb_bytes, hipHostMallocDefault) != hipSuccess) {
+            ctx->readback = nullptr;
+            return fail(PDD_E_NOMEM, "pinned allocation of %zu bytes failed", rb_bytes);
+        }
+        ctx->readback_cap = rb_bytes;
+    }
+    pdd_node_stats *pilot = static_cast<pdd_node_stats *>(ctx->readback);
+    std::vector<size_t> at(n_items, 0);
+    size_t used = 0;
+    for (int32_t q = 0; q < n_items; ++q) {
+        const int64_t n = witems[q].n_nodes;
+        at[q] = used;
+        if (n <= 0) continue;
+        HIP_TRY(hipMemcpyAsync(pilot + used, witems[q].out, n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost, s));
+        used += (size_t)n;
+    }
     HIP_TRY(hipStreamSynchronize(s));
+    // plan; items whose pilot already meets the target are done
     std::vector<std::vector<uint64_t>> counts(n_items);
-    std::vector<pdd_node_stats> pilot;
+    std::vector<HostItem> cont;
+    cont.reserve(n_items);
     for (int32_t q = 0; q < n_items; ++q) {
         const int64_t n = witems[q].n_nodes;
         if (n <= 0) continue;
-        pilot.resize(n);
-        HIP_TRY(hipMemcpy(pilot.data(), witems[q].out, n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost));
         counts[q].resize(n);
-        if ((st = pdd_plan_paths(pilot.data(), n, target_se[q], n_max, counts[q].data()))) return st;
-        for (auto &c : counts[q]) c -= n_pilot;
+        if ((st = pdd_plan_paths(pilot + at[q], n, target_se[q], n_max, counts[q].data()))) return st;
+        bool more = false;
+        for (auto &c : counts[q]) {
+            c -= n_pilot;
+            more |= c > 0;
+        }
+        if (!more) continue;
         opts[q].n_paths_per_node = counts[q].data();
         opts[q].path_offset += n_pilot;
         opts[q].flags |= PDD_ACCUMULATE;
+        HostItem it;
+        it.prob = witems[q].problem;
+        it.u_prev = witems[q].u_prev;
+        it.resid = witems[q].resid;
+        it.nodes = witems[q].nodes;
+        it.n_nodes = n;
+        it.o = &opts[q];
+        it.out = witems[q].out;
+        cont.push_back(std::move(it));
     }
-    for (int32_t q = 0; q < n_items; ++q) {
-        items[q] = HostItem{};
-        items[q].prob = witems[q].problem;
-        items[q].u_prev = witems[q].u_prev;
-        items[q].resid = witems[q].resid;
-        items[q].nodes = witems[q].nodes;
-        items[q].n_nodes = witems[q].n_nodes;
-        items[q].o = &opts[q];
-        items[q].out = witems[q].out;
-    }
-    return run_items(ctx, items, s);  // continuation
+    if (cont.empty()) return PDD_OK;
+    return run_items(ctx, cont, s);  // continuation
 }
 
 pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n)

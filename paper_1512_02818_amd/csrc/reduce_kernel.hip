@@ -41,6 +41,12 @@ constexpr int kReduceBlock = 256;
 __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r)
 {
     const uint32_t node = r.node_lo + blockIdx.x;
+    int32_t has_phi = r.has_phi;
+    if (r.node_item) {
+        const FinalItem &fi = r.fitems[r.node_item[node]];
+        if (fi.own_reduce) return;  // whole workgroup: the item is uniform per node
+        has_phi = fi.has_phi;
+    }
     uint64_t ns, ne;
     if (r.node_start) {
         ns = r.node_start[node];
@@ -60,7 +66,7 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
         steps += sw & ~kCappedBit;
         capped += sw >> 31;
         double phi = 0.0, e = 0.0;
-        if (r.has_phi) {
+        if (has_phi) {
             phi = r.rec_phi[i];
             nadd(acc[0], phi);
             nadd(acc[1], phi * phi);
@@ -69,7 +75,7 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
             e = r.rec_e[i];
             nadd(acc[2], e);
             nadd(acc[3], e * e);
-            if (r.has_phi) nadd(acc[4], phi * e);
+            if (has_phi) nadd(acc[4], phi * e);
         }
     }
     // butterfly across the 64 lanes of the wave
@@ -117,13 +123,13 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
     }
 }
 
-__device__ __forceinline__ double grid_at(const FinalizeArgs &f, size_t i)
+__device__ __forceinline__ double grid_at(const FinalItem &f, size_t i)
 {
     return f.up_f64 ? static_cast<const double *>(f.up_data)[i]
                     : (double)static_cast<const float *>(f.up_data)[i];
 }
 
-__device__ double interp_node(const FinalizeArgs &g, int dim, const double *x)
+__device__ double interp_node(const FinalItem &g, int dim, const double *x)
 {
     int i[3] = {0, 0, 0};
     double w[3] = {0, 0, 0};
@@ -162,6 +168,8 @@ __global__ void finalize_kernel(const FinalizeArgs f)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= f.n_nodes) return;
     const NodeAcc &A = f.acc[i];
+    const FinalItem &fi = f.fitems[f.node_item[i]];
+    const bool has_phi = fi.has_phi != 0;
     pdd_node_stats st;
     const double nan = __builtin_nan("");
     st.n = A.n;
@@ -178,7 +186,7 @@ __global__ void finalize_kernel(const FinalizeArgs f)
         const double Sp = A.s[0] + A.c[0], Sp2 = A.s[1] + A.c[1];
         const double Se = A.s[2] + A.c[2], Se2 = A.s[3] + A.c[3], Spe = A.s[4] + A.c[4];
         st.mean_steps = (double)A.steps / n;
-        if (f.has_phi) {
+        if (has_phi) {
             st.mean_plain = Sp / n;
             st.var_plain = A.n > 1 ? (Sp2 - Sp * Sp / n) / (n - 1.0) : nan;
         }
@@ -187,10 +195,10 @@ __global__ void finalize_kernel(const FinalizeArgs f)
             st.var = st.var_plain;
             st.stderr_ = sqrt(st.var / n);
         } else {
-            st.mean = interp_node(f, f.dim, f.nodes + (size_t)i * f.dim) + Se / n;
+            st.mean = interp_node(fi, f.dim, f.nodes + (size_t)i * f.dim) + Se / n;
             st.var = A.n > 1 ? (Se2 - Se * Se / n) / (n - 1.0) : nan;
             st.stderr_ = sqrt(st.var / n);
-            if (f.has_phi) {
+            if (has_phi) {
                 // xi = u_prev(x0) + e - phi is the pathwise control variate
                 const double cpe = A.n > 1 ? (Spe - Sp * Se / n) / (n - 1.0) : nan;
                 const double vxi = st.var + st.var_plain - 2.0 * cpe;
@@ -201,23 +209,30 @@ __global__ void finalize_kernel(const FinalizeArgs f)
             }
         }
     }
-    static_cast<pdd_node_stats *>(f.out)[i] = st;
+    fi.out[i - fi.gnode] = st;
 }
 
-// Starting sums of an accumulating solve: the statistics of earlier paths.
-__global__ void load_acc_kernel(const pdd_node_stats *in, NodeAcc *acc, uint32_t n)
+// Starting sums: zero, or for an accumulating solve the statistics of the
+// earlier paths.
+__global__ void init_acc_kernel(NodeAcc *acc, uint32_t n, const uint32_t *node_item, const FinalItem *fitems)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const pdd_node_stats &p = in[i];
+    const FinalItem &fi = fitems[node_item[i]];
     NodeAcc a;
-    for (int q = 0; q < 5; ++q) {
-        a.s[q] = p.sums[2 * q];
-        a.c[q] = p.sums[2 * q + 1];
+    if (fi.accumulate) {
+        const pdd_node_stats &p = fi.out[i - fi.gnode];
+        for (int q = 0; q < 5; ++q) {
+            a.s[q] = p.sums[2 * q];
+            a.c[q] = p.sums[2 * q + 1];
+        }
+        a.n = p.n;
+        a.steps = p.steps_sum;
+        a.capped = p.n_capped;
+    } else {
+        for (int q = 0; q < 5; ++q) a.s[q] = a.c[q] = 0.0;
+        a.n = a.steps = a.capped = 0;
     }
-    a.n = p.n;
-    a.steps = p.steps_sum;
-    a.capped = p.n_capped;
     a.pad = 0;
     acc[i] = a;
 }
@@ -245,10 +260,11 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_load_acc(const pdd_node_stats *in, NodeAcc *acc, uint32_t n, hipStream_t s)
+hipError_t launch_init_acc(NodeAcc *acc, uint32_t n, const uint32_t *node_item, const FinalItem *fitems,
+                           hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(load_acc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, acc, n);
+    hipLaunchKernelGGL(init_acc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n, node_item, fitems);
     return hipGetLastError();
 }
 
