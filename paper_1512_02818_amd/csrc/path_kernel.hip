@@ -558,24 +558,44 @@ struct Walker {
                                                 const T *Xn, T mn, uint32_t s)
     {
         if (P.domain == kBox) {
-            T Pe = (T)0, bestp = (T)-1;
-            int bestf = 0;
+            T arg[2 * D];
+            T amin = (T)0;
+            int fmin = -1, nlive = 0;
 #pragma unroll
             for (int q = 0; q < 2 * D; ++q) {
                 const int d = q >> 1;
                 const T prod = (q & 1) ? (P.hi[d] - X[d]) * (P.hi[d] - Xn[d])
                                        : (X[d] - P.lo[d]) * (Xn[d] - P.lo[d]);
-                const T arg = prod * a.two_over_s2h;
-                if (arg <= a.bridge_thresh) {
-                    const T p = Arith<T>::exp_neg(arg);
-                    Pe = madd(p, (T)1 - Pe, Pe);
-                    if (p > bestp) {
-                        bestp = p;
-                        bestf = q;
+                arg[q] = prod * a.two_over_s2h;
+                if (arg[q] <= a.bridge_thresh) {
+                    ++nlive;
+                    if (fmin < 0 || arg[q] < amin) {
+                        amin = arg[q];
+                        fmin = q;
                     }
                 }
             }
-            if (bestp >= (T)0 && bridge_uniform(a, s) < Pe) {
+            if (nlive == 0) return false;
+            // One live face (the usual case): P is its p and it is the exit
+            // face. Several (near a corner): combine them in face order.
+            T Pe = Arith<T>::exp_neg(amin);
+            int bestf = fmin;
+            if (nlive > 1) {
+                T bestp = (T)-1;
+                Pe = (T)0;
+#pragma unroll
+                for (int q = 0; q < 2 * D; ++q) {
+                    if (arg[q] <= a.bridge_thresh) {
+                        const T p = Arith<T>::exp_neg(arg[q]);
+                        Pe = madd(p, (T)1 - Pe, Pe);
+                        if (p > bestp) {
+                            bestp = p;
+                            bestf = q;
+                        }
+                    }
+                }
+            }
+            if (bridge_uniform(a, s) < Pe) {
 #pragma unroll
                 for (int d = 0; d < D; ++d)
                     Xt[d] = (bestf >> 1) == d ? ((bestf & 1) ? P.hi[d] : P.lo[d]) : Xn[d];
@@ -605,6 +625,15 @@ struct Walker {
         a.rec_steps[r] = k | (capped ? kCappedBit : 0u);
     }
 };
+
+// Lanes end paths at any step but take new ones only every kRefillPeriod
+// iterations of the walk loop (two steps per iteration in 2D, one in 3D), so
+// every path of a wave starts at a step count that is the same modulo 4
+// across its lanes: the bridge uniforms of four consecutive steps share one
+// Philox block, which the wave then draws at most once per four steps, and
+// the scoring and start of new paths run for several lanes at once.
+template <int D>
+constexpr uint32_t kRefillPeriod = D == 2 ? 2 : 4;
 
 // Item whose slot range holds group slot s (items are sorted, non-empty
 // ranges never overlap). Wave-uniform: a scalar binary search.
@@ -668,22 +697,24 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     Pool pool;
 
-    for (;;) {
-        if (st == 2) {
-            w.finish(a, P, a.rec_base);  // set per launch by the host
-            st = 0;
-        }
-        const uint64_t idle = __ballot(st == 0);
-        if (idle) {
-            pool.refill(L, lane);
-            const uint32_t avail = pool.end - pool.next;
-            const uint32_t rank = (uint32_t)__popcll(idle & below);
-            if (st == 0 && rank < avail) st = w.start(a, P, L.slot_begin + pool.next + rank) ? 1 : 2;  // the one item starts at slot 0
-            pool.next += min(avail, (uint32_t)__popcll(idle));
-        }
-        if (__ballot(st != 0) == 0) {
-            if (pool.exhausted) break;
-            continue;
+    for (uint32_t iter = 0;; ++iter) {
+        if ((iter & (kRefillPeriod<D> - 1)) == 0) {  // refill turn (wave-uniform)
+            if (st == 2) {
+                w.finish(a, P, a.rec_base);  // set per launch by the host
+                st = 0;
+            }
+            const uint64_t idle = __ballot(st == 0);
+            if (idle) {
+                pool.refill(L, lane);
+                const uint32_t avail = pool.end - pool.next;
+                const uint32_t rank = (uint32_t)__popcll(idle & below);
+                if (st == 0 && rank < avail) st = w.start(a, P, L.slot_begin + pool.next + rank) ? 1 : 2;  // the one item starts at slot 0
+                pool.next += min(avail, (uint32_t)__popcll(idle));
+            }
+            if (__ballot(st != 0) == 0) {
+                if (pool.exhausted) break;
+                continue;
+            }
         }
         if (st == 1) {
             // One Philox block feeds two steps in 2D (words 0,1 then 2,3), one in 3D.
@@ -722,36 +753,38 @@ __global__ void __launch_bounds__(256)
     int cur = -1;          // item of the wave (wave-uniform)
     uint32_t cur_end = 0;  // launch-relative end of its slots
 
-    for (;;) {
-        if (st == 2) {
-            const ItemDesc<T> &it = items[cur];
-            // scratch records sit at group slot - launch start (modular arithmetic)
-            w.finish(it, probs[it.prob], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
-            st = 0;
-        }
-        const uint64_t idle = __ballot(st == 0);
-        if (idle) {
-            pool.refill(L, lane);
-            if (pool.next < pool.end && (cur < 0 || pool.next >= cur_end) && idle == ~0ull) {
-                cur = __builtin_amdgcn_readfirstlane(find_item(items, L.n_items, L.slot_begin + pool.next));
+    for (uint32_t iter = 0;; ++iter) {
+        if ((iter & (kRefillPeriod<D> - 1)) == 0) {  // refill turn (wave-uniform)
+            if (st == 2) {
                 const ItemDesc<T> &it = items[cur];
-                const uint64_t e = it.slot_begin + it.n_slots - L.slot_begin;
-                cur_end = e < (uint64_t)L.launch_slots ? (uint32_t)e : L.launch_slots;
-                w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
-                if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
+                // scratch records sit at group slot - launch start (modular arithmetic)
+                w.finish(it, probs[it.prob], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
+                st = 0;
             }
-            if (cur >= 0 && pool.next < cur_end) {
-                const uint32_t avail = min(pool.end, cur_end) - pool.next;
-                const uint32_t rank = (uint32_t)__popcll(idle & below);
-                if (st == 0 && rank < avail)
-                    st = w.start(items[cur], probs[items[cur].prob],
-                                 L.slot_begin + pool.next + rank - items[cur].slot_begin) ? 1 : 2;
-                pool.next += min(avail, (uint32_t)__popcll(idle));
+            const uint64_t idle = __ballot(st == 0);
+            if (idle) {
+                pool.refill(L, lane);
+                if (pool.next < pool.end && (cur < 0 || pool.next >= cur_end) && idle == ~0ull) {
+                    cur = __builtin_amdgcn_readfirstlane(find_item(items, L.n_items, L.slot_begin + pool.next));
+                    const ItemDesc<T> &it = items[cur];
+                    const uint64_t e = it.slot_begin + it.n_slots - L.slot_begin;
+                    cur_end = e < (uint64_t)L.launch_slots ? (uint32_t)e : L.launch_slots;
+                    w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
+                    if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
+                }
+                if (cur >= 0 && pool.next < cur_end) {
+                    const uint32_t avail = min(pool.end, cur_end) - pool.next;
+                    const uint32_t rank = (uint32_t)__popcll(idle & below);
+                    if (st == 0 && rank < avail)
+                        st = w.start(items[cur], probs[items[cur].prob],
+                                     L.slot_begin + pool.next + rank - items[cur].slot_begin) ? 1 : 2;
+                    pool.next += min(avail, (uint32_t)__popcll(idle));
+                }
             }
-        }
-        if (__ballot(st != 0) == 0) {
-            if (pool.exhausted && pool.next == pool.end) break;
-            continue;
+            if (__ballot(st != 0) == 0) {
+                if (pool.exhausted && pool.next == pool.end) break;
+                continue;
+            }
         }
         if (st == 1) {
             const ItemDesc<T> &a = items[cur];
