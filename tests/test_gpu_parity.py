@@ -112,8 +112,7 @@ def test_unit_square_fp32_within_3se(ctx):
     print(f"fp32: max |mean32 - mean64| = {diff.max():.3e}, exit-step agreement {same.mean():.5f}")
 
 
-@pytest.mark.parametrize("case", ["ball2d_exit", "ball3d_exit", "ball3d_kill", "box3d"])
-def test_other_geometries_fp64(ctx, case):
+def geometry_case(case):
     if case == "ball2d_exit":
         pd = W.ball_exit_time_problem(dim=2, sigma=0.8, seed=3)
         nodes = np.array([[0.0, 0.0], [0.5, 0.2], [-0.3, 0.7]])
@@ -132,10 +131,35 @@ def test_other_geometries_fp64(ctx, case):
               "fx": [{"coef": 0.25, "e": [1, 0, 1]}], "gx": [{"coef": 0.1, "e": [0, 0, 0]}],
               "seed": 99}
         nodes = np.array([[0.5, 0.6, 0.4], [0.2, 0.3, 0.7]])
+    return pd, nodes
+
+
+GEOMETRIES = ["ball2d_exit", "ball3d_exit", "ball3d_kill", "box3d"]
+
+
+@pytest.mark.parametrize("case", GEOMETRIES)
+def test_other_geometries_fp64(ctx, case):
+    pd, nodes = geometry_case(case)
     n = 3000
     st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp64")
     ost, orec = oracle_solve(pd, nodes, n, dt=1e-3)
     check_fp64_parity(st, rec, ost, orec, n)
+
+
+@pytest.mark.parametrize("case", GEOMETRIES)
+@pytest.mark.parametrize("exit_mode", ["bridge", "shift", "naive"])
+def test_other_geometries_fp32_within_3se(ctx, case, exit_mode):
+    """FP32 paths in 2D/3D balls and a 3D box with a full drift matrix, every
+    exit test: node means within 3 SE + 1e-5 of the FP64 oracle on the same
+    streams, and the walks mostly identical."""
+    pd, nodes = geometry_case(case)
+    n = 4000
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp32", exit=exit_mode)
+    ost, orec = oracle_solve(pd, nodes, n, dt=1e-3, exit=exit_mode)
+    diff = np.abs(st["mean"] - ost["mean"])
+    assert np.all(diff <= 3 * ost["stderr"] + 1e-5), (diff, ost["stderr"])
+    same = (rec["steps"] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
+    assert same.mean() > 0.98, same.mean()
 
 
 def test_rademacher_law_fp64(ctx):
@@ -197,10 +221,45 @@ def test_exact_control_variate_on_gpu(ctx):
         assert np.all(st["var_plain"] > 1e-2)
 
 
+def test_big_square_benchmark_launch(ctx):
+    """The throughput workload exactly as the benchmark launches it: all 1,792
+    nodes, 62,500 paths per node (benchmark step 3), FP32, library scratch
+    records, the cached launch shape. The same solve with caller records gives
+    bitwise the same statistics, and sampled paths from those records are
+    replayed one by one by the oracle."""
+    from oracle import oracle as O
+    from paper_1512_02818_amd import tuning
+    tuning.load(ctx)
+    pd = W.big_square_problem(seed=0)
+    nodes = W.big_square_nodes()
+    h, n = 1e-4, 62500
+    off = 3 * n
+    prob = pdd.Problem(ctx, pd)
+    bench = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=h, n_paths=n, path_offset=off))
+    prob.close()
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=h, precision="fp32", path_offset=off)
+    assert bench.tobytes() == st.tobytes()
+    assert np.all(st["n"] == n) and np.all(st["n_capped"] == 0)
+    rng = np.random.default_rng(11)
+    ni = rng.integers(0, len(nodes), 200)
+    pj = rng.integers(0, n, 200)
+    orec = O.run_paths(pd, nodes, ni, off + pj, h=h)
+    slot = ni * n + pj
+    same = (rec["steps"][slot] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
+    assert same.mean() >= 0.95
+    assert np.median(np.abs(rec["phi"][slot][same] - orec["phi"][same])) < 1e-4
+    exact = W.manufactured_u(pd, nodes)
+    z = np.abs(st["mean"] - exact) / st["stderr"]
+    assert np.mean(z < 3.5) > 0.98, np.sort(z)[-10:]
+    for prec in ("fp32", "fp64"):
+        for dim in (2, 3):
+            for cv in (False, True):
+                pdd.set_tuning(ctx, prec, dim, cv, None)
+
+
 def test_big_square_sampled_paths(ctx):
-    """The throughput workload in the launch configuration the benchmark times
-    (all 1,792 nodes, one batch of paths per node, FP32), checked on sampled
-    paths the oracle replays one by one, plus FP64 on a smaller batch."""
+    """The throughput workload on smaller batches: FP32 and FP64 paths checked
+    on sampled paths the oracle replays one by one."""
     from oracle import oracle as O
     pd = W.big_square_problem(seed=0)
     nodes = W.big_square_nodes()
