@@ -737,8 +737,10 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 // only once all its lanes are idle. Each wave keeps the source coefficients
 // of its current problem in its own LDS slot (written when it changes item;
 // a wave's LDS accesses complete in order, so no barrier is needed).
+// FP64 walks are asked to fit three waves per SIMD (168 registers; the few
+// spilled values live outside the step loop), which is faster than two.
 template <class T, int D, bool CV>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1, 8)))
     path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
                      const DevProblem<T> *__restrict__ probs)
 {
