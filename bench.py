@@ -10,8 +10,11 @@ one solve call over every node with the next block of `--paths-per-step` paths
 
 Prints one JSON line: path-steps/s over the timed steps (inputs resident on
 the device, timed with HIP events on the solve's stream), the roofline of the
-path kernel (VALU-issue bound; see the design doc for the per-step operation
-count), and the CPU oracle timed on a bounded sample of the same workload.
+path kernel (VALU-issue bound; the per-step operation count is STEP_COST
+below), node-solves/s at a fixed RMS error for the correction estimator in
+FP32 and the plain estimator in FP64, the correction iterates, a batched
+solve, a serving run, and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -31,8 +34,8 @@ SEED = 0
 # Algorithmic VALU cost of one 2D path step of this workload, in full-rate
 # FP32 lane slots; transcendentals (log2, sqrt, sin, cos, exp2) and 32x32-bit
 # multiplies issue at a quarter of the FP32 rate and count 4, an FP64 add 2.
-# Derived from the operations the step must perform ("Roofline of
-# the path kernel"), not from the compiled code.
+# Derived from the operations the step must perform, not from the compiled
+# code.
 STEP_COST = {
     "philox_half_block": (10 * 2 * 4 + 10 * 2) // 2,  # 10 rounds x (2 wide mul + 2 xor3); 2 steps/block
     "uniforms": 2 * 2,                                # convert + fma per word
@@ -284,7 +287,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(the nodal solve is sharded by node across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(a multi-GPU run would split each node's paths across GPUs and merge the "
+              "per-node sums)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

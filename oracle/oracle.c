@@ -31,7 +31,7 @@
  * as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications on a
  * 128-bit counter, the 64-bit key bumped by the Weyl constants between rounds.
  * The paper itself draws with Matlab's randn; the generator and the layout of
- * its counter are this build's choice.
+ * its counter are a choice of this implementation (same in the GPU code).
  * ------------------------------------------------------------------------- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
