@@ -330,10 +330,30 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
     return acc;
 }
 
+// Domain, exit test and increment law: read from the problem and item at run
+// time, or fixed at compile time for the common box / bridge / Gaussian case,
+// which removes their branches and frees the registers of the other cases.
+struct RuntimeMode {
+    template <class T>
+    __device__ static __forceinline__ int domain(const DevProblem<T> &P) { return P.domain; }
+    template <class T>
+    __device__ static __forceinline__ int exit(const ItemDesc<T> &a) { return a.exit_mode; }
+    template <class T>
+    __device__ static __forceinline__ int law(const ItemDesc<T> &a) { return a.law; }
+};
+struct BoxBridgeGauss {
+    template <class T>
+    __device__ static constexpr int domain(const DevProblem<T> &) { return kBox; }
+    template <class T>
+    __device__ static constexpr int exit(const ItemDesc<T> &) { return kExitBridge; }
+    template <class T>
+    __device__ static constexpr int law(const ItemDesc<T> &) { return kLawGauss; }
+};
+
 template <class T, int D>
-__device__ __forceinline__ T inner_distance(const DevProblem<T> &P, const T *x)
+__device__ __forceinline__ T inner_distance(const DevProblem<T> &P, int domain, const T *x)
 {
-    if (P.domain == kBox) {
+    if (domain == kBox) {
         T m = x[0] - P.lo[0];
         m = fmin(m, P.hi[0] - x[0]);
 #pragma unroll
@@ -371,9 +391,9 @@ __device__ __forceinline__ void radial(const DevProblem<T> &P, const T *x, T *ou
 // Closest boundary point: inside a box the nearest face (ties to the lowest
 // face index, faces ordered x-lo, x-hi, y-lo, ...), outside the clamp.
 template <class T, int D>
-__device__ __forceinline__ void project(const DevProblem<T> &P, const T *x, T *out)
+__device__ __forceinline__ void project(const DevProblem<T> &P, int domain, const T *x, T *out)
 {
-    if (P.domain == kBall) {
+    if (domain == kBall) {
         radial<T, D>(P, x, out);
         return;
     }
@@ -405,7 +425,7 @@ __device__ __forceinline__ void project(const DevProblem<T> &P, const T *x, T *o
 }
 
 // State of the path a lane is walking.
-template <class T, int D, bool CV>
+template <class T, int D, bool CV, class M>
 struct Walker {
     T X[D], Xt[D];
     T Y;
@@ -448,15 +468,15 @@ struct Walker {
         j = (uint32_t)(a.path_offset + jj);
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
-        m = inner_distance<T, D>(P, X);
+        m = inner_distance<T, D>(P, M::domain(P), X);
         Y = (T)1;
         Z = 0.0;
         R = 0.0;
         k = 0;
         capped = 0;
         bb_blk = 0xffffffffu;
-        if (a.exit_mode == kExitShift && m <= a.gm_thresh) {
-            project<T, D>(P, X, Xt);
+        if (M::exit(a) == kExitShift && m <= a.gm_thresh) {
+            project<T, D>(P, M::domain(P), X, Xt);
             return false;
         }
         return true;
@@ -484,7 +504,7 @@ struct Walker {
                                          uint32_t wb, uint32_t wc, uint32_t wd)
     {
         T n[D];
-        if (a.law == kLawGauss) {
+        if (M::law(a) == kLawGauss) {
             Arith<T>::box_muller(wa, wb, n[0], n[1]);
             if (D == 3) n[2 % D] = Arith<T>::box_muller_cos(wc, wd);
         } else {
@@ -506,7 +526,7 @@ struct Walker {
 
         // distance of the new point to the boundary (negative outside)
         T mn;
-        if (P.domain == kBox) {
+        if (M::domain(P) == kBox) {
             mn = Xn[0] - P.lo[0];
             mn = fmin(mn, P.hi[0] - Xn[0]);
 #pragma unroll
@@ -523,25 +543,25 @@ struct Walker {
             }
             mn = r2n < P.radius2 ? P.radius - Arith<T>::sqrt_(r2n) : (T)-1;
         }
-        const bool shift = a.exit_mode == kExitShift;
+        const bool shift = M::exit(a) == kExitShift;
         // Bridge: a face f is live when a_f a'_f 2/(sigma^2 h) <= 36 ln 2; since
         // a_f >= m and a'_f >= mn, no face is live unless m mn passes that test.
         const bool out = !shift && !(mn > (T)0);
-        const bool maybe = a.exit_mode == kExitBridge && m * mn * a.two_over_s2h <= a.bridge_thresh;
+        const bool maybe = M::exit(a) == kExitBridge && m * mn * a.two_over_s2h <= a.bridge_thresh;
         const bool next_stop = k == a.max_steps || (shift && mn <= a.gm_thresh);
         if (out || maybe || next_stop) {
             if (out) {
-                project<T, D>(P, Xn, Xt);
+                project<T, D>(P, M::domain(P), Xn, Xt);
                 return false;
             }
             if (maybe && bridge_exit(a, P, Xn, mn, s)) return false;
             if (shift && mn <= a.gm_thresh) {  // stops before the next step
-                project<T, D>(P, Xn, Xt);
+                project<T, D>(P, M::domain(P), Xn, Xt);
                 return false;
             }
             if (k == a.max_steps) {
                 capped = 1;
-                project<T, D>(P, Xn, Xt);
+                project<T, D>(P, M::domain(P), Xn, Xt);
                 return false;
             }
         }
@@ -557,7 +577,7 @@ struct Walker {
     __device__ __forceinline__ bool bridge_exit(const ItemDesc<T> &a, const DevProblem<T> &P,
                                                 const T *Xn, T mn, uint32_t s)
     {
-        if (P.domain == kBox) {
+        if (M::domain(P) == kBox) {
             T arg[2 * D];
             T amin = (T)0;
             int fmin = -1, nlive = 0;
@@ -679,7 +699,7 @@ struct Pool {
 // they stay in vector registers for the whole loop (about 96 registers, five
 // waves per SIMD) instead of being reloaded by scalar loads at every step,
 // which the scalar register file cannot hold next to the other constants.
-template <class T, int D, bool CV>
+template <class T, int D, bool CV, class M>
 __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 {
     static_assert(kOneItemKernel<T, D, CV>, "single-item kernel is for FP32 2D plain solves");
@@ -691,7 +711,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     __shared__ T s_cf[kMaxDense];
     for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
     __syncthreads();
-    Walker<T, D, CV> w;
+    Walker<T, D, CV, M> w;
     w.cf = s_cf;
     w.ks = key_schedule(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
@@ -739,7 +759,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 // a wave's LDS accesses complete in order, so no barrier is needed).
 // FP64 walks are asked to fit three waves per SIMD (168 registers; the few
 // spilled values live outside the step loop), which is faster than two.
-template <class T, int D, bool CV>
+template <class T, int D, bool CV, class M>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1, 8)))
     path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
                      const DevProblem<T> *__restrict__ probs)
@@ -748,7 +768,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[256 / 64][kMaxDense];
     T *my_cf = s_cf[threadIdx.x >> 6];
-    Walker<T, D, CV> w;
+    Walker<T, D, CV, M> w;
     w.cf = my_cf;
     int st = 0;
     Pool pool;
@@ -809,18 +829,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 
 template <class T, int D, bool CV>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
-                              const DevProblem<T> *probs, int grid, int block, hipStream_t s)
+                              const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s)
 {
-    hipLaunchKernelGGL((path_kernel_many<T, D, CV>), dim3(grid), dim3(block), 0, s, l, items, probs);
+    if (spec)
+        hipLaunchKernelGGL((path_kernel_many<T, D, CV, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
+                           items, probs);
+    else
+        hipLaunchKernelGGL((path_kernel_many<T, D, CV, RuntimeMode>), dim3(grid), dim3(block), 0, s, l, items,
+                           probs);
     return hipGetLastError();
 }
 
 template <class T, int D, bool CV>
-hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, hipStream_t s)
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s)
 {
     static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
     if constexpr (kOneItemKernel<T, D, CV>) {
-        hipLaunchKernelGGL((path_kernel_one<T, D, CV>), dim3(grid), dim3(block), 0, s, a);
+        if (spec)
+            hipLaunchKernelGGL((path_kernel_one<T, D, CV, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
+        else
+            hipLaunchKernelGGL((path_kernel_one<T, D, CV, RuntimeMode>), dim3(grid), dim3(block), 0, s, a);
         return hipGetLastError();
     } else {
         return hipErrorInvalidDeviceFunction;
@@ -828,18 +856,21 @@ hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, 
 }
 
 template <class T, int D, bool CV>
-const void *path_kernel_symbol(bool one)
+const void *path_kernel_symbol(bool one, bool spec)
 {
     if constexpr (kOneItemKernel<T, D, CV>)
-        if (one) return reinterpret_cast<const void *>(&path_kernel_one<T, D, CV>);
-    return reinterpret_cast<const void *>(&path_kernel_many<T, D, CV>);
+        if (one)
+            return spec ? reinterpret_cast<const void *>(&path_kernel_one<T, D, CV, BoxBridgeGauss>)
+                        : reinterpret_cast<const void *>(&path_kernel_one<T, D, CV, RuntimeMode>);
+    return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, CV, BoxBridgeGauss>)
+                : reinterpret_cast<const void *>(&path_kernel_many<T, D, CV, RuntimeMode>);
 }
 
 #define PDD_INSTANTIATE(T, D, CV)                                                              \
     template hipError_t launch_path_kernel<T, D, CV>(const LaunchArgs &, const ItemDesc<T> *, \
-                                                     const DevProblem<T> *, int, int, hipStream_t); \
-    template hipError_t launch_path_kernel_one<T, D, CV>(const OneItemArgs<T> &, int, int, hipStream_t); \
-    template const void *path_kernel_symbol<T, D, CV>(bool);
+                                                     const DevProblem<T> *, int, int, bool, hipStream_t); \
+    template hipError_t launch_path_kernel_one<T, D, CV>(const OneItemArgs<T> &, int, int, bool, hipStream_t); \
+    template const void *path_kernel_symbol<T, D, CV>(bool, bool);
 
 PDD_INSTANTIATE(float, 2, false)
 PDD_INSTANTIATE(float, 2, true)

@@ -184,14 +184,16 @@ struct OneItemArgs {
 template <class T, int D, bool CV>
 constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && !CV;
 
-// Launchers (defined in the .hip files).
+// Launchers (defined in the .hip files). `spec`: every item of the launch is
+// a box problem with the bridge exit test and Gaussian increments, for which
+// a specialised kernel is compiled.
 template <class T, int D, bool CV>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
-                              const DevProblem<T> *probs, int grid, int block, hipStream_t s);
+                              const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s);
 template <class T, int D, bool CV>
-hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, hipStream_t s);
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s);
 template <class T, int D, bool CV>
-const void *path_kernel_symbol(bool one);
+const void *path_kernel_symbol(bool one, bool spec);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);

@@ -568,7 +568,12 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
 
     const int block = tune.block;
     const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
-    const void *fn = path_kernel_symbol<T, D, CV>(one);
+    // box / bridge / Gaussian throughout: the specialised kernel
+    const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) {
+        return i->prob->desc.domain == PDD_DOMAIN_BOX && i->o->exit_mode == PDD_EXIT_BRIDGE &&
+               i->o->law == PDD_LAW_GAUSS;
+    });
+    const void *fn = path_kernel_symbol<T, D, CV>(one, spec);
     // more workgroups than fit at once only queue behind the resident ones
     const int occ = occupancy(ctx, fn, block);
     const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
@@ -605,9 +610,9 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             // the single item starts at slot 0; scratch records of this launch
             // start at slot b
             if (!items[0]->caller_records) A.item.rec_base = b;
-            HIP_TRY((launch_path_kernel_one<T, D, CV>(A, grid, block, s)));
+            HIP_TRY((launch_path_kernel_one<T, D, CV>(A, grid, block, spec, s)));
         } else {
-            HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, s)));
+            HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, spec, s)));
         }
         if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
         // reduction of the nodes this launch touched: one launch for the items
@@ -974,13 +979,15 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     if (prec != PDD_FP32 && prec != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
     HIP_TRY(hipSetDevice(ctx->device));
     // the kernel this group launches for a single item, and its occupancy
+    const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX &&
+                      item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS;
     const void *fn = nullptr;
     if (prec == PDD_FP32)
-        fn = dim == 2 ? (cv ? path_kernel_symbol<float, 2, true>(true) : path_kernel_symbol<float, 2, false>(true))
-                      : (cv ? path_kernel_symbol<float, 3, true>(true) : path_kernel_symbol<float, 3, false>(true));
+        fn = dim == 2 ? (cv ? path_kernel_symbol<float, 2, true>(true, spec) : path_kernel_symbol<float, 2, false>(true, spec))
+                      : (cv ? path_kernel_symbol<float, 3, true>(true, spec) : path_kernel_symbol<float, 3, false>(true, spec));
     else
-        fn = dim == 2 ? (cv ? path_kernel_symbol<double, 2, true>(true) : path_kernel_symbol<double, 2, false>(true))
-                      : (cv ? path_kernel_symbol<double, 3, true>(true) : path_kernel_symbol<double, 3, false>(true));
+        fn = dim == 2 ? (cv ? path_kernel_symbol<double, 2, true>(true, spec) : path_kernel_symbol<double, 2, false>(true, spec))
+                      : (cv ? path_kernel_symbol<double, 3, true>(true, spec) : path_kernel_symbol<double, 3, false>(true, spec));
     const int occ256 = occupancy(ctx, fn, 256);
     // sample: up to 32 nodes spread over the item's, about 8 (then 16) paths
     // per resident lane of the default shape
