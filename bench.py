@@ -96,6 +96,9 @@ def parse():
                     help="1: report the correction iterates 10^3 -> 10^5 (0 = skip)")
     ap.add_argument("--batch-scale", type=float, default=0.1,
                     help="path-count scale of the 64-problem batched solve (0 = skip)")
+    ap.add_argument("--profile-correction", type=int, default=0,
+                    help="only run the correction solve (unit square, 257^2 FP32 grids, h=1e-3) with "
+                         "this many paths per node three times and print its timing (for profilers)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -283,8 +286,54 @@ def batch_solve(ctx, scale):
             "median_abs_z_vs_exact": float(np.median(z))}
 
 
+def calibration_copy(mib):
+    """One plain device copy of `mib` MiB: its HBM byte counters give the
+    scale of a profiler's FETCH_SIZE / WRITE_SIZE readings."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def profile_correction(paths, calibrate_mib=0):
+    """The correction estimator alone, for kernel-trace and counter runs: 18
+    unit-square nodes, u_prev = U + p and its residual on 257^2 FP32 grids
+    (about 0.26 MB each, so the grid gathers are served by L2), h = 1e-3."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    ctx = pdd.Context(0)
+    pd = W.unit_square_problem(seed=SEED)
+    nodes = W.unit_square_nodes()
+    prob = pdd.Problem(ctx, pd)
+    gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    out = pdd.alloc_stats(len(nodes))
+    if calibrate_mib > 0:
+        calibration_copy(calibrate_mib)
+    steps = 0
+    for r in range(3):
+        pdd.solve_correction(prob, gu, tu, gr, tr, nodes, out=out, dt=1e-3, n_paths=paths,
+                             path_offset=r * paths, precision="fp32", time_kernel=True)
+        steps += int(pdd.stats_to_numpy(out)["steps_sum"].sum())
+    ms = pdd.kernel_times(ctx)
+    print(json.dumps({"correction_profile": {"paths_per_node": paths, "nodes": len(nodes),
+                                             "path_steps": steps, "kernel_ms": ms,
+                                             "path_steps_per_s": steps / (sum(ms) / 1e3)}}), flush=True)
+    prob.close()
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.profile_correction > 0:
+        profile_correction(args.profile_correction, args.calibrate_copy_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(a multi-GPU run would split each node's paths across GPUs and merge the "
@@ -310,11 +359,7 @@ def main():
     outs = [pdd.alloc_stats(len(nodes)) for _ in range(args.warmup + args.steps)]
 
     if args.calibrate_copy_mib > 0:
-        src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(args.calibrate_copy_mib)
 
     def step(s):
         pdd.solve_nodes(prob, nodes, out=outs[s], dt=H, n_paths=P, path_offset=s * P,

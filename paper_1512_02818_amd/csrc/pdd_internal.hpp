@@ -156,7 +156,14 @@ struct ReduceArgs {
     int32_t has_phi, has_e;
     const uint32_t *node_item;
     const FinalItem *fitems;
+    // segments longer than kReduceChunk paths are split: chunk c of node
+    // node_lo + b is reduced by workgroup (b, c) into partials[b * n_chunks +
+    // c], and the chunks are then merged into acc in chunk order
+    NodeAcc *partials;
+    uint32_t n_chunks;
 };
+
+constexpr uint64_t kReduceChunk = 1ull << 16;
 
 struct FinalizeArgs {
     const NodeAcc *acc;

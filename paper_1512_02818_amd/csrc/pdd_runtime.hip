@@ -556,6 +556,22 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         std::memcpy(&h_probs[p], sizeof(T) == 4 ? (const void *)&probs[p]->pf : (const void *)&probs[p]->pd,
                     sizeof(DevProblem<T>));
 
+    // chunk partials of long node segments (reduce kernel): sized for the
+    // longest node of the group before anything of the group is enqueued
+    uint64_t longest = 0;
+    for (uint64_t i = 0; i < n_nodes_all; ++i) longest = std::max(longest, h_gstart[i + 1] - h_gstart[i]);
+    const uint64_t max_chunks = std::max<uint64_t>(1, (longest + kReduceChunk - 1) / kReduceChunk);
+    if (max_chunks > 1 && (st = ensure(ctx, ctx->partials, n_nodes_all * max_chunks * sizeof(NodeAcc)))) return st;
+    // chunks needed by nodes [n_lo, n_hi] of gs restricted to slots [a, b)
+    auto chunks_in = [&](const uint64_t *gs, uint32_t n_lo, uint32_t n_hi, uint64_t a, uint64_t b) {
+        uint64_t mx = 0;
+        for (uint32_t i = n_lo; i <= n_hi; ++i) {
+            const uint64_t x = std::max(gs[i], a), y = std::min(gs[i + 1], b);
+            if (y > x) mx = std::max(mx, y - x);
+        }
+        return (uint32_t)std::max<uint64_t>(1, (mx + kReduceChunk - 1) / kReduceChunk);
+    };
+
     HIP_TRY(hipMemcpyAsync(dv, h, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->staged, s));
     ctx->any_staged = true;
@@ -635,6 +651,8 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             r.has_e = CV;
             r.node_item = d_nitem;
             r.fitems = d_fitems;
+            r.n_chunks = chunks_in(h_gstart, n_lo, n_hi, b, b + len);
+            r.partials = static_cast<NodeAcc *>(ctx->partials.ptr);
             HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
         }
         for (int q = 0; q < n_items; ++q) {
@@ -658,6 +676,8 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             r.node_lo = n_lo;
             r.has_phi = it.score_plain;
             r.has_e = CV;
+            r.n_chunks = chunks_in(gs, n_lo, n_hi, lo, hi);
+            r.partials = static_cast<NodeAcc *>(ctx->partials.ptr);
             HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
         }
     }
@@ -755,7 +775,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
-    for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec})
+    for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);

@@ -38,15 +38,9 @@ __device__ __forceinline__ Pair nmerge(Pair a, Pair b)
 
 constexpr int kReduceBlock = 256;
 
-__global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r)
+// Node segment [lo, hi) of the launch and its number of chunks.
+__device__ __forceinline__ void segment(const ReduceArgs &r, uint32_t node, uint64_t &lo, uint64_t &hi)
 {
-    const uint32_t node = r.node_lo + blockIdx.x;
-    int32_t has_phi = r.has_phi;
-    if (r.node_item) {
-        const FinalItem &fi = r.fitems[r.node_item[node]];
-        if (fi.own_reduce) return;  // whole workgroup: the item is uniform per node
-        has_phi = fi.has_phi;
-    }
     uint64_t ns, ne;
     if (r.node_start) {
         ns = r.node_start[node];
@@ -55,8 +49,35 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
         ns = (uint64_t)node * r.uniform_n;
         ne = ns + r.uniform_n;
     }
-    const uint64_t lo = ns > r.slot_begin ? ns : r.slot_begin;
-    const uint64_t hi = ne < r.slot_end ? ne : r.slot_end;
+    lo = ns > r.slot_begin ? ns : r.slot_begin;
+    hi = ne < r.slot_end ? ne : r.slot_end;
+}
+
+__device__ __forceinline__ uint32_t n_chunks_of(uint64_t lo, uint64_t hi)
+{
+    return hi > lo ? (uint32_t)((hi - lo + kReduceChunk - 1) / kReduceChunk) : 0u;
+}
+
+__global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r)
+{
+    const uint32_t node = r.node_lo + blockIdx.x;
+    const uint32_t chunk = blockIdx.y;
+    int32_t has_phi = r.has_phi;
+    if (r.node_item) {
+        const FinalItem &fi = r.fitems[r.node_item[node]];
+        if (fi.own_reduce) return;  // whole workgroup: the item is uniform per node
+        has_phi = fi.has_phi;
+    }
+    uint64_t lo, hi;
+    segment(r, node, lo, hi);
+    const uint32_t nch = n_chunks_of(lo, hi);
+    // one chunk (or none): this workgroup merges straight into the node's sums
+    const bool direct = nch <= 1;
+    if (direct ? chunk != 0 : chunk >= nch) return;  // whole workgroup
+    if (!direct) {
+        lo += (uint64_t)chunk * kReduceChunk;
+        if (hi - lo > kReduceChunk) hi = lo + kReduceChunk;
+    }
 
     Pair acc[5] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
     long long steps = 0, capped = 0;
@@ -99,7 +120,29 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
         part_i[wave][1] = capped;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !direct) {  // a chunk partial, merged by merge_chunks_kernel
+        NodeAcc p;
+        Pair tot[5] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        for (int w = 0; w < kReduceBlock / 64; ++w)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) tot[q] = nmerge(tot[q], part[w][q]);
+        long long st = 0, cp = 0;
+        for (int w = 0; w < kReduceBlock / 64; ++w) {
+            st += part_i[w][0];
+            cp += part_i[w][1];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            p.s[q] = tot[q].s;
+            p.c[q] = tot[q].c;
+        }
+        p.steps = st;
+        p.capped = cp;
+        p.n = (long long)(hi - lo);
+        p.pad = 0;
+        r.partials[(size_t)blockIdx.x * r.n_chunks + chunk] = p;
+    }
+    if (threadIdx.x == 0 && direct) {
         NodeAcc &A = r.acc[node];
         Pair tot[5];
 #pragma unroll
@@ -121,6 +164,38 @@ __global__ void __launch_bounds__(kReduceBlock) reduce_kernel(const ReduceArgs r
         A.capped = cp;
         A.n += (long long)(hi > lo ? hi - lo : 0);
     }
+}
+
+// Chunk partials of the split segments, merged into the node sums in chunk
+// order (one thread per node of the launch range).
+__global__ void merge_chunks_kernel(const ReduceArgs r, uint32_t n_nodes)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const uint32_t node = r.node_lo + b;
+    if (r.node_item && r.fitems[r.node_item[node]].own_reduce) return;
+    uint64_t lo, hi;
+    segment(r, node, lo, hi);
+    const uint32_t nch = n_chunks_of(lo, hi);
+    if (nch <= 1) return;
+    NodeAcc &A = r.acc[node];
+    Pair tot[5];
+    for (int q = 0; q < 5; ++q) tot[q] = {A.s[q], A.c[q]};
+    long long st = A.steps, cp = A.capped, n = A.n;
+    for (uint32_t c = 0; c < nch; ++c) {
+        const NodeAcc &p = r.partials[(size_t)b * r.n_chunks + c];
+        for (int q = 0; q < 5; ++q) tot[q] = nmerge(tot[q], Pair{p.s[q], p.c[q]});
+        st += p.steps;
+        cp += p.capped;
+        n += p.n;
+    }
+    for (int q = 0; q < 5; ++q) {
+        A.s[q] = tot[q].s;
+        A.c[q] = tot[q].c;
+    }
+    A.steps = st;
+    A.capped = cp;
+    A.n = n;
 }
 
 __device__ __forceinline__ double grid_at(const FinalItem &f, size_t i)
@@ -249,7 +324,13 @@ __global__ void zero_kernel(uint64_t *p, uint64_t n_words)
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(n_blocks), dim3(kReduceBlock), 0, s, a);
+    const uint32_t nc = a.n_chunks > 0 ? a.n_chunks : 1;
+    hipLaunchKernelGGL(reduce_kernel, dim3(n_blocks, nc), dim3(kReduceBlock), 0, s, a);
+    if (nc > 1) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(merge_chunks_kernel, dim3((n_blocks + 255) / 256), dim3(256), 0, s, a, n_blocks);
+    }
     return hipGetLastError();
 }
 

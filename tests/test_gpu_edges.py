@@ -2,6 +2,8 @@
 the step cap, invalid arguments, resume by path offset, independence of the
 launch shape (block size, persistent grid, queue grab, launch chunking) and
 run-to-run determinism."""
+import math
+
 import numpy as np
 import pytest
 
@@ -179,3 +181,33 @@ def test_kernel_times_reported(ctx, prob):
     ms = pdd.kernel_times(ctx)
     assert len(ms) == 3 and all(t > 0 for t in ms)
     assert pdd.kernel_times(ctx) == []
+
+
+def test_long_node_segments_are_reduced_in_chunks(prob):
+    """Node segments longer than one reduction chunk (65,536 paths) are summed
+    chunk by chunk and merged in chunk order; the sums still agree with the
+    per-path records, and scratch and caller records give the same bits."""
+    nodes = W.unit_square_nodes()[:3]
+    counts = np.array([150_001, 10, 70_000], dtype=np.uint64)
+    total = int(counts.sum())
+    st, rec = run(prob, nodes, total, dt=1e-3, n_paths_per_node=counts, precision="fp32")
+    scratch = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths_per_node=counts,
+                                                 precision="fp32"))
+    assert scratch.tobytes() == st.tobytes()
+    ends = np.cumsum(counts.astype(np.int64))
+    for i in range(3):
+        seg = slice(int(ends[i] - counts[i]), int(ends[i]))
+        phi = rec["phi"][seg].astype(np.float64)
+        steps = rec["steps"][seg].view(np.uint32)
+        assert st["n"][i] == counts[i]
+        assert st["steps_sum"][i] == int((steps & 0x7FFFFFFF).astype(np.int64).sum())
+        assert st["n_capped"][i] == int((steps >> 31).sum())
+        s1 = st["sums"][i][0] + st["sums"][i][1]
+        s2 = st["sums"][i][2] + st["sums"][i][3]
+        assert abs(s1 - math.fsum(phi)) <= 1e-12 * max(1.0, abs(math.fsum(np.abs(phi))))
+        assert abs(s2 - math.fsum(phi * phi)) <= 1e-12 * max(1.0, math.fsum(phi * phi))
+    # a launch cap that cuts the long node: same counts, sums to rounding
+    cut = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths_per_node=counts,
+                                             precision="fp32", tuning=(256, 0, 64, 100_003)))
+    assert np.array_equal(cut["n"], st["n"]) and np.array_equal(cut["steps_sum"], st["steps_sum"])
+    assert np.allclose(cut["mean"], st["mean"], rtol=1e-14, atol=1e-15)
