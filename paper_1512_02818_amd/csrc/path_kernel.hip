@@ -671,9 +671,9 @@ __device__ __forceinline__ int find_item(const ItemDesc<T> *__restrict__ items, 
     return lo;
 }
 
-// Queue refill shared by both loops: takes `grab` slots at a time from the
-// launch counter and hands the wave's idle lanes consecutive slots below
-// `limit` (launch-relative). Returns the number handed out.
+// Queue of the single-item kernel: a wave takes `grab` slots at a time from
+// the launch counter, [next, end) launch-relative, and hands them to its idle
+// lanes in order.
 struct Pool {
     uint32_t next = 0, end = 0;
     bool exhausted = false;
@@ -752,11 +752,86 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     }
 }
 
+// Per-item queues of a batch launch. A wave walks the paths of one item at a
+// time and may move to another item only once all its lanes are idle, so it
+// takes its tickets from its own item's queue for as long as that has slots:
+// a single shared queue would hand it the next slots of the whole launch,
+// which with many waves lie in another item almost every time and would make
+// it wait for its slowest lane at nearly every refill. Waves start spread over
+// the items in proportion to their slots; a wave whose item has run dry looks
+// for the next item that still has slots (64 candidates per probe).
+template <class T>
+struct ItemQueue {
+    int cur = -1;                     // item of the wave (wave-uniform)
+    uint32_t seg_lo = 0, seg_hi = 0;  // its launch-relative slots
+    uint32_t next = 0, end = 0;       // the wave's current ticket
+    bool dry = true;                  // the current item's queue is used up
+    bool done = false;                // every queue of the launch is used up
+
+    // Next ticket of the current item's queue, or dry.
+    __device__ __forceinline__ void take(const LaunchArgs &L, int lane)
+    {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(L.counter + (cur - L.item_lo), (uint32_t)L.grab);
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (base < seg_hi - seg_lo) {
+            next = seg_lo + base;
+            end = min(next + (uint32_t)L.grab, seg_hi);
+        } else {
+            dry = true;
+        }
+    }
+
+    // Moves the (idle) wave to an item with slots left, starting with queue k
+    // and then probing the ones after it, and takes a ticket there; done when
+    // none has slots left. Counters only grow, so every failed attempt means
+    // another wave took those slots and the search ends.
+    __device__ __forceinline__ void move(const ItemDesc<T> *__restrict__ items, const LaunchArgs &L, int lane,
+                                         uint32_t k)
+    {
+        const uint32_t n = L.n_seg;
+        for (;;) {
+            cur = __builtin_amdgcn_readfirstlane(L.item_lo + (int)k);
+            seg_lo = L.seg[2 * k];
+            seg_hi = L.seg[2 * k + 1];
+            dry = false;
+            take(L, lane);
+            if (!dry) return;
+            // the probe window nearest after k that has slots left; in it, the
+            // item with the most slots left (spreads the waves that move)
+            uint32_t found = n;
+            for (uint32_t off = 1; off < n && found == n; off += 64) {
+                const uint32_t i = off + (uint32_t)lane;
+                uint32_t key = 0;  // slots left (capped) << 6 | 63 - lane: the largest wins
+                if (i < n) {
+                    uint32_t kk = k + i;
+                    if (kk >= n) kk -= n;
+                    const uint32_t lo = L.seg[2 * kk], hi = L.seg[2 * kk + 1];
+                    const uint32_t taken =
+                        __hip_atomic_load(L.counter + kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (taken < hi - lo) key = (min(hi - lo - taken, 0x3ffffffu) << 6) | (uint32_t)(63 - lane);
+                }
+#pragma unroll
+                for (int x = 32; x >= 1; x >>= 1) key = max(key, (uint32_t)__shfl_xor((int)key, x));
+                key = __builtin_amdgcn_readfirstlane(key);  // every lane holds the maximum
+                if (key) {
+                    found = k + off + (63 - (key & 63));
+                    if (found >= n) found -= n;
+                }
+            }
+            if (found == n) {
+                done = true;
+                return;
+            }
+            k = found;
+        }
+    }
+};
+
 // A batch: items and problems in device tables read at wave-uniform indices.
-// A wave walks the paths of one item at a time and moves to the next item
-// only once all its lanes are idle. Each wave keeps the source coefficients
-// of its current problem in its own LDS slot (written when it changes item;
-// a wave's LDS accesses complete in order, so no barrier is needed).
+// Each wave keeps the source coefficients of its current problem in its own
+// LDS slot (written when it changes item; a wave's LDS accesses complete in
+// order, so no barrier is needed).
 // FP64 walks are asked to fit three waves per SIMD (168 registers; the few
 // spilled values live outside the step loop), which is faster than two.
 template <class T, int D, bool CV, class M>
@@ -771,55 +846,66 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     Walker<T, D, CV, M> w;
     w.cf = my_cf;
     int st = 0;
-    Pool pool;
-    int cur = -1;          // item of the wave (wave-uniform)
-    uint32_t cur_end = 0;  // launch-relative end of its slots
+    ItemQueue<T> q;
 
     for (uint32_t iter = 0;; ++iter) {
         if ((iter & (kRefillPeriod<D> - 1)) == 0) {  // refill turn (wave-uniform)
             if (st == 2) {
-                const ItemDesc<T> &it = items[cur];
+                const ItemDesc<T> &it = items[q.cur];
                 // scratch records sit at group slot - launch start (modular arithmetic)
                 w.finish(it, probs[it.prob], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
                 st = 0;
             }
             const uint64_t idle = __ballot(st == 0);
-            if (idle) {
-                pool.refill(L, lane);
-                if (pool.next < pool.end && (cur < 0 || pool.next >= cur_end) && idle == ~0ull) {
-                    cur = __builtin_amdgcn_readfirstlane(find_item(items, L.n_items, L.slot_begin + pool.next));
-                    const ItemDesc<T> &it = items[cur];
-                    const uint64_t e = it.slot_begin + it.n_slots - L.slot_begin;
-                    cur_end = e < (uint64_t)L.launch_slots ? (uint32_t)e : L.launch_slots;
-                    w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
-                    if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
-                }
-                if (cur >= 0 && pool.next < cur_end) {
-                    const uint32_t avail = min(pool.end, cur_end) - pool.next;
-                    const uint32_t rank = (uint32_t)__popcll(idle & below);
-                    if (st == 0 && rank < avail)
-                        st = w.start(items[cur], probs[items[cur].prob],
-                                     L.slot_begin + pool.next + rank - items[cur].slot_begin) ? 1 : 2;
-                    pool.next += min(avail, (uint32_t)__popcll(idle));
+            if (idle && q.next == q.end && !q.done) {
+                if (!q.dry) q.take(L, lane);
+                if (q.dry && idle == ~0ull) {
+                    const int prev = q.cur;
+                    uint32_t k;
+                    if (prev < 0) {  // first item: the one holding this wave's share of the launch
+                        const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+                        const uint32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+                        const uint64_t s0 = L.slot_begin + (uint64_t)gw * L.launch_slots / waves;
+                        k = (uint32_t)(find_item(items, L.n_items, s0) - L.item_lo);
+                        if (k >= L.n_seg) k = 0;
+                    } else {
+                        k = (uint32_t)(prev - L.item_lo) + 1;
+                        if (k >= L.n_seg) k = 0;
+                    }
+                    q.move(items, L, lane, k);
+                    if (!q.done && q.cur != prev) {
+                        const ItemDesc<T> &it = items[q.cur];
+                        w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
+                        if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
+                    }
                 }
             }
+            if (idle && q.next < q.end) {
+                const uint32_t avail = q.end - q.next;
+                const uint32_t rank = (uint32_t)__popcll(idle & below);
+                if (st == 0 && rank < avail) {
+                    const ItemDesc<T> &it = items[q.cur];
+                    st = w.start(it, probs[it.prob], L.slot_begin + q.next + rank - it.slot_begin) ? 1 : 2;
+                }
+                q.next += min(avail, (uint32_t)__popcll(idle));
+            }
             if (__ballot(st != 0) == 0) {
-                if (pool.exhausted && pool.next == pool.end) break;
+                if (q.done) break;
                 continue;
             }
         }
         if (st == 1) {
-            const ItemDesc<T> &a = items[cur];
+            const ItemDesc<T> &a = items[q.cur];
             const DevProblem<T> &P = probs[a.prob];
             if (D == 2) {
-                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
-                if (!w.step(a, P, q.w0, q.w1, 0u, 0u))
+                const Block4 b4 = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
+                if (!w.step(a, P, b4.w0, b4.w1, 0u, 0u))
                     st = 2;
-                else if (!w.step(a, P, q.w2, q.w3, 0u, 0u))
+                else if (!w.step(a, P, b4.w2, b4.w3, 0u, 0u))
                     st = 2;
             } else {
-                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
-                if (!w.step(a, P, q.w0, q.w1, q.w2, q.w3)) st = 2;
+                const Block4 b4 = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
+                if (!w.step(a, P, b4.w0, b4.w1, b4.w2, b4.w3)) st = 2;
             }
         }
     }

@@ -106,13 +106,20 @@ struct ItemDesc {
 
 // One launch of the path kernel: slots [slot_begin, slot_begin + launch_slots)
 // of the group's slot space, handed out through *counter.
+// The batch kernel keeps one queue per item that the launch touches (items
+// item_lo .. item_lo + n_seg - 1: counter[k] for item item_lo + k, whose
+// launch-relative slots are [seg[2k], seg[2k+1])); the single-item kernel
+// uses counter[0].
 struct LaunchArgs {
     uint64_t slot_begin;
     uint32_t launch_slots;
     int32_t n_items;
     int32_t grab;
-    int32_t pad;
+    int32_t item_lo;
+    uint32_t n_seg;
+    uint32_t pad;
     uint32_t *counter;
+    const uint32_t *seg;
 };
 
 // Compensated (Neumaier) per-node accumulators: phi, phi^2, e, e^2, phi*e.

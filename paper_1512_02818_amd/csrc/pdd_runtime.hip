@@ -450,8 +450,23 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
     const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
 
+    // queue counters: one per launch for the single-item kernel, one per item
+    // a launch touches for the batch kernel (items are sorted by slot), with
+    // that item's launch-relative slot range
+    std::vector<uint32_t> ctr_at(n_launch + 1, 0), seg_lo(n_launch, 0), seg_n(n_launch, 0);
+    for (uint64_t l = 0; l < n_launch; ++l) {
+        const uint64_t b = l * per_launch, e = std::min(total, b + per_launch);
+        const auto first = std::upper_bound(slot_begin.begin(), slot_begin.end(), b) - slot_begin.begin() - 1;
+        const auto last = std::upper_bound(slot_begin.begin(), slot_begin.end(), e - 1) - slot_begin.begin() - 1;
+        seg_lo[l] = (uint32_t)first;
+        seg_n[l] = (uint32_t)(last - first + 1);
+        ctr_at[l + 1] = ctr_at[l] + std::max<uint32_t>(seg_n[l], 1);
+    }
+    const size_t n_ctr = (size_t)ctr_at[n_launch] + 2;
+    const size_t ctr_bytes = (n_ctr * sizeof(uint32_t) + 7) & ~size_t(7);  // cleared in 8-byte words
+
     // staged upload: nodes | global node starts | item node starts | items |
-    // problems | node -> item | per-item post-processing entries
+    // problems | node -> item | per-item post-processing entries | queue ranges
     const size_t off_nodes = 0;
     const size_t off_gstart = align_up(off_nodes + n_nodes_all * D * sizeof(double), 256);
     const size_t off_istart = align_up(off_gstart + (n_nodes_all + 1) * sizeof(uint64_t), 256);
@@ -459,12 +474,13 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     const size_t off_probs = align_up(off_items + n_items * sizeof(ItemDesc<T>), 256);
     const size_t off_nitem = align_up(off_probs + probs.size() * sizeof(DevProblem<T>), 256);
     const size_t off_fitems = align_up(off_nitem + n_nodes_all * sizeof(uint32_t), 256);
-    const size_t bytes = align_up(off_fitems + n_items * sizeof(FinalItem), 256);
+    const size_t off_seg = align_up(off_fitems + n_items * sizeof(FinalItem), 256);
+    const size_t bytes = align_up(off_seg + n_ctr * 2 * sizeof(uint32_t), 256);
 
     pdd_status st;
     if ((st = ensure(ctx, ctx->nodes, bytes))) return st;
     if ((st = ensure(ctx, ctx->acc, n_nodes_all * sizeof(NodeAcc)))) return st;
-    if ((st = ensure(ctx, ctx->counters, (size_t)(n_launch + 2) * sizeof(uint32_t)))) return st;
+    if ((st = ensure(ctx, ctx->counters, ctr_bytes))) return st;
     const bool need_phi = std::any_of(items.begin(), items.end(), [](HostItem *i) { return i->score_plain && !i->caller_records; });
     const size_t per_slot = sizeof(uint32_t) + (need_phi ? 8 : 0) + (CV ? 8 : 0);
     double *sc_phi = nullptr, *sc_e = nullptr;
@@ -485,6 +501,16 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     DevProblem<T> *h_probs = reinterpret_cast<DevProblem<T> *>(h + off_probs);
     uint32_t *h_nitem = reinterpret_cast<uint32_t *>(h + off_nitem);
     FinalItem *h_fitems = reinterpret_cast<FinalItem *>(h + off_fitems);
+    uint32_t *h_seg = reinterpret_cast<uint32_t *>(h + off_seg);
+    for (uint64_t l = 0; l < n_launch; ++l) {
+        const uint64_t b = l * per_launch, e = std::min(total, b + per_launch);
+        for (uint32_t k = 0; k < seg_n[l]; ++k) {
+            const int q = (int)(seg_lo[l] + k);
+            const uint64_t lo = std::max(slot_begin[q], b), hi = std::min(slot_begin[q] + items[q]->total, e);
+            h_seg[2 * (ctr_at[l] + k)] = (uint32_t)(lo - b);
+            h_seg[2 * (ctr_at[l] + k) + 1] = (uint32_t)(std::max(lo, hi) - b);
+        }
+    }
     std::memset(h_items, 0, n_items * sizeof(ItemDesc<T>));
     std::memset(h_fitems, 0, n_items * sizeof(FinalItem));
     size_t istart_used = 0;
@@ -580,7 +606,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     NodeAcc *d_acc = static_cast<NodeAcc *>(ctx->acc.ptr);
     // zero sums, or the earlier paths' sums of accumulating items
     HIP_TRY(launch_init_acc(d_acc, (uint32_t)n_nodes_all, d_nitem, d_fitems, s));
-    HIP_TRY(launch_zero(ctx->counters.ptr, ((n_launch + 2) * sizeof(uint32_t) + 7) & ~size_t(7), s));
+    HIP_TRY(launch_zero(ctx->counters.ptr, ctr_bytes, s));
 
     const int block = tune.block;
     const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
@@ -613,7 +639,10 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         L.launch_slots = (uint32_t)len;
         L.n_items = n_items;
         L.grab = tune.grab;
-        L.counter = static_cast<uint32_t *>(ctx->counters.ptr) + launch;
+        L.counter = static_cast<uint32_t *>(ctx->counters.ptr) + ctr_at[launch];
+        L.item_lo = (int32_t)seg_lo[launch];
+        L.n_seg = seg_n[launch];
+        L.seg = reinterpret_cast<const uint32_t *>(dv + off_seg) + 2 * ctr_at[launch];
         const uint64_t waves_needed = (len + 63) / 64;
         const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));

@@ -87,3 +87,37 @@ def test_batch_chunked_and_empty(ctx):
     for a, b in zip(ref, got):
         assert np.array_equal(a["n"], b["n"]) and np.array_equal(a["steps_sum"], b["steps_sum"])
         assert np.allclose(a["mean"], b["mean"], rtol=1e-13, atol=1e-14, equal_nan=True)
+
+
+def test_many_small_items_under_any_launch_shape(ctx):
+    """Hundreds of small items in one group (empty items and nodes with no
+    paths among them), so waves move between the items' queues often: every
+    item's statistics equal its solo solve, bit for bit, under every launch
+    shape; with launches cut inside items (a node's paths then reach its sums
+    in two parts) counts are equal and means agree to rounding."""
+    prob = pdd.Problem(ctx, W.unit_square_problem(seed=11))
+    rng = np.random.default_rng(7)
+    base = W.unit_square_nodes()
+    items = []
+    for q in range(300):
+        nn = int(rng.integers(0, 8))
+        counts = rng.integers(0, 400, size=nn).astype(np.uint64)
+        if nn and q % 5 == 0:
+            counts[0] = 0
+        items.append({"problem": prob, "nodes": np.resize(base, (nn, 2)),
+                      "opts": dict(dt=1e-3, n_paths_per_node=counts, precision="fp32", stream_id=q)})
+    solo = [pdd.stats_to_numpy(pdd.solve_nodes(prob, it["nodes"], **it["opts"])) for it in items]
+    for tune in (None, (64, 1, 16, 0), (256, 0, 256, 0), (128, 3, 64, 5003)):
+        for it in items:
+            it["opts"] = {k: v for k, v in it["opts"].items() if k != "tuning"}
+            if tune:
+                it["opts"]["tuning"] = tune
+        got = [pdd.stats_to_numpy(o) for o in pdd.solve_batch(ctx, items)]
+        torch.cuda.synchronize()
+        for q, (a, b) in enumerate(zip(solo, got)):
+            if tune is None or tune[3] == 0:
+                assert a.tobytes() == b.tobytes(), (tune, q)
+            else:
+                assert np.array_equal(a["n"], b["n"]) and np.array_equal(a["steps_sum"], b["steps_sum"]), q
+                assert np.allclose(a["mean"], b["mean"], rtol=1e-13, atol=1e-14, equal_nan=True), q
+    prob.close()
