@@ -182,6 +182,14 @@ struct FinalizeArgs {
     const FinalItem *fitems;
 };
 
+// One item's statistics to copy into a contiguous buffer: n entries from src
+// to dst + at (so that many items come back to the host in one copy).
+struct GatherItem {
+    const pdd_node_stats *src;
+    uint64_t n;
+    uint64_t at;
+};
+
 // Kernel arguments of a launch that holds a single item: the item and its
 // problem travel by value (scalar loads from the argument segment).
 template <class T>
@@ -215,5 +223,7 @@ hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 // item's output for an accumulating solve.
 hipError_t launch_init_acc(NodeAcc *acc, uint32_t n, const uint32_t *node_item, const FinalItem *fitems,
                            hipStream_t s);
+// Copies the statistics of n_items items (table in device memory) into dst.
+hipError_t launch_gather_stats(const GatherItem *table, uint32_t n_items, pdd_node_stats *dst, hipStream_t s);
 
 }  // namespace pdd

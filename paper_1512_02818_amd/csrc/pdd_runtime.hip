@@ -804,7 +804,8 @@ void pdd_shutdown(pdd_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
-    for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials})
+    for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials,
+                            &ctx->gather})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);
@@ -941,10 +942,17 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int
     }
     pdd_status st = run_items(ctx, items, s);  // pilot
     if (st) return st;
-    // all pilot statistics back in one batch of copies into pinned memory
-    size_t total_nodes = 0;
-    for (int32_t q = 0; q < n_items; ++q) total_nodes += (size_t)std::max<int64_t>(0, witems[q].n_nodes);
-    const size_t rb_bytes = std::max<size_t>(total_nodes, 1) * sizeof(pdd_node_stats);
+    // all pilot statistics back in one copy into pinned memory, after a
+    // kernel has gathered the items' outputs into one device buffer (the
+    // gather table travels in the same pinned buffer, behind the statistics)
+    size_t total_nodes = 0, n_live = 0;
+    for (int32_t q = 0; q < n_items; ++q) {
+        total_nodes += (size_t)std::max<int64_t>(0, witems[q].n_nodes);
+        n_live += witems[q].n_nodes > 0;
+    }
+    const size_t stats_bytes = align_up(std::max<size_t>(total_nodes, 1) * sizeof(pdd_node_stats), 256);
+    const size_t rb_bytes = stats_bytes + std::max<size_t>(n_live, 1) * sizeof(GatherItem);
+    if ((st = ensure(ctx, ctx->gather, rb_bytes))) return st;
     if (rb_bytes > ctx->readback_cap) {
         if (ctx->readback) HIP_TRY(hipHostFree(ctx->readback));
         ctx->readback = nullptr;
@@ -956,15 +964,21 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int
         ctx->readback_cap = rb_bytes;
     }
     pdd_node_stats *pilot = static_cast<pdd_node_stats *>(ctx->readback);
+    GatherItem *table = reinterpret_cast<GatherItem *>(static_cast<char *>(ctx->readback) + stats_bytes);
     std::vector<size_t> at(n_items, 0);
-    size_t used = 0;
+    size_t used = 0, k = 0;
     for (int32_t q = 0; q < n_items; ++q) {
         const int64_t n = witems[q].n_nodes;
         at[q] = used;
         if (n <= 0) continue;
-        HIP_TRY(hipMemcpyAsync(pilot + used, witems[q].out, n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost, s));
+        table[k++] = GatherItem{static_cast<const pdd_node_stats *>(witems[q].out), (uint64_t)n, (uint64_t)used};
         used += (size_t)n;
     }
+    char *dg = static_cast<char *>(ctx->gather.ptr);
+    HIP_TRY(hipMemcpyAsync(dg + stats_bytes, table, k * sizeof(GatherItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_gather_stats(reinterpret_cast<const GatherItem *>(dg + stats_bytes), (uint32_t)k,
+                                reinterpret_cast<pdd_node_stats *>(dg), s));
+    HIP_TRY(hipMemcpyAsync(pilot, dg, used * sizeof(pdd_node_stats), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     // plan; items whose pilot already meets the target are done
     std::vector<std::vector<uint64_t>> counts(n_items);

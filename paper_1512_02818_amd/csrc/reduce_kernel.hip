@@ -312,6 +312,17 @@ __global__ void init_acc_kernel(NodeAcc *acc, uint32_t n, const uint32_t *node_i
     acc[i] = a;
 }
 
+// One workgroup per item, copying its statistics word by word.
+__global__ void gather_stats_kernel(const GatherItem *table, pdd_node_stats *dst)
+{
+    static_assert(sizeof(pdd_node_stats) % 8 == 0, "statistics are copied in 8-byte words");
+    const GatherItem g = table[blockIdx.x];
+    const uint64_t words = g.n * (sizeof(pdd_node_stats) / 8);
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(g.src);
+    uint64_t *out = reinterpret_cast<uint64_t *>(dst + g.at);
+    for (uint64_t q = threadIdx.x; q < words; q += blockDim.x) out[q] = src[q];
+}
+
 __global__ void zero_kernel(uint64_t *p, uint64_t n_words)
 {
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n_words;
@@ -346,6 +357,13 @@ hipError_t launch_init_acc(NodeAcc *acc, uint32_t n, const uint32_t *node_item, 
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(init_acc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n, node_item, fitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_stats(const GatherItem *table, uint32_t n_items, pdd_node_stats *dst, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_stats_kernel, dim3(n_items), dim3(256), 0, s, table, dst);
     return hipGetLastError();
 }
 
