@@ -69,11 +69,24 @@ struct DevProblem {
 template <class T>
 struct GridView {
     const T *data;
+    const T *cells;  // the same values by cell, corners of a cell together (or null)
     int32_t n[3];
     int32_t pad;
     T lo[3];
     T inv[3];  // (n - 1) / (hi - lo)
 };
+
+// Values of a grid gathered by cell: cell (i, j[, k]) at ((k (n1 - 1) + j)
+// (n0 - 1) + i) 2^dim, its corners in the order (0,0[,0]), (1,0), (0,1),
+// (1,1)[, then the same at k + 1]. One interpolation then reads one aligned
+// block instead of 2^dim scattered values.
+template <class T>
+size_t cell_values(const int32_t *n, int dim)
+{
+    size_t c = (size_t)1 << dim;
+    for (int d = 0; d < dim; ++d) c *= (size_t)(n[d] - 1);
+    return c;
+}
 
 // One work item: the paths of one solve (one problem, its nodes, its
 // estimator and options). Items occupy consecutive ranges of a launch group's
@@ -216,6 +229,9 @@ template <class T, int D, bool CV>
 hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s);
 template <class T, int D, bool CV>
 const void *path_kernel_symbol(bool one, bool spec);
+// Fills `cells` (cell_values entries) from the point values of a grid.
+template <class T, int D>
+hipError_t launch_grid_cells(const T *data, const int32_t *n, T *cells, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);

@@ -492,6 +492,30 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         sc_e = CV ? reinterpret_cast<double *>(base + (need_phi ? per_launch * 8 : 0)) : nullptr;
         sc_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((need_phi ? 8 : 0) + (CV ? 8 : 0)));
     }
+    // residual grids of a correction group in cell layout (the path kernel
+    // reads them at every step): one copy per distinct grid, rebuilt per
+    // solve since the caller may change a grid's values between solves
+    std::vector<const pdd_grid *> cell_grid;
+    std::vector<size_t> cell_off, cell_at(n_items, 0);
+    if (CV) {
+        size_t used = 0;
+        for (int q = 0; q < n_items; ++q) {
+            const pdd_grid *g = items[q]->resid;
+            size_t k = 0;
+            while (k < cell_grid.size() &&
+                   !(cell_grid[k]->data == g->data && std::equal(g->n, g->n + D, cell_grid[k]->n)))
+                ++k;
+            if (k == cell_grid.size()) {
+                cell_grid.push_back(g);
+                cell_off.push_back(used);
+                used += align_up(cell_values<T>(g->n, D), 64);
+            }
+            cell_at[q] = cell_off[k];
+        }
+        if ((st = ensure(ctx, ctx->cells, used * sizeof(T)))) return st;
+    }
+    T *d_cells = static_cast<T *>(ctx->cells.ptr);
+
     if ((st = ensure_stage(ctx, bytes))) return st;
     char *h = static_cast<char *>(ctx->stage);
     char *dv = static_cast<char *>(ctx->nodes.ptr);
@@ -576,6 +600,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         a.bridge_thresh = (T)kBridgeSkip;
         a.u_prev = make_view<T>(it.u_prev, D);
         a.resid = make_view<T>(it.resid, D);
+        if (CV) a.resid.cells = d_cells + cell_at[q];
     }
     h_gstart[n_nodes_all] = total;
     for (size_t p = 0; p < probs.size(); ++p)
@@ -607,6 +632,9 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     // zero sums, or the earlier paths' sums of accumulating items
     HIP_TRY(launch_init_acc(d_acc, (uint32_t)n_nodes_all, d_nitem, d_fitems, s));
     HIP_TRY(launch_zero(ctx->counters.ptr, ctr_bytes, s));
+    for (size_t k = 0; k < cell_grid.size(); ++k)
+        HIP_TRY((launch_grid_cells<T, D>(static_cast<const T *>(cell_grid[k]->data), cell_grid[k]->n,
+                                         d_cells + cell_off[k], s)));
 
     const int block = tune.block;
     const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
@@ -805,7 +833,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
     for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials,
-                            &ctx->gather})
+                            &ctx->gather, &ctx->cells})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);

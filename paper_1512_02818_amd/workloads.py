@@ -240,13 +240,14 @@ def _pert_grid(pert, shape, lo, hi):
 
 
 def correction_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=1e-2):
-    """u_prev = U + p on an n x n grid over the box, and the residual
-    r = f - (L + c) u_prev = -(1/2 sigma^2 Lap p + b.grad p + c p), both
-    evaluated exactly at the grid points in float64 and stored in `dtype`.
-    Returns (u_prev_grid, resid_grid, perturbation)."""
+    """u_prev = U + p on an n x n grid over the box (n: points per axis, or one
+    count per axis), and the residual r = f - (L + c) u_prev =
+    -(1/2 sigma^2 Lap p + b.grad p + c p), both evaluated exactly at the grid
+    points in float64 and stored in `dtype`. Returns (u_prev_grid,
+    resid_grid, perturbation)."""
     lo, hi = pd["lo"], pd["hi"]
     D = pd["dim"]
-    shape = (n,) * D
+    shape = tuple(int(v) for v in np.broadcast_to(np.asarray(n), (D,)))
     pts = grid_points(shape, lo, hi)
     pert = fourier_perturbation(seed, n_modes=n_modes, amp=amp, dim=D)
     p, gp, lp = _pert_grid(pert, shape, lo, hi)
@@ -255,8 +256,8 @@ def correction_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=
     s2 = pd["sigma"] ** 2
     resid = -(0.5 * s2 * lp + np.sum(b * gp, axis=1) + c * p)
     u_prev = manufactured_u(pd, pts) + p
-    mk = lambda v: {"dim": D, "n": [n] * D, "lo": list(lo), "hi": list(hi),  # noqa: E731
-                    "data": v.astype(dtype).reshape(shape)}
+    mk = lambda v: {"dim": D, "n": list(shape), "lo": list(lo), "hi": list(hi),  # noqa: E731
+                    "data": v.astype(dtype).reshape(shape[::-1])}
     return mk(u_prev), mk(resid), pert
 
 

@@ -188,6 +188,23 @@ def test_correction_fp64_per_path(ctx):
         assert np.allclose(st[f], ost[f], rtol=1e-6, atol=1e-9), f
 
 
+def test_correction_3d_fp64_per_path(ctx):
+    """The correction estimator in a 3D box with a full drift matrix and grids
+    of different sizes per axis (trilinear gathers of the residual at every
+    step, of u_prev at the exit), FP64 paths against the oracle path by path."""
+    pd, nodes = geometry_case("box3d")
+    gu, gr, _ = W.correction_grids(pd, n=(9, 13, 11), seed=2, dtype=np.float64)
+    n = 2000
+    st, rec = gpu_solve(ctx, pd, nodes, n, grids=(gu, gr), dt=1e-3, precision="fp64",
+                        plain_alongside=True)
+    ost, orec = oracle_solve(pd, nodes, n, grids=(gu, gr), dt=1e-3)
+    check_fp64_parity(st, rec, ost, orec, n, cv=True)
+    # FP32 paths on FP32 copies of the grids: means within 3 SE of the oracle
+    gu32, gr32, _ = W.correction_grids(pd, n=(9, 13, 11), seed=2, dtype=np.float32)
+    st32, _ = gpu_solve(ctx, pd, nodes, n, grids=(gu32, gr32), dt=1e-3, precision="fp32")
+    assert np.all(np.abs(st32["mean"] - ost["mean"]) <= 3 * ost["stderr"] + 1e-5)
+
+
 def test_correction_fp32_within_3se(ctx):
     pd = W.unit_square_problem(seed=13)
     gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)

@@ -48,6 +48,22 @@ def test_correction_grid_residual_by_finite_differences():
     assert np.isclose(gu["data"][i] - W.manufactured_u(pd, x[None, :])[0], p(x), rtol=0, atol=1e-14)
 
 
+def test_correction_grids_with_one_size_per_axis():
+    # n given per axis: data indexed [z, y, x] with x fastest, the point of
+    # index (i, j, k) at lo + (i, j, k) (hi - lo) / (n - 1)
+    rng = np.random.default_rng(3)
+    pd = W.random_problem(rng, dim=3)
+    shape = (9, 13, 11)
+    gu, gr, pert = W.correction_grids(pd, n=shape, seed=4, dtype=np.float64)
+    assert gu["n"] == list(shape) and gu["data"].shape == shape[::-1] == gr["data"].shape
+    lo, hi = np.asarray(pd["lo"]), np.asarray(pd["hi"])
+    for idx in ((0, 0, 0), (8, 12, 10), (3, 7, 5)):
+        x = lo + np.asarray(idx) * (hi - lo) / (np.asarray(shape) - 1)
+        p = W._pert_eval(pert, x[None, :], pd["lo"], pd["hi"])[0][0]
+        u = W.manufactured_u(pd, x[None, :])[0]
+        assert np.isclose(gu["data"][idx[::-1]], u + p, rtol=0, atol=1e-13)
+
+
 def test_serving_stream():
     problems, reqs = W.serving_stream(seed=5, rate=200.0, duration=5.0)
     assert 900 < len(reqs) < 1100  # Poisson(1000)
