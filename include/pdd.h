@@ -196,6 +196,31 @@ pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_pr
 /* Frees a problem; the caller ensures no solve using it is in flight. */
 void pdd_destroy_problem(pdd_problem *problem);
 
+/* Coefficients given on grids (Sec. 2.1, eq. F:EllipticBVP: b, c and f are
+ * general functions of x; the analytic family of pdd_problem_desc is a special
+ * case). Each non-NULL grid replaces one coefficient of the descriptor by its
+ * bilinear / trilinear interpolant (the pdd_grid rule): b[d] the drift
+ * component d (d < dim), c the killing rate, f the source. A grid has the
+ * problem's dim, n[d] >= 2 points per axis, dtype PDD_DTYPE_F32 or F64, data
+ * in device memory (x fastest) and a box [lo, hi] that contains the domain
+ * (the box itself, or the ball's bounding box). A NULL f keeps the source's
+ * analytic form, which uses the descriptor's analytic b and c; the boundary
+ * data g is always analytic. */
+typedef struct {
+    const pdd_grid *b[3];
+    const pdd_grid *c;
+    const pdd_grid *f;
+} pdd_coef_grids;
+
+/* As pdd_create_problem, with tabulated coefficients. The grids are read
+ * during the call: the library keeps its own copies (laid out by cell, in both
+ * path precisions) and the caller may free the grids when the call returns.
+ * Synchronous on the device. Errors: PDD_E_INVALID for a NULL `grids`, a
+ * malformed grid or one that does not contain the domain; PDD_E_NOMEM when
+ * the copies cannot be allocated; PDD_E_HIP on a device error. */
+pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *desc,
+                                        const pdd_coef_grids *grids, pdd_problem **out);
+
 /* Plain estimator phi at n_nodes nodes (host array, n_nodes x dim). Every
  * node must lie strictly inside Omega. `out` is device memory of n_nodes
  * entries. n_nodes == 0 is a no-op. */

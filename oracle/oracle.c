@@ -135,7 +135,8 @@ static double ipow(double x, int n)
     return r;
 }
 
-void orc_drift(const orc_problem *p, const double *x, double *b)
+/* The analytic drift and killing rate of the descriptor. */
+static void drift_analytic(const orc_problem *p, const double *x, double *b)
 {
     for (int i = 0; i < p->dim; ++i) {
         double v = p->b0[i];
@@ -144,11 +145,25 @@ void orc_drift(const orc_problem *p, const double *x, double *b)
     }
 }
 
-double orc_kill(const orc_problem *p, const double *x)
+static double kill_analytic(const orc_problem *p, const double *x)
 {
     double r2 = 0.0;
     for (int i = 0; i < p->dim; ++i) r2 += x[i] * x[i];
     return p->c_a + p->c_b * r2;
+}
+
+/* The coefficients the walk uses: a tabulated component where one is given
+ * (its grid interpolant), the analytic one otherwise. */
+void orc_drift(const orc_problem *p, const double *x, double *b)
+{
+    drift_analytic(p, x, b);
+    for (int i = 0; i < p->dim; ++i)
+        if (p->tab_b[i]) b[i] = orc_interp(p->tab_b[i], x);
+}
+
+double orc_kill(const orc_problem *p, const double *x)
+{
+    return p->tab_c ? orc_interp(p->tab_c, x) : kill_analytic(p, x);
 }
 
 static double mono_value(const orc_mono *m, int dim, const double *x)
@@ -219,12 +234,13 @@ double orc_U(const orc_problem *p, const double *x)
  * solves eq. F:EllipticBVP (written L u + c u = f). */
 double orc_source(const orc_problem *p, const double *x)
 {
+    if (p->tab_f) return orc_interp(p->tab_f, x);
     double u, l, g[3], b[3];
     U_full(p, x, &u, g, &l);
-    orc_drift(p, x, b);
+    drift_analytic(p, x, b);
     double f = 0.5 * p->sigma * p->sigma * l;
     for (int d = 0; d < p->dim; ++d) f += b[d] * g[d];
-    f += orc_kill(p, x) * u;
+    f += kill_analytic(p, x) * u;
     for (int m = 0; m < p->n_fx; ++m) f += mono_value(&p->fx[m], p->dim, x);
     return f;
 }
@@ -400,6 +416,14 @@ static int bad_problem(const orc_problem *p, const orc_opts *o)
     if (p->dim != 2 && p->dim != 3) return 1;
     if (!(o->h > 0.0) || !(p->sigma > 0.0)) return 1;
     if ((o->u_prev == NULL) != (o->resid == NULL)) return 1;
+    const orc_grid *tab[5] = {p->tab_b[0], p->tab_b[1], p->tab_b[2], p->tab_c, p->tab_f};
+    for (int q = 0; q < 5; ++q) {
+        if (!tab[q]) continue;
+        if (q < 3 && q >= p->dim) return 1;
+        if (tab[q]->dim != p->dim || !tab[q]->data) return 1;
+        for (int d = 0; d < p->dim; ++d)
+            if (tab[q]->n[d] < 2 || !(tab[q]->hi[d] > tab[q]->lo[d])) return 1;
+    }
     return 0;
 }
 

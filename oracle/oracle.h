@@ -42,10 +42,15 @@ typedef struct { double amp; double k[3]; double phase[3]; } orc_trig;
 /* coef * prod_d x_d^e[d] */
 typedef struct { double coef; int32_t e[3]; } orc_mono;
 
+struct orc_grid_s;
+
 /* Problem: (1/2) sigma^2 Lap u + b.grad u + c u = f in Omega, u = g on dOmega.
  * b(x) = b0 + B x, c(x) = c_a + c_b |x|^2.
  * U = sum of trig terms + sum of monomials (the manufactured solution);
- * f = (1/2) sigma^2 Lap U + b.grad U + c U + sum(fx),  g = U + sum(gx). */
+ * f = (1/2) sigma^2 Lap U + b.grad U + c U + sum(fx),  g = U + sum(gx).
+ * Tabulated coefficients: a non-NULL grid replaces the analytic b_d, c or f
+ * by its interpolant (f's analytic form always uses the analytic b and c);
+ * g is never tabulated. */
 typedef struct {
     int32_t dim;      /* 2 or 3 */
     int32_t domain;   /* ORC_BOX or ORC_BALL */
@@ -61,11 +66,14 @@ typedef struct {
     orc_mono fx[ORC_MAX_MONO];
     orc_mono gx[ORC_MAX_MONO];
     uint64_t seed;
+    const struct orc_grid_s *tab_b[3]; /* drift components, or NULL */
+    const struct orc_grid_s *tab_c;    /* killing rate, or NULL */
+    const struct orc_grid_s *tab_f;    /* source, or NULL */
 } orc_problem;
 
 /* Values at the n[0] x n[1] (x n[2]) points of a uniform grid on [lo,hi],
  * x fastest. */
-typedef struct {
+typedef struct orc_grid_s {
     int32_t dim;
     int32_t n[3];
     double lo[3], hi[3];

@@ -30,6 +30,12 @@ class _Mono(C.Structure):
     _fields_ = [("coef", C.c_double), ("e", C.c_int32 * 3)]
 
 
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("data", C.POINTER(C.c_double))]
+
+
 class Problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("domain", C.c_int32),
@@ -42,13 +48,8 @@ class Problem(C.Structure):
         ("trig", _Trig * MAX_TRIG), ("mono", _Mono * MAX_MONO),
         ("fx", _Mono * MAX_MONO), ("gx", _Mono * MAX_MONO),
         ("seed", C.c_uint64),
+        ("tab_b", C.POINTER(Grid) * 3), ("tab_c", C.POINTER(Grid)), ("tab_f", C.POINTER(Grid)),
     ]
-
-
-class Grid(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("data", C.POINTER(C.c_double))]
 
 
 class Opts(C.Structure):
@@ -166,6 +167,18 @@ def make_problem(pd: dict) -> Problem:
             for d in range(len(t["e"])):
                 arr[m].e[d] = int(t["e"][d])
     p.seed = int(pd.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    # tabulated coefficients: {"b": [grid or None per axis], "c": grid, "f": grid}
+    tab = pd.get("tab") or {}
+    keep = []
+    for d, gd in enumerate(tab.get("b") or []):
+        if gd is not None:
+            keep.append(_GridHolder(gd))
+            p.tab_b[d] = C.pointer(keep[-1].grid)
+    for field in ("c", "f"):
+        if tab.get(field) is not None:
+            keep.append(_GridHolder(tab[field]))
+            setattr(p, "tab_" + field, C.pointer(keep[-1].grid))
+    p._keep = keep  # noqa: SLF001 - lifetime of the grid copies
     return p
 
 

@@ -86,4 +86,5 @@ struct pdd_problem {
     pdd_problem_desc desc{};
     pdd::DevProblem<float> pf{};
     pdd::DevProblem<double> pd{};
+    pdd::DeviceBuffer tab;  // cell layouts of tabulated coefficients (FP32, then FP64)
 };

@@ -227,13 +227,21 @@ __device__ __forceinline__ T dense_poly(const T *c, const T *x)
     return accz;
 }
 
+template <class T, int D>
+__device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x);
+template <class T, int D>
+__device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T *x, const T *b, T c, T &f,
+                                                const T *cf);
+
 // b(x), c(x) and, when asked, f(x) = F(x) + sum over trig terms T of
 // (1/2) sigma^2 Lap T + b.grad T + c T, where Lap T = -|k|^2 T and
 // d_d T = amp k_d cos(k_d x_d + ph_d) prod_{e != d} sin(k_e x_e + ph_e).
 // The dense coefficients of F come from `cf` (a copy of P.fdense in LDS).
+// Tabulated coefficients (bit q of `tab`: tabv[q] replaces b_0, b_1, b_2, c,
+// f) are interpolated instead; the analytic f always uses the analytic b, c.
 template <class T, int D>
 __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x, T *b, T &c,
-                                             T &f, bool want_f, const T *cf)
+                                             T &f, bool want_f, const T *cf, uint32_t tab)
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -246,7 +254,26 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
 #pragma unroll
     for (int d = 0; d < D; ++d) r2 = madd(x[d], x[d], r2);
     c = madd(P.c_b, r2, P.c_a);
-    if (!want_f) return;
+    if (tab) {
+        if (want_f && (tab & 16u)) {
+            f = interp_cells<T, D>(P.tabv[4], x);
+            want_f = false;
+        }
+        if (want_f) analytic_source<T, D>(P, x, b, c, f, cf);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (tab & (1u << d)) b[d] = interp_cells<T, D>(P.tabv[d], x);
+        if (tab & 8u) c = interp_cells<T, D>(P.tabv[3], x);
+        return;
+    }
+    if (want_f) analytic_source<T, D>(P, x, b, c, f, cf);
+}
+
+// The analytic source for the analytic b and c.
+template <class T, int D>
+__device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T *x, const T *b, T c, T &f,
+                                                const T *cf)
+{
     T acc = (T)0;
     if (P.f_mode == kPolyDense)
         acc = dense_poly<T, D>(cf, x);
@@ -371,9 +398,10 @@ __device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
     return acc;
 }
 
-// Cell layout of a grid (see cell_values): one thread per cell.
-template <class T, int D>
-__global__ void grid_cells_kernel(const T *__restrict__ data, int n0, int n1, int n2, T *__restrict__ cells)
+// Cell layout of a grid (see cell_values), values converted from S to T: one
+// thread per cell.
+template <class S, class T, int D>
+__global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, int n2, T *__restrict__ cells)
 {
     const uint64_t m0 = (uint64_t)(n0 - 1), m1 = (uint64_t)(n1 - 1), m2 = D == 3 ? (uint64_t)(n2 - 1) : 1;
     const uint64_t n_cells = m0 * m1 * m2;
@@ -387,7 +415,7 @@ __global__ void grid_cells_kernel(const T *__restrict__ data, int n0, int n1, in
             for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 2; ++dx)
-                    out[(dz * 2 + dy) * 2 + dx] = data[((k + dz) * (uint64_t)n1 + (j + dy)) * (uint64_t)n0 + i + dx];
+                    out[(dz * 2 + dy) * 2 + dx] = (T)data[((k + dz) * (uint64_t)n1 + (j + dy)) * (uint64_t)n0 + i + dx];
     }
 }
 
@@ -401,6 +429,8 @@ struct RuntimeMode {
     __device__ static __forceinline__ int exit(const ItemDesc<T> &a) { return a.exit_mode; }
     template <class T>
     __device__ static __forceinline__ int law(const ItemDesc<T> &a) { return a.law; }
+    template <class T>
+    __device__ static __forceinline__ uint32_t tab(const DevProblem<T> &P) { return P.tab; }
 };
 struct BoxBridgeGauss {
     template <class T>
@@ -409,6 +439,8 @@ struct BoxBridgeGauss {
     __device__ static constexpr int exit(const ItemDesc<T> &) { return kExitBridge; }
     template <class T>
     __device__ static constexpr int law(const ItemDesc<T> &) { return kLawGauss; }
+    template <class T>
+    __device__ static constexpr uint32_t tab(const DevProblem<T> &) { return 0u; }
 };
 
 template <class T, int D>
@@ -574,7 +606,7 @@ struct Walker {
             if (D == 3) n[2 % D] = (wc >> 31) ? (T)1 : (T)-1;
         }
         T b[D], c, f = (T)0;
-        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0, cf);
+        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0, cf, M::tab(P));
         const T hY = a.h * Y;
         if (a.score_plain) Z -= (double)(hY * f);
         if (CV) R += (double)(hY * interp_cells<T, D>(a.resid, X));
@@ -1013,21 +1045,27 @@ const void *path_kernel_symbol(bool one, bool spec)
                 : reinterpret_cast<const void *>(&path_kernel_many<T, D, CV, RuntimeMode>);
 }
 
-template <class T, int D>
-hipError_t launch_grid_cells(const T *data, const int32_t *n, T *cells, hipStream_t s)
+template <class S, class T, int D>
+hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s)
 {
     const uint64_t n_cells = cell_values<T>(n, D) >> D;
     if (n_cells == 0) return hipSuccess;
     const uint64_t blocks = std::min<uint64_t>((n_cells + 255) / 256, 4096);
-    hipLaunchKernelGGL((grid_cells_kernel<T, D>), dim3((uint32_t)blocks), dim3(256), 0, s, data, n[0], n[1],
+    hipLaunchKernelGGL((grid_cells_kernel<S, T, D>), dim3((uint32_t)blocks), dim3(256), 0, s, data, n[0], n[1],
                        D == 3 ? n[2] : 2, cells);
     return hipGetLastError();
 }
 
-template hipError_t launch_grid_cells<float, 2>(const float *, const int32_t *, float *, hipStream_t);
-template hipError_t launch_grid_cells<float, 3>(const float *, const int32_t *, float *, hipStream_t);
-template hipError_t launch_grid_cells<double, 2>(const double *, const int32_t *, double *, hipStream_t);
-template hipError_t launch_grid_cells<double, 3>(const double *, const int32_t *, double *, hipStream_t);
+#define PDD_GRID_CELLS(S, T, D) \
+    template hipError_t launch_grid_cells<S, T, D>(const S *, const int32_t *, T *, hipStream_t);
+PDD_GRID_CELLS(float, float, 2)
+PDD_GRID_CELLS(float, float, 3)
+PDD_GRID_CELLS(double, double, 2)
+PDD_GRID_CELLS(double, double, 3)
+PDD_GRID_CELLS(float, double, 2)
+PDD_GRID_CELLS(float, double, 3)
+PDD_GRID_CELLS(double, float, 2)
+PDD_GRID_CELLS(double, float, 3)
 
 #define PDD_INSTANTIATE(T, D, CV)                                                              \
     template hipError_t launch_path_kernel<T, D, CV>(const LaunchArgs &, const ItemDesc<T> *, \

@@ -45,6 +45,18 @@ constexpr int kPolyNone = 0, kPolyDense = 1, kPolySparse = 2;
 // F = (1/2) sigma^2 Lap P + b.grad P + c P + fx and G = P + gx into monomials,
 // so that f = F + sum over trig terms of ((1/2) sigma^2 Lap + b.grad + c) T and
 // g = G + sum(trig).
+// A grid as the kernels read it: value(x) = bilinear / trilinear interpolation.
+// The values have the type of the path arithmetic.
+template <class T>
+struct GridView {
+    const T *data;
+    const T *cells;  // the same values by cell, corners of a cell together (or null)
+    int32_t n[3];
+    int32_t pad;
+    T lo[3];
+    T inv[3];  // (n - 1) / (hi - lo)
+};
+
 template <class T>
 struct DevProblem {
     int32_t dim, domain;
@@ -62,19 +74,13 @@ struct DevProblem {
     // dense coefficients of F, ordered for nested Horner evaluation: 2D by
     // j (power of y) then i (power of x), i + j <= 5; 3D by k, j, i
     T fdense[kMaxDense];
+    // tabulated coefficients: bit q of tab set when tabv[q] replaces the
+    // analytic b_0, b_1, b_2, c, f (q = 0..4); read through their cell layout
+    uint32_t tab;
+    int32_t tab_pad;
+    GridView<T> tabv[5];
 };
 
-// A grid as the kernels read it: value(x) = bilinear / trilinear interpolation.
-// The values have the type of the path arithmetic.
-template <class T>
-struct GridView {
-    const T *data;
-    const T *cells;  // the same values by cell, corners of a cell together (or null)
-    int32_t n[3];
-    int32_t pad;
-    T lo[3];
-    T inv[3];  // (n - 1) / (hi - lo)
-};
 
 // Values of a grid gathered by cell: cell (i, j[, k]) at ((k (n1 - 1) + j)
 // (n0 - 1) + i) 2^dim, its corners in the order (0,0[,0]), (1,0), (0,1),
@@ -229,9 +235,10 @@ template <class T, int D, bool CV>
 hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s);
 template <class T, int D, bool CV>
 const void *path_kernel_symbol(bool one, bool spec);
-// Fills `cells` (cell_values entries) from the point values of a grid.
-template <class T, int D>
-hipError_t launch_grid_cells(const T *data, const int32_t *n, T *cells, hipStream_t s);
+// Fills `cells` (cell_values entries) from the point values of a grid,
+// converted from S to T.
+template <class S, class T, int D>
+hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);

@@ -280,10 +280,15 @@ pdd_status check_grid(const pdd_problem_desc &d, const pdd_grid *g, int precisio
     if (!g) return fail(PDD_E_INVALID, "%s grid is NULL", name);
     if (g->dim != d.dim) return fail(PDD_E_INVALID, "%s grid dim %d != problem dim %d", name, g->dim, d.dim);
     if (!g->data) return fail(PDD_E_INVALID, "%s grid has no data", name);
-    const int want = precision == PDD_FP64 ? PDD_DTYPE_F64 : PDD_DTYPE_F32;
-    if (g->dtype != want)
-        return fail(PDD_E_UNSUPPORTED, "%s grid dtype must match the path precision (%s)", name,
-                    precision == PDD_FP64 ? "f64" : "f32");
+    if (precision < 0) {  // any supported dtype (converted by the library)
+        if (g->dtype != PDD_DTYPE_F32 && g->dtype != PDD_DTYPE_F64)
+            return fail(PDD_E_INVALID, "%s grid has an unknown dtype %d", name, g->dtype);
+    } else {
+        const int want = precision == PDD_FP64 ? PDD_DTYPE_F64 : PDD_DTYPE_F32;
+        if (g->dtype != want)
+            return fail(PDD_E_UNSUPPORTED, "%s grid dtype must match the path precision (%s)", name,
+                        precision == PDD_FP64 ? "f64" : "f32");
+    }
     for (int i = 0; i < d.dim; ++i) {
         if (g->n[i] < 2) return fail(PDD_E_INVALID, "%s grid needs >= 2 points per axis", name);
         if (!(g->lo[i] < g->hi[i])) return fail(PDD_E_INVALID, "%s grid needs lo < hi", name);
@@ -633,7 +638,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     HIP_TRY(launch_init_acc(d_acc, (uint32_t)n_nodes_all, d_nitem, d_fitems, s));
     HIP_TRY(launch_zero(ctx->counters.ptr, ctr_bytes, s));
     for (size_t k = 0; k < cell_grid.size(); ++k)
-        HIP_TRY((launch_grid_cells<T, D>(static_cast<const T *>(cell_grid[k]->data), cell_grid[k]->n,
+        HIP_TRY((launch_grid_cells<T, T, D>(static_cast<const T *>(cell_grid[k]->data), cell_grid[k]->n,
                                          d_cells + cell_off[k], s)));
 
     const int block = tune.block;
@@ -641,7 +646,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     // box / bridge / Gaussian throughout: the specialised kernel
     const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) {
         return i->prob->desc.domain == PDD_DOMAIN_BOX && i->o->exit_mode == PDD_EXIT_BRIDGE &&
-               i->o->law == PDD_LAW_GAUSS;
+               i->o->law == PDD_LAW_GAUSS && i->prob->pf.tab == 0;
     });
     const void *fn = path_kernel_symbol<T, D, CV>(one, spec);
     // more workgroups than fit at once only queue behind the resident ones
@@ -865,7 +870,99 @@ pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_pr
     return PDD_OK;
 }
 
-void pdd_destroy_problem(pdd_problem *problem) { delete problem; }
+void pdd_destroy_problem(pdd_problem *problem)
+{
+    if (!problem) return;
+    if (problem->tab.ptr) {
+        (void)hipSetDevice(problem->ctx->device);
+        (void)hipFree(problem->tab.ptr);
+    }
+    delete problem;
+}
+
+pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *desc, const pdd_coef_grids *grids,
+                                        pdd_problem **out)
+{
+    if (!ctx || !out) return fail(PDD_E_INVALID, "ctx and out must not be NULL");
+    *out = nullptr;
+    if (!grids) return fail(PDD_E_INVALID, "grids is NULL");
+    pdd_status st = check_desc(desc);
+    if (st) return st;
+    const pdd_grid *g[5] = {grids->b[0], grids->b[1], grids->b[2], grids->c, grids->f};
+    static const char *names[5] = {"b[0]", "b[1]", "b[2]", "c", "f"};
+    const int D = desc->dim;
+    if (D == 2 && g[2]) return fail(PDD_E_INVALID, "b[2] grid given for a 2D problem");
+    // both precisions' cell layouts of every given grid, in one allocation
+    size_t off32[5] = {}, off64[5] = {}, n32 = 0;
+    uint32_t tab = 0;
+    for (int q = 0; q < 5; ++q) {
+        if (!g[q]) continue;
+        if ((st = check_grid(*desc, g[q], -1, names[q]))) return st;
+        tab |= 1u << q;
+        off32[q] = n32;
+        n32 += align_up(cell_values<float>(g[q]->n, D), 64);
+    }
+    size_t n64 = 0;
+    for (int q = 0; q < 5; ++q)
+        if (tab & (1u << q)) {
+            off64[q] = n64;
+            n64 += align_up(cell_values<double>(g[q]->n, D), 64);
+        }
+    pdd_problem *p = new pdd_problem();
+    p->ctx = ctx;
+    p->desc = *desc;
+    if ((st = fill_problem(*desc, p->pf, true)) || (st = fill_problem(*desc, p->pd, false))) {
+        delete p;
+        return st;
+    }
+    if (tab) {
+        auto bail = [&](pdd_status s2) {
+            pdd_destroy_problem(p);
+            return s2;
+        };
+        if (hipSetDevice(ctx->device) != hipSuccess) return bail(fail(PDD_E_HIP, "hipSetDevice failed"));
+        const size_t bytes = align_up(n32 * sizeof(float), 256) + n64 * sizeof(double);
+        if (hipMalloc(&p->tab.ptr, bytes) != hipSuccess) {
+            p->tab.ptr = nullptr;
+            return bail(fail(PDD_E_NOMEM, "hipMalloc of %zu bytes for tabulated coefficients failed", bytes));
+        }
+        p->tab.cap = bytes;
+        float *c32 = static_cast<float *>(p->tab.ptr);
+        double *c64 = reinterpret_cast<double *>(static_cast<char *>(p->tab.ptr) + align_up(n32 * sizeof(float), 256));
+        for (int q = 0; q < 5; ++q) {
+            if (!(tab & (1u << q))) continue;
+            const pdd_grid *gq = g[q];
+            hipError_t e1, e2;
+            if (gq->dtype == PDD_DTYPE_F32) {
+                const float *src = static_cast<const float *>(gq->data);
+                e1 = D == 2 ? launch_grid_cells<float, float, 2>(src, gq->n, c32 + off32[q], nullptr)
+                            : launch_grid_cells<float, float, 3>(src, gq->n, c32 + off32[q], nullptr);
+                e2 = D == 2 ? launch_grid_cells<float, double, 2>(src, gq->n, c64 + off64[q], nullptr)
+                            : launch_grid_cells<float, double, 3>(src, gq->n, c64 + off64[q], nullptr);
+            } else {
+                const double *src = static_cast<const double *>(gq->data);
+                e1 = D == 2 ? launch_grid_cells<double, float, 2>(src, gq->n, c32 + off32[q], nullptr)
+                            : launch_grid_cells<double, float, 3>(src, gq->n, c32 + off32[q], nullptr);
+                e2 = D == 2 ? launch_grid_cells<double, double, 2>(src, gq->n, c64 + off64[q], nullptr)
+                            : launch_grid_cells<double, double, 3>(src, gq->n, c64 + off64[q], nullptr);
+            }
+            if (e1 != hipSuccess || e2 != hipSuccess)
+                return bail(fail(PDD_E_HIP, "cell layout of the %s grid: %s", names[q],
+                                 hipGetErrorString(e1 != hipSuccess ? e1 : e2)));
+            p->pf.tabv[q] = make_view<float>(gq, D);
+            p->pf.tabv[q].data = nullptr;
+            p->pf.tabv[q].cells = c32 + off32[q];
+            p->pd.tabv[q] = make_view<double>(gq, D);
+            p->pd.tabv[q].data = nullptr;
+            p->pd.tabv[q].cells = c64 + off64[q];
+        }
+        const hipError_t e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) return bail(fail(PDD_E_HIP, "tabulated coefficients: %s", hipGetErrorString(e)));
+        p->pf.tab = p->pd.tab = tab;
+    }
+    *out = p;
+    return PDD_OK;
+}
 
 pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                            const pdd_solve_opts *opts, pdd_node_stats *out, void *stream)
@@ -1070,7 +1167,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     if (prec != PDD_FP32 && prec != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
     HIP_TRY(hipSetDevice(ctx->device));
     // the kernel this group launches for a single item, and its occupancy
-    const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX &&
+    const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX && item->problem->pf.tab == 0 &&
                       item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS;
     const void *fn = nullptr;
     if (prec == PDD_FP32)

@@ -53,6 +53,10 @@ class Grid(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("data", C.c_void_p)]
 
 
+class CoefGrids(C.Structure):
+    _fields_ = [("b", C.POINTER(Grid) * 3), ("c", C.POINTER(Grid)), ("f", C.POINTER(Grid))]
+
+
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32),
                 ("max_launch_paths", C.c_int32)]
@@ -127,6 +131,8 @@ SIGNATURES = {
     "pdd_shutdown": (None, [C.c_void_p]),
     "pdd_create_problem": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.POINTER(C.c_void_p)]),
     "pdd_destroy_problem": (None, [C.c_void_p]),
+    "pdd_create_problem_tabulated": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.POINTER(CoefGrids),
+                                                 C.POINTER(C.c_void_p)]),
     "pdd_solve_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
                                     C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
     "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
@@ -281,15 +287,39 @@ class Context:
 
 
 class Problem:
-    """A problem uploaded to a context (pdd_create_problem)."""
+    """A problem uploaded to a context (pdd_create_problem). A "tab" entry of
+    the problem dict ({"b": [grid or None per axis], "c": grid, "f": grid},
+    grids as for correction solves) gives tabulated coefficients
+    (pdd_create_problem_tabulated); their values are copied to the device for
+    the call and kept by the library."""
 
     def __init__(self, ctx: Context, pd: dict):
+        import torch
         self.ctx = ctx
         self.pd = pd
         self.dim = int(pd["dim"])
         self.desc = problem_desc(pd)
         h = C.c_void_p()
-        _check(lib().pdd_create_problem(ctx.handle, C.byref(self.desc), C.byref(h)))
+        tab = pd.get("tab")
+        if tab:
+            cg = CoefGrids()
+            keep = []
+
+            def dev(gd):
+                t = torch.as_tensor(np.ascontiguousarray(gd["data"])).cuda().contiguous()
+                g = grid_struct(gd, t)
+                keep.append((t, g))
+                return C.pointer(g)
+            for d, gd in enumerate(tab.get("b") or []):
+                if gd is not None:
+                    cg.b[d] = dev(gd)
+            for field in ("c", "f"):
+                if tab.get(field) is not None:
+                    setattr(cg, field, dev(tab[field]))
+            _check(lib().pdd_create_problem_tabulated(ctx.handle, C.byref(self.desc), C.byref(cg),
+                                                      C.byref(h)))
+        else:
+            _check(lib().pdd_create_problem(ctx.handle, C.byref(self.desc), C.byref(h)))
         self.handle = h
 
     def close(self):

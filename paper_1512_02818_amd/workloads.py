@@ -175,6 +175,84 @@ def manufactured_u(pd: dict, pts) -> np.ndarray:
     return out
 
 
+def manufactured_derivs(pd: dict, pts):
+    """U, grad U (n x dim) and Lap U at the points, term by term from the
+    trig and monomial terms of U."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    dim = pd["dim"]
+    u = np.zeros(len(pts))
+    grad = np.zeros((len(pts), dim))
+    lap = np.zeros(len(pts))
+    for t in pd.get("trig", []):
+        s = np.stack([np.sin(t["k"][d] * pts[:, d] + t["phase"][d]) for d in range(dim)], axis=1)
+        c = np.stack([np.cos(t["k"][d] * pts[:, d] + t["phase"][d]) for d in range(dim)], axis=1)
+        v = float(t["amp"]) * np.prod(s, axis=1)
+        u += v
+        lap -= sum(t["k"][d] ** 2 for d in range(dim)) * v
+        for d in range(dim):
+            grad[:, d] += float(t["amp"]) * t["k"][d] * c[:, d] * np.prod(np.delete(s, d, axis=1), axis=1)
+    for m in pd.get("mono", []):
+        e = [int(m["e"][d]) for d in range(dim)]
+        pw = lambda d, k: pts[:, d] ** k if k >= 0 else np.zeros(len(pts))  # noqa: E731
+        u += float(m["coef"]) * np.prod([pw(d, e[d]) for d in range(dim)], axis=0)
+        for d in range(dim):
+            rest = np.prod([pw(q, e[q]) for q in range(dim) if q != d], axis=0)
+            grad[:, d] += float(m["coef"]) * e[d] * pw(d, e[d] - 1) * rest
+            lap += float(m["coef"]) * e[d] * (e[d] - 1) * pw(d, e[d] - 2) * rest
+    return u, grad, lap
+
+
+def bounding_box(pd: dict):
+    """lo, hi of the domain's bounding box."""
+    D = pd["dim"]
+    if pd.get("domain", "box") == "box":
+        return [float(v) for v in pd["lo"][:D]], [float(v) for v in pd["hi"][:D]]
+    c, r = pd["center"], float(pd["radius"])
+    return [float(c[d]) - r for d in range(D)], [float(c[d]) + r for d in range(D)]
+
+
+def tabulated_problem(pd: dict, n=65, fields=("b", "c", "f"), seed=0, amp=0.3, dtype=np.float64):
+    """pd with tabulated coefficients ("tab") on n^dim grids over the domain's
+    bounding box. Tabulated b and c are the analytic ones plus smooth
+    non-affine terms (amp = 0: exactly the analytic ones):
+      b_d += amp sin(2 pi k_d.x + ph_d),  c -= amp (1 + cos(2 pi k_c.x + ph_c)) / 2,
+    with random integer wave vectors k in 1..2; a tabulated f is
+    (1/2) sigma^2 Lap U + b.grad U + c U + sum(fx) for the b and c the walk
+    uses, so U stays the exact solution up to the interpolation error (with f
+    analytic, only amp = 0 keeps that)."""
+    D = pd["dim"]
+    lo, hi = bounding_box(pd)
+    shape = (int(n),) * D
+    pts = grid_points(shape, lo, hi)
+    rng = np.random.default_rng(seed)
+    b = np.asarray(pd.get("b0", [0.0] * 3), dtype=np.float64)[None, :D] + pts @ np.asarray(
+        pd.get("B", np.zeros((3, 3))), dtype=np.float64)[:D, :D].T
+    c = pd.get("c_a", 0.0) + pd.get("c_b", 0.0) * np.sum(pts ** 2, axis=1)
+    if "b" in fields:
+        for d in range(D):
+            k = rng.integers(1, 3, size=D)
+            b[:, d] += amp * np.sin(2 * PI * pts @ k + rng.uniform(0, 2 * PI))
+    if "c" in fields:
+        k = rng.integers(1, 3, size=D)
+        c = c - amp * 0.5 * (1.0 + np.cos(2 * PI * pts @ k + rng.uniform(0, 2 * PI)))
+    mk = lambda v: {"dim": D, "n": list(shape), "lo": list(lo), "hi": list(hi),  # noqa: E731
+                    "data": np.asarray(v).astype(dtype).reshape(shape[::-1])}
+    tab = {}
+    if "b" in fields:
+        tab["b"] = [mk(b[:, d]) for d in range(D)]
+    if "c" in fields:
+        tab["c"] = mk(c)
+    if "f" in fields:
+        u, grad, lap = manufactured_derivs(pd, pts)
+        f = 0.5 * pd["sigma"] ** 2 * lap + np.sum(b * grad, axis=1) + c * u
+        for m in pd.get("fx", []):
+            f += m["coef"] * np.prod([pts[:, d] ** m["e"][d] for d in range(D)], axis=0)
+        tab["f"] = mk(f)
+    out = dict(pd)
+    out["tab"] = tab
+    return out
+
+
 # --------------------------------------------------------------------------- grids
 def grid_points(n, lo, hi):
     """Coordinates of an n[0] x n[1] (x n[2]) uniform grid, x fastest, shape

@@ -33,7 +33,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(built_lib):
     names = declared_functions()
-    assert len(names) == 18, names
+    assert len(names) == 19, names
     for n in names:
         assert hasattr(built_lib, n), n
     assert set(names) == set(pdd.SIGNATURES)
@@ -55,6 +55,7 @@ def test_null_arguments_are_rejected_without_gpu(built_lib):
     assert built_lib.pdd_init(None, 0) == -1
     assert b"NULL" in built_lib.pdd_last_error()
     assert built_lib.pdd_create_problem(None, None, None) == -1
+    assert built_lib.pdd_create_problem_tabulated(None, None, None, None) == -1
     assert built_lib.pdd_solve_nodes(None, None, 0, None, None, None) == -1
     assert built_lib.pdd_solve_batch(None, None, 0, None) == -1
     assert built_lib.pdd_server_create(None, None, None) == -1
@@ -70,6 +71,7 @@ STRUCTS = {
     "pdd_problem_desc": (pdd.ProblemDesc, ["dim", "lo", "radius", "sigma", "B", "c_b", "n_gx",
                                            "trig", "mono", "fx", "gx", "seed"]),
     "pdd_grid": (pdd.Grid, ["dtype", "n", "lo", "hi", "data"]),
+    "pdd_coef_grids": (pdd.CoefGrids, ["b", "c", "f"]),
     "pdd_tuning": (pdd.Tuning, ["block", "grab"]),
     "pdd_solve_opts": (pdd.SolveOpts, ["dt", "n_paths_per_node", "path_offset", "stream_id",
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),
