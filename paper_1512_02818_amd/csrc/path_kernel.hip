@@ -316,22 +316,23 @@ __device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x)
     return u;
 }
 
-// Cell of a grid holding x (indices clamped to the grid, so points on or
-// just outside the boundary use the edge cells) and the weights within it.
+// Cell of a grid holding x and the weights within it: cell index floor(t)
+// clamped to [0, n - 2] and weight t - index clamped to [0, 1], for
+// t = (x - lo) inv. Clamping t to [0, n - 1] first gives exactly those values
+// (below 0: cell 0, weight 0; from n - 1 up: cell n - 2, weight 1) with one
+// truncation and no floor.
 template <class T, int D>
 __device__ __forceinline__ void grid_cell(const GridView<T> &g, const T *x, int *i, T *w)
 {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const T t = (x[d] - g.lo[d]) * g.inv[d];
-        const T fl = floor(t);
-        int id = (int)fl;
-        if (fl < (T)0) id = 0;
-        if (fl > (T)(g.n[d] - 2)) id = g.n[d] - 2;
-        T wd = t - (T)id;
-        wd = wd < (T)0 ? (T)0 : (wd > (T)1 ? (T)1 : wd);
+        const T top = (T)(g.n[d] - 1);
+        T t = (x[d] - g.lo[d]) * g.inv[d];
+        t = t > (T)0 ? (t < top ? t : top) : (T)0;
+        int id = (int)t;
+        id = id < g.n[d] - 2 ? id : g.n[d] - 2;
         i[d] = id;
-        w[d] = wd;
+        w[d] = t - (T)id;
     }
 }
 
