@@ -121,3 +121,25 @@ def test_malformed_grids_are_rejected(ctx):
     assert create(good, slot="b2") == -1                  # b[2] of a 2D problem
     h = C.c_void_p()
     assert L.pdd_create_problem_tabulated(ctx.handle, C.byref(desc), None, C.byref(h)) == -1
+
+
+def test_tabulated_problem_served_like_solved_to_tolerance(ctx):
+    """A tabulated problem through the serving loop and through
+    pdd_solve_to_tolerance: the same plan (path counts, steps) and means."""
+    pd, tab = _tab_2d(n=33)
+    prob = pdd.Problem(ctx, tab)
+    nodes = W.unit_square_nodes()[::4]
+    se = 3e-3
+    sv = pdd.Server(ctx, epoch_paths=1 << 22, chunk_paths=1 << 17)
+    rid = sv.submit(prob, nodes, 1e-3, se, precision="fp32", stream_id=9, tag=9)
+    assert sv.wait_all(120)
+    got = sv.results[rid]
+    sv.close()
+    assert got["status"] == 0
+    item = {"problem": prob, "nodes": nodes, "opts": dict(dt=1e-3, precision="fp32", stream_id=9)}
+    (o,) = pdd.solve_to_tolerance(ctx, [item], se, 1000, 1 << 31)
+    st = pdd.stats_to_numpy(o)
+    assert np.array_equal(st["n"], got["stats"]["n"]) and np.array_equal(st["steps_sum"], got["stats"]["steps_sum"])
+    assert np.allclose(st["mean"], got["stats"]["mean"], rtol=1e-12, atol=1e-14)
+    assert np.all(st["stderr"] <= 1.3 * se)
+    prob.close()
