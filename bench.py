@@ -13,8 +13,8 @@ the device, timed with HIP events on the solve's stream), the roofline of the
 path kernel (VALU-issue bound; the per-step operation count is STEP_COST
 below), node-solves/s at a fixed RMS error for the correction estimator in
 FP32 and the plain estimator in FP64, the correction iterates, a batched
-solve, a serving run, and the CPU oracle timed on a bounded sample of the
-same workload.
+solve, two serving runs (overload and a sustainable load), and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -86,7 +86,8 @@ def parse():
     ap.add_argument("--rms-replicas-cv", type=int, default=2000,
                     help="copies of the 18 unit-square nodes (distinct streams), CV + FP32")
     ap.add_argument("--serve-duration", type=float, default=2.0,
-                    help="seconds of Poisson arrivals (200 requests/s) for the serving loop (0 = skip)")
+                    help="seconds of Poisson arrivals at 200 requests/s for the serving loop, then twice "
+                         "as long at 10 requests/s (0 = skip)")
     ap.add_argument("--serve-drain", type=float, default=10.0,
                     help="seconds to wait for completions after the last arrival")
     ap.add_argument("--tuning", default="cache",
@@ -457,6 +458,15 @@ def main():
                            "(129^2-513^2 or 65^3), FP32, 64 GiB budget; requests still running after "
                            "the drain are cancelled and reported")
         result["serving"] = rep
+        # the same kind of stream at a load one GPU sustains: latency without a backlog
+        problems, reqs = W.serving_stream(seed=6, rate=10.0, duration=2 * args.serve_duration)
+        rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=args.serve_drain,
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
+        rep["workload"] = ("the same request mix as 'serving' (seed 6), Poisson 10 requests/s for "
+                           f"{2 * args.serve_duration:g} s")
+        result["serving_light"] = rep
+        print(f"serving at 10 requests/s: {rep['completed']} of {rep['offered_requests']} completed, "
+              f"p50 {rep['p50_ms']:.0f} ms, p99 {rep['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
     if args.cpu_paths > 0:
         print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(pd, nodes, args.cpu_paths)
