@@ -17,6 +17,10 @@
  *                          time (Fourier series), the time-step bias trend.
  *   discrete scheme      - brute-force enumeration of every Rademacher path.
  *   correction estimator - zero-variance invariant for a bilinear solution.
+ *   tabulated b, c, f    - affine drift / constant killing on grids walk the
+ *                          analytic problem's paths; non-affine tabulated
+ *                          coefficients with the matching f keep the
+ *                          manufactured solution.
  *   sums / statistics    - math.fsum of the per-path records.
  * No function here is "parity unpinned".
  */
