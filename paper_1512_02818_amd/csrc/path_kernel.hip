@@ -427,9 +427,9 @@ struct RuntimeMode {
     template <class T>
     __device__ static __forceinline__ int domain(const DevProblem<T> &P) { return P.domain; }
     template <class T>
-    __device__ static __forceinline__ int exit(const ItemDesc<T> &a) { return a.exit_mode; }
+    __device__ static __forceinline__ int exit(const ItemCore<T> &a) { return a.exit_mode; }
     template <class T>
-    __device__ static __forceinline__ int law(const ItemDesc<T> &a) { return a.law; }
+    __device__ static __forceinline__ int law(const ItemCore<T> &a) { return a.law; }
     template <class T>
     __device__ static __forceinline__ uint32_t tab(const DevProblem<T> &P) { return P.tab; }
 };
@@ -437,9 +437,9 @@ struct BoxBridgeGauss {
     template <class T>
     __device__ static constexpr int domain(const DevProblem<T> &) { return kBox; }
     template <class T>
-    __device__ static constexpr int exit(const ItemDesc<T> &) { return kExitBridge; }
+    __device__ static constexpr int exit(const ItemCore<T> &) { return kExitBridge; }
     template <class T>
-    __device__ static constexpr int law(const ItemDesc<T> &) { return kLawGauss; }
+    __device__ static constexpr int law(const ItemCore<T> &) { return kLawGauss; }
     template <class T>
     __device__ static constexpr uint32_t tab(const DevProblem<T> &) { return 0u; }
 };
@@ -519,7 +519,9 @@ __device__ __forceinline__ void project(const DevProblem<T> &P, int domain, cons
 }
 
 // State of the path a lane is walking.
-template <class T, int D, bool CV, class M>
+// RNG_TABLE: items may be merged solves with a per-node RNG table (batch
+// kernel); the single-item kernel takes the stream tag from its item.
+template <class T, int D, bool CV, class M, bool RNG_TABLE>
 struct Walker {
     T X[D], Xt[D];
     T Y;
@@ -527,6 +529,11 @@ struct Walker {
     double Z, R;
     uint64_t slot;
     uint32_t k, j, node, capped;
+    uint32_t tag;  // stream tag of the path's solve (RNG_TABLE)
+
+    // Stream tag of the path: its own with an RNG table, else the item's
+    // (a wave-uniform scalar).
+    __device__ __forceinline__ uint32_t stream(const ItemCore<T> &a) const { return RNG_TABLE ? tag : a.stream_tag; }
     uint32_t bb_blk;
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
     KeySchedule ks;
@@ -534,7 +541,7 @@ struct Walker {
 
     // Starts path r (slot within the item) of item a. Returns false when it
     // ends before any step (a node inside the shift band of the shifted test).
-    __device__ __forceinline__ bool start(const ItemDesc<T> &a, const DevProblem<T> &P, uint64_t r)
+    __device__ __forceinline__ bool start(const ItemCore<T> &a, const DevProblem<T> &P, uint64_t r, const uint32_t *node_rng)
     {
         slot = r;
         uint64_t jj;
@@ -559,9 +566,21 @@ struct Walker {
             node = lo;
             jj = r - a.node_start[lo];
         }
+        // the path's RNG counter: its node, stream and path index in its own solve
         j = (uint32_t)(a.path_offset + jj);
+        uint32_t rnode = node;
+        if (RNG_TABLE) {
+            tag = a.stream_tag;
+            if (node_rng) {
+                const uint4 v = reinterpret_cast<const uint4 *>(node_rng)[node];
+                rnode = v.x;
+                tag = v.y;
+                j = v.z + (uint32_t)jj;
+            }
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
+        node = rnode;
         m = inner_distance<T, D>(P, M::domain(P), X);
         Y = (T)1;
         Z = 0.0;
@@ -576,11 +595,11 @@ struct Walker {
         return true;
     }
 
-    __device__ __forceinline__ T bridge_uniform(const ItemDesc<T> &a, uint32_t s)
+    __device__ __forceinline__ T bridge_uniform(const ItemCore<T> &a, uint32_t s)
     {
         const uint32_t blk = s >> 2;
         if (blk != bb_blk) {
-            const Block4 q = philox(blk, j, node, a.stream_tag | 1u, ks);
+            const Block4 q = philox(blk, j, node, stream(a) | 1u, ks);
             bw01 = (uint64_t)q.w0 | ((uint64_t)q.w1 << 32);
             bw23 = (uint64_t)q.w2 | ((uint64_t)q.w3 << 32);
             bb_blk = blk;
@@ -594,7 +613,7 @@ struct Walker {
     // false when the path has ended (exit point in Xt). Everything that ends a
     // path (leaving the domain, a live bridge face, the shift band of the next
     // step, the step cap) goes through one rarely taken branch.
-    __device__ __forceinline__ bool step(const ItemDesc<T> &a, const DevProblem<T> &P, uint32_t wa,
+    __device__ __forceinline__ bool step(const ItemCore<T> &a, const DevProblem<T> &P, uint32_t wa,
                                          uint32_t wb, uint32_t wc, uint32_t wd)
     {
         T n[D];
@@ -668,7 +687,7 @@ struct Walker {
     // Brownian-bridge exit between X and Xn (both inside, Xn at distance mn).
     // Per flat face P(cross) = exp(-2 a a' / (sigma^2 h)), faces combined as
     // independent; exit onto the live face with the largest probability.
-    __device__ __forceinline__ bool bridge_exit(const ItemDesc<T> &a, const DevProblem<T> &P,
+    __device__ __forceinline__ bool bridge_exit(const ItemCore<T> &a, const DevProblem<T> &P,
                                                 const T *Xn, T mn, uint32_t s)
     {
         if (M::domain(P) == kBox) {
@@ -726,7 +745,7 @@ struct Walker {
     }
 
     // Score the ended path and write its record at slot - rec_base.
-    __device__ __forceinline__ void finish(const ItemDesc<T> &a, const DevProblem<T> &P,
+    __device__ __forceinline__ void finish(const ItemCore<T> &a, const DevProblem<T> &P,
                                            uint64_t rec_base)
     {
         const T gv = boundary_value<T, D>(P, Xt);
@@ -798,14 +817,14 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 {
     static_assert(kOneItemKernel<T, D, CV>, "single-item kernel is for FP32 2D plain solves");
     const LaunchArgs &L = A.launch;
-    const ItemDesc<T> &a = A.item;
+    const ItemCore<T> &a = A.item;
     const DevProblem<T> &P = A.prob;
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[kMaxDense];
     for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
     __syncthreads();
-    Walker<T, D, CV, M> w;
+    Walker<T, D, CV, M, false> w;
     w.cf = s_cf;
     w.ks = key_schedule(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
@@ -822,7 +841,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
                 pool.refill(L, lane);
                 const uint32_t avail = pool.end - pool.next;
                 const uint32_t rank = (uint32_t)__popcll(idle & below);
-                if (st == 0 && rank < avail) st = w.start(a, P, L.slot_begin + pool.next + rank) ? 1 : 2;  // the one item starts at slot 0
+                if (st == 0 && rank < avail) st = w.start(a, P, L.slot_begin + pool.next + rank, nullptr) ? 1 : 2;  // the one item starts at slot 0
                 pool.next += min(avail, (uint32_t)__popcll(idle));
             }
             if (__ballot(st != 0) == 0) {
@@ -833,13 +852,13 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
         if (st == 1) {
             // One Philox block feeds two steps in 2D (words 0,1 then 2,3), one in 3D.
             if (D == 2) {
-                const Block4 q = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
+                const Block4 q = philox(w.k >> 1, w.j, w.node, w.stream(a), w.ks);
                 if (!w.step(a, P, q.w0, q.w1, 0u, 0u))
                     st = 2;
                 else if (!w.step(a, P, q.w2, q.w3, 0u, 0u))
                     st = 2;
             } else {
-                const Block4 q = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
+                const Block4 q = philox(w.k, w.j, w.node, w.stream(a), w.ks);
                 if (!w.step(a, P, q.w0, q.w1, q.w2, q.w3)) st = 2;
             }
         }
@@ -937,7 +956,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[256 / 64][kMaxDense];
     T *my_cf = s_cf[threadIdx.x >> 6];
-    Walker<T, D, CV, M> w;
+    Walker<T, D, CV, M, true> w;
     w.cf = my_cf;
     int st = 0;
     ItemQueue<T> q;
@@ -979,7 +998,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const uint32_t rank = (uint32_t)__popcll(idle & below);
                 if (st == 0 && rank < avail) {
                     const ItemDesc<T> &it = items[q.cur];
-                    st = w.start(it, probs[it.prob], L.slot_begin + q.next + rank - it.slot_begin) ? 1 : 2;
+                    st = w.start(it, probs[it.prob], L.slot_begin + q.next + rank - it.slot_begin, it.node_rng) ? 1 : 2;
                 }
                 q.next += min(avail, (uint32_t)__popcll(idle));
             }
@@ -992,13 +1011,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             const ItemDesc<T> &a = items[q.cur];
             const DevProblem<T> &P = probs[a.prob];
             if (D == 2) {
-                const Block4 b4 = philox(w.k >> 1, w.j, w.node, a.stream_tag, w.ks);
+                const Block4 b4 = philox(w.k >> 1, w.j, w.node, w.stream(a), w.ks);
                 if (!w.step(a, P, b4.w0, b4.w1, 0u, 0u))
                     st = 2;
                 else if (!w.step(a, P, b4.w2, b4.w3, 0u, 0u))
                     st = 2;
             } else {
-                const Block4 b4 = philox(w.k, w.j, w.node, a.stream_tag, w.ks);
+                const Block4 b4 = philox(w.k, w.j, w.node, w.stream(a), w.ks);
                 if (!w.step(a, P, b4.w0, b4.w1, b4.w2, b4.w3)) st = 2;
             }
         }

@@ -101,7 +101,7 @@ size_t cell_values(const int32_t *n, int dim)
 // / uniform_n). Every lane of a wave reads it at the same address, so the
 // kernels serve it from the scalar cache.
 template <class T>
-struct ItemDesc {
+struct ItemCore {
     int32_t prob;               // index into the problem table (batches)
     int32_t exit_mode, law;
     int32_t score_plain;        // 1: evaluate f and score phi
@@ -121,6 +121,16 @@ struct ItemDesc {
     uint32_t *rec_steps;
     T h, sig_sqh, two_over_s2h, gm_thresh, bridge_thresh;
     GridView<T> u_prev, resid;
+};
+
+// A work item of the batch kernel: the core fields, plus (per node, 4 words)
+// the node index, stream tag and path offset (low word) of the node in the
+// solve it belongs to, when several solves that walk alike are merged into
+// this item; null: node, stream_tag, path_offset of the core. The
+// single-item kernel takes the core alone.
+template <class T>
+struct ItemDesc : ItemCore<T> {
+    const uint32_t *node_rng;
 };
 
 // One launch of the path kernel: slots [slot_begin, slot_begin + launch_slots)
@@ -214,7 +224,7 @@ struct GatherItem {
 template <class T>
 struct OneItemArgs {
     LaunchArgs launch;
-    ItemDesc<T> item;
+    ItemCore<T> item;
     DevProblem<T> prob;
 };
 

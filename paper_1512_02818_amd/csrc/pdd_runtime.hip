@@ -451,6 +451,43 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     bool any_scratch = false;
     for (auto *it : items) any_scratch |= !it->caller_records;
 
+    // Kernel items: runs of consecutive items that walk alike (same problem,
+    // step, exit test, law, max steps, scoring, grids, the same number of
+    // paths for every node, and records in the scratch) are merged into one
+    // kernel item whose nodes carry their own RNG node index, stream and path
+    // offset. A wave can then take paths of the whole run without waiting for
+    // its lanes at every item boundary; every path still draws the numbers of
+    // its own solve. (Ragged items are not merged: finding a path's node in a
+    // long ragged table costs more than the boundaries.)
+    auto alike = [&](const HostItem *x, const HostItem *y) {
+        if (x->prob != y->prob || x->caller_records || y->caller_records) return false;
+        if (!x->uniform || !y->uniform || x->o->n_paths != y->o->n_paths) return false;
+        const pdd_solve_opts *a = x->o, *b = y->o;
+        if (a->dt != b->dt || a->exit_mode != b->exit_mode || a->law != b->law || x->max_steps != y->max_steps ||
+            x->score_plain != y->score_plain)
+            return false;
+        if (!CV) return true;
+        auto same = [](const pdd_grid *g, const pdd_grid *h) {
+            if (g->data != h->data || g->dtype != h->dtype) return false;
+            for (int i = 0; i < D; ++i)
+                if (g->n[i] != h->n[i] || g->lo[i] != h->lo[i] || g->hi[i] != h->hi[i]) return false;
+            return true;
+        };
+        return same(x->u_prev, y->u_prev) && same(x->resid, y->resid);
+    };
+    std::vector<int> kfirst;  // first item of each kernel item, then n_items
+    for (int q = 0; q < n_items; ++q)
+        if (q == 0 || !alike(items[q - 1], items[q])) kfirst.push_back(q);
+    const int n_k = (int)kfirst.size();
+    kfirst.push_back(n_items);
+    std::vector<uint64_t> kslot(n_k + 1);  // slot ranges of the kernel items
+    bool any_merged = false;
+    for (int k = 0; k < n_k; ++k) {
+        kslot[k] = slot_begin[kfirst[k]];
+        any_merged |= kfirst[k + 1] - kfirst[k] > 1;
+    }
+    kslot[n_k] = total;
+
     uint64_t per_launch = std::min(kScratchSlots, std::max<uint64_t>(total, 1));
     if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
     const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
@@ -461,8 +498,8 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     std::vector<uint32_t> ctr_at(n_launch + 1, 0), seg_lo(n_launch, 0), seg_n(n_launch, 0);
     for (uint64_t l = 0; l < n_launch; ++l) {
         const uint64_t b = l * per_launch, e = std::min(total, b + per_launch);
-        const auto first = std::upper_bound(slot_begin.begin(), slot_begin.end(), b) - slot_begin.begin() - 1;
-        const auto last = std::upper_bound(slot_begin.begin(), slot_begin.end(), e - 1) - slot_begin.begin() - 1;
+        const auto first = std::upper_bound(kslot.begin(), kslot.begin() + n_k, b) - kslot.begin() - 1;
+        const auto last = std::upper_bound(kslot.begin(), kslot.begin() + n_k, e - 1) - kslot.begin() - 1;
         seg_lo[l] = (uint32_t)first;
         seg_n[l] = (uint32_t)(last - first + 1);
         ctr_at[l + 1] = ctr_at[l] + std::max<uint32_t>(seg_n[l], 1);
@@ -470,17 +507,19 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     const size_t n_ctr = (size_t)ctr_at[n_launch] + 2;
     const size_t ctr_bytes = (n_ctr * sizeof(uint32_t) + 7) & ~size_t(7);  // cleared in 8-byte words
 
-    // staged upload: nodes | global node starts | item node starts | items |
-    // problems | node -> item | per-item post-processing entries | queue ranges
+    // staged upload: nodes | global node starts | item node starts | kernel
+    // items | problems | node -> item | per-item post-processing entries |
+    // queue ranges | per-node RNG table of merged items
     const size_t off_nodes = 0;
     const size_t off_gstart = align_up(off_nodes + n_nodes_all * D * sizeof(double), 256);
     const size_t off_istart = align_up(off_gstart + (n_nodes_all + 1) * sizeof(uint64_t), 256);
     const size_t off_items = align_up(off_istart + n_starts * sizeof(uint64_t), 256);
-    const size_t off_probs = align_up(off_items + n_items * sizeof(ItemDesc<T>), 256);
+    const size_t off_probs = align_up(off_items + n_k * sizeof(ItemDesc<T>), 256);
     const size_t off_nitem = align_up(off_probs + probs.size() * sizeof(DevProblem<T>), 256);
     const size_t off_fitems = align_up(off_nitem + n_nodes_all * sizeof(uint32_t), 256);
     const size_t off_seg = align_up(off_fitems + n_items * sizeof(FinalItem), 256);
-    const size_t bytes = align_up(off_seg + n_ctr * 2 * sizeof(uint32_t), 256);
+    const size_t off_rng = align_up(off_seg + n_ctr * 2 * sizeof(uint32_t), 256);
+    const size_t bytes = align_up(off_rng + (any_merged ? n_nodes_all * 4 * sizeof(uint32_t) : 0), 256);
 
     pdd_status st;
     if ((st = ensure(ctx, ctx->nodes, bytes))) return st;
@@ -535,12 +574,13 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         const uint64_t b = l * per_launch, e = std::min(total, b + per_launch);
         for (uint32_t k = 0; k < seg_n[l]; ++k) {
             const int q = (int)(seg_lo[l] + k);
-            const uint64_t lo = std::max(slot_begin[q], b), hi = std::min(slot_begin[q] + items[q]->total, e);
+            const uint64_t lo = std::max(kslot[q], b), hi = std::min(kslot[q + 1], e);
             h_seg[2 * (ctr_at[l] + k)] = (uint32_t)(lo - b);
             h_seg[2 * (ctr_at[l] + k) + 1] = (uint32_t)(std::max(lo, hi) - b);
         }
     }
-    std::memset(h_items, 0, n_items * sizeof(ItemDesc<T>));
+    std::vector<ItemDesc<T>> oitems(n_items);  // one per item, before merging
+    std::memset(oitems.data(), 0, n_items * sizeof(ItemDesc<T>));
     std::memset(h_fitems, 0, n_items * sizeof(FinalItem));
     size_t istart_used = 0;
     for (int q = 0; q < n_items; ++q) {
@@ -566,7 +606,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
                 fi.up_inv[i] = i < D ? (double)(it.u_prev->n[i] - 1) / (it.u_prev->hi[i] - it.u_prev->lo[i]) : 0.0;
             }
         }
-        ItemDesc<T> &a = h_items[q];
+        ItemDesc<T> &a = oitems[q];
         a.prob = prob_of[q];
         a.exit_mode = o->exit_mode;
         a.law = o->law;
@@ -608,6 +648,27 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         if (CV) a.resid.cells = d_cells + cell_at[q];
     }
     h_gstart[n_nodes_all] = total;
+    // kernel items: a merged one walks the nodes of its items in order, each
+    // node with its own RNG node index, stream tag and path offset
+    uint32_t *h_rng = reinterpret_cast<uint32_t *>(h + off_rng);
+    for (int k = 0; k < n_k; ++k) {
+        const int q0 = kfirst[k], q1 = kfirst[k + 1];
+        h_items[k] = oitems[q0];
+        if (q1 - q0 == 1) continue;
+        ItemDesc<T> &a = h_items[k];
+        for (int q = q0; q < q1; ++q)
+            for (uint64_t i = gnode[q]; i < gnode[q + 1]; ++i) {
+                h_rng[4 * i] = (uint32_t)(i - gnode[q]);
+                h_rng[4 * i + 1] = oitems[q].stream_tag;
+                h_rng[4 * i + 2] = (uint32_t)oitems[q].path_offset;
+                h_rng[4 * i + 3] = 0;
+            }
+        a.n_nodes = (uint32_t)(gnode[q1] - gnode[q0]);
+        a.n_slots = kslot[k + 1] - kslot[k];
+        a.node_rng = reinterpret_cast<const uint32_t *>(dv + off_rng) + 4 * gnode[q0];
+        a.path_offset = 0;
+        a.stream_tag = 0;
+    }
     for (size_t p = 0; p < probs.size(); ++p)
         std::memcpy(&h_probs[p], sizeof(T) == 4 ? (const void *)&probs[p]->pf : (const void *)&probs[p]->pd,
                     sizeof(DevProblem<T>));
@@ -642,7 +703,8 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
                                          d_cells + cell_off[k], s)));
 
     const int block = tune.block;
-    const bool one = n_items == 1 && kOneItemKernel<T, D, CV>;
+    // (the single-item kernel has no per-node RNG table)
+    const bool one = n_k == 1 && kOneItemKernel<T, D, CV> && kfirst[1] == 1;
     // box / bridge / Gaussian throughout: the specialised kernel
     const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) {
         return i->prob->desc.domain == PDD_DOMAIN_BOX && i->o->exit_mode == PDD_EXIT_BRIDGE &&
@@ -670,7 +732,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         LaunchArgs L{};
         L.slot_begin = b;
         L.launch_slots = (uint32_t)len;
-        L.n_items = n_items;
+        L.n_items = n_k;
         L.grab = tune.grab;
         L.counter = static_cast<uint32_t *>(ctx->counters.ptr) + ctr_at[launch];
         L.item_lo = (int32_t)seg_lo[launch];
@@ -687,7 +749,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             A.prob = h_probs[0];
             // the single item starts at slot 0; scratch records of this launch
             // start at slot b
-            if (!items[0]->caller_records) A.item.rec_base = b;
+            if (A.item.rec_launch) A.item.rec_base = b;
             HIP_TRY((launch_path_kernel_one<T, D, CV>(A, grid, block, spec, s)));
         } else {
             HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, spec, s)));
