@@ -263,12 +263,17 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int3
                                   const double *target_se, uint64_t n_pilot, uint64_t n_max,
                                   void *stream);
 
-/* Key of the context's launch-shape table. */
+/* Key of the context's launch-shape table: the path kernel a group of
+ * items runs. `generic` selects between the kernel compiled for a box domain
+ * with the bridge exit test, Gaussian increments and analytic coefficients
+ * (0: used when every item of the group is of that kind) and the generic one
+ * (1: ball domains, the shifted or naive exit test, the test law, tabulated
+ * coefficients). */
 typedef struct {
     int32_t precision;  /* PDD_FP32 or PDD_FP64 */
     int32_t dim;        /* 2 or 3 */
     int32_t correction; /* 0 plain, 1 correction estimator */
-    int32_t reserved;
+    int32_t generic;    /* 0 or 1, as above */
 } pdd_tuning_key;
 
 /* Times samples of `item` (up to 32 of its nodes, about 8 and 16 paths per
@@ -285,7 +290,8 @@ typedef struct {
 pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out);
 
 /* Sets (t non-NULL) or removes (t NULL) the context's table entry for `key`,
- * e.g. to restore shapes tuned earlier. PDD_E_INVALID for a bad key or shape. */
+ * e.g. to restore shapes tuned earlier. PDD_E_INVALID for a bad key (any
+ * field out of its range) or shape. */
 pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tuning *t);
 
 /* GPU milliseconds between the first path-kernel launch and the end of the

@@ -53,8 +53,14 @@ struct HostItem {
 
 // Checks an item's arguments against its problem (nothing is enqueued).
 pdd_status validate_item(HostItem &it);
-// Key of the launch-shape table: precision, dimension and estimator.
-inline int tuning_key(int precision, int dim, bool cv) { return precision * 4 + (dim - 2) * 2 + (cv ? 1 : 0); }
+// Key of the launch-shape table: precision, dimension, estimator and kernel
+// (specialised box / bridge / Gaussian / analytic, or generic).
+inline int tuning_key(int precision, int dim, bool cv, bool generic)
+{
+    return precision * 8 + (dim - 2) * 4 + (cv ? 2 : 0) + (generic ? 1 : 0);
+}
+// Whether an item can run in the specialised kernel.
+bool specialised(const HostItem &it);
 
 // Validates items, then enqueues them on `s`, grouped by (precision,
 // dimension, estimator); a group of at most kScratchSlots paths without

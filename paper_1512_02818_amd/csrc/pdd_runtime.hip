@@ -328,6 +328,12 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
 
 }  // namespace
 
+bool pdd::specialised(const HostItem &it)
+{
+    return it.prob->desc.domain == PDD_DOMAIN_BOX && it.o->exit_mode == PDD_EXIT_BRIDGE &&
+           it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0;
+}
+
 pdd_status pdd::validate_item(HostItem &it)
 {
     const pdd_solve_opts *o = it.o;
@@ -705,11 +711,8 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     const int block = tune.block;
     // (the single-item kernel has no per-node RNG table)
     const bool one = n_k == 1 && kOneItemKernel<T, D, CV> && kfirst[1] == 1;
-    // box / bridge / Gaussian throughout: the specialised kernel
-    const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) {
-        return i->prob->desc.domain == PDD_DOMAIN_BOX && i->o->exit_mode == PDD_EXIT_BRIDGE &&
-               i->o->law == PDD_LAW_GAUSS && i->prob->pf.tab == 0;
-    });
+    // box / bridge / Gaussian / analytic throughout: the specialised kernel
+    const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) { return specialised(*i); });
     const void *fn = path_kernel_symbol<T, D, CV>(one, spec);
     // more workgroups than fit at once only queue behind the resident ones
     const int occ = occupancy(ctx, fn, block);
@@ -844,7 +847,8 @@ pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_
                     if (it.o->precision == prec && it.prob->desc.dim == dim && (int)it.cv == cv && it.n_nodes > 0)
                         g.push_back(&it);
                 if (g.empty()) continue;
-                if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, cv), tune))) return st;
+                const bool generic = !std::all_of(g.begin(), g.end(), [](const HostItem *i) { return specialised(*i); });
+                if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, cv, generic), tune))) return st;
                 if (prec == PDD_FP32) {
                     if (dim == 2)
                         st = cv ? run_group<float, 2, true>(ctx, g, tune, timed, s) : run_group<float, 2, false>(ctx, g, tune, timed, s);
@@ -1329,7 +1333,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     }
     cleanup();
     if (st) return st;
-    ctx->tuned[tuning_key(prec, dim, cv)] = best;
+    ctx->tuned[tuning_key(prec, dim, cv, !spec)] = best;
     *out = best;
     return PDD_OK;
 }
@@ -1338,9 +1342,9 @@ pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tun
 {
     if (!ctx || !key) return fail(PDD_E_INVALID, "NULL argument");
     if ((key->precision != PDD_FP32 && key->precision != PDD_FP64) || key->dim < 2 || key->dim > 3 ||
-        (key->correction != 0 && key->correction != 1))
+        (key->correction != 0 && key->correction != 1) || (key->generic != 0 && key->generic != 1))
         return fail(PDD_E_INVALID, "bad tuning key");
-    const int k = tuning_key(key->precision, key->dim, key->correction != 0);
+    const int k = tuning_key(key->precision, key->dim, key->correction != 0, key->generic != 0);
     if (!t) {
         ctx->tuned.erase(k);
         return PDD_OK;

@@ -94,7 +94,7 @@ assert STATS_DTYPE.itemsize == C.sizeof(NodeStats)
 
 class TuningKey(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dim", C.c_int32), ("correction", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("generic", C.c_int32)]
 
 
 class ServerOpts(C.Structure):
@@ -495,9 +495,10 @@ def autotune(ctx: Context, item: dict):
     return (t.block, t.blocks_per_cu, t.grab)
 
 
-def set_tuning(ctx: Context, precision: str, dim: int, correction: bool, tuning=None):
-    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key, or None to remove it."""
-    k = TuningKey(PRECISIONS[precision], int(dim), 1 if correction else 0, 0)
+def set_tuning(ctx: Context, precision: str, dim: int, correction: bool, tuning=None, generic=False):
+    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key (generic: the
+    generic rather than the box / bridge / Gaussian kernel), or None to remove it."""
+    k = TuningKey(PRECISIONS[precision], int(dim), 1 if correction else 0, 1 if generic else 0)
     t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]), 0)
     _check(lib().pdd_set_tuning(ctx.handle, C.byref(k), C.byref(t) if t is not None else None))
 

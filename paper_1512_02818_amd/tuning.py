@@ -1,10 +1,12 @@
 """Launch-shape cache of the autotuner (pdd_autotune).
 
-A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction>" to
-[block, blocks_per_cu, grab]. `load` installs the entries of the running
-GPU's architecture in a context (pdd_set_tuning), so solves without an
-explicit tuning use them; `tune` runs pdd_autotune on an item and records
-the winner. Shapes change only speed, never results.
+A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction>", with
+"/generic" appended for the generic kernel (ball domains, the shifted or
+naive exit test, tabulated coefficients), to [block, blocks_per_cu, grab].
+`load` installs the entries of the running GPU's architecture in a context
+(pdd_set_tuning), so solves without an explicit tuning use them; `tune` runs
+pdd_autotune on an item and records the winner. Shapes change only speed,
+never results.
 
     python -m paper_1512_02818_amd.tuning   # tunes the standard workloads, writes the cache
 """
@@ -19,15 +21,28 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "tuning_cache.json")
 
 
-def key(arch: str, precision: str, dim: int, correction: bool) -> str:
-    return f"{arch}/{precision}/D{int(dim)}/{'correction' if correction else 'plain'}"
+def key(arch: str, precision: str, dim: int, correction: bool, generic: bool = False) -> str:
+    k = f"{arch}/{precision}/D{int(dim)}/{'correction' if correction else 'plain'}"
+    return k + "/generic" if generic else k
 
 
 def parse_key(k: str):
-    arch, prec, d, est = k.split("/")
+    """(arch, precision, dim, correction, generic) of a cache key."""
+    parts = k.split("/")
+    if len(parts) not in (4, 5) or (len(parts) == 5 and parts[4] != "generic"):
+        raise ValueError(f"bad tuning key {k!r}")
+    arch, prec, d, est = parts[:4]
     if prec not in pdd.PRECISIONS or not d.startswith("D") or est not in ("plain", "correction"):
         raise ValueError(f"bad tuning key {k!r}")
-    return arch, prec, int(d[1:]), est == "correction"
+    return arch, prec, int(d[1:]), est == "correction", len(parts) == 5
+
+
+def generic_item(item: dict) -> bool:
+    """Whether a batch-style item runs in the generic kernel."""
+    pd = item["problem"].pd
+    opts = item["opts"]
+    return not (pd.get("domain", "box") == "box" and opts.get("exit", "bridge") == "bridge"
+                and opts.get("law", "gauss") == "gauss" and not pd.get("tab"))
 
 
 def read(path: str = DEFAULT_PATH) -> dict:
@@ -65,9 +80,9 @@ def load(ctx: pdd.Context, path: str = DEFAULT_PATH, arch: str | None = None) ->
     arch = arch or arch_name()
     n = 0
     for k, shape in read(path).items():
-        a, prec, dim, cv = parse_key(k)
+        a, prec, dim, cv, generic = parse_key(k)
         if a == arch:
-            pdd.set_tuning(ctx, prec, dim, cv, shape)
+            pdd.set_tuning(ctx, prec, dim, cv, shape, generic=generic)
             n += 1
     return n
 
@@ -78,7 +93,8 @@ def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: st
     if path:
         prob = item["problem"]
         prec = item["opts"].get("precision", "fp32")
-        save_entry(path, key(arch or arch_name(), prec, prob.dim, item.get("u_prev") is not None), shape)
+        save_entry(path, key(arch or arch_name(), prec, prob.dim, item.get("u_prev") is not None,
+                             generic_item(item)), shape)
     return shape
 
 
@@ -97,8 +113,13 @@ def main():
     unit = W.unit_square_problem(seed=0)
     rng = np.random.default_rng(4)
     cube = W.random_problem(rng, dim=3)
-    probs = {"sq": pdd.Problem(ctx, sq), "unit": pdd.Problem(ctx, unit), "cube": pdd.Problem(ctx, cube)}
+    ball2 = W.ball_exit_time_problem(dim=2, seed=1)
+    ball3 = W.ball_exit_time_problem(dim=3, seed=2)
+    probs = {"sq": pdd.Problem(ctx, sq), "unit": pdd.Problem(ctx, unit), "cube": pdd.Problem(ctx, cube),
+             "ball2": pdd.Problem(ctx, ball2), "ball3": pdd.Problem(ctx, ball3)}
     cube_nodes = W.face_nodes(rng, cube, 64)
+    ball2_nodes = rng.uniform(-0.5, 0.5, size=(64, 2))
+    ball3_nodes = rng.uniform(-0.4, 0.4, size=(64, 3))
     for prec in ("fp32", "fp64"):
         dt = np.float32 if prec == "fp32" else np.float64
         items = [{"problem": probs["sq"], "nodes": W.big_square_nodes(), "opts": dict(dt=1e-4, precision=prec)},
@@ -111,9 +132,15 @@ def main():
         items.append({"problem": probs["cube"], "nodes": cube_nodes, "opts": dict(dt=1e-3, precision=prec),
                       "u_prev": gu3, "u_prev_t": torch.as_tensor(gu3["data"]).cuda().contiguous(),
                       "resid": gr3, "resid_t": torch.as_tensor(gr3["data"]).cuda().contiguous()})
+        # the generic kernel: ball domains (plain), the shifted exit test (correction)
+        items.append({"problem": probs["ball2"], "nodes": ball2_nodes, "opts": dict(dt=1e-3, precision=prec)})
+        items.append({"problem": probs["ball3"], "nodes": ball3_nodes, "opts": dict(dt=1e-3, precision=prec)})
+        items.append(dict(items[2], opts=dict(items[2]["opts"], exit="shift")))
+        items.append(dict(items[3], opts=dict(items[3]["opts"], exit="shift")))
         for it in items:
             shape = tune(ctx, it, path=args.out)
-            print(prec, it["problem"].dim, "correction" if "u_prev" in it else "plain", shape, flush=True)
+            print(prec, it["problem"].dim, "correction" if "u_prev" in it else "plain",
+                  "generic" if generic_item(it) else "", shape, flush=True)
     for p in probs.values():
         p.close()
     ctx.close()

@@ -77,7 +77,7 @@ STRUCTS = {
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),
     "pdd_node_stats": (pdd.NodeStats, ["mean", "stderr_", "vr_opt", "sums"]),
     "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out"]),
-    "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction"]),
+    "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction", "generic"]),
     "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",
                                   "user_tag"]),

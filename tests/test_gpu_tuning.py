@@ -53,6 +53,11 @@ def test_set_tuning_validates(ctx):
         pdd.set_tuning(ctx, "fp32", 2, False, (96, 1, 64))
     pdd.set_tuning(ctx, "fp32", 2, False, (128, 3, 16))
     pdd.set_tuning(ctx, "fp32", 2, False, None)
+    pdd.set_tuning(ctx, "fp32", 2, False, (64, 2, 16), generic=True)
+    pdd.set_tuning(ctx, "fp32", 2, False, None, generic=True)
+    k = pdd.TuningKey(0, 2, 0, 2)  # generic must be 0 or 1
+    t = pdd.Tuning(128, 1, 64, 0)
+    assert pdd.lib().pdd_set_tuning(ctx.handle, pdd.C.byref(k), pdd.C.byref(t)) == -1
 
 
 def test_cache_load(ctx, tmp_path):

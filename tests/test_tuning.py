@@ -9,9 +9,13 @@ from paper_1512_02818_amd import tuning as T
 def test_key_round_trip():
     k = T.key("gfx950", "fp32", 2, False)
     assert k == "gfx950/fp32/D2/plain"
-    assert T.parse_key(k) == ("gfx950", "fp32", 2, False)
-    assert T.parse_key(T.key("gfx950", "fp64", 3, True)) == ("gfx950", "fp64", 3, True)
-    for bad in ("gfx950/fp16/D2/plain", "gfx950/fp32/2/plain", "gfx950/fp32/D2/cv", "x"):
+    assert T.parse_key(k) == ("gfx950", "fp32", 2, False, False)
+    assert T.parse_key(T.key("gfx950", "fp64", 3, True)) == ("gfx950", "fp64", 3, True, False)
+    g = T.key("gfx950", "fp32", 3, True, generic=True)
+    assert g == "gfx950/fp32/D3/correction/generic"
+    assert T.parse_key(g) == ("gfx950", "fp32", 3, True, True)
+    for bad in ("gfx950/fp16/D2/plain", "gfx950/fp32/2/plain", "gfx950/fp32/D2/cv", "x",
+                "gfx950/fp32/D2/plain/special", "gfx950/fp32/D2/plain/generic/x"):
         with pytest.raises(ValueError):
             T.parse_key(bad)
 
