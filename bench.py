@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--profile-correction", type=int, default=0,
                     help="only run the correction solve (unit square, 257^2 FP32 grids, h=1e-3) with "
                          "this many paths per node three times and print its timing (for profilers)")
+    ap.add_argument("--profile-replicas", type=int, default=1,
+                    help="with --profile-correction: that many 18-node solves (distinct streams) in one batch")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
@@ -302,32 +304,44 @@ def calibration_copy(mib):
     del src, dst
 
 
-def profile_correction(paths, calibrate_mib=0):
+def profile_correction(paths, calibrate_mib=0, replicas=1):
     """The correction estimator alone, for kernel-trace and counter runs: 18
     unit-square nodes, u_prev = U + p and its residual on 257^2 FP32 grids
-    (about 0.26 MB each, so the grid gathers are served by L2), h = 1e-3."""
+    (about 0.26 MB each, so the grid gathers are served by L2), h = 1e-3.
+    replicas > 1: that many solves of the 18 nodes with distinct RNG streams
+    in one pdd_solve_batch, as in the node-solve measurement."""
     import numpy as np
     import torch
 
-    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import pdd, tuning
     from paper_1512_02818_amd import workloads as W
     ctx = pdd.Context(0)
+    tuning.load(ctx)  # the launch shapes of the node-solve measurement
     pd = W.unit_square_problem(seed=SEED)
     nodes = W.unit_square_nodes()
     prob = pdd.Problem(ctx, pd)
     gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
     tu = torch.as_tensor(gu["data"]).cuda().contiguous()
     tr = torch.as_tensor(gr["data"]).cuda().contiguous()
-    out = pdd.alloc_stats(len(nodes))
+    out = pdd.alloc_stats(replicas * len(nodes))
+    nstat = pdd.STATS_DTYPE.itemsize
     if calibrate_mib > 0:
         calibration_copy(calibrate_mib)
     steps = 0
     for r in range(3):
-        pdd.solve_correction(prob, gu, tu, gr, tr, nodes, out=out, dt=1e-3, n_paths=paths,
-                             path_offset=r * paths, precision="fp32", time_kernel=True)
+        if replicas == 1:
+            pdd.solve_correction(prob, gu, tu, gr, tr, nodes, out=out, dt=1e-3, n_paths=paths,
+                                 path_offset=r * paths, precision="fp32", time_kernel=True)
+        else:
+            pdd.solve_batch(ctx, [{"problem": prob, "nodes": nodes,
+                                   "out": out[q * len(nodes) * nstat:(q + 1) * len(nodes) * nstat],
+                                   "opts": dict(dt=1e-3, n_paths=paths, path_offset=r * paths, precision="fp32",
+                                                stream_id=16 + q, time_kernel=q == 0),
+                                   "u_prev": gu, "u_prev_t": tu, "resid": gr, "resid_t": tr}
+                                  for q in range(replicas)])
         steps += int(pdd.stats_to_numpy(out)["steps_sum"].sum())
     ms = pdd.kernel_times(ctx)
-    print(json.dumps({"correction_profile": {"paths_per_node": paths, "nodes": len(nodes),
+    print(json.dumps({"correction_profile": {"paths_per_node": paths, "nodes": len(nodes), "replicas": replicas,
                                              "path_steps": steps, "kernel_ms": ms,
                                              "path_steps_per_s": steps / (sum(ms) / 1e3)}}), flush=True)
     prob.close()
@@ -337,7 +351,7 @@ def profile_correction(paths, calibrate_mib=0):
 def main():
     args = parse()
     if args.profile_correction > 0:
-        profile_correction(args.profile_correction, args.calibrate_copy_mib)
+        profile_correction(args.profile_correction, args.calibrate_copy_mib, args.profile_replicas)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "

@@ -87,9 +87,43 @@ def load(ctx: pdd.Context, path: str = DEFAULT_PATH, arch: str | None = None) ->
     return n
 
 
-def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: str | None = None):
-    """pdd_autotune on `item` (batch-style dict); records the winner under its key."""
+DEFAULT_SHAPE = (256, 0, 64)  # the library's default: block 256 at full occupancy, grab 64
+
+
+def whole_launch_ms(ctx: pdd.Context, item: dict, shape, n_paths: int, reps: int = 3) -> float:
+    """Median path-kernel time of a full solve of `item` with n_paths per node
+    under `shape` (exit-time tail included)."""
+    import numpy as np
+    import torch
+    it = dict(item, opts=dict(item["opts"], n_paths=int(n_paths), time_kernel=True,
+                              tuning=tuple(shape) + (0,)))
+    ms = []
+    for r in range(reps + 1):
+        it["opts"]["path_offset"] = r * int(n_paths)
+        pdd.kernel_times(ctx)
+        pdd.solve_batch(ctx, [it])
+        torch.cuda.synchronize()
+        t = pdd.kernel_times(ctx)
+        if r:  # the first solve warms up
+            ms.append(sum(t))
+    return float(np.median(ms))
+
+
+def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: str | None = None,
+         verify_paths: int = 0):
+    """pdd_autotune on `item` (batch-style dict); records the winner under its key.
+    With verify_paths, the winner must also beat the default by 2 % on a full
+    solve with that many paths per node (its sampled timing leaves the tail
+    out), else the default is recorded."""
     shape = pdd.autotune(ctx, item)
+    if verify_paths:
+        prob = item["problem"]
+        prec = item["opts"].get("precision", "fp32")
+        t_tuned = whole_launch_ms(ctx, item, shape, verify_paths)
+        t_default = whole_launch_ms(ctx, item, DEFAULT_SHAPE, verify_paths)
+        if not t_tuned < 0.98 * t_default:
+            shape = DEFAULT_SHAPE
+            pdd.set_tuning(ctx, prec, prob.dim, item.get("u_prev") is not None, None, generic=generic_item(item))
     if path:
         prob = item["problem"]
         prec = item["opts"].get("precision", "fp32")
@@ -138,7 +172,9 @@ def main():
         items.append(dict(items[2], opts=dict(items[2]["opts"], exit="shift")))
         items.append(dict(items[3], opts=dict(items[3]["opts"], exit="shift")))
         for it in items:
-            shape = tune(ctx, it, path=args.out)
+            # full solves of about 4e7 paths (2e6 for the long-path problem) check the winner
+            verify = max(1000, int((2e6 if it["problem"] is probs["sq"] else 4e7) / len(it["nodes"])))
+            shape = tune(ctx, it, path=args.out, verify_paths=verify)
             print(prec, it["problem"].dim, "correction" if "u_prev" in it else "plain",
                   "generic" if generic_item(it) else "", shape, flush=True)
     for p in probs.values():
