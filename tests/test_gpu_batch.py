@@ -121,3 +121,39 @@ def test_many_small_items_under_any_launch_shape(ctx):
                 assert np.array_equal(a["n"], b["n"]) and np.array_equal(a["steps_sum"], b["steps_sum"]), q
                 assert np.allclose(a["mean"], b["mean"], rtol=1e-13, atol=1e-14, equal_nan=True), q
     prob.close()
+
+
+@pytest.mark.parametrize("cv", [False, True])
+def test_merged_uniform_solves_equal_solo(ctx, cv):
+    """Runs of alike uniform solves (same problem and step, distinct streams
+    and path offsets) are merged into one kernel item with a per-node RNG
+    table; runs are broken by a different path count, step or exit test.
+    Every solve's statistics equal its solo solve bit for bit."""
+    pd = W.unit_square_problem(seed=21)
+    prob = pdd.Problem(ctx, pd)
+    nodes = W.unit_square_nodes()
+    gu, gr, _ = W.correction_grids(pd, n=65, seed=2, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    items = []
+    for q in range(40):
+        opts = dict(dt=1e-3, n_paths=300, precision="fp32", stream_id=100 + q, path_offset=7 * q)
+        if q in (13, 14):
+            opts["n_paths"] = 301          # breaks the run
+        if q == 25:
+            opts["dt"] = 2e-3              # breaks the run
+        if q == 31:
+            opts["exit"] = "shift"         # breaks the run (and the kernel variant)
+        it = {"problem": prob, "nodes": nodes[q % 5::3], "opts": opts}
+        if cv:
+            it.update(u_prev=gu, u_prev_t=tu, resid=gr, resid_t=tr)
+        items.append(it)
+    got = [pdd.stats_to_numpy(o) for o in pdd.solve_batch(ctx, items)]
+    torch.cuda.synchronize()
+    for q, (it, g) in enumerate(zip(items, got)):
+        if cv:
+            solo = pdd.solve_correction(prob, gu, tu, gr, tr, it["nodes"], **it["opts"])
+        else:
+            solo = pdd.solve_nodes(prob, it["nodes"], **it["opts"])
+        assert pdd.stats_to_numpy(solo).tobytes() == g.tobytes(), q
+    prob.close()
