@@ -67,6 +67,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def stored_traffic(path: str, precision: str, paths_per_step: int):
+    """HBM bytes per launch from the profiler counters stored at `path`, or
+    None unless they were taken for this precision, launch size and the
+    current kernel sources."""
+    try:
+        with open(path) as f:
+            tj = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (tj.get("precision") == precision and tj.get("paths_per_step") == paths_per_step
+            and tj.get("source_sha256") == kernel_source_hash()):
+        return tj.get("bytes_per_launch")
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,15 +422,7 @@ def main():
     value = total_steps / (elapsed_ms / 1e3)
     avg_kern_s = float(np.mean(kern_ms)) / 1e3
     achieved = OPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if (tj.get("precision") == args.precision and tj.get("paths_per_step") == P
-                    and tj.get("source_sha256") == kernel_source_hash()):
-                traffic = tj.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    traffic = stored_traffic(args.traffic_json, args.precision, P)
     exact = W.manufactured_u(pd, nodes)
     z = np.abs(timed[-1]["mean"] - exact) / timed[-1]["stderr"]
     print(f"timed {args.steps} steps: {elapsed_ms:.1f} ms, path kernel {np.mean(kern_ms):.1f} ms/launch, "

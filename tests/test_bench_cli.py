@@ -1,0 +1,37 @@
+"""bench.py on the host: more than one GPU is refused with a message (the
+measured path runs on one GPU), and stored HBM byte counts are reported only
+for the kernel sources, precision and launch size they were taken for."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_stored_traffic_is_guarded(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = {"precision": "fp32", "paths_per_step": 62500, "source_sha256": bench.kernel_source_hash(),
+           "bytes_per_launch": 123.0}
+    path = str(tmp_path / "t.json")
+    with open(path, "w") as f:
+        json.dump(rec, f)
+    assert bench.stored_traffic(path, "fp32", 62500) == 123.0
+    assert bench.stored_traffic(path, "fp64", 62500) is None
+    assert bench.stored_traffic(path, "fp32", 6250) is None
+    with open(path, "w") as f:
+        json.dump(dict(rec, source_sha256="0" * 64), f)
+    assert bench.stored_traffic(path, "fp32", 62500) is None   # counters of another kernel version
+    assert bench.stored_traffic(str(tmp_path / "missing.json"), "fp32", 62500) is None
+    # the committed profile names its summary file
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        t = json.load(f)
+    assert os.path.exists(os.path.join(ROOT, "profiles", t["summary"]))
