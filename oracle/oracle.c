@@ -17,6 +17,11 @@
  *                          time (Fourier series), the time-step bias trend.
  *   discrete scheme      - brute-force enumeration of every Rademacher path.
  *   correction estimator - zero-variance invariant for a bilinear solution.
+ *   Ito control variate  - E[xi] = 0 over every enumerated Rademacher path;
+ *                          the closed form phi + xi = x0 + (Pi(X_K) - X_K)
+ *                          for a linear solution; variance that vanishes
+ *                          with h for the exact gradient; and agreement, path
+ *                          by path, with the correction estimator as h -> 0.
  *   tabulated b, c, f    - affine drift / constant killing on grids walk the
  *                          analytic problem's paths; non-affine tabulated
  *                          coefficients with the matching f keep the
@@ -420,6 +425,11 @@ static int bad_problem(const orc_problem *p, const orc_opts *o)
     if (p->dim != 2 && p->dim != 3) return 1;
     if (!(o->h > 0.0) || !(p->sigma > 0.0)) return 1;
     if ((o->u_prev == NULL) != (o->resid == NULL)) return 1;
+    if (o->grad[0]) {
+        if (o->u_prev) return 1;
+        for (int d = 0; d < p->dim; ++d)
+            if (!o->grad[d] || o->grad[d]->dim != p->dim || !o->grad[d]->data) return 1;
+    }
     const orc_grid *tab[5] = {p->tab_b[0], p->tab_b[1], p->tab_b[2], p->tab_c, p->tab_f};
     for (int q = 0; q < 5; ++q) {
         if (!tab[q]) continue;
@@ -436,7 +446,7 @@ static int run_core(const orc_problem *p, const orc_opts *o, const double *x0,
 {
     int D = p->dim;
     double X[3] = {0, 0, 0}, Xn[3] = {0, 0, 0}, Xt[3] = {0, 0, 0};
-    double Y = 1.0, Z = 0.0, R = 0.0;
+    double Y = 1.0, Z = 0.0, R = 0.0, xi = 0.0;
     uint64_t k = 0;
     int capped = 0;
     double h = o->h;
@@ -444,6 +454,7 @@ static int run_core(const orc_problem *p, const orc_opts *o, const double *x0,
     double sig_sqh = p->sigma * sqh;
     double two_over_s2h = 2.0 / (p->sigma * p->sigma * h);
     int cv = o->u_prev != NULL;
+    int ito = o->grad[0] != NULL;
     uint64_t cap = o->max_steps;
     if (ns->normals && ns->n_given < cap) cap = ns->n_given;
     for (int d = 0; d < D; ++d) X[d] = x0[d];
@@ -469,6 +480,14 @@ static int run_core(const orc_problem *p, const orc_opts *o, const double *x0,
         double hY = h * Y;
         Z = Z - hY * f;
         if (cv) R = R + hY * orc_interp(o->resid, X);
+        if (ito) {
+            /* eq. F:xiControlVariate by its left-point quadrature: the
+             * integrand Y sigma grad(u~) at X_k times the increment
+             * W_{k+1} - W_k = sqrt(h) N_k of the same step. */
+            double gn = 0.0;
+            for (int d = 0; d < D; ++d) gn = gn + orc_interp(o->grad[d], X) * nrm[d];
+            xi = xi - Y * sig_sqh * gn;
+        }
         Y = Y + hY * c;
         for (int d = 0; d < D; ++d) Xn[d] = X[d] + h * b[d] + sig_sqh * nrm[d];
         uint64_t s = k;
@@ -524,7 +543,12 @@ static int run_core(const orc_problem *p, const orc_opts *o, const double *x0,
 
     double gval = orc_boundary(p, Xt);
     out->phi = gval * Y + Z;
-    out->e = cv ? (gval - orc_interp(o->u_prev, Xt)) * Y - R : NAN;
+    if (cv)
+        out->e = (gval - orc_interp(o->u_prev, Xt)) * Y - R;
+    else if (ito)
+        out->e = out->phi + xi;
+    else
+        out->e = NAN;
     out->steps = k;
     out->capped = capped;
     out->pad = 0;
@@ -572,7 +596,8 @@ int orc_solve_nodes(const orc_problem *p, const orc_opts *o, const double *nodes
 {
     if (bad_problem(p, o) || n_nodes < 0) return -1;
     int D = p->dim;
-    int cv = o->u_prev != NULL;
+    int ito = o->grad[0] != NULL;
+    int cv = o->u_prev != NULL || ito;
     for (int64_t i = 0; i < n_nodes; ++i) {
         const double *x0 = nodes + i * D;
         nsum sp = {0, 0}, sp2 = {0, 0}, se = {0, 0}, se2 = {0, 0}, spe = {0, 0};
@@ -620,10 +645,12 @@ int orc_solve_nodes(const orc_problem *p, const orc_opts *o, const double *nodes
             continue;
         }
         double Se = nval(se), Se2 = nval(se2), Spe = nval(spe);
-        st->mean = orc_interp(o->u_prev, x0) + Se / n;
+        /* correction: u_prev(x0) + mean(e); Ito: mean(phi + xi) */
+        st->mean = (ito ? 0.0 : orc_interp(o->u_prev, x0)) + Se / n;
         st->var = o->n_paths > 1 ? (Se2 - Se * Se / n) / (n - 1.0) : NAN;
         st->stderr_ = sqrt(st->var / n);
-        /* xi = u_prev(x0) + e - phi is the paper's pathwise control variate. */
+        /* xi = u_prev(x0) + e - phi is the paper's pathwise control variate
+         * (Ito: xi = e - phi); the constant does not enter cov or rho. */
         double cpe = o->n_paths > 1 ? (Spe - Sp * Se / n) / (n - 1.0) : NAN;
         double vxi = st->var + st->var_plain - 2.0 * cpe;
         st->cov = cpe - st->var_plain;

@@ -18,7 +18,11 @@
  * r = f - (L + c) u_prev, both given on grids:
  *   u(x0) = u_prev(x0) + E[ (g - u_prev)(X_tau) Y_tau - int r Y dt ],
  * which is phi + xi of eqs. F:Statistics_VR / F:xiControlVariate written
- * without the gradient of u_prev (Ito's formula applied to u_prev).
+ * without the gradient of u_prev (Ito's formula applied to u_prev). The
+ * paper's own form of that control variate is also computed: the pathwise
+ * Ito integral xi = -int Y sigma grad(u~) . dW of eq. F:xiControlVariate,
+ * accumulated along the same Euler-Maruyama path from grids of the
+ * components of grad(u~), with the estimator phi + xi (E[xi] = 0).
  *
  * Parity status of each function is stated in oracle.c beside it.
  */
@@ -90,11 +94,16 @@ typedef struct {
     uint64_t max_steps;   /* cap on steps per path */
     const orc_grid *u_prev;  /* both NULL: plain estimator */
     const orc_grid *resid;
+    /* Ito control variate (eq. F:xiControlVariate): grad[d] holds the
+     * component d of grad(u~) for d < dim; grad[0] == NULL: not used.
+     * Exclusive with u_prev / resid. */
+    const orc_grid *grad[3];
 } orc_opts;
 
 typedef struct {
     double phi;      /* plain score g(X_tau) Y + Z */
-    double e;        /* correction score (NaN in plain mode) */
+    double e;        /* correction score; with the Ito control variate phi + xi
+                        (NaN in plain mode) */
     uint64_t steps;  /* exit step k */
     int32_t capped;  /* 1 if stopped by max_steps */
     int32_t pad;

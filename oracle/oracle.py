@@ -56,7 +56,8 @@ class Opts(C.Structure):
     _fields_ = [("h", C.c_double), ("n_paths", C.c_uint64), ("path_offset", C.c_uint64),
                 ("stream", C.c_uint32), ("exit_mode", C.c_int32), ("law", C.c_int32),
                 ("max_steps", C.c_uint64),
-                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid))]
+                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)),
+                ("grad", C.POINTER(Grid) * 3)]
 
 
 class PathRec(C.Structure):
@@ -198,7 +199,9 @@ class _GridHolder:
 
 
 def make_opts(h, n_paths=1, path_offset=0, stream=0, exit="bridge", law="gauss",
-              max_steps=1 << 26, u_prev=None, resid=None):
+              max_steps=1 << 26, u_prev=None, resid=None, grad=None):
+    """Options; u_prev + resid select the correction estimator, grad (a list of
+    dim grids, the components of grad(u~)) the Ito control variate."""
     o = Opts()
     o.h = float(h)
     o.n_paths = int(n_paths)
@@ -215,6 +218,12 @@ def make_opts(h, n_paths=1, path_offset=0, stream=0, exit="bridge", law="gauss",
         keep = [gu, gr]
         o.u_prev = C.pointer(gu.grid)
         o.resid = C.pointer(gr.grid)
+    if grad is not None:
+        if u_prev is not None:
+            raise ValueError("grad excludes u_prev / resid")
+        for d, g in enumerate(grad):
+            keep.append(_GridHolder(g))
+            o.grad[d] = C.pointer(keep[-1].grid)
     o._keep = keep  # noqa: SLF001 - lifetime of the grid copies
     return o
 

@@ -339,6 +339,25 @@ def correction_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=
     return mk(u_prev), mk(resid), pert
 
 
+def gradient_grids(pd: dict, n=257, seed=1, dtype=np.float32, n_modes=32, amp=1e-2):
+    """The components of grad(U + p) on an n^dim grid over the domain's
+    bounding box (n: points per axis, or one count per axis), evaluated
+    exactly at the grid points in float64 and stored in `dtype`: a list of dim
+    grids. p is the perturbation of correction_grids with the same seed,
+    n_modes and amp (amp = 0: grad U, the exact gradient when fx = gx = 0), so
+    both estimators can use the same u~."""
+    lo, hi = bounding_box(pd)
+    D = pd["dim"]
+    shape = tuple(int(v) for v in np.broadcast_to(np.asarray(n), (D,)))
+    pts = grid_points(shape, lo, hi)
+    _, grad, _ = manufactured_derivs(pd, pts)
+    if amp:
+        pert = fourier_perturbation(seed, n_modes=n_modes, amp=amp, dim=D)
+        grad = grad + _pert_grid(pert, shape, lo, hi)[1]
+    return [{"dim": D, "n": list(shape), "lo": list(lo), "hi": list(hi),
+             "data": grad[:, d].astype(dtype).reshape(shape[::-1])} for d in range(D)]
+
+
 def sampled_grid(pd: dict, fn, n=257, dtype=np.float64):
     """fn sampled on an n x n grid over the box of pd."""
     lo, hi = pd["lo"], pd["hi"]
