@@ -11,7 +11,8 @@
  * with a Brownian-bridge (default), shifted-boundary (Alg. 1) or naive exit
  * test, and the correction estimator of the multigrid-like iteration, where
  * a previous approximation u_prev is the control variate (eqs. F:Statistics_VR,
- * F:xiControlVariate; Alg. 4, the nodal solves inside the outer loop).
+ * F:xiControlVariate; Alg. 4, the nodal solves inside the outer loop), or
+ * with the paper's pathwise Ito control variate xi itself.
  *
  * Conventions
  *  - All functions return a pdd_status; 0 is success. No exception crosses
@@ -62,7 +63,8 @@ enum { PDD_FP32 = 0, PDD_FP64 = 1 };
 enum { PDD_DTYPE_F32 = 0, PDD_DTYPE_F64 = 1 };
 
 /* Solve flags. */
-#define PDD_PLAIN_ALONGSIDE 1u /* correction solve: also score phi, report rho, VR */
+#define PDD_PLAIN_ALONGSIDE 1u /* correction solve: also score phi, report rho, VR
+                                  (Ito solves always do) */
 #define PDD_TIME_KERNEL 2u     /* record HIP events around the solve's path-kernel launches */
 /* `out` (device) already holds this library's statistics of the same nodes,
  * in the same order, from earlier paths of the same problem, estimator, dt,
@@ -153,7 +155,8 @@ typedef struct {
     int32_t reserved;
     /* Optional per-path records (device, NULL = not kept). Path jj of node i
      * sits at slot s = sum_{i'<i} N_i' + jj: rec_phi[s] = phi, rec_e[s] = e
-     * (correction solves), rec_steps[s] = exit step | (capped << 31). */
+     * (correction solves) or phi + xi (Ito solves), rec_steps[s] = exit step
+     * | (capped << 31). */
     double *rec_phi;
     double *rec_e;
     uint32_t *rec_steps;
@@ -165,7 +168,9 @@ typedef struct {
  * Correction solve: mean = u_prev(x0) + mean(e), var/stderr of e; with
  * PDD_PLAIN_ALONGSIDE also mean_plain/var_plain of phi, cov = Cov[phi, xi]
  * and rho = rho[phi, xi] for the control variate xi = u_prev(x0) + e - phi,
- * vr = var_plain / var and vr_opt = 1 / (1 - rho^2). Unused fields are NaN.
+ * vr = var_plain / var and vr_opt = 1 / (1 - rho^2). Ito solve: the same
+ * with e = phi + xi and mean = mean(e) (no u_prev term), the plain fields
+ * always filled. Unused fields are NaN.
  * sums: Neumaier pairs (sum, compensation) of phi, phi^2, e, e^2, phi*e, so
  * that results of disjoint path ranges can be merged exactly enough. */
 typedef struct {
@@ -184,6 +189,8 @@ typedef struct {
     const pdd_grid *u_prev;     /* both NULL: plain estimator */
     const pdd_grid *resid;
     pdd_node_stats *out;        /* device, n_nodes entries */
+    const pdd_grid *grad;       /* NULL, or dim gradient grids: Ito control variate
+                                   (as pdd_solve_ito; excludes u_prev / resid) */
 } pdd_work_item;
 
 /* Creates a context on HIP device `hip_device` (made current for the call). */
@@ -233,6 +240,21 @@ pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,
                                 const pdd_grid *resid, const double *nodes, int64_t n_nodes,
                                 const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
 
+/* The plain estimator with the paper's pathwise control variate (Sec. 2.3,
+ * eqs. F:VR_Milstein_sys with F = -sigma grad(u~), F:xiControlVariate): along
+ * each path xi_{k+1} = xi_k - Y_k sigma grad(u~)(X_k) . sqrt(h) N_k, with the
+ * normals N_k of the same Euler-Maruyama step (the Alg. 1 xi line read with
+ * the Brownian increment, as the Ito integral requires), and the score is
+ * phi + xi; E[xi] = 0, so the estimate is unbiased for any u~, and its
+ * variance vanishes with h when u~ = u. `grad` points to dim grids, grad[d]
+ * holding the component d of grad(u~), all with the same n, lo and hi and
+ * the dtype of the path precision (rules of pdd_grid; borrowed until the
+ * stream completes). Statistics as described at pdd_node_stats; records need
+ * rec_phi and rec_e. Errors as for pdd_solve_nodes, and PDD_E_INVALID for a
+ * NULL `grad`, a malformed grid or grids of different geometries. */
+pdd_status pdd_solve_ito(pdd_problem *problem, const pdd_grid *grad, const double *nodes, int64_t n_nodes,
+                         const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
+
 /* Several problems in one persistent launch per (dim, precision, estimator)
  * group. Each item's results equal those of its own solve call. */
 pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items,
@@ -272,8 +294,9 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int3
 typedef struct {
     int32_t precision;  /* PDD_FP32 or PDD_FP64 */
     int32_t dim;        /* 2 or 3 */
-    int32_t correction; /* 0 plain, 1 correction estimator */
-    int32_t generic;    /* 0 or 1, as above */
+    int32_t correction; /* 0 plain, 1 correction estimator, 2 Ito control variate */
+    int32_t generic;    /* 0 or 1, as above (1 for the Ito control variate, which
+                           runs the generic kernel only) */
 } pdd_tuning_key;
 
 /* Times samples of `item` (up to 32 of its nodes, about 8 and 16 paths per

@@ -42,22 +42,24 @@ struct DeviceBuffer {
 struct HostItem {
     pdd_problem *prob = nullptr;
     const pdd_grid *u_prev = nullptr, *resid = nullptr;
+    const pdd_grid *grad = nullptr;  // dim gradient grids (Ito control variate)
     const double *nodes = nullptr;
     int64_t n_nodes = 0;
     const pdd_solve_opts *o = nullptr;
     pdd_node_stats *out = nullptr;
-    bool cv = false, score_plain = true, uniform = true, caller_records = false, accumulate = false;
+    int est = kEstPlain;  // kEstPlain, kEstCorrection or kEstIto
+    bool score_plain = true, uniform = true, caller_records = false, accumulate = false;
     uint64_t total = 0, max_steps = 0;
     std::vector<uint64_t> starts;  // item-relative prefix (non-uniform counts)
 };
 
 // Checks an item's arguments against its problem (nothing is enqueued).
 pdd_status validate_item(HostItem &it);
-// Key of the launch-shape table: precision, dimension, estimator and kernel
-// (specialised box / bridge / Gaussian / analytic, or generic).
-inline int tuning_key(int precision, int dim, bool cv, bool generic)
+// Key of the launch-shape table: precision, dimension, estimator (kEst*) and
+// kernel (specialised box / bridge / Gaussian / analytic, or generic).
+inline int tuning_key(int precision, int dim, int est, bool generic)
 {
-    return precision * 8 + (dim - 2) * 4 + (cv ? 2 : 0) + (generic ? 1 : 0);
+    return precision * 12 + (dim - 2) * 6 + est * 2 + (generic ? 1 : 0);
 }
 // Whether an item can run in the specialised kernel.
 bool specialised(const HostItem &it);

@@ -370,13 +370,12 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
 // The same interpolation from the grid's cell layout: the corners of the
 // cell come in one aligned vector load (two in 3D) instead of 2^D gathers;
 // operands and operations are those of interp, so the value is identical.
+// interp_cell_at takes the cell and weights already found by grid_cell (for
+// several grids of one geometry).
 template <class T, int D>
-__device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
+__device__ __forceinline__ T interp_cell_at(const GridView<T> &g, const int *i, const T *w)
 {
     typedef T V4 __attribute__((ext_vector_type(4)));
-    int i[D];
-    T w[D];
-    grid_cell<T, D>(g, x, i, w);
     const size_t mx = (size_t)(g.n[0] - 1);
     if (D == 2) {
         const V4 c = *reinterpret_cast<const V4 *>(g.cells + (((size_t)i[1] * mx + i[0]) << 2));
@@ -397,6 +396,15 @@ __device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
         acc = madd(dz ? w[2 % D] : (T)1 - w[2 % D], layer, acc);
     }
     return acc;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
+{
+    int i[D];
+    T w[D];
+    grid_cell<T, D>(g, x, i, w);
+    return interp_cell_at<T, D>(g, i, w);
 }
 
 // Cell layout of a grid (see cell_values), values converted from S to T: one
@@ -521,12 +529,12 @@ __device__ __forceinline__ void project(const DevProblem<T> &P, int domain, cons
 // State of the path a lane is walking.
 // RNG_TABLE: items may be merged solves with a per-node RNG table (batch
 // kernel); the single-item kernel takes the stream tag from its item.
-template <class T, int D, bool CV, class M, bool RNG_TABLE>
+template <class T, int D, int EST, class M, bool RNG_TABLE>
 struct Walker {
     T X[D], Xt[D];
     T Y;
     T m;  // distance from X to the boundary (inside; cached between steps)
-    double Z, R;
+    double Z, R;  // R: sum h Y r (correction estimator) or xi (Ito control variate)
     uint64_t slot;
     uint32_t k, j, node, capped;
     uint32_t tag;  // stream tag of the path's solve (RNG_TABLE)
@@ -613,7 +621,8 @@ struct Walker {
     // false when the path has ended (exit point in Xt). Everything that ends a
     // path (leaving the domain, a live bridge face, the shift band of the next
     // step, the step cap) goes through one rarely taken branch.
-    __device__ __forceinline__ bool step(const ItemCore<T> &a, const DevProblem<T> &P, uint32_t wa,
+    template <class A>
+    __device__ __forceinline__ bool step(const A &a, const DevProblem<T> &P, uint32_t wa,
                                          uint32_t wb, uint32_t wc, uint32_t wd)
     {
         T n[D];
@@ -626,10 +635,22 @@ struct Walker {
             if (D == 3) n[2 % D] = (wc >> 31) ? (T)1 : (T)-1;
         }
         T b[D], c, f = (T)0;
-        coefficients<T, D>(P, X, b, c, f, a.score_plain != 0, cf, M::tab(P));
+        coefficients<T, D>(P, X, b, c, f, EST == kEstIto || a.score_plain != 0, cf, M::tab(P));
         const T hY = a.h * Y;
-        if (a.score_plain) Z -= (double)(hY * f);
-        if (CV) R += (double)(hY * interp_cells<T, D>(a.resid, X));
+        if (EST == kEstIto || a.score_plain) Z -= (double)(hY * f);
+        if (EST == kEstCorrection) R += (double)(hY * interp_cells<T, D>(a.resid, X));
+        if constexpr (EST == kEstIto) {
+            // eq. F:xiControlVariate, left-point rule: -Y sigma grad(u~)(X_k)
+            // . sqrt(h) N_k, with this step's normals; the gradient grids
+            // share one geometry, so the cell is found once
+            int gi[D];
+            T gw[D];
+            grid_cell<T, D>(a.grad[0], X, gi, gw);
+            T gn = (T)0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) gn = madd(interp_cell_at<T, D>(a.grad[d], gi, gw), n[d], gn);
+            R -= (double)((Y * a.sig_sqh) * gn);
+        }
         Y = madd(hY, c, Y);
         T Xn[D];
 #pragma unroll
@@ -750,8 +771,14 @@ struct Walker {
     {
         const T gv = boundary_value<T, D>(P, Xt);
         const uint64_t r = slot - rec_base;
-        if (a.score_plain) a.rec_phi[r] = madd((double)gv, (double)Y, Z);
-        if (CV) {
+        if (EST == kEstIto) {  // phi and phi + xi
+            const double phi = madd((double)gv, (double)Y, Z);
+            a.rec_phi[r] = phi;
+            a.rec_e[r] = phi + R;
+        } else if (a.score_plain) {
+            a.rec_phi[r] = madd((double)gv, (double)Y, Z);
+        }
+        if (EST == kEstCorrection) {
             const T up = interp<T, D>(a.u_prev, Xt);
             a.rec_e[r] = madd((double)gv - (double)up, (double)Y, -R);
         }
@@ -812,10 +839,10 @@ struct Pool {
 // they stay in vector registers for the whole loop (about 96 registers, five
 // waves per SIMD) instead of being reloaded by scalar loads at every step,
 // which the scalar register file cannot hold next to the other constants.
-template <class T, int D, bool CV, class M>
+template <class T, int D, int EST, class M>
 __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
 {
-    static_assert(kOneItemKernel<T, D, CV>, "single-item kernel is for FP32 2D plain solves");
+    static_assert(kOneItemKernel<T, D, EST>, "single-item kernel is for FP32 2D plain solves");
     const LaunchArgs &L = A.launch;
     const ItemCore<T> &a = A.item;
     const DevProblem<T> &P = A.prob;
@@ -824,7 +851,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     __shared__ T s_cf[kMaxDense];
     for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
     __syncthreads();
-    Walker<T, D, CV, M, false> w;
+    Walker<T, D, EST, M, false> w;
     w.cf = s_cf;
     w.ks = key_schedule(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
@@ -947,7 +974,7 @@ struct ItemQueue {
 // order, so no barrier is needed).
 // FP64 walks are asked to fit three waves per SIMD (168 registers; the few
 // spilled values live outside the step loop), which is faster than two.
-template <class T, int D, bool CV, class M>
+template <class T, int D, int EST, class M>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1, 8)))
     path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
                      const DevProblem<T> *__restrict__ probs)
@@ -956,7 +983,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[256 / 64][kMaxDense];
     T *my_cf = s_cf[threadIdx.x >> 6];
-    Walker<T, D, CV, M, true> w;
+    Walker<T, D, EST, M, true> w;
     w.cf = my_cf;
     int st = 0;
     ItemQueue<T> q;
@@ -1026,43 +1053,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 
 }  // namespace
 
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
                               const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s)
 {
-    if (spec)
-        hipLaunchKernelGGL((path_kernel_many<T, D, CV, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
-                           items, probs);
-    else
-        hipLaunchKernelGGL((path_kernel_many<T, D, CV, RuntimeMode>), dim3(grid), dim3(block), 0, s, l, items,
+    if constexpr (EST == kEstIto) {  // generic kernel only
+        if (spec) return hipErrorInvalidDeviceFunction;
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, l, items,
                            probs);
+    } else {
+        if (spec)
+            hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
+                               items, probs);
+        else
+            hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, l,
+                               items, probs);
+    }
     return hipGetLastError();
 }
 
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s)
 {
     static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
-    if constexpr (kOneItemKernel<T, D, CV>) {
+    if constexpr (kOneItemKernel<T, D, EST>) {
         if (spec)
-            hipLaunchKernelGGL((path_kernel_one<T, D, CV, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((path_kernel_one<T, D, CV, RuntimeMode>), dim3(grid), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, a);
         return hipGetLastError();
     } else {
         return hipErrorInvalidDeviceFunction;
     }
 }
 
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 const void *path_kernel_symbol(bool one, bool spec)
 {
-    if constexpr (kOneItemKernel<T, D, CV>)
+    if constexpr (kOneItemKernel<T, D, EST>)
         if (one)
-            return spec ? reinterpret_cast<const void *>(&path_kernel_one<T, D, CV, BoxBridgeGauss>)
-                        : reinterpret_cast<const void *>(&path_kernel_one<T, D, CV, RuntimeMode>);
-    return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, CV, BoxBridgeGauss>)
-                : reinterpret_cast<const void *>(&path_kernel_many<T, D, CV, RuntimeMode>);
+            return spec ? reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, BoxBridgeGauss>)
+                        : reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, RuntimeMode>);
+    if constexpr (EST == kEstIto)
+        return spec ? nullptr : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
+    else
+        return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGauss>)
+                    : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
 }
 
 template <class S, class T, int D>
@@ -1087,19 +1123,23 @@ PDD_GRID_CELLS(float, double, 3)
 PDD_GRID_CELLS(double, float, 2)
 PDD_GRID_CELLS(double, float, 3)
 
-#define PDD_INSTANTIATE(T, D, CV)                                                              \
-    template hipError_t launch_path_kernel<T, D, CV>(const LaunchArgs &, const ItemDesc<T> *, \
+#define PDD_INSTANTIATE(T, D, EST)                                                              \
+    template hipError_t launch_path_kernel<T, D, EST>(const LaunchArgs &, const ItemDesc<T> *, \
                                                      const DevProblem<T> *, int, int, bool, hipStream_t); \
-    template hipError_t launch_path_kernel_one<T, D, CV>(const OneItemArgs<T> &, int, int, bool, hipStream_t); \
-    template const void *path_kernel_symbol<T, D, CV>(bool, bool);
+    template hipError_t launch_path_kernel_one<T, D, EST>(const OneItemArgs<T> &, int, int, bool, hipStream_t); \
+    template const void *path_kernel_symbol<T, D, EST>(bool, bool);
 
-PDD_INSTANTIATE(float, 2, false)
-PDD_INSTANTIATE(float, 2, true)
-PDD_INSTANTIATE(float, 3, false)
-PDD_INSTANTIATE(float, 3, true)
-PDD_INSTANTIATE(double, 2, false)
-PDD_INSTANTIATE(double, 2, true)
-PDD_INSTANTIATE(double, 3, false)
-PDD_INSTANTIATE(double, 3, true)
+PDD_INSTANTIATE(float, 2, kEstPlain)
+PDD_INSTANTIATE(float, 2, kEstCorrection)
+PDD_INSTANTIATE(float, 2, kEstIto)
+PDD_INSTANTIATE(float, 3, kEstPlain)
+PDD_INSTANTIATE(float, 3, kEstCorrection)
+PDD_INSTANTIATE(float, 3, kEstIto)
+PDD_INSTANTIATE(double, 2, kEstPlain)
+PDD_INSTANTIATE(double, 2, kEstCorrection)
+PDD_INSTANTIATE(double, 2, kEstIto)
+PDD_INSTANTIATE(double, 3, kEstPlain)
+PDD_INSTANTIATE(double, 3, kEstCorrection)
+PDD_INSTANTIATE(double, 3, kEstIto)
 
 }  // namespace pdd

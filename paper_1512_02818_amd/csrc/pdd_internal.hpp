@@ -15,6 +15,9 @@ constexpr int kExitBridge = 0, kExitShift = 1, kExitNaive = 2;
 constexpr int kLawGauss = 0, kLawRademacher = 1;
 constexpr int kBox = 0, kBall = 1;
 constexpr uint32_t kCappedBit = 0x80000000u;
+// Estimators: plain phi; the correction estimator (u_prev and its residual on
+// grids); phi + xi with the Ito control variate xi (gradient grids).
+constexpr int kEstPlain = 0, kEstCorrection = 1, kEstIto = 2;
 
 // One trig term amp * prod_d sin(k_d x_d + ph_d). In FP32, k and ph are in
 // revolutions (k / 2 pi, ph / 2 pi: the hardware sine takes revolutions); in
@@ -127,10 +130,12 @@ struct ItemCore {
 // the node index, stream tag and path offset (low word) of the node in the
 // solve it belongs to, when several solves that walk alike are merged into
 // this item; null: node, stream_tag, path_offset of the core. The
-// single-item kernel takes the core alone.
+// single-item kernel takes the core alone. Ito items read the components of
+// grad(u~) from grad[0 .. dim - 1] (one grid geometry, cell layout).
 template <class T>
 struct ItemDesc : ItemCore<T> {
     const uint32_t *node_rng;
+    GridView<T> grad[3];
 };
 
 // One launch of the path kernel: slots [slot_begin, slot_begin + launch_slots)
@@ -167,7 +172,8 @@ struct FinalItem {
     int32_t accumulate;   // start from the statistics already in `out`
     int32_t own_reduce;   // caller records: reduced by a launch of its own
     int32_t up_f64;
-    // u_prev for the node value u_prev(x0) + mean(e), read in its own dtype
+    // u_prev for the node value u_prev(x0) + mean(e), read in its own dtype;
+    // null (Ito items): the node value is mean(e), e = phi + xi
     const void *up_data;
     int32_t up_n[3];
     int32_t pad;
@@ -232,18 +238,19 @@ struct OneItemArgs {
 // fits seven waves per SIMD there without spilling, while with FP64 or the
 // correction terms the larger argument block spills and the table kernel is
 // as fast. Both kernels give bitwise identical results.
-template <class T, int D, bool CV>
-constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && !CV;
+template <class T, int D, int EST>
+constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && EST == kEstPlain;
 
 // Launchers (defined in the .hip files). `spec`: every item of the launch is
 // a box problem with the bridge exit test and Gaussian increments, for which
-// a specialised kernel is compiled.
-template <class T, int D, bool CV>
+// a specialised kernel is compiled (plain and correction estimators; Ito
+// groups run the generic kernel). EST: kEstPlain, kEstCorrection or kEstIto.
+template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
                               const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s);
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s);
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 const void *path_kernel_symbol(bool one, bool spec);
 // Fills `cells` (cell_values entries) from the point values of a grid,
 // converted from S to T.

@@ -331,7 +331,7 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
 bool pdd::specialised(const HostItem &it)
 {
     return it.prob->desc.domain == PDD_DOMAIN_BOX && it.o->exit_mode == PDD_EXIT_BRIDGE &&
-           it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0;
+           it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0 && it.est != kEstIto;
 }
 
 pdd_status pdd::validate_item(HostItem &it)
@@ -345,8 +345,10 @@ pdd_status pdd::validate_item(HostItem &it)
     if (it.n_nodes > 0 && !it.out) return fail(PDD_E_INVALID, "out is NULL");
     const pdd_problem_desc &d = it.prob->desc;
     const int dim = d.dim;
-    it.cv = it.u_prev || it.resid;
-    if (it.cv && (!it.u_prev || !it.resid)) return fail(PDD_E_INVALID, "correction needs u_prev and residual grids");
+    const bool cv = it.u_prev || it.resid;
+    if (cv && (!it.u_prev || !it.resid)) return fail(PDD_E_INVALID, "correction needs u_prev and residual grids");
+    if (cv && it.grad) return fail(PDD_E_INVALID, "an item takes the correction grids or the gradient grids, not both");
+    it.est = cv ? kEstCorrection : (it.grad ? kEstIto : kEstPlain);
     if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(PDD_E_INVALID, "dt must be > 0");
     if (o->precision != PDD_FP32 && o->precision != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
     if (o->exit_mode < PDD_EXIT_BRIDGE || o->exit_mode > PDD_EXIT_NAIVE) return fail(PDD_E_INVALID, "bad exit mode");
@@ -354,15 +356,26 @@ pdd_status pdd::validate_item(HostItem &it)
     if (o->stream_id >= (1u << 28)) return fail(PDD_E_INVALID, "stream_id must be < 2^28");
     it.max_steps = o->max_steps ? o->max_steps : kDefaultMaxSteps;
     if (it.max_steps >= (1ull << 31)) return fail(PDD_E_INVALID, "max_steps must be < 2^31");
-    if (it.cv) {
+    if (cv) {
         pdd_status st = check_grid(d, it.u_prev, o->precision, "u_prev");
         if (st) return st;
         st = check_grid(d, it.resid, o->precision, "residual");
         if (st) return st;
     }
+    if (it.est == kEstIto) {
+        for (int q = 0; q < dim; ++q) {
+            pdd_status st = check_grid(d, &it.grad[q], o->precision, "gradient");
+            if (st) return st;
+            for (int i = 0; i < dim; ++i)
+                if (it.grad[q].n[i] != it.grad[0].n[i] || it.grad[q].lo[i] != it.grad[0].lo[i] ||
+                    it.grad[q].hi[i] != it.grad[0].hi[i])
+                    return fail(PDD_E_INVALID, "gradient grids must share one geometry (n, lo, hi)");
+        }
+    }
     if ((o->rec_phi || o->rec_e) && !o->rec_steps) return fail(PDD_E_INVALID, "per-path records need rec_steps");
-    if (o->rec_steps && it.cv && !o->rec_e) return fail(PDD_E_INVALID, "correction records need rec_e");
-    it.score_plain = !it.cv || (o->flags & PDD_PLAIN_ALONGSIDE);
+    if (o->rec_steps && it.est != kEstPlain && !o->rec_e) return fail(PDD_E_INVALID, "correction and Ito records need rec_e");
+    // the Ito control variate rides on phi, which is therefore always scored
+    it.score_plain = it.est != kEstCorrection || (o->flags & PDD_PLAIN_ALONGSIDE);
     if (o->rec_steps && it.score_plain && !o->rec_phi) return fail(PDD_E_INVALID, "records need rec_phi");
     it.caller_records = o->rec_steps != nullptr;
     it.accumulate = (o->flags & PDD_ACCUMULATE) != 0;
@@ -429,7 +442,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Runs a group of items that share precision, dimension and estimator: one
 // slot space, launches of the persistent path kernel over it, per-item
 // reductions and statistics.
-template <class T, int D, bool CV>
+template <class T, int D, int EST>
 pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tuning &tune,
                      bool timed, hipStream_t s)
 {
@@ -472,13 +485,18 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         if (a->dt != b->dt || a->exit_mode != b->exit_mode || a->law != b->law || x->max_steps != y->max_steps ||
             x->score_plain != y->score_plain)
             return false;
-        if (!CV) return true;
+        if (EST == kEstPlain) return true;
         auto same = [](const pdd_grid *g, const pdd_grid *h) {
             if (g->data != h->data || g->dtype != h->dtype) return false;
             for (int i = 0; i < D; ++i)
                 if (g->n[i] != h->n[i] || g->lo[i] != h->lo[i] || g->hi[i] != h->hi[i]) return false;
             return true;
         };
+        if (EST == kEstIto) {
+            for (int d = 0; d < D; ++d)
+                if (!same(&x->grad[d], &y->grad[d])) return false;
+            return true;
+        }
         return same(x->u_prev, y->u_prev) && same(x->resid, y->resid);
     };
     std::vector<int> kfirst;  // first item of each kernel item, then n_items
@@ -532,36 +550,39 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     if ((st = ensure(ctx, ctx->acc, n_nodes_all * sizeof(NodeAcc)))) return st;
     if ((st = ensure(ctx, ctx->counters, ctr_bytes))) return st;
     const bool need_phi = std::any_of(items.begin(), items.end(), [](HostItem *i) { return i->score_plain && !i->caller_records; });
-    const size_t per_slot = sizeof(uint32_t) + (need_phi ? 8 : 0) + (CV ? 8 : 0);
+    constexpr bool HAS_E = EST != kEstPlain;
+    const size_t per_slot = sizeof(uint32_t) + (need_phi ? 8 : 0) + (HAS_E ? 8 : 0);
     double *sc_phi = nullptr, *sc_e = nullptr;
     uint32_t *sc_steps = nullptr;
     if (any_scratch && total) {
         if ((st = ensure(ctx, ctx->rec, per_launch * per_slot))) return st;
         char *base = static_cast<char *>(ctx->rec.ptr);
         sc_phi = need_phi ? reinterpret_cast<double *>(base) : nullptr;
-        sc_e = CV ? reinterpret_cast<double *>(base + (need_phi ? per_launch * 8 : 0)) : nullptr;
-        sc_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((need_phi ? 8 : 0) + (CV ? 8 : 0)));
+        sc_e = HAS_E ? reinterpret_cast<double *>(base + (need_phi ? per_launch * 8 : 0)) : nullptr;
+        sc_steps = reinterpret_cast<uint32_t *>(base + per_launch * ((need_phi ? 8 : 0) + (HAS_E ? 8 : 0)));
     }
-    // residual grids of a correction group in cell layout (the path kernel
-    // reads them at every step): one copy per distinct grid, rebuilt per
+    // grids the path kernel reads at every step, in cell layout: the residual
+    // of a correction item, the gradient components of an Ito item (grid c of
+    // item q at cell_at[3 q + c]); one copy per distinct grid, rebuilt per
     // solve since the caller may change a grid's values between solves
     std::vector<const pdd_grid *> cell_grid;
-    std::vector<size_t> cell_off, cell_at(n_items, 0);
-    if (CV) {
+    std::vector<size_t> cell_off, cell_at(3 * (size_t)n_items, 0);
+    if (HAS_E) {
         size_t used = 0;
-        for (int q = 0; q < n_items; ++q) {
-            const pdd_grid *g = items[q]->resid;
-            size_t k = 0;
-            while (k < cell_grid.size() &&
-                   !(cell_grid[k]->data == g->data && std::equal(g->n, g->n + D, cell_grid[k]->n)))
-                ++k;
-            if (k == cell_grid.size()) {
-                cell_grid.push_back(g);
-                cell_off.push_back(used);
-                used += align_up(cell_values<T>(g->n, D), 64);
+        for (int q = 0; q < n_items; ++q)
+            for (int c = 0; c < (EST == kEstIto ? D : 1); ++c) {
+                const pdd_grid *g = EST == kEstIto ? &items[q]->grad[c] : items[q]->resid;
+                size_t k = 0;
+                while (k < cell_grid.size() &&
+                       !(cell_grid[k]->data == g->data && std::equal(g->n, g->n + D, cell_grid[k]->n)))
+                    ++k;
+                if (k == cell_grid.size()) {
+                    cell_grid.push_back(g);
+                    cell_off.push_back(used);
+                    used += align_up(cell_values<T>(g->n, D), 64);
+                }
+                cell_at[3 * (size_t)q + c] = cell_off[k];
             }
-            cell_at[q] = cell_off[k];
-        }
         if ((st = ensure(ctx, ctx->cells, used * sizeof(T)))) return st;
     }
     T *d_cells = static_cast<T *>(ctx->cells.ptr);
@@ -603,7 +624,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         fi.has_phi = it.score_plain ? 1 : 0;
         fi.accumulate = it.accumulate ? 1 : 0;
         fi.own_reduce = it.caller_records ? 1 : 0;
-        if (CV) {
+        if (EST == kEstCorrection) {
             fi.up_data = it.u_prev->data;
             fi.up_f64 = it.u_prev->dtype == PDD_DTYPE_F64;
             for (int i = 0; i < 3; ++i) {
@@ -651,7 +672,12 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         a.bridge_thresh = (T)kBridgeSkip;
         a.u_prev = make_view<T>(it.u_prev, D);
         a.resid = make_view<T>(it.resid, D);
-        if (CV) a.resid.cells = d_cells + cell_at[q];
+        if (EST == kEstCorrection) a.resid.cells = d_cells + cell_at[3 * (size_t)q];
+        if (EST == kEstIto)
+            for (int c = 0; c < D; ++c) {
+                a.grad[c] = make_view<T>(&it.grad[c], D);
+                a.grad[c].cells = d_cells + cell_at[3 * (size_t)q + c];
+            }
     }
     h_gstart[n_nodes_all] = total;
     // kernel items: a merged one walks the nodes of its items in order, each
@@ -710,10 +736,10 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
 
     const int block = tune.block;
     // (the single-item kernel has no per-node RNG table)
-    const bool one = n_k == 1 && kOneItemKernel<T, D, CV> && kfirst[1] == 1;
+    const bool one = n_k == 1 && kOneItemKernel<T, D, EST> && kfirst[1] == 1;
     // box / bridge / Gaussian / analytic throughout: the specialised kernel
     const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) { return specialised(*i); });
-    const void *fn = path_kernel_symbol<T, D, CV>(one, spec);
+    const void *fn = path_kernel_symbol<T, D, EST>(one, spec);
     // more workgroups than fit at once only queue behind the resident ones
     const int occ = occupancy(ctx, fn, block);
     const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
@@ -753,9 +779,9 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             // the single item starts at slot 0; scratch records of this launch
             // start at slot b
             if (A.item.rec_launch) A.item.rec_base = b;
-            HIP_TRY((launch_path_kernel_one<T, D, CV>(A, grid, block, spec, s)));
+            HIP_TRY((launch_path_kernel_one<T, D, EST>(A, grid, block, spec, s)));
         } else {
-            HIP_TRY((launch_path_kernel<T, D, CV>(L, d_items, d_probs, grid, block, spec, s)));
+            HIP_TRY((launch_path_kernel<T, D, EST>(L, d_items, d_probs, grid, block, spec, s)));
         }
         if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
         // reduction of the nodes this launch touched: one launch for the items
@@ -775,7 +801,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             r.slot_end = b + len;
             r.acc = d_acc;
             r.node_lo = n_lo;
-            r.has_e = CV;
+            r.has_e = HAS_E;
             r.node_item = d_nitem;
             r.fitems = d_fitems;
             r.n_chunks = chunks_in(h_gstart, n_lo, n_hi, b, b + len);
@@ -802,7 +828,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             r.acc = d_acc + gnode[q];
             r.node_lo = n_lo;
             r.has_phi = it.score_plain;
-            r.has_e = CV;
+            r.has_e = HAS_E;
             r.n_chunks = chunks_in(gs, n_lo, n_hi, lo, hi);
             r.partials = static_cast<NodeAcc *>(ctx->partials.ptr);
             HIP_TRY(launch_reduce(r, n_hi - n_lo + 1, s));
@@ -814,11 +840,20 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     f.nodes = reinterpret_cast<const double *>(dv + off_nodes);
     f.n_nodes = (uint32_t)n_nodes_all;
     f.dim = D;
-    f.has_e = CV;
+    f.has_e = HAS_E;
     f.node_item = d_nitem;
     f.fitems = d_fitems;
     HIP_TRY(launch_finalize(f, s));
     return PDD_OK;
+}
+
+template <class T, int D>
+pdd_status run_group_est(int est, pdd_ctx *ctx, std::vector<HostItem *> &g, const pdd_tuning &tune, bool timed,
+                         hipStream_t s)
+{
+    if (est == kEstCorrection) return run_group<T, D, kEstCorrection>(ctx, g, tune, timed, s);
+    if (est == kEstIto) return run_group<T, D, kEstIto>(ctx, g, tune, timed, s);
+    return run_group<T, D, kEstPlain>(ctx, g, tune, timed, s);
 }
 
 }  // namespace
@@ -841,25 +876,20 @@ pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_
     if (ctx->any_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
     for (int prec = 0; prec < 2; ++prec)
         for (int dim = 2; dim <= 3; ++dim)
-            for (int cv = 0; cv < 2; ++cv) {
+            for (int est = kEstPlain; est <= kEstIto; ++est) {
                 std::vector<HostItem *> g;
                 for (auto &it : items)
-                    if (it.o->precision == prec && it.prob->desc.dim == dim && (int)it.cv == cv && it.n_nodes > 0)
+                    if (it.o->precision == prec && it.prob->desc.dim == dim && it.est == est && it.n_nodes > 0)
                         g.push_back(&it);
                 if (g.empty()) continue;
                 const bool generic = !std::all_of(g.begin(), g.end(), [](const HostItem *i) { return specialised(*i); });
-                if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, cv, generic), tune))) return st;
-                if (prec == PDD_FP32) {
-                    if (dim == 2)
-                        st = cv ? run_group<float, 2, true>(ctx, g, tune, timed, s) : run_group<float, 2, false>(ctx, g, tune, timed, s);
-                    else
-                        st = cv ? run_group<float, 3, true>(ctx, g, tune, timed, s) : run_group<float, 3, false>(ctx, g, tune, timed, s);
-                } else {
-                    if (dim == 2)
-                        st = cv ? run_group<double, 2, true>(ctx, g, tune, timed, s) : run_group<double, 2, false>(ctx, g, tune, timed, s);
-                    else
-                        st = cv ? run_group<double, 3, true>(ctx, g, tune, timed, s) : run_group<double, 3, false>(ctx, g, tune, timed, s);
-                }
+                if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, est, generic), tune))) return st;
+                if (prec == PDD_FP32)
+                    st = dim == 2 ? run_group_est<float, 2>(est, ctx, g, tune, timed, s)
+                                  : run_group_est<float, 3>(est, ctx, g, tune, timed, s);
+                else
+                    st = dim == 2 ? run_group_est<double, 2>(est, ctx, g, tune, timed, s)
+                                  : run_group_est<double, 3>(est, ctx, g, tune, timed, s);
                 if (st) return st;
                 // the next group reuses the staging buffer and the scratch
                 HIP_TRY(hipEventRecord(ctx->done, s));
@@ -1060,6 +1090,21 @@ pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev, co
     return run_items(problem->ctx, items, static_cast<hipStream_t>(stream));
 }
 
+pdd_status pdd_solve_ito(pdd_problem *problem, const pdd_grid *grad, const double *nodes, int64_t n_nodes,
+                         const pdd_solve_opts *opts, pdd_node_stats *out, void *stream)
+{
+    if (!problem) return fail(PDD_E_INVALID, "problem is NULL");
+    if (!grad) return fail(PDD_E_INVALID, "the Ito control variate needs the gradient grids");
+    std::vector<HostItem> items(1);
+    items[0].prob = problem;
+    items[0].grad = grad;
+    items[0].nodes = nodes;
+    items[0].n_nodes = n_nodes;
+    items[0].o = opts;
+    items[0].out = out;
+    return run_items(problem->ctx, items, static_cast<hipStream_t>(stream));
+}
+
 pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *witems, int32_t n_items, void *stream)
 {
     if (!ctx) return fail(PDD_E_INVALID, "ctx is NULL");
@@ -1073,6 +1118,7 @@ pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *witems, int32_t n_
         items[q].prob = w.problem;
         items[q].u_prev = w.u_prev;
         items[q].resid = w.resid;
+        items[q].grad = w.grad;
         items[q].nodes = w.nodes;
         items[q].n_nodes = w.n_nodes;
         items[q].o = w.opts;
@@ -1126,6 +1172,7 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int
         it.prob = w.problem;
         it.u_prev = w.u_prev;
         it.resid = w.resid;
+        it.grad = w.grad;
         it.nodes = w.nodes;
         it.n_nodes = w.n_nodes;
         it.o = &opts[q];
@@ -1193,6 +1240,7 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *witems, int
         it.prob = witems[q].problem;
         it.u_prev = witems[q].u_prev;
         it.resid = witems[q].resid;
+        it.grad = witems[q].grad;
         it.nodes = witems[q].nodes;
         it.n_nodes = n;
         it.o = &opts[q];
@@ -1227,21 +1275,28 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     if (item->n_nodes < 1 || !item->nodes) return fail(PDD_E_INVALID, "autotuning needs nodes");
     if ((item->u_prev == nullptr) != (item->resid == nullptr))
         return fail(PDD_E_INVALID, "correction needs u_prev and residual grids");
+    if (item->u_prev && item->grad)
+        return fail(PDD_E_INVALID, "an item takes the correction grids or the gradient grids, not both");
     const int dim = item->problem->desc.dim;
-    const bool cv = item->u_prev != nullptr;
+    const int est = item->u_prev ? kEstCorrection : (item->grad ? kEstIto : kEstPlain);
     const int prec = item->opts->precision;
     if (prec != PDD_FP32 && prec != PDD_FP64) return fail(PDD_E_INVALID, "bad precision");
     HIP_TRY(hipSetDevice(ctx->device));
     // the kernel this group launches for a single item, and its occupancy
     const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX && item->problem->pf.tab == 0 &&
-                      item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS;
-    const void *fn = nullptr;
-    if (prec == PDD_FP32)
-        fn = dim == 2 ? (cv ? path_kernel_symbol<float, 2, true>(true, spec) : path_kernel_symbol<float, 2, false>(true, spec))
-                      : (cv ? path_kernel_symbol<float, 3, true>(true, spec) : path_kernel_symbol<float, 3, false>(true, spec));
-    else
-        fn = dim == 2 ? (cv ? path_kernel_symbol<double, 2, true>(true, spec) : path_kernel_symbol<double, 2, false>(true, spec))
-                      : (cv ? path_kernel_symbol<double, 3, true>(true, spec) : path_kernel_symbol<double, 3, false>(true, spec));
+                      item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS &&
+                      est != kEstIto;
+    auto symbol = [&](auto tag) -> const void * {
+        using T = decltype(tag);
+        if (dim == 2)
+            return est == kEstCorrection ? path_kernel_symbol<T, 2, kEstCorrection>(true, spec)
+                   : est == kEstIto      ? path_kernel_symbol<T, 2, kEstIto>(true, spec)
+                                         : path_kernel_symbol<T, 2, kEstPlain>(true, spec);
+        return est == kEstCorrection ? path_kernel_symbol<T, 3, kEstCorrection>(true, spec)
+               : est == kEstIto      ? path_kernel_symbol<T, 3, kEstIto>(true, spec)
+                                     : path_kernel_symbol<T, 3, kEstPlain>(true, spec);
+    };
+    const void *fn = prec == PDD_FP32 ? symbol(0.0f) : symbol(0.0);
     const int occ256 = occupancy(ctx, fn, 256);
     // sample: up to 32 nodes spread over the item's, about 8 (then 16) paths
     // per resident lane of the default shape
@@ -1286,6 +1341,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
         items[0].prob = item->problem;
         items[0].u_prev = item->u_prev;
         items[0].resid = item->resid;
+        items[0].grad = item->grad;
         items[0].nodes = nodes.data();
         items[0].n_nodes = ns;
         items[0].o = &o;
@@ -1333,7 +1389,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     }
     cleanup();
     if (st) return st;
-    ctx->tuned[tuning_key(prec, dim, cv, !spec)] = best;
+    ctx->tuned[tuning_key(prec, dim, est, !spec)] = best;
     *out = best;
     return PDD_OK;
 }
@@ -1342,9 +1398,11 @@ pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tun
 {
     if (!ctx || !key) return fail(PDD_E_INVALID, "NULL argument");
     if ((key->precision != PDD_FP32 && key->precision != PDD_FP64) || key->dim < 2 || key->dim > 3 ||
-        (key->correction != 0 && key->correction != 1) || (key->generic != 0 && key->generic != 1))
+        key->correction < 0 || key->correction > 2 || (key->generic != 0 && key->generic != 1))
         return fail(PDD_E_INVALID, "bad tuning key");
-    const int k = tuning_key(key->precision, key->dim, key->correction != 0, key->generic != 0);
+    if (key->correction == kEstIto && key->generic != 1)
+        return fail(PDD_E_INVALID, "the Ito control variate runs the generic kernel only (generic = 1)");
+    const int k = tuning_key(key->precision, key->dim, key->correction, key->generic != 0);
     if (!t) {
         ctx->tuned.erase(k);
         return PDD_OK;

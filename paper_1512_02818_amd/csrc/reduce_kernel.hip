@@ -270,11 +270,12 @@ __global__ void finalize_kernel(const FinalizeArgs f)
             st.var = st.var_plain;
             st.stderr_ = sqrt(st.var / n);
         } else {
-            st.mean = interp_node(fi, f.dim, f.nodes + (size_t)i * f.dim) + Se / n;
+            st.mean = (fi.up_data ? interp_node(fi, f.dim, f.nodes + (size_t)i * f.dim) : 0.0) + Se / n;
             st.var = A.n > 1 ? (Se2 - Se * Se / n) / (n - 1.0) : nan;
             st.stderr_ = sqrt(st.var / n);
             if (has_phi) {
                 // xi = u_prev(x0) + e - phi is the pathwise control variate
+                // (Ito items: xi = e - phi); the constant enters neither cov nor rho
                 const double cpe = A.n > 1 ? (Spe - Sp * Se / n) / (n - 1.0) : nan;
                 const double vxi = st.var + st.var_plain - 2.0 * cpe;
                 st.cov = cpe - st.var_plain;

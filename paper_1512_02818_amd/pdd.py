@@ -83,7 +83,8 @@ class NodeStats(C.Structure):
 class WorkItem(C.Structure):
     _fields_ = [("problem", C.c_void_p), ("nodes", C.POINTER(C.c_double)),
                 ("n_nodes", C.c_int64), ("opts", C.POINTER(SolveOpts)),
-                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)), ("out", C.c_void_p)]
+                ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)), ("out", C.c_void_p),
+                ("grad", C.POINTER(Grid))]
 
 
 STATS_DTYPE = np.dtype([("n", "<i8"), ("n_capped", "<i8"), ("steps_sum", "<i8"),
@@ -138,6 +139,8 @@ SIGNATURES = {
     "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
                                          C.POINTER(C.c_double), C.c_int64, C.POINTER(SolveOpts),
                                          C.c_void_p, C.c_void_p]),
+    "pdd_solve_ito": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(C.c_double), C.c_int64,
+                                  C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
     "pdd_solve_batch": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.c_int32, C.c_void_p]),
     "pdd_autotune": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.POINTER(Tuning)]),
     "pdd_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(TuningKey), C.POINTER(Tuning)]),
@@ -410,6 +413,30 @@ def solve_correction(problem: Problem, u_prev: dict, u_prev_t, resid: dict, resi
     return out
 
 
+def grid_array(grids, tensors):
+    """A C array of Grid structs (the gradient components of an Ito solve)."""
+    if len(grids) != len(tensors):
+        raise ValueError("one device tensor per grid")
+    arr = (Grid * len(grids))()
+    for d, (gd, t) in enumerate(zip(grids, tensors)):
+        arr[d] = grid_struct(gd, t)
+    return arr
+
+
+def solve_ito(problem: Problem, grad: list, grad_t: list, nodes, out=None, stream=None, **opt):
+    """pdd_solve_ito: grad is the list of dim gradient grid dicts, grad_t their
+    device tensors."""
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+    n = len(nodes)
+    if out is None:
+        out = alloc_stats(n)
+    ga = grid_array(grad, grad_t)
+    o = make_opts(**opt)
+    _check(lib().pdd_solve_ito(problem.handle, ga, nodes.ctypes.data_as(C.POINTER(C.c_double)), n,
+                               C.byref(o), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
 class Batch:
     """Marshalled pdd_work_item array (and what it points to) of batch-style
     item dicts, reusable across calls."""
@@ -445,6 +472,10 @@ def _work_items(items):
             keep += [gu, gr]
             arr[q].u_prev = C.pointer(gu)
             arr[q].resid = C.pointer(gr)
+        if it.get("grad") is not None:
+            ga = grid_array(it["grad"], it["grad_t"])
+            keep.append(ga)
+            arr[q].grad = C.cast(ga, C.POINTER(Grid))
         arr[q].out = out.data_ptr()
         outs.append(out)
     return arr, outs, keep
@@ -452,7 +483,8 @@ def _work_items(items):
 
 def solve_batch(ctx: Context, items, stream=None):
     """pdd_solve_batch over dicts {problem, nodes, opts(dict), out, [u_prev, u_prev_t, resid,
-    resid_t]}; returns the list of stats tensors."""
+    resid_t] or [grad, grad_t] (lists: Ito control variate)}; returns the list of stats
+    tensors."""
     b = _as_batch(items)
     _check(lib().pdd_solve_batch(ctx.handle, b.arr, b.n, _stream_handle(stream)))
     return b.outs
@@ -495,10 +527,11 @@ def autotune(ctx: Context, item: dict):
     return (t.block, t.blocks_per_cu, t.grab)
 
 
-def set_tuning(ctx: Context, precision: str, dim: int, correction: bool, tuning=None, generic=False):
-    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key (generic: the
+def set_tuning(ctx: Context, precision: str, dim: int, correction, tuning=None, generic=False):
+    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key (correction: 0 / False
+    plain, 1 / True correction estimator, 2 Ito control variate; generic: the
     generic rather than the box / bridge / Gaussian kernel), or None to remove it."""
-    k = TuningKey(PRECISIONS[precision], int(dim), 1 if correction else 0, 1 if generic else 0)
+    k = TuningKey(PRECISIONS[precision], int(dim), int(correction), 1 if generic else 0)
     t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]), 0)
     _check(lib().pdd_set_tuning(ctx.handle, C.byref(k), C.byref(t) if t is not None else None))
 

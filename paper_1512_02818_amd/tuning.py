@@ -1,8 +1,9 @@
 """Launch-shape cache of the autotuner (pdd_autotune).
 
-A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction>", with
+A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction|ito>", with
 "/generic" appended for the generic kernel (ball domains, the shifted or
-naive exit test, tabulated coefficients), to [block, blocks_per_cu, grab].
+naive exit test, tabulated coefficients; always for the Ito control
+variate), to [block, blocks_per_cu, grab].
 `load` installs the entries of the running GPU's architecture in a context
 (pdd_set_tuning), so solves without an explicit tuning use them; `tune` runs
 pdd_autotune on an item and records the winner. Shapes change only speed,
@@ -21,20 +22,31 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "tuning_cache.json")
 
 
-def key(arch: str, precision: str, dim: int, correction: bool, generic: bool = False) -> str:
-    k = f"{arch}/{precision}/D{int(dim)}/{'correction' if correction else 'plain'}"
+ESTIMATORS = ("plain", "correction", "ito")
+
+
+def key(arch: str, precision: str, dim: int, correction, generic: bool = False) -> str:
+    """correction: 0 / False plain, 1 / True correction estimator, 2 Ito control variate."""
+    k = f"{arch}/{precision}/D{int(dim)}/{ESTIMATORS[int(correction)]}"
     return k + "/generic" if generic else k
 
 
 def parse_key(k: str):
-    """(arch, precision, dim, correction, generic) of a cache key."""
+    """(arch, precision, dim, estimator 0 / 1 / 2, generic) of a cache key."""
     parts = k.split("/")
     if len(parts) not in (4, 5) or (len(parts) == 5 and parts[4] != "generic"):
         raise ValueError(f"bad tuning key {k!r}")
     arch, prec, d, est = parts[:4]
-    if prec not in pdd.PRECISIONS or not d.startswith("D") or est not in ("plain", "correction"):
+    if prec not in pdd.PRECISIONS or not d.startswith("D") or est not in ESTIMATORS:
         raise ValueError(f"bad tuning key {k!r}")
-    return arch, prec, int(d[1:]), est == "correction", len(parts) == 5
+    if est == "ito" and len(parts) != 5:
+        raise ValueError(f"the Ito control variate runs the generic kernel only: {k!r}")
+    return arch, prec, int(d[1:]), ESTIMATORS.index(est), len(parts) == 5
+
+
+def item_estimator(item: dict) -> int:
+    """0 plain, 1 correction estimator, 2 Ito control variate."""
+    return 2 if item.get("grad") is not None else (1 if item.get("u_prev") is not None else 0)
 
 
 def generic_item(item: dict) -> bool:
@@ -42,7 +54,8 @@ def generic_item(item: dict) -> bool:
     pd = item["problem"].pd
     opts = item["opts"]
     return not (pd.get("domain", "box") == "box" and opts.get("exit", "bridge") == "bridge"
-                and opts.get("law", "gauss") == "gauss" and not pd.get("tab"))
+                and opts.get("law", "gauss") == "gauss" and not pd.get("tab")
+                and item.get("grad") is None)
 
 
 def read(path: str = DEFAULT_PATH) -> dict:
@@ -123,11 +136,11 @@ def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: st
         t_default = whole_launch_ms(ctx, item, DEFAULT_SHAPE, verify_paths)
         if not t_tuned < 0.98 * t_default:
             shape = DEFAULT_SHAPE
-            pdd.set_tuning(ctx, prec, prob.dim, item.get("u_prev") is not None, None, generic=generic_item(item))
+            pdd.set_tuning(ctx, prec, prob.dim, item_estimator(item), None, generic=generic_item(item))
     if path:
         prob = item["problem"]
         prec = item["opts"].get("precision", "fp32")
-        save_entry(path, key(arch or arch_name(), prec, prob.dim, item.get("u_prev") is not None,
+        save_entry(path, key(arch or arch_name(), prec, prob.dim, item_estimator(item),
                              generic_item(item)), shape)
     return shape
 
@@ -175,7 +188,7 @@ def main():
             # full solves of about 4e7 paths (2e6 for the long-path problem) check the winner
             verify = max(1000, int((2e6 if it["problem"] is probs["sq"] else 4e7) / len(it["nodes"])))
             shape = tune(ctx, it, path=args.out, verify_paths=verify)
-            print(prec, it["problem"].dim, "correction" if "u_prev" in it else "plain",
+            print(prec, it["problem"].dim, ESTIMATORS[item_estimator(it)],
                   "generic" if generic_item(it) else "", shape, flush=True)
     for p in probs.values():
         p.close()

@@ -33,7 +33,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(built_lib):
     names = declared_functions()
-    assert len(names) == 19, names
+    assert len(names) == 20, names
     for n in names:
         assert hasattr(built_lib, n), n
     assert set(names) == set(pdd.SIGNATURES)
@@ -57,6 +57,7 @@ def test_null_arguments_are_rejected_without_gpu(built_lib):
     assert built_lib.pdd_create_problem(None, None, None) == -1
     assert built_lib.pdd_create_problem_tabulated(None, None, None, None) == -1
     assert built_lib.pdd_solve_nodes(None, None, 0, None, None, None) == -1
+    assert built_lib.pdd_solve_ito(None, None, None, 0, None, None, None) == -1
     assert built_lib.pdd_solve_batch(None, None, 0, None) == -1
     assert built_lib.pdd_server_create(None, None, None) == -1
     assert built_lib.pdd_server_submit(None, None, None) == -1
@@ -76,7 +77,7 @@ STRUCTS = {
     "pdd_solve_opts": (pdd.SolveOpts, ["dt", "n_paths_per_node", "path_offset", "stream_id",
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),
     "pdd_node_stats": (pdd.NodeStats, ["mean", "stderr_", "vr_opt", "sums"]),
-    "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out"]),
+    "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out", "grad"]),
     "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction", "generic"]),
     "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",

@@ -14,8 +14,12 @@ def test_key_round_trip():
     g = T.key("gfx950", "fp32", 3, True, generic=True)
     assert g == "gfx950/fp32/D3/correction/generic"
     assert T.parse_key(g) == ("gfx950", "fp32", 3, True, True)
+    ito = T.key("gfx950", "fp64", 2, 2, generic=True)
+    assert ito == "gfx950/fp64/D2/ito/generic"
+    assert T.parse_key(ito) == ("gfx950", "fp64", 2, 2, True)
     for bad in ("gfx950/fp16/D2/plain", "gfx950/fp32/2/plain", "gfx950/fp32/D2/cv", "x",
-                "gfx950/fp32/D2/plain/special", "gfx950/fp32/D2/plain/generic/x"):
+                "gfx950/fp32/D2/plain/special", "gfx950/fp32/D2/plain/generic/x",
+                "gfx950/fp32/D2/ito"):
         with pytest.raises(ValueError):
             T.parse_key(bad)
 
