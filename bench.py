@@ -100,6 +100,8 @@ def parse():
                     help="copies of the 18 unit-square nodes (distinct streams), plain FP64")
     ap.add_argument("--rms-replicas-cv", type=int, default=2000,
                     help="copies of the 18 unit-square nodes (distinct streams), CV + FP32")
+    ap.add_argument("--rms-replicas-ito", type=int, default=500,
+                    help="copies of the 18 unit-square nodes (distinct streams), Ito CV + FP32")
     ap.add_argument("--serve-duration", type=float, default=2.0,
                     help="seconds of Poisson arrivals at 200 requests/s for the serving loop, then twice "
                          "as long at 10 requests/s (0 = skip)")
@@ -115,6 +117,9 @@ def parse():
     ap.add_argument("--profile-correction", type=int, default=0,
                     help="only run the correction solve (unit square, 257^2 FP32 grids, h=1e-3) with "
                          "this many paths per node three times and print its timing (for profilers)")
+    ap.add_argument("--profile-estimator", choices=["correction", "ito"], default="correction",
+                    help="with --profile-correction: the correction estimator, or phi + xi with the Ito "
+                         "control variate from 257^2 FP32 gradient grids of the same u_prev")
     ap.add_argument("--profile-replicas", type=int, default=1,
                     help="with --profile-correction: that many 18-node solves (distinct streams) in one batch")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -138,12 +143,14 @@ DT_LADDER = (1e-3, 5e-4, 2.5e-4, 1e-4)
 N_PILOT = 1000
 
 
-def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
+def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
     """Interface-node solves per second at an RMS error `tol` against the
-    manufactured solution, for the plain FP64 estimator and for the FP32
+    manufactured solution, for the plain FP64 estimator, for the FP32
     correction estimator with u_prev = U + p on a 257^2 grid (32 Fourier modes
-    of amplitude 1e-2) as control variate, on the 18 unit-square nodes
-    replicated with distinct RNG streams. The error budget is split evenly:
+    of amplitude 1e-2) as control variate, and for the FP32 plain estimator
+    with the pathwise Ito control variate built from the gradient of the same
+    U + p on 257^2 grids, on the 18 unit-square nodes replicated with distinct
+    RNG streams. The error budget is split evenly:
     RMS bias <= tol/sqrt(2) picks dt from a ladder (largest first; bias
     measured against U with many paths, untimed), SE <= tol/sqrt(2) per node
     sets the paths through a 1,000-path pilot and the planner (timed, with the
@@ -163,6 +170,8 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
     gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
     tu = torch.as_tensor(gu["data"]).cuda().contiguous()
     tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    gg = W.gradient_grids(pd, n=257, seed=1, dtype=np.float32)
+    gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     budget = tol / np.sqrt(2.0)
@@ -177,11 +186,13 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
                                stream_id=stream0 + r)}
             if kind == "cv":
                 it.update(u_prev=gu, u_prev_t=tu, resid=gr, resid_t=tr)
+            elif kind == "ito":
+                it.update(grad=gg, grad_t=gt)
             its.append(it)
         return its
 
     res = {}
-    for kind, reps in (("plain", replicas_plain), ("cv", replicas_cv)):
+    for kind, reps in (("plain", replicas_plain), ("cv", replicas_cv), ("ito", replicas_ito)):
         # dt: the largest rung whose measured RMS bias fits half the budget
         # (the bias estimate removes the sampling variance of the means)
         ladder = []
@@ -192,7 +203,7 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
             its = items_for(kind, dt, cal_reps, 1 << 20, cal_out)
             for it in its:
                 it["opts"]["n_paths"] = cal_paths
-                it["opts"]["plain_alongside"] = kind == "cv"  # variance reduction, reported
+                it["opts"]["plain_alongside"] = kind == "cv"  # variance reduction, reported (Ito: always)
             pdd.solve_batch(ctx, its)
             st = pdd.stats_to_numpy(cal_out).reshape(cal_reps, len(nodes))
             m = st["mean"].mean(axis=0)
@@ -200,8 +211,8 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
             bias = float(np.sqrt(max(0.0, np.mean((m - exact) ** 2 - se2))))
             noise = float(np.sqrt(np.mean(se2)))
             ladder.append({"dt": dt, "rms_bias": bias, "rms_se_of_estimate": noise,
-                           "mean_vr": float(np.mean(st["vr"])) if kind == "cv" else None,
-                           "mean_abs_rho": float(np.mean(np.abs(st["rho"]))) if kind == "cv" else None})
+                           "mean_vr": float(np.mean(st["vr"])) if kind != "plain" else None,
+                           "mean_abs_rho": float(np.mean(np.abs(st["rho"]))) if kind != "plain" else None})
             if bias + noise <= budget:
                 chosen = dt
                 break
@@ -230,16 +241,20 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv):
     prob.close()
     return {"tol": tol, "setup_s": setup_s, "pilot_paths": N_PILOT,
             "workload": "unit square, 18 interface nodes per replica, manufactured u; "
-                        "CV: u_prev = u + 32-mode Fourier perturbation (amplitude 1e-2) on 257^2, FP32 grids",
-            "plain_fp64": res["plain"], "cv_fp32": res["cv"],
-            "ratio_cv_fp32_over_plain_fp64": res["cv"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"]}
+                        "CV: u_prev = u + 32-mode Fourier perturbation (amplitude 1e-2) on 257^2, FP32 grids; "
+                        "Ito CV: the gradient of the same u_prev on 257^2 FP32 grids",
+            "plain_fp64": res["plain"], "cv_fp32": res["cv"], "ito_cv_fp32": res["ito"],
+            "ratio_cv_fp32_over_plain_fp64": res["cv"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"],
+            "ratio_ito_cv_fp32_over_plain_fp64": res["ito"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"]}
 
 
 def cv_iteration(ctx):
     """The correction estimator on the unit-square problem with u_prev = U + p
     on a 257^2 FP32 grid and its residual: iterates of 10^3, 10^4 and 10^5
     paths per node (RNG stream = iterate, u_prev fixed), FP32, with the plain
-    score alongside for the variance reduction V[phi]/V[e] and rho."""
+    score alongside for the variance reduction V[phi]/V[e] and rho; beside it
+    the paper's Ito control variate from the gradient of the same u_prev on
+    257^2 FP32 grids, on the same paths."""
     import numpy as np
     import torch
 
@@ -252,6 +267,8 @@ def cv_iteration(ctx):
     gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
     tu = torch.as_tensor(gu["data"]).cuda().contiguous()
     tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    gg = W.gradient_grids(pd, n=257, seed=1, dtype=np.float32)
+    gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
     out = []
     for it, n in enumerate((1_000, 10_000, 100_000)):
         torch.cuda.synchronize()
@@ -264,9 +281,18 @@ def cv_iteration(ctx):
                     "rms_error": float(np.sqrt(np.mean((st["mean"] - exact) ** 2))),
                     "rms_error_plain": float(np.sqrt(np.mean((st["mean_plain"] - exact) ** 2))),
                     "mean_stderr": float(np.mean(st["stderr"])), "wall_s": wall})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        si = pdd.stats_to_numpy(pdd.solve_ito(prob, gg, gt, nodes, dt=1e-3, n_paths=n, stream_id=it,
+                                              precision="fp32"))
+        out[-1]["ito"] = {"mean_vr": float(np.mean(si["vr"])), "min_vr": float(np.min(si["vr"])),
+                          "mean_abs_rho": float(np.mean(np.abs(si["rho"]))),
+                          "rms_error": float(np.sqrt(np.mean((si["mean"] - exact) ** 2))),
+                          "mean_stderr": float(np.mean(si["stderr"])), "wall_s": time.perf_counter() - t0}
     prob.close()
     return {"workload": "unit square, 18 nodes, dt=1e-3, u_prev = u + 32-mode Fourier perturbation "
-                        "(amplitude 1e-2) on 257^2 with its residual, FP32", "iterates": out}
+                        "(amplitude 1e-2) on 257^2 with its residual, FP32; 'ito': phi + xi with xi "
+                        "from the gradient of the same u_prev on 257^2 FP32 grids", "iterates": out}
 
 
 def batch_solve(ctx, scale):
@@ -319,12 +345,14 @@ def calibration_copy(mib):
     del src, dst
 
 
-def profile_correction(paths, calibrate_mib=0, replicas=1):
+def profile_correction(paths, calibrate_mib=0, replicas=1, estimator="correction"):
     """The correction estimator alone, for kernel-trace and counter runs: 18
     unit-square nodes, u_prev = U + p and its residual on 257^2 FP32 grids
     (about 0.26 MB each, so the grid gathers are served by L2), h = 1e-3.
     replicas > 1: that many solves of the 18 nodes with distinct RNG streams
-    in one pdd_solve_batch, as in the node-solve measurement."""
+    in one pdd_solve_batch, as in the node-solve measurement. estimator
+    "ito": the Ito control variate instead, from the gradient of the same
+    u_prev on two 257^2 FP32 grids."""
     import numpy as np
     import torch
 
@@ -338,6 +366,10 @@ def profile_correction(paths, calibrate_mib=0, replicas=1):
     gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
     tu = torch.as_tensor(gu["data"]).cuda().contiguous()
     tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    grids = {"u_prev": gu, "u_prev_t": tu, "resid": gr, "resid_t": tr}
+    if estimator == "ito":
+        gg = W.gradient_grids(pd, n=257, seed=1, dtype=np.float32)
+        grids = {"grad": gg, "grad_t": [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]}
     out = pdd.alloc_stats(replicas * len(nodes))
     nstat = pdd.STATS_DTYPE.itemsize
     if calibrate_mib > 0:
@@ -345,18 +377,20 @@ def profile_correction(paths, calibrate_mib=0, replicas=1):
     steps = 0
     for r in range(3):
         if replicas == 1:
-            pdd.solve_correction(prob, gu, tu, gr, tr, nodes, out=out, dt=1e-3, n_paths=paths,
-                                 path_offset=r * paths, precision="fp32", time_kernel=True)
+            pdd.solve_batch(ctx, [dict({"problem": prob, "nodes": nodes, "out": out,
+                                        "opts": dict(dt=1e-3, n_paths=paths, path_offset=r * paths,
+                                                     precision="fp32", time_kernel=True)}, **grids)])
         else:
-            pdd.solve_batch(ctx, [{"problem": prob, "nodes": nodes,
-                                   "out": out[q * len(nodes) * nstat:(q + 1) * len(nodes) * nstat],
-                                   "opts": dict(dt=1e-3, n_paths=paths, path_offset=r * paths, precision="fp32",
-                                                stream_id=16 + q, time_kernel=q == 0),
-                                   "u_prev": gu, "u_prev_t": tu, "resid": gr, "resid_t": tr}
+            pdd.solve_batch(ctx, [dict({"problem": prob, "nodes": nodes,
+                                        "out": out[q * len(nodes) * nstat:(q + 1) * len(nodes) * nstat],
+                                        "opts": dict(dt=1e-3, n_paths=paths, path_offset=r * paths,
+                                                     precision="fp32", stream_id=16 + q, time_kernel=q == 0)},
+                                       **grids)
                                   for q in range(replicas)])
         steps += int(pdd.stats_to_numpy(out)["steps_sum"].sum())
     ms = pdd.kernel_times(ctx)
-    print(json.dumps({"correction_profile": {"paths_per_node": paths, "nodes": len(nodes), "replicas": replicas,
+    print(json.dumps({"correction_profile": {"estimator": estimator, "paths_per_node": paths,
+                                             "nodes": len(nodes), "replicas": replicas,
                                              "path_steps": steps, "kernel_ms": ms,
                                              "path_steps_per_s": steps / (sum(ms) / 1e3)}}), flush=True)
     prob.close()
@@ -366,7 +400,8 @@ def profile_correction(paths, calibrate_mib=0, replicas=1):
 def main():
     args = parse()
     if args.profile_correction > 0:
-        profile_correction(args.profile_correction, args.calibrate_copy_mib, args.profile_replicas)
+        profile_correction(args.profile_correction, args.calibrate_copy_mib, args.profile_replicas,
+                           args.profile_estimator)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -459,7 +494,7 @@ def main():
     if args.rms_tol > 0:
         print("node solves at fixed RMS error ...", file=sys.stderr, flush=True)
         result["node_solves_at_rms"] = node_solves_at_rms(ctx, args.rms_tol, args.rms_replicas_plain,
-                                                          args.rms_replicas_cv)
+                                                          args.rms_replicas_cv, args.rms_replicas_ito)
     if args.cv_iterates:
         print("correction iterates ...", file=sys.stderr, flush=True)
         result["cv_iteration"] = cv_iteration(ctx)

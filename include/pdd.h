@@ -295,8 +295,7 @@ typedef struct {
     int32_t precision;  /* PDD_FP32 or PDD_FP64 */
     int32_t dim;        /* 2 or 3 */
     int32_t correction; /* 0 plain, 1 correction estimator, 2 Ito control variate */
-    int32_t generic;    /* 0 or 1, as above (1 for the Ito control variate, which
-                           runs the generic kernel only) */
+    int32_t generic;    /* 0 or 1, as above */
 } pdd_tuning_key;
 
 /* Times samples of `item` (up to 32 of its nodes, about 8 and 16 paths per

@@ -1057,18 +1057,12 @@ template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
                               const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s)
 {
-    if constexpr (EST == kEstIto) {  // generic kernel only
-        if (spec) return hipErrorInvalidDeviceFunction;
+    if (spec)
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
+                           items, probs);
+    else
         hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, l, items,
                            probs);
-    } else {
-        if (spec)
-            hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
-                               items, probs);
-        else
-            hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, l,
-                               items, probs);
-    }
     return hipGetLastError();
 }
 
@@ -1094,11 +1088,8 @@ const void *path_kernel_symbol(bool one, bool spec)
         if (one)
             return spec ? reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, BoxBridgeGauss>)
                         : reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, RuntimeMode>);
-    if constexpr (EST == kEstIto)
-        return spec ? nullptr : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
-    else
-        return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGauss>)
-                    : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
+    return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGauss>)
+                : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
 }
 
 template <class S, class T, int D>

@@ -243,8 +243,7 @@ constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && EST == kEstPlain;
 
 // Launchers (defined in the .hip files). `spec`: every item of the launch is
 // a box problem with the bridge exit test and Gaussian increments, for which
-// a specialised kernel is compiled (plain and correction estimators; Ito
-// groups run the generic kernel). EST: kEstPlain, kEstCorrection or kEstIto.
+// a specialised kernel is compiled. EST: kEstPlain, kEstCorrection or kEstIto.
 template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
                               const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s);

@@ -331,7 +331,7 @@ int occupancy(pdd_ctx *ctx, const void *fn, int block)
 bool pdd::specialised(const HostItem &it)
 {
     return it.prob->desc.domain == PDD_DOMAIN_BOX && it.o->exit_mode == PDD_EXIT_BRIDGE &&
-           it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0 && it.est != kEstIto;
+           it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0;
 }
 
 pdd_status pdd::validate_item(HostItem &it)
@@ -1284,8 +1284,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     HIP_TRY(hipSetDevice(ctx->device));
     // the kernel this group launches for a single item, and its occupancy
     const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX && item->problem->pf.tab == 0 &&
-                      item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS &&
-                      est != kEstIto;
+                      item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS;
     auto symbol = [&](auto tag) -> const void * {
         using T = decltype(tag);
         if (dim == 2)
@@ -1400,8 +1399,6 @@ pdd_status pdd_set_tuning(pdd_ctx *ctx, const pdd_tuning_key *key, const pdd_tun
     if ((key->precision != PDD_FP32 && key->precision != PDD_FP64) || key->dim < 2 || key->dim > 3 ||
         key->correction < 0 || key->correction > 2 || (key->generic != 0 && key->generic != 1))
         return fail(PDD_E_INVALID, "bad tuning key");
-    if (key->correction == kEstIto && key->generic != 1)
-        return fail(PDD_E_INVALID, "the Ito control variate runs the generic kernel only (generic = 1)");
     const int k = tuning_key(key->precision, key->dim, key->correction, key->generic != 0);
     if (!t) {
         ctx->tuned.erase(k);

@@ -2,8 +2,7 @@
 
 A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction|ito>", with
 "/generic" appended for the generic kernel (ball domains, the shifted or
-naive exit test, tabulated coefficients; always for the Ito control
-variate), to [block, blocks_per_cu, grab].
+naive exit test, tabulated coefficients), to [block, blocks_per_cu, grab].
 `load` installs the entries of the running GPU's architecture in a context
 (pdd_set_tuning), so solves without an explicit tuning use them; `tune` runs
 pdd_autotune on an item and records the winner. Shapes change only speed,
@@ -39,8 +38,6 @@ def parse_key(k: str):
     arch, prec, d, est = parts[:4]
     if prec not in pdd.PRECISIONS or not d.startswith("D") or est not in ESTIMATORS:
         raise ValueError(f"bad tuning key {k!r}")
-    if est == "ito" and len(parts) != 5:
-        raise ValueError(f"the Ito control variate runs the generic kernel only: {k!r}")
     return arch, prec, int(d[1:]), ESTIMATORS.index(est), len(parts) == 5
 
 
@@ -54,8 +51,7 @@ def generic_item(item: dict) -> bool:
     pd = item["problem"].pd
     opts = item["opts"]
     return not (pd.get("domain", "box") == "box" and opts.get("exit", "bridge") == "bridge"
-                and opts.get("law", "gauss") == "gauss" and not pd.get("tab")
-                and item.get("grad") is None)
+                and opts.get("law", "gauss") == "gauss" and not pd.get("tab"))
 
 
 def read(path: str = DEFAULT_PATH) -> dict:

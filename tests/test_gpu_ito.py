@@ -184,12 +184,12 @@ def test_ito_invalid_arguments(ctx):
     rec = pdd.alloc_records(20, correction=True, plain=False)
     with pytest.raises(pdd.PDDError):
         pdd.solve_ito(prob, grad, gt, nodes, dt=1e-3, n_paths=10, records=rec)
-    # a tuning key for the Ito estimator names the generic kernel
+    # a bad estimator in a tuning key
     with pytest.raises(pdd.PDDError):
-        pdd.set_tuning(ctx, "fp32", 2, 2, (256, 0, 64), generic=False)
-    pdd.set_tuning(ctx, "fp32", 2, 2, (128, 0, 16), generic=True)
+        pdd.set_tuning(ctx, "fp32", 2, 3, (256, 0, 64))
+    pdd.set_tuning(ctx, "fp32", 2, 2, (128, 0, 16))
     st = pdd.stats_to_numpy(pdd.solve_ito(prob, grad, gt, nodes, dt=1e-3, n_paths=500))
-    pdd.set_tuning(ctx, "fp32", 2, 2, None, generic=True)
+    pdd.set_tuning(ctx, "fp32", 2, 2, None)
     st2 = pdd.stats_to_numpy(pdd.solve_ito(prob, grad, gt, nodes, dt=1e-3, n_paths=500))
     assert np.array_equal(st["mean"], st2["mean"])  # the launch shape never changes results
     prob.close()

@@ -19,7 +19,7 @@ def test_key_round_trip():
     assert T.parse_key(ito) == ("gfx950", "fp64", 2, 2, True)
     for bad in ("gfx950/fp16/D2/plain", "gfx950/fp32/2/plain", "gfx950/fp32/D2/cv", "x",
                 "gfx950/fp32/D2/plain/special", "gfx950/fp32/D2/plain/generic/x",
-                "gfx950/fp32/D2/ito"):
+                "gfx950/fp32/D2/Ito"):
         with pytest.raises(ValueError):
             T.parse_key(bad)
 
