@@ -285,6 +285,51 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int3
                                   const double *target_se, uint64_t n_pilot, uint64_t n_max,
                                   void *stream);
 
+/* ------------------------------------------------------------------------
+ * Fast fit of nodal constants (appendix H5, Alg. A:Fitting). Host only
+ * except for the batched solve of pdd_fit_constants.
+ * ------------------------------------------------------------------------ */
+enum { PDD_GLM_NORMAL = 0, PDD_GLM_GAMMA = 1 };
+
+/* Maximum-likelihood fit of y = coef[0] + coef[1] x (identity link) with normal
+ * noise (least squares; the first-moment model of eq. F:Noisy_model_moment1)
+ * or gamma noise (Fisher scoring from mu = y, weights 1 / mu^2, a step that
+ * would make a mean non-positive is halved; the second-moment model of eq.
+ * F:Noisy_model_moment2), n >= 3 points (host arrays). se[k] =
+ * sqrt(dispersion * (X'WX)^-1_kk), the dispersion from the Pearson residuals
+ * with n - 2 degrees of freedom; iterations (nullable) = scoring passes (1 for
+ * the normal family). Errors: NULL pointers, n < 3, non-finite data,
+ * non-positive y for the gamma family, x values that do not span a line. */
+pdd_status pdd_glm_fit(const double *x, const double *y, int32_t n, int32_t family, double *coef, double *se,
+                       int32_t *iterations);
+
+/* Fitted constants of one node. The model in x = h^delta: E[phi_h] = E_phi +
+ * beta x (normal fit of the node means; beta is the bias constant of eq.
+ * F:Bound_of_error), V[phi_h] = V_phi + alpha x (gamma fit of the sample
+ * variances), E[tau_h] = E_tau + beta_tau x (normal fit of h times the mean
+ * exit step), with standard errors; iterations of the gamma fit. For a
+ * correction or Ito item, phi is that estimator's score and mean its node
+ * value. */
+typedef struct {
+    double E_phi, beta, se_E_phi, se_beta;
+    double V_phi, alpha, se_V_phi, se_alpha;
+    double E_tau, beta_tau, se_E_tau;
+    int32_t iterations, pad;
+} pdd_node_constants;
+
+/* Alg. A:Fitting for the nodes of `item`: n_h >= 3 solves of n_hat >= 2
+ * paths per node at the steps h[0 .. n_h - 1] (host; the paper takes a cloud
+ * of about 100 equispaced steps and n_hat = 1000), solve j with RNG stream
+ * item->opts->stream_id + j and otherwise the item's options (its dt,
+ * n_paths, records and accumulate flag are ignored), run as one
+ * pdd_solve_batch; then per node the three fits of pdd_node_constants in
+ * x = h^delta (delta > 0: 1 for the bridge and shifted exits, 1/2 for the
+ * naive one). `out`: host, item->n_nodes entries. Synchronous. Errors as for
+ * the solve, and PDD_E_INVALID for bad h, n_h, n_hat or delta, or a node whose
+ * sample variance is 0 at some step. */
+pdd_status pdd_fit_constants(pdd_ctx *ctx, const pdd_work_item *item, const double *h, int32_t n_h,
+                             uint64_t n_hat, double delta, pdd_node_constants *out, void *stream);
+
 /* Key of the context's launch-shape table: the path kernel a group of
  * items runs. `generic` selects between the kernel compiled for a box domain
  * with the bridge exit test, Gaussian increments and analytic coefficients

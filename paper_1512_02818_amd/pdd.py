@@ -93,6 +93,21 @@ STATS_DTYPE = np.dtype([("n", "<i8"), ("n_capped", "<i8"), ("steps_sum", "<i8"),
                         ("rho", "<f8"), ("vr", "<f8"), ("vr_opt", "<f8"), ("sums", "<f8", (10,))])
 assert STATS_DTYPE.itemsize == C.sizeof(NodeStats)
 
+class NodeConstants(C.Structure):
+    _fields_ = [("E_phi", C.c_double), ("beta", C.c_double), ("se_E_phi", C.c_double),
+                ("se_beta", C.c_double), ("V_phi", C.c_double), ("alpha", C.c_double),
+                ("se_V_phi", C.c_double), ("se_alpha", C.c_double), ("E_tau", C.c_double),
+                ("beta_tau", C.c_double), ("se_E_tau", C.c_double), ("iterations", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+CONSTANTS_DTYPE = np.dtype([(n, "<f8") for n in ("E_phi", "beta", "se_E_phi", "se_beta", "V_phi", "alpha",
+                                                   "se_V_phi", "se_alpha", "E_tau", "beta_tau", "se_E_tau")]
+                           + [("iterations", "<i4"), ("pad", "<i4")])
+assert CONSTANTS_DTYPE.itemsize == C.sizeof(NodeConstants)
+GLM_FAMILIES = {"normal": 0, "gamma": 1}
+
+
 class TuningKey(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dim", C.c_int32), ("correction", C.c_int32),
                 ("generic", C.c_int32)]
@@ -157,6 +172,10 @@ SIGNATURES = {
                                     C.POINTER(C.c_int32), C.c_int32]),
     "pdd_server_report_get": (C.c_int32, [C.c_void_p, C.POINTER(ServerReport)]),
     "pdd_server_destroy": (None, [C.c_void_p]),
+    "pdd_glm_fit": (C.c_int32, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "pdd_fit_constants": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.POINTER(C.c_double), C.c_int32,
+                                      C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -508,6 +527,31 @@ def solve_to_tolerance(ctx: Context, items, target_se, n_pilot, n_max, stream=No
                                         se.ctypes.data_as(C.POINTER(C.c_double)), int(n_pilot),
                                         int(n_max), _stream_handle(stream)))
     return b.outs
+
+
+def glm_fit(x, y, family="normal"):
+    """pdd_glm_fit (host only): (coef[2], se[2], iterations) of y = coef[0] + coef[1] x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if len(x) != len(y):
+        raise ValueError("x and y differ in length")
+    coef, se, it = (C.c_double * 2)(), (C.c_double * 2)(), C.c_int32()
+    _check(lib().pdd_glm_fit(x.ctypes.data_as(C.POINTER(C.c_double)), y.ctypes.data_as(C.POINTER(C.c_double)),
+                             len(x), GLM_FAMILIES[family], coef, se, C.byref(it)))
+    return np.array(coef[:]), np.array(se[:]), it.value
+
+
+def fit_constants(ctx: Context, item: dict, h, n_hat, delta=1.0, stream=None) -> np.ndarray:
+    """pdd_fit_constants on a batch-style item dict (its opts need no dt: the
+    cloud h sets it): a CONSTANTS_DTYPE array, one per node."""
+    opts = dict({"dt": float(h[0])}, **item["opts"])
+    b = Batch([dict(item, opts=opts, out=item.get("out", alloc_stats(0)))])
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.zeros(b.arr[0].n_nodes, dtype=CONSTANTS_DTYPE)
+    _check(lib().pdd_fit_constants(ctx.handle, b.arr, h.ctypes.data_as(C.POINTER(C.c_double)), len(h),
+                                   int(n_hat), float(delta), out.ctypes.data_as(C.c_void_p),
+                                   _stream_handle(stream)))
+    return out
 
 
 def kernel_times(ctx: Context, cap=4096):

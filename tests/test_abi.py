@@ -33,7 +33,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(built_lib):
     names = declared_functions()
-    assert len(names) == 20, names
+    assert len(names) == 22, names
     for n in names:
         assert hasattr(built_lib, n), n
     assert set(names) == set(pdd.SIGNATURES)
@@ -66,6 +66,8 @@ def test_null_arguments_are_rejected_without_gpu(built_lib):
     built_lib.pdd_server_destroy(None)
     assert built_lib.pdd_autotune(None, None, None) == -1
     assert built_lib.pdd_set_tuning(None, None, None) == -1
+    assert built_lib.pdd_glm_fit(None, None, 0, 0, None, None, None) == -1
+    assert built_lib.pdd_fit_constants(None, None, None, 0, 0, 1.0, None, None) == -1
 
 
 STRUCTS = {
@@ -79,6 +81,7 @@ STRUCTS = {
     "pdd_node_stats": (pdd.NodeStats, ["mean", "stderr_", "vr_opt", "sums"]),
     "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out", "grad"]),
     "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction", "generic"]),
+    "pdd_node_constants": (pdd.NodeConstants, ["E_phi", "se_beta", "alpha", "E_tau", "se_E_tau", "iterations"]),
     "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",
                                   "user_tag"]),
