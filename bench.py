@@ -112,6 +112,8 @@ def parse():
                          "autotuner's cached shape for this GPU, else the default) or 'default'")
     ap.add_argument("--cv-iterates", type=int, default=1,
                     help="1: report the correction iterates 10^3 -> 10^5 (0 = skip)")
+    ap.add_argument("--fit-cloud", type=int, default=100,
+                    help="time steps of the nodal-constant fit's cloud in [1e-3, 1e-2] (0 = skip)")
     ap.add_argument("--batch-scale", type=float, default=0.1,
                     help="path-count scale of the 64-problem batched solve (0 = skip)")
     ap.add_argument("--profile-correction", type=int, default=0,
@@ -293,6 +295,43 @@ def cv_iteration(ctx):
     return {"workload": "unit square, 18 nodes, dt=1e-3, u_prev = u + 32-mode Fourier perturbation "
                         "(amplitude 1e-2) on 257^2 with its residual, FP32; 'ito': phi + xi with xi "
                         "from the gradient of the same u_prev on 257^2 FP32 grids", "iterates": out}
+
+
+def fit_cloud(ctx, m_hat, n_hat=1000, tol=1e-3):
+    """The fast fit of nodal constants (Alg. A:Fitting) on the 18 unit-square
+    nodes: a cloud of m_hat equispaced steps in [1e-3, 1e-2], n_hat paths per
+    node and step, FP32, one batched launch, then the per-node fits. Reports
+    the wall time (launch + fits), the fitted limits against the exact u, and
+    the step a planner would take from the fitted bias: the largest h with
+    RMS(beta) h <= tol / sqrt(2)."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    pd = W.unit_square_problem(seed=SEED)
+    nodes = W.unit_square_nodes()
+    exact = W.manufactured_u(pd, nodes)
+    prob = pdd.Problem(ctx, pd)
+    h = np.linspace(1e-3, 1e-2, m_hat)
+    item = {"problem": prob, "nodes": nodes, "opts": dict(precision="fp32", stream_id=1000)}
+    pdd.fit_constants(ctx, item, h[:3], 64)  # warm-up: code and buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = pdd.fit_constants(ctx, item, h, n_hat)
+    wall = time.perf_counter() - t0
+    prob.close()
+    z = (c["E_phi"] - exact) / c["se_E_phi"]
+    beta_rms = float(np.sqrt(np.mean(c["beta"] ** 2)))
+    return {"workload": f"unit square, 18 nodes, {m_hat} steps in [1e-3, 1e-2], {n_hat} paths per node and "
+                        "step, FP32, bridge exit, delta = 1",
+            "wall_s": wall, "paths": int(m_hat * n_hat * len(nodes)),
+            "rms_abs_error_E_phi": float(np.sqrt(np.mean((c["E_phi"] - exact) ** 2))),
+            "median_abs_z_E_phi": float(np.median(np.abs(z))), "mean_se_E_phi": float(np.mean(c["se_E_phi"])),
+            "beta_rms": beta_rms, "beta_range": [float(c["beta"].min()), float(c["beta"].max())],
+            "V_phi_mean": float(np.mean(c["V_phi"])), "alpha_mean": float(np.mean(c["alpha"])),
+            "E_tau_mean": float(np.mean(c["E_tau"])),
+            "dt_from_beta": tol / np.sqrt(2.0) / beta_rms}
 
 
 def batch_solve(ctx, scale):
@@ -498,6 +537,12 @@ def main():
     if args.cv_iterates:
         print("correction iterates ...", file=sys.stderr, flush=True)
         result["cv_iteration"] = cv_iteration(ctx)
+    if args.fit_cloud > 0:
+        print("nodal-constant fit ...", file=sys.stderr, flush=True)
+        result["fit_constants"] = fit_cloud(ctx, args.fit_cloud)
+        f = result["fit_constants"]
+        print(f"fit: {f['paths']} paths in {f['wall_s']:.3f} s, beta RMS {f['beta_rms']:.3f}, "
+              f"dt from beta {f['dt_from_beta']:.2e}", file=sys.stderr, flush=True)
     if args.batch_scale > 0:
         print("batched solve ...", file=sys.stderr, flush=True)
         result["batch"] = batch_solve(ctx, args.batch_scale)
