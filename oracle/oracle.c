@@ -257,6 +257,7 @@ double orc_source(const orc_problem *p, const double *x)
 /* g = U + sum(gx) on the boundary. */
 double orc_boundary(const orc_problem *p, const double *x)
 {
+    if (p->tab_g) return orc_interp(p->tab_g, x);
     double v = orc_U(p, x);
     for (int m = 0; m < p->n_gx; ++m) v += mono_value(&p->gx[m], p->dim, x);
     return v;
@@ -430,8 +431,8 @@ static int bad_problem(const orc_problem *p, const orc_opts *o)
         for (int d = 0; d < p->dim; ++d)
             if (!o->grad[d] || o->grad[d]->dim != p->dim || !o->grad[d]->data) return 1;
     }
-    const orc_grid *tab[5] = {p->tab_b[0], p->tab_b[1], p->tab_b[2], p->tab_c, p->tab_f};
-    for (int q = 0; q < 5; ++q) {
+    const orc_grid *tab[6] = {p->tab_b[0], p->tab_b[1], p->tab_b[2], p->tab_c, p->tab_f, p->tab_g};
+    for (int q = 0; q < 6; ++q) {
         if (!tab[q]) continue;
         if (q < 3 && q >= p->dim) return 1;
         if (tab[q]->dim != p->dim || !tab[q]->data) return 1;

@@ -54,7 +54,8 @@ struct orc_grid_s;
  * f = (1/2) sigma^2 Lap U + b.grad U + c U + sum(fx),  g = U + sum(gx).
  * Tabulated coefficients: a non-NULL grid replaces the analytic b_d, c or f
  * by its interpolant (f's analytic form always uses the analytic b and c);
- * g is never tabulated. */
+ * a tabulated g replaces the boundary data U + sum(gx) by its interpolant at
+ * the exit point. */
 typedef struct {
     int32_t dim;      /* 2 or 3 */
     int32_t domain;   /* ORC_BOX or ORC_BALL */
@@ -73,6 +74,7 @@ typedef struct {
     const struct orc_grid_s *tab_b[3]; /* drift components, or NULL */
     const struct orc_grid_s *tab_c;    /* killing rate, or NULL */
     const struct orc_grid_s *tab_f;    /* source, or NULL */
+    const struct orc_grid_s *tab_g;    /* boundary data, or NULL */
 } orc_problem;
 
 /* Values at the n[0] x n[1] (x n[2]) points of a uniform grid on [lo,hi],

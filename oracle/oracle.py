@@ -49,6 +49,7 @@ class Problem(C.Structure):
         ("fx", _Mono * MAX_MONO), ("gx", _Mono * MAX_MONO),
         ("seed", C.c_uint64),
         ("tab_b", C.POINTER(Grid) * 3), ("tab_c", C.POINTER(Grid)), ("tab_f", C.POINTER(Grid)),
+        ("tab_g", C.POINTER(Grid)),
     ]
 
 
@@ -168,14 +169,14 @@ def make_problem(pd: dict) -> Problem:
             for d in range(len(t["e"])):
                 arr[m].e[d] = int(t["e"][d])
     p.seed = int(pd.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
-    # tabulated coefficients: {"b": [grid or None per axis], "c": grid, "f": grid}
+    # tabulated coefficients: {"b": [grid or None per axis], "c": grid, "f": grid, "g": grid}
     tab = pd.get("tab") or {}
     keep = []
     for d, gd in enumerate(tab.get("b") or []):
         if gd is not None:
             keep.append(_GridHolder(gd))
             p.tab_b[d] = C.pointer(keep[-1].grid)
-    for field in ("c", "f"):
+    for field in ("c", "f", "g"):
         if tab.get(field) is not None:
             keep.append(_GridHolder(tab[field]))
             setattr(p, "tab_" + field, C.pointer(keep[-1].grid))

@@ -253,6 +253,71 @@ def tabulated_problem(pd: dict, n=65, fields=("b", "c", "f"), seed=0, amp=0.3, d
     return out
 
 
+PAPER_SIDE = 2.0  # stand-in box [0, 2]^2 for the paper's example (its figure is missing)
+
+
+def paper_example_u(pts) -> np.ndarray:
+    """The exact solution of the paper's example (Sec. 5, eq. F:PDE_ejemplo):
+    2 cos(2 (y - 2) x) + sin(3 (x - 2) y) + 3.1."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    x, y = pts[:, 0], pts[:, 1]
+    return 2.0 * np.cos(2.0 * (y - 2.0) * x) + np.sin(3.0 * (x - 2.0) * y) + 3.1
+
+
+def paper_example_fields(pts):
+    """b (n x 2), c, f and u of the paper's example at the points. With
+    sigma = sqrt(2) (so (1/2) sigma^2 Lap = Lap), b = cos(x + y) [1, 1] /
+    (1.1 + sin(x + y)), c = -(x^2 + y^2) / (1.1 + sin(x + y)); the source in
+    this library's convention (1/2 sigma^2 Lap u + b.grad u + c u = f) is
+    f = Lap u + b.grad u + c u with u's derivatives written out (the paper's
+    f is the negative of this)."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    x, y = pts[:, 0], pts[:, 1]
+    den = 1.1 + np.sin(x + y)
+    b = np.stack([np.cos(x + y) / den] * 2, axis=1)
+    c = -(x * x + y * y) / den
+    A, B = 2.0 * (y - 2.0) * x, 3.0 * (x - 2.0) * y
+    Ax, Ay, Bx, By = 2.0 * (y - 2.0), 2.0 * x, 3.0 * y, 3.0 * (x - 2.0)
+    u = 2.0 * np.cos(A) + np.sin(B) + 3.1
+    ux = -2.0 * np.sin(A) * Ax + np.cos(B) * Bx
+    uy = -2.0 * np.sin(A) * Ay + np.cos(B) * By
+    lap = -2.0 * np.cos(A) * (Ax * Ax + Ay * Ay) - np.sin(B) * (Bx * Bx + By * By)
+    f = lap + b[:, 0] * ux + b[:, 1] * uy + c * u
+    return b, c, f, u
+
+
+def paper_example_problem(n=257, dtype=np.float64, seed=0):
+    """The paper's example PDE on the stand-in box [0, 2]^2: every
+    coefficient, the source and the boundary data tabulated on n x n grids
+    (the descriptor's analytic parts are zero)."""
+    lo, hi = [0.0, 0.0], [PAPER_SIDE, PAPER_SIDE]
+    pts = grid_points((n, n), lo, hi)
+    b, c, f, u = paper_example_fields(pts)
+    mk = lambda v: {"dim": 2, "n": [n, n], "lo": list(lo), "hi": list(hi),  # noqa: E731
+                    "data": np.asarray(v).astype(dtype).reshape(n, n)}
+    return {"dim": 2, "domain": "box", "lo": lo, "hi": hi, "sigma": float(np.sqrt(2.0)),
+            "b0": [0.0, 0.0], "B": [[0.0, 0.0], [0.0, 0.0]], "c_a": 0.0, "c_b": 0.0, "seed": int(seed),
+            "tab": {"b": [mk(b[:, 0]), mk(b[:, 1])], "c": mk(c), "f": mk(f), "g": mk(u)}}
+
+
+def paper_example_gradient_grids(n=257, dtype=np.float64):
+    """grad u of the paper's example on n x n grids over [0, 2]^2 (the
+    gradient grids of an Ito control variate with u~ = u)."""
+    lo, hi = [0.0, 0.0], [PAPER_SIDE, PAPER_SIDE]
+    pts = grid_points((n, n), lo, hi)
+    x, y = pts[:, 0], pts[:, 1]
+    A, B = 2.0 * (y - 2.0) * x, 3.0 * (x - 2.0) * y
+    ux = -2.0 * np.sin(A) * 2.0 * (y - 2.0) + np.cos(B) * 3.0 * y
+    uy = -2.0 * np.sin(A) * 2.0 * x + np.cos(B) * 3.0 * (x - 2.0)
+    return [{"dim": 2, "n": [n, n], "lo": lo, "hi": hi, "data": v.astype(dtype).reshape(n, n)} for v in (ux, uy)]
+
+
+def paper_example_nodes():
+    """18 nodes laid out like the unit-square ones, scaled to [0, 2]^2: three
+    vertical interfaces x = 0.5, 1, 1.5, six nodes each at y = 2 j / 7."""
+    return unit_square_nodes() * PAPER_SIDE
+
+
 # --------------------------------------------------------------------------- grids
 def grid_points(n, lo, hi):
     """Coordinates of an n[0] x n[1] (x n[2]) uniform grid, x fastest, shape
