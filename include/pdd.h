@@ -207,16 +207,17 @@ void pdd_destroy_problem(pdd_problem *problem);
  * general functions of x; the analytic family of pdd_problem_desc is a special
  * case). Each non-NULL grid replaces one coefficient of the descriptor by its
  * bilinear / trilinear interpolant (the pdd_grid rule): b[d] the drift
- * component d (d < dim), c the killing rate, f the source. A grid has the
+ * component d (d < dim), c the killing rate, f the source, g the boundary
+ * data (read at the exit point; without it g = U + sum(gx)). A grid has the
  * problem's dim, n[d] >= 2 points per axis, dtype PDD_DTYPE_F32 or F64, data
  * in device memory (x fastest) and a box [lo, hi] that contains the domain
  * (the box itself, or the ball's bounding box). A NULL f keeps the source's
- * analytic form, which uses the descriptor's analytic b and c; the boundary
- * data g is always analytic. */
+ * analytic form, which uses the descriptor's analytic b and c. */
 typedef struct {
     const pdd_grid *b[3];
     const pdd_grid *c;
     const pdd_grid *f;
+    const pdd_grid *g;
 } pdd_coef_grids;
 
 /* As pdd_create_problem, with tabulated coefficients. The grids are read

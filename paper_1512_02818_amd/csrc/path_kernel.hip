@@ -303,8 +303,9 @@ __device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T 
 
 // g = G + sum(trig) at a boundary point.
 template <class T, int D>
-__device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x)
+__device__ __forceinline__ T boundary_value(const DevProblem<T> &P, const T *x, uint32_t tab)
 {
+    if (tab & 32u) return interp_cells<T, D>(P.tabv[5], x);  // tabulated g
     T u = poly_value<T, D>(P.gpoly, P.n_g, x);
     for (int m = 0; m < P.n_trig; ++m) {
         const DevTrig<T> &t = P.trig[m];
@@ -769,7 +770,7 @@ struct Walker {
     __device__ __forceinline__ void finish(const ItemCore<T> &a, const DevProblem<T> &P,
                                            uint64_t rec_base)
     {
-        const T gv = boundary_value<T, D>(P, Xt);
+        const T gv = boundary_value<T, D>(P, Xt, M::tab(P));
         const uint64_t r = slot - rec_base;
         if (EST == kEstIto) {  // phi and phi + xi
             const double phi = madd((double)gv, (double)Y, Z);

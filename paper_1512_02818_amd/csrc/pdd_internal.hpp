@@ -78,10 +78,10 @@ struct DevProblem {
     // j (power of y) then i (power of x), i + j <= 5; 3D by k, j, i
     T fdense[kMaxDense];
     // tabulated coefficients: bit q of tab set when tabv[q] replaces the
-    // analytic b_0, b_1, b_2, c, f (q = 0..4); read through their cell layout
+    // analytic b_0, b_1, b_2, c, f, g (q = 0..5); read through their cell layout
     uint32_t tab;
     int32_t tab_pad;
-    GridView<T> tabv[5];
+    GridView<T> tabv[6];
 };
 
 

@@ -984,14 +984,14 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
     if (!grids) return fail(PDD_E_INVALID, "grids is NULL");
     pdd_status st = check_desc(desc);
     if (st) return st;
-    const pdd_grid *g[5] = {grids->b[0], grids->b[1], grids->b[2], grids->c, grids->f};
-    static const char *names[5] = {"b[0]", "b[1]", "b[2]", "c", "f"};
+    const pdd_grid *g[6] = {grids->b[0], grids->b[1], grids->b[2], grids->c, grids->f, grids->g};
+    static const char *names[6] = {"b[0]", "b[1]", "b[2]", "c", "f", "g"};
     const int D = desc->dim;
     if (D == 2 && g[2]) return fail(PDD_E_INVALID, "b[2] grid given for a 2D problem");
     // both precisions' cell layouts of every given grid, in one allocation
-    size_t off32[5] = {}, off64[5] = {}, n32 = 0;
+    size_t off32[6] = {}, off64[6] = {}, n32 = 0;
     uint32_t tab = 0;
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < 6; ++q) {
         if (!g[q]) continue;
         if ((st = check_grid(*desc, g[q], -1, names[q]))) return st;
         tab |= 1u << q;
@@ -999,7 +999,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         n32 += align_up(cell_values<float>(g[q]->n, D), 64);
     }
     size_t n64 = 0;
-    for (int q = 0; q < 5; ++q)
+    for (int q = 0; q < 6; ++q)
         if (tab & (1u << q)) {
             off64[q] = n64;
             n64 += align_up(cell_values<double>(g[q]->n, D), 64);
@@ -1025,7 +1025,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         p->tab.cap = bytes;
         float *c32 = static_cast<float *>(p->tab.ptr);
         double *c64 = reinterpret_cast<double *>(static_cast<char *>(p->tab.ptr) + align_up(n32 * sizeof(float), 256));
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < 6; ++q) {
             if (!(tab & (1u << q))) continue;
             const pdd_grid *gq = g[q];
             hipError_t e1, e2;

@@ -54,7 +54,8 @@ class Grid(C.Structure):
 
 
 class CoefGrids(C.Structure):
-    _fields_ = [("b", C.POINTER(Grid) * 3), ("c", C.POINTER(Grid)), ("f", C.POINTER(Grid))]
+    _fields_ = [("b", C.POINTER(Grid) * 3), ("c", C.POINTER(Grid)), ("f", C.POINTER(Grid)),
+                ("g", C.POINTER(Grid))]
 
 
 class Tuning(C.Structure):
@@ -310,7 +311,7 @@ class Context:
 
 class Problem:
     """A problem uploaded to a context (pdd_create_problem). A "tab" entry of
-    the problem dict ({"b": [grid or None per axis], "c": grid, "f": grid},
+    the problem dict ({"b": [grid or None per axis], "c": grid, "f": grid, "g": grid},
     grids as for correction solves) gives tabulated coefficients
     (pdd_create_problem_tabulated); their values are copied to the device for
     the call and kept by the library."""
@@ -335,7 +336,7 @@ class Problem:
             for d, gd in enumerate(tab.get("b") or []):
                 if gd is not None:
                     cg.b[d] = dev(gd)
-            for field in ("c", "f"):
+            for field in ("c", "f", "g"):
                 if tab.get(field) is not None:
                     setattr(cg, field, dev(tab[field]))
             _check(lib().pdd_create_problem_tabulated(ctx.handle, C.byref(self.desc), C.byref(cg),

@@ -74,7 +74,7 @@ STRUCTS = {
     "pdd_problem_desc": (pdd.ProblemDesc, ["dim", "lo", "radius", "sigma", "B", "c_b", "n_gx",
                                            "trig", "mono", "fx", "gx", "seed"]),
     "pdd_grid": (pdd.Grid, ["dtype", "n", "lo", "hi", "data"]),
-    "pdd_coef_grids": (pdd.CoefGrids, ["b", "c", "f"]),
+    "pdd_coef_grids": (pdd.CoefGrids, ["b", "c", "f", "g"]),
     "pdd_tuning": (pdd.Tuning, ["block", "grab"]),
     "pdd_solve_opts": (pdd.SolveOpts, ["dt", "n_paths_per_node", "path_offset", "stream_id",
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),

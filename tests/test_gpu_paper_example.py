@@ -1,0 +1,87 @@
+"""The paper's own example PDE (Sec. 5, eq. F:PDE_ejemplo) on the GPU: all
+coefficients, the source and the boundary data tabulated on grids over the
+stand-in box [0, 2]^2, through the C ABI, against the CPU oracle on the same
+streams (FP64 path by path, FP32 within 3 SE), the exact solution kept, the
+Ito control variate on it, and a tabulated g checked on its own."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_02818_amd import pdd  # noqa: E402
+from paper_1512_02818_amd import workloads as W  # noqa: E402
+
+from test_gpu_parity import check_fp64_parity, gpu_solve, oracle_solve  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("exit_mode", ["bridge", "shift"])
+def test_paper_example_fp64_per_path(ctx, exit_mode):
+    pd = W.paper_example_problem(n=257)
+    nodes = W.paper_example_nodes()
+    n = 1500
+    st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp64", exit=exit_mode)
+    ost, orec = oracle_solve(pd, nodes, n, dt=1e-3, exit=exit_mode)
+    check_fp64_parity(st, rec, ost, orec, n)
+
+
+def test_paper_example_fp32_and_exact_solution(ctx):
+    pd64 = W.paper_example_problem(n=513)
+    pd32 = W.paper_example_problem(n=513, dtype=np.float32)
+    nodes = W.paper_example_nodes()
+    exact = W.paper_example_u(nodes)
+    n = 4000
+    st, _ = gpu_solve(ctx, pd32, nodes, n, dt=1e-3, precision="fp32")
+    ost, _ = oracle_solve(pd64, nodes, n, dt=1e-3)
+    # FP32 grids (the library keeps an FP32 and an FP64 copy of each) against the FP64 oracle
+    assert np.all(np.abs(st["mean"] - ost["mean"]) <= 3 * ost["stderr"] + 1e-4), (st["mean"] - ost["mean"])
+    # many more paths on the GPU: the exact u within 3 SE + the O(h) bias
+    big, _ = gpu_solve(ctx, pd32, nodes, 200_000, dt=2.5e-4, precision="fp32", stream_id=1)
+    assert np.all(np.abs(big["mean"] - exact) <= 3 * big["stderr"] + 0.01), (big["mean"] - exact, big["stderr"])
+
+
+def test_paper_example_ito_control_variate(ctx):
+    pd = W.paper_example_problem(n=513)
+    nodes = W.paper_example_nodes()
+    exact = W.paper_example_u(nodes)
+    gg = W.paper_example_gradient_grids(n=513)
+    gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
+    prob = pdd.Problem(ctx, pd)
+    st = pdd.stats_to_numpy(pdd.solve_ito(prob, gg, gt, nodes, dt=2.5e-4, n_paths=20_000, precision="fp64"))
+    assert np.all(st["vr"] > 100)
+    assert np.all(np.abs(st["mean"] - exact) <= 3 * st["stderr"] + 0.008), (st["mean"] - exact, st["stderr"])
+    # E[xi] = 0: the plain score of the same paths agrees within the noise of xi
+    var_xi = st["var"] - st["var_plain"] - 2 * st["cov"]
+    assert np.all(np.abs(st["mean"] - st["mean_plain"]) <= 3.5 * np.sqrt(var_xi / 20_000))
+    prob.close()
+
+
+def test_tabulated_g_alone(ctx):
+    """A tabulated g reproducing an analytic g exactly (bilinear data) walks
+    and scores like the analytic problem, FP64 and FP32."""
+    pd = W.bilinear_problem(seed=12)
+    nodes = W.unit_square_nodes()[::3]
+    for prec, dt_np in (("fp64", np.float64), ("fp32", np.float32)):
+        g = W.sampled_grid(pd, lambda p: W.manufactured_u(pd, p), n=17, dtype=dt_np)
+        st0, r0 = gpu_solve(ctx, pd, nodes, 2000, dt=1e-3, precision=prec)
+        st1, r1 = gpu_solve(ctx, dict(pd, tab={"g": g}), nodes, 2000, dt=1e-3, precision=prec)
+        assert np.array_equal(r0["steps"], r1["steps"])
+        tol = 1e-13 if prec == "fp64" else 2e-6
+        assert np.max(np.abs(r0["phi"] - r1["phi"])) < tol, prec
+
+
+def test_g_grid_is_validated(ctx):
+    pd = W.unit_square_problem(seed=0)
+    g = W.sampled_grid(pd, lambda p: W.manufactured_u(pd, p), n=9)
+    with pytest.raises(pdd.PDDError):
+        pdd.Problem(ctx, dict(pd, tab={"g": dict(g, hi=[0.5, 1.0])}))  # does not cover the box
