@@ -114,6 +114,8 @@ def parse():
                     help="1: report the correction iterates 10^3 -> 10^5 (0 = skip)")
     ap.add_argument("--fit-cloud", type=int, default=100,
                     help="time steps of the nodal-constant fit's cloud in [1e-3, 1e-2] (0 = skip)")
+    ap.add_argument("--paper-example", type=int, default=1,
+                    help="1: solve the paper's example PDE on the stand-in box (0 = skip)")
     ap.add_argument("--batch-scale", type=float, default=0.1,
                     help="path-count scale of the 64-problem batched solve (0 = skip)")
     ap.add_argument("--profile-correction", type=int, default=0,
@@ -334,6 +336,46 @@ def fit_cloud(ctx, m_hat, n_hat=1000, tol=1e-3):
             "dt_from_beta": tol / np.sqrt(2.0) / beta_rms}
 
 
+def paper_example(ctx):
+    """The paper's own example (Sec. 5, eq. F:PDE_ejemplo: trig-rational b and
+    c, sigma = sqrt(2)) with b, c, f and g tabulated on 513^2 FP32 grids over
+    the stand-in box [0, 2]^2, at 18 nodes laid out like the unit square's:
+    10^6 paths per node at h = 1e-3 (plain, FP32), and the Ito control variate
+    with the exact gradient (257^2 grids) at h = 2.5e-4 with 10^5 paths."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    pd = W.paper_example_problem(n=513, dtype=np.float32)
+    nodes = W.paper_example_nodes()
+    exact = W.paper_example_u(nodes)
+    prob = pdd.Problem(ctx, pd)
+    pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=1000, precision="fp32")  # warm-up
+    torch.cuda.synchronize()
+    pdd.kernel_times(ctx)
+    t0 = time.perf_counter()
+    st = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=1_000_000, precision="fp32",
+                                            stream_id=1, time_kernel=True))
+    wall = time.perf_counter() - t0
+    kern = pdd.kernel_times(ctx)
+    steps = int(st["steps_sum"].sum())
+    gg = W.paper_example_gradient_grids(n=257, dtype=np.float32)
+    gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
+    si = pdd.stats_to_numpy(pdd.solve_ito(prob, gg, gt, nodes, dt=2.5e-4, n_paths=100_000, precision="fp32",
+                                          stream_id=2))
+    prob.close()
+    return {"workload": "paper's example PDE (trig-rational b, c; sigma = sqrt(2)) on [0,2]^2, b, c, f, g on "
+                        "513^2 FP32 grids, 18 nodes, 10^6 paths per node, h = 1e-3, FP32, bridge exit",
+            "wall_s": wall, "path_kernel_ms": [float(k) for k in kern], "path_steps": steps,
+            "path_steps_per_s": steps / (sum(kern) / 1e3), "mean_steps_per_path": float(st["mean_steps"].mean()),
+            "rms_error": float(np.sqrt(np.mean((st["mean"] - exact) ** 2))),
+            "mean_stderr": float(np.mean(st["stderr"])), "mean_var_phi": float(np.mean(st["var"])),
+            "ito_exact_gradient": {"dt": 2.5e-4, "paths_per_node": 100_000,
+                                   "rms_error": float(np.sqrt(np.mean((si["mean"] - exact) ** 2))),
+                                   "mean_stderr": float(np.mean(si["stderr"])), "mean_vr": float(np.mean(si["vr"]))}}
+
+
 def batch_solve(ctx, scale):
     """64 random 2D/3D box problems (uneven node counts, paths per node and
     exit times; dt 1e-3 or 1e-4) in one pdd_solve_batch, FP32."""
@@ -543,6 +585,12 @@ def main():
         f = result["fit_constants"]
         print(f"fit: {f['paths']} paths in {f['wall_s']:.3f} s, beta RMS {f['beta_rms']:.3f}, "
               f"dt from beta {f['dt_from_beta']:.2e}", file=sys.stderr, flush=True)
+    if args.paper_example:
+        print("the paper's example PDE ...", file=sys.stderr, flush=True)
+        result["paper_example"] = paper_example(ctx)
+        pe = result["paper_example"]
+        print(f"paper example: {pe['path_steps_per_s']:.3e} path-steps/s, RMS err {pe['rms_error']:.2e} "
+              f"(SE {pe['mean_stderr']:.1e})", file=sys.stderr, flush=True)
     if args.batch_scale > 0:
         print("batched solve ...", file=sys.stderr, flush=True)
         result["batch"] = batch_solve(ctx, args.batch_scale)
