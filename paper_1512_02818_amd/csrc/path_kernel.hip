@@ -230,6 +230,12 @@ __device__ __forceinline__ T dense_poly(const T *c, const T *x)
 template <class T, int D>
 __device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x);
 template <class T, int D>
+__device__ __forceinline__ void grid_cell(const GridView<T> &g, const T *x, int *i, T *w);
+template <class T, int D>
+__device__ __forceinline__ size_t cell_index(const GridView<T> &g, const int *i);
+template <class T, int D>
+__device__ __forceinline__ T interp_corners(const T *p, const T *w);
+template <class T, int D>
 __device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T *x, const T *b, T c, T &f,
                                                 const T *cf);
 
@@ -254,6 +260,17 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
 #pragma unroll
     for (int d = 0; d < D; ++d) r2 = madd(x[d], x[d], r2);
     c = madd(P.c_b, r2, P.c_a);
+    if (tab & 64u) {  // every coefficient tabulated, one record per cell
+        int i[D];
+        T w[D];
+        grid_cell<T, D>(P.tabv[3], x, i, w);
+        const T *rec = P.tab_fused + cell_index<T, D>(P.tabv[3], i) * (size_t)((D + 2) << D);
+#pragma unroll
+        for (int d = 0; d < D; ++d) b[d] = interp_corners<T, D>(rec + (d << D), w);
+        c = interp_corners<T, D>(rec + (D << D), w);
+        if (want_f) f = interp_corners<T, D>(rec + ((D + 1) << D), w);
+        return;
+    }
     if (tab) {
         if (want_f && (tab & 16u)) {
             f = interp_cells<T, D>(P.tabv[4], x);
@@ -374,18 +391,25 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
 // interp_cell_at takes the cell and weights already found by grid_cell (for
 // several grids of one geometry).
 template <class T, int D>
-__device__ __forceinline__ T interp_cell_at(const GridView<T> &g, const int *i, const T *w)
+__device__ __forceinline__ size_t cell_index(const GridView<T> &g, const int *i)
+{
+    const size_t mx = (size_t)(g.n[0] - 1);
+    if (D == 2) return (size_t)i[1] * mx + i[0];
+    return ((size_t)i[2 % D] * (size_t)(g.n[1] - 1) + i[1]) * mx + i[0];
+}
+
+// Interpolation from the 2^D corner values of one cell, stored together at p.
+template <class T, int D>
+__device__ __forceinline__ T interp_corners(const T *p, const T *w)
 {
     typedef T V4 __attribute__((ext_vector_type(4)));
-    const size_t mx = (size_t)(g.n[0] - 1);
     if (D == 2) {
-        const V4 c = *reinterpret_cast<const V4 *>(g.cells + (((size_t)i[1] * mx + i[0]) << 2));
+        const V4 c = *reinterpret_cast<const V4 *>(p);
         const T l0 = madd(w[0], c.y, ((T)1 - w[0]) * c.x);
         const T l1 = madd(w[0], c.w, ((T)1 - w[0]) * c.z);
         return madd(w[1], l1, ((T)1 - w[1]) * l0);
     }
-    const size_t my = (size_t)(g.n[1] - 1);
-    const V4 *cv = reinterpret_cast<const V4 *>(g.cells + ((((size_t)i[2 % D] * my + i[1]) * mx + i[0]) << 3));
+    const V4 *cv = reinterpret_cast<const V4 *>(p);
     T acc = (T)0;
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz) {
@@ -400,6 +424,12 @@ __device__ __forceinline__ T interp_cell_at(const GridView<T> &g, const int *i, 
 }
 
 template <class T, int D>
+__device__ __forceinline__ T interp_cell_at(const GridView<T> &g, const int *i, const T *w)
+{
+    return interp_corners<T, D>(g.cells + (cell_index<T, D>(g, i) << D), w);
+}
+
+template <class T, int D>
 __device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
 {
     int i[D];
@@ -411,14 +441,15 @@ __device__ __forceinline__ T interp_cells(const GridView<T> &g, const T *x)
 // Cell layout of a grid (see cell_values), values converted from S to T: one
 // thread per cell.
 template <class S, class T, int D>
-__global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, int n2, T *__restrict__ cells)
+__global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, int n2, T *__restrict__ cells,
+                                  uint32_t stride, uint32_t off)
 {
     const uint64_t m0 = (uint64_t)(n0 - 1), m1 = (uint64_t)(n1 - 1), m2 = D == 3 ? (uint64_t)(n2 - 1) : 1;
     const uint64_t n_cells = m0 * m1 * m2;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < n_cells;
          c += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t i = c % m0, j = (c / m0) % m1, k = c / (m0 * m1);
-        T *out = cells + (c << D);
+        T *out = cells + c * stride + off;
 #pragma unroll
         for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
 #pragma unroll
@@ -1094,18 +1125,27 @@ const void *path_kernel_symbol(bool one, bool spec)
 }
 
 template <class S, class T, int D>
-hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s)
+hipError_t launch_grid_cells_strided(const S *data, const int32_t *n, T *cells, uint32_t stride, uint32_t off,
+                                     hipStream_t s)
 {
     const uint64_t n_cells = cell_values<T>(n, D) >> D;
     if (n_cells == 0) return hipSuccess;
     const uint64_t blocks = std::min<uint64_t>((n_cells + 255) / 256, 4096);
     hipLaunchKernelGGL((grid_cells_kernel<S, T, D>), dim3((uint32_t)blocks), dim3(256), 0, s, data, n[0], n[1],
-                       D == 3 ? n[2] : 2, cells);
+                       D == 3 ? n[2] : 2, cells, stride, off);
     return hipGetLastError();
 }
 
+template <class S, class T, int D>
+hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s)
+{
+    return launch_grid_cells_strided<S, T, D>(data, n, cells, 1u << D, 0u, s);
+}
+
 #define PDD_GRID_CELLS(S, T, D) \
-    template hipError_t launch_grid_cells<S, T, D>(const S *, const int32_t *, T *, hipStream_t);
+    template hipError_t launch_grid_cells<S, T, D>(const S *, const int32_t *, T *, hipStream_t); \
+    template hipError_t launch_grid_cells_strided<S, T, D>(const S *, const int32_t *, T *, uint32_t, uint32_t, \
+                                                            hipStream_t);
 PDD_GRID_CELLS(float, float, 2)
 PDD_GRID_CELLS(float, float, 3)
 PDD_GRID_CELLS(double, double, 2)

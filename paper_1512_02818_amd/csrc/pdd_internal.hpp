@@ -82,6 +82,11 @@ struct DevProblem {
     uint32_t tab;
     int32_t tab_pad;
     GridView<T> tabv[6];
+    // bit 6 of tab: b_0 .. b_{dim-1}, c and f are all tabulated on one
+    // geometry and their cell layouts are interleaved: cell r's record at
+    // tab_fused + r (dim + 2) 2^dim holds the 2^dim corners of b_0, ..., c, f
+    // in that order (tabv[q] then keep only the geometry)
+    const T *tab_fused;
 };
 
 
@@ -255,6 +260,10 @@ const void *path_kernel_symbol(bool one, bool spec);
 // converted from S to T.
 template <class S, class T, int D>
 hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s);
+// The same into records of `stride` values per cell, at offset `off` in each.
+template <class S, class T, int D>
+hipError_t launch_grid_cells_strided(const S *data, const int32_t *n, T *cells, uint32_t stride, uint32_t off,
+                                     hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);

@@ -989,21 +989,39 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
     const int D = desc->dim;
     if (D == 2 && g[2]) return fail(PDD_E_INVALID, "b[2] grid given for a 2D problem");
     // both precisions' cell layouts of every given grid, in one allocation
-    size_t off32[6] = {}, off64[6] = {}, n32 = 0;
     uint32_t tab = 0;
     for (int q = 0; q < 6; ++q) {
         if (!g[q]) continue;
         if ((st = check_grid(*desc, g[q], -1, names[q]))) return st;
         tab |= 1u << q;
-        off32[q] = n32;
-        n32 += align_up(cell_values<float>(g[q]->n, D), 64);
     }
-    size_t n64 = 0;
+    // b_0 .. b_{D-1}, c and f all given on one geometry: interleaved into one
+    // record per cell (slot 6), so a step reads one cache line for all of them
+    auto in_record = [&](int q) { return q < D || q == 3 || q == 4; };
+    bool fused = g[3] != nullptr;  // the geometry is compared with c's grid
+    for (int q = 0; q < 5; ++q)
+        if (in_record(q)) {
+            fused = fused && g[q];
+            for (int i = 0; fused && i < D; ++i)
+                fused = g[q]->n[i] == g[3]->n[i] && g[q]->lo[i] == g[3]->lo[i] && g[q]->hi[i] == g[3]->hi[i];
+        }
+    const uint32_t rec_vals = (uint32_t)((D + 2) << D);
+    size_t off32[7] = {}, off64[7] = {}, n32 = 0, n64 = 0;
     for (int q = 0; q < 6; ++q)
-        if (tab & (1u << q)) {
+        if ((tab & (1u << q)) && !(fused && in_record(q))) {
+            off32[q] = n32;
+            n32 += align_up(cell_values<float>(g[q]->n, D), 64);
             off64[q] = n64;
             n64 += align_up(cell_values<double>(g[q]->n, D), 64);
         }
+    if (fused) {
+        const size_t recs = cell_values<float>(g[3]->n, D) >> D;
+        off32[6] = n32;
+        n32 += align_up(recs * rec_vals, 64);
+        off64[6] = n64;
+        n64 += align_up(recs * rec_vals, 64);
+        tab |= 64u;
+    }
     pdd_problem *p = new pdd_problem();
     p->ctx = ctx;
     p->desc = *desc;
@@ -1028,29 +1046,39 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         for (int q = 0; q < 6; ++q) {
             if (!(tab & (1u << q))) continue;
             const pdd_grid *gq = g[q];
+            // own cell layout, or field k of the interleaved records
+            const bool rec = fused && in_record(q);
+            const uint32_t k = q < 3 ? (uint32_t)q : (uint32_t)(q - 3 + D);
+            const uint32_t stride = rec ? rec_vals : (1u << D), off = rec ? (k << D) : 0u;
+            float *d32 = c32 + (rec ? off32[6] : off32[q]);
+            double *d64 = c64 + (rec ? off64[6] : off64[q]);
             hipError_t e1, e2;
             if (gq->dtype == PDD_DTYPE_F32) {
                 const float *src = static_cast<const float *>(gq->data);
-                e1 = D == 2 ? launch_grid_cells<float, float, 2>(src, gq->n, c32 + off32[q], nullptr)
-                            : launch_grid_cells<float, float, 3>(src, gq->n, c32 + off32[q], nullptr);
-                e2 = D == 2 ? launch_grid_cells<float, double, 2>(src, gq->n, c64 + off64[q], nullptr)
-                            : launch_grid_cells<float, double, 3>(src, gq->n, c64 + off64[q], nullptr);
+                e1 = D == 2 ? launch_grid_cells_strided<float, float, 2>(src, gq->n, d32, stride, off, nullptr)
+                            : launch_grid_cells_strided<float, float, 3>(src, gq->n, d32, stride, off, nullptr);
+                e2 = D == 2 ? launch_grid_cells_strided<float, double, 2>(src, gq->n, d64, stride, off, nullptr)
+                            : launch_grid_cells_strided<float, double, 3>(src, gq->n, d64, stride, off, nullptr);
             } else {
                 const double *src = static_cast<const double *>(gq->data);
-                e1 = D == 2 ? launch_grid_cells<double, float, 2>(src, gq->n, c32 + off32[q], nullptr)
-                            : launch_grid_cells<double, float, 3>(src, gq->n, c32 + off32[q], nullptr);
-                e2 = D == 2 ? launch_grid_cells<double, double, 2>(src, gq->n, c64 + off64[q], nullptr)
-                            : launch_grid_cells<double, double, 3>(src, gq->n, c64 + off64[q], nullptr);
+                e1 = D == 2 ? launch_grid_cells_strided<double, float, 2>(src, gq->n, d32, stride, off, nullptr)
+                            : launch_grid_cells_strided<double, float, 3>(src, gq->n, d32, stride, off, nullptr);
+                e2 = D == 2 ? launch_grid_cells_strided<double, double, 2>(src, gq->n, d64, stride, off, nullptr)
+                            : launch_grid_cells_strided<double, double, 3>(src, gq->n, d64, stride, off, nullptr);
             }
             if (e1 != hipSuccess || e2 != hipSuccess)
                 return bail(fail(PDD_E_HIP, "cell layout of the %s grid: %s", names[q],
                                  hipGetErrorString(e1 != hipSuccess ? e1 : e2)));
             p->pf.tabv[q] = make_view<float>(gq, D);
             p->pf.tabv[q].data = nullptr;
-            p->pf.tabv[q].cells = c32 + off32[q];
+            p->pf.tabv[q].cells = rec ? nullptr : d32;
             p->pd.tabv[q] = make_view<double>(gq, D);
             p->pd.tabv[q].data = nullptr;
-            p->pd.tabv[q].cells = c64 + off64[q];
+            p->pd.tabv[q].cells = rec ? nullptr : d64;
+        }
+        if (fused) {
+            p->pf.tab_fused = c32 + off32[6];
+            p->pd.tab_fused = c64 + off64[6];
         }
         const hipError_t e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return bail(fail(PDD_E_HIP, "tabulated coefficients: %s", hipGetErrorString(e)));
