@@ -135,3 +135,23 @@ def test_fit_rejects_bad_arguments(ctx):
         pdd.fit_constants(ctx, dict(it, opts=dict(precision="fp32", stream_id=(1 << 28) - 2)),
                           [1e-3, 2e-3, 3e-3], 100)
     prob.close()
+
+
+def test_fit_of_a_correction_item(ctx):
+    """The fit takes a correction item: its means are u_prev(x0) + mean(e), with
+    a much smaller variance and bias constant than the plain estimator's."""
+    pd = W.unit_square_problem(seed=0)
+    prob = pdd.Problem(ctx, pd)
+    nodes = W.unit_square_nodes()
+    exact = W.manufactured_u(pd, nodes)
+    gu, gr, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float32)
+    tu = torch.as_tensor(gu["data"]).cuda().contiguous()
+    tr = torch.as_tensor(gr["data"]).cuda().contiguous()
+    h = np.linspace(1e-3, 1e-2, 30)
+    plain = pdd.fit_constants(ctx, {"problem": prob, "nodes": nodes, "opts": dict(precision="fp32")}, h, 1000)
+    cv = pdd.fit_constants(ctx, {"problem": prob, "nodes": nodes, "opts": dict(precision="fp32"),
+                                 "u_prev": gu, "u_prev_t": tu, "resid": gr, "resid_t": tr}, h, 1000)
+    assert np.all(np.abs(cv["E_phi"] - exact) <= 4 * cv["se_E_phi"] + 2e-4)
+    assert np.all(cv["V_phi"] < plain["V_phi"] / 100)
+    assert np.sqrt(np.mean(cv["beta"] ** 2)) < np.sqrt(np.mean(plain["beta"] ** 2)) / 3
+    prob.close()

@@ -233,3 +233,28 @@ def test_ito_large_launch_sampled_paths(ctx):
     st = pdd.stats_to_numpy(outs[0])
     assert np.all(st["n"] == n) and np.all(st["vr"] > 20)
     prob.close()
+
+
+def test_ito_solved_to_tolerance(ctx):
+    """pdd_solve_to_tolerance takes an Ito item like any other: every node
+    gets to the target standard error (pilot, plan on V[phi + xi], merged
+    continuation), and the result is a merge of the same paths' sums."""
+    pd = W.unit_square_problem(seed=3)
+    prob = pdd.Problem(ctx, pd)
+    nodes = W.unit_square_nodes()
+    grad = W.gradient_grids(pd, n=257, seed=1, dtype=np.float32)
+    gt = dev(grad, "fp32")
+    item = {"problem": prob, "nodes": nodes, "grad": grad, "grad_t": gt,
+            "opts": dict(dt=1e-3, precision="fp32", stream_id=5)}
+    se = 2e-4
+    st = pdd.stats_to_numpy(pdd.solve_to_tolerance(ctx, [item], se, 1000, 1 << 24)[0])
+    # the plan uses the pilot's variance (1,000 paths), so the final SE lands
+    # near the target, within the pilot's sampling noise
+    assert np.all(st["stderr"] < 1.25 * se) and np.median(st["stderr"]) > 0.8 * se, st["stderr"]
+    assert np.all(st["n"] > 1000)  # the pilot alone does not reach it
+    # the same paths in one solve give the same statistics
+    one = pdd.stats_to_numpy(pdd.solve_batch(ctx, [dict(item, opts=dict(item["opts"],
+                                                                       n_paths_per_node=st["n"].astype(np.uint64)))])[0])
+    assert np.allclose(one["mean"], st["mean"], rtol=1e-12, atol=1e-14)
+    assert np.allclose(one["var"], st["var"], rtol=1e-9)
+    prob.close()
