@@ -331,6 +331,19 @@ typedef struct {
 pdd_status pdd_fit_constants(pdd_ctx *ctx, const pdd_work_item *item, const double *h, int32_t n_h,
                              uint64_t n_hat, double delta, pdd_node_constants *out, void *stream);
 
+/* Gradient of a gridded u~ by second-order finite differences (the grad(u~)
+ * grids of pdd_solve_ito when only values of u~ on a grid are known, as
+ * inside the outer iteration of Sec. 2.3): with dx_d = (hi_d - lo_d) /
+ * (n_d - 1), the central difference (u[i+1] - u[i-1]) / (2 dx_d) inside and
+ * (-3 u[0] + 4 u[1] - u[2]) / (2 dx_d), (3 u[n-1] - 4 u[n-2] + u[n-3]) /
+ * (2 dx_d) at the two ends of each axis; exact for quadratics. `u`: a grid
+ * (pdd_grid rules, n_d >= 3, device data); `grad`: host array of dim device
+ * pointers, grad[d] receiving the n_0 n_1 (n_2) values of component d in u's
+ * dtype and layout (the caller allocates them; with u's n, lo, hi they form
+ * the gradient grids). Asynchronous on `stream`. Errors: NULL pointers, a
+ * malformed grid, n_d < 3; PDD_E_HIP on a launch failure. */
+pdd_status pdd_grid_gradient(pdd_ctx *ctx, const pdd_grid *u, void *const *grad, void *stream);
+
 /* Key of the context's launch-shape table: the path kernel a group of
  * items runs. `generic` selects between the kernel compiled for a box domain
  * with the bridge exit test, Gaussian increments and analytic coefficients

@@ -177,6 +177,7 @@ SIGNATURES = {
                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "pdd_fit_constants": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.POINTER(C.c_double), C.c_int32,
                                       C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]),
+    "pdd_grid_gradient": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(C.c_void_p), C.c_void_p]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -553,6 +554,19 @@ def fit_constants(ctx: Context, item: dict, h, n_hat, delta=1.0, stream=None) ->
                                    int(n_hat), float(delta), out.ctypes.data_as(C.c_void_p),
                                    _stream_handle(stream)))
     return out
+
+
+def grid_gradient(ctx: Context, grid: dict, tensor, stream=None):
+    """pdd_grid_gradient: (grid dicts, device tensors) of the dim gradient
+    components of a grid whose values are in the device tensor `tensor`."""
+    import torch
+    D = int(grid["dim"])
+    g = grid_struct(grid, tensor)
+    outs = [torch.empty_like(tensor) for _ in range(D)]
+    ptrs = (C.c_void_p * D)(*[o.data_ptr() for o in outs])
+    _check(lib().pdd_grid_gradient(ctx.handle, C.byref(g), ptrs, _stream_handle(stream)))
+    dicts = [{"dim": D, "n": list(grid["n"]), "lo": list(grid["lo"]), "hi": list(grid["hi"])} for _ in range(D)]
+    return dicts, outs
 
 
 def kernel_times(ctx: Context, cap=4096):
