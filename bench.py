@@ -232,6 +232,20 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
         wall = time.perf_counter() - t0
         st = pdd.stats_to_numpy(out).reshape(reps, len(nodes))
         err = st["mean"] - exact[None, :]
+        if kind == "cv":
+            # the same batch with a 128-path pilot: the balanced plan of eq.
+            # F:N_y_h needs only ~100 paths per node here (V[e] ~ 5e-5), so the
+            # 1,000-path pilot alone overshoots the accuracy (untimed warm-up first)
+            pdd.solve_to_tolerance(ctx, batch, 10 * budget, 128, 1 << 31)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pdd.solve_to_tolerance(ctx, batch, budget, 128, 1 << 31)
+            torch.cuda.synchronize()
+            wall_small = time.perf_counter() - t1
+            ss = pdd.stats_to_numpy(out).reshape(reps, len(nodes))
+            small = {"pilot_paths": 128, "wall_s": wall_small, "node_solves_per_s": reps * len(nodes) / wall_small,
+                     "rms_error": float(np.sqrt(np.mean((ss["mean"] - exact[None, :]) ** 2))),
+                     "mean_paths_per_node": float(ss["n"].mean()), "max_paths_per_node": int(ss["n"].max())}
         res[kind] = {"node_solves": int(reps * len(nodes)), "wall_s": wall,
                      "node_solves_per_s": reps * len(nodes) / wall,
                      "rms_error": float(np.sqrt(np.mean(err ** 2))),
@@ -239,6 +253,10 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
                      "path_steps": int(st["steps_sum"].sum()),
                      "precision": "fp64" if kind == "plain" else "fp32",
                      "dt_ladder": ladder}
+        if kind == "cv":
+            res[kind]["small_pilot"] = small
+            print(f"cv with a 128-path pilot: {small['node_solves_per_s']:.3e} node-solves/s, RMS err "
+                  f"{small['rms_error']:.2e}, mean N {small['mean_paths_per_node']:.0f}", file=sys.stderr, flush=True)
         print(f"{kind}: dt={chosen} {reps * len(nodes)} node-solves in {wall:.3f} s, "
               f"RMS err {res[kind]['rms_error']:.2e}, mean N {st['n'].mean():.0f}",
               file=sys.stderr, flush=True)
