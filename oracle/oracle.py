@@ -285,6 +285,20 @@ def kill(problem, pts):
     return _point_fn("orc_kill", problem, pts)
 
 
+def drift(problem, pts):
+    """b at the points, n x dim."""
+    p = make_problem(problem)
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    out = np.zeros((len(pts), p.dim))
+    b = (C.c_double * 3)()
+    for q, x in enumerate(pts):
+        xx = np.zeros(3)
+        xx[: len(x)] = x
+        lib().orc_drift(C.byref(p), _dptr(xx), b)
+        out[q] = b[: p.dim]
+    return out
+
+
 def interp(grid: dict, pts):
     gh = _GridHolder(grid)
     pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
