@@ -344,6 +344,20 @@ pdd_status pdd_fit_constants(pdd_ctx *ctx, const pdd_work_item *item, const doub
  * malformed grid, n_d < 3; PDD_E_HIP on a launch failure. */
 pdd_status pdd_grid_gradient(pdd_ctx *ctx, const pdd_grid *u, void *const *grad, void *stream);
 
+/* Residual r = f - ((1/2) sigma^2 Lap u~ + b.grad u~ + c u~) of a gridded u~
+ * (the residual grid of pdd_solve_correction when only values of u~ are
+ * known, as inside the outer iteration), at the grid's points, with the
+ * problem's b, c, f (analytic or tabulated, evaluated in FP64) and the
+ * derivatives of u~ by second-order differences: those of pdd_grid_gradient
+ * for grad u~, (u[i+1] - 2 u[i] + u[i-1]) / dx^2 inside and
+ * (2 u[0] - 5 u[1] + 4 u[2] - u[3]) / dx^2 (mirrored) at the ends for the
+ * second derivatives; exact for quadratic u~. `u`: a grid of the problem's
+ * dim (pdd_grid rules, n_d >= 4, device data); `resid`: device buffer of the
+ * same size and dtype (caller-allocated; with u's n, lo, hi it is the residual
+ * grid). Asynchronous on `stream`. Errors: NULL pointers, dim mismatch, a
+ * malformed grid, n_d < 4; PDD_E_HIP on a launch failure. */
+pdd_status pdd_grid_residual(pdd_problem *problem, const pdd_grid *u, void *resid, void *stream);
+
 /* Key of the context's launch-shape table: the path kernel a group of
  * items runs. `generic` selects between the kernel compiled for a box domain
  * with the bridge exit test, Gaussian increments and analytic coefficients

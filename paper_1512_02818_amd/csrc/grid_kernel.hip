@@ -57,6 +57,27 @@ hipError_t launch_gradient(const pdd_grid *g, void *const *out, hipStream_t s)
 
 }  // namespace
 
+extern "C" pdd_status pdd_grid_residual(pdd_problem *problem, const pdd_grid *u, void *resid, void *stream)
+{
+    if (!problem || !u || !resid) return fail(PDD_E_INVALID, "NULL argument");
+    const int D = u->dim;
+    if (D != problem->desc.dim) return fail(PDD_E_INVALID, "grid dim %d != problem dim %d", D, problem->desc.dim);
+    if (!u->data) return fail(PDD_E_INVALID, "grid has no data");
+    if (u->dtype != PDD_DTYPE_F32 && u->dtype != PDD_DTYPE_F64) return fail(PDD_E_INVALID, "bad grid dtype");
+    for (int d = 0; d < D; ++d) {
+        if (u->n[d] < 4) return fail(PDD_E_INVALID, "second derivatives at the edges need n >= 4 per axis");
+        if (!(u->hi[d] > u->lo[d]) || !std::isfinite(u->hi[d] - u->lo[d]))
+            return fail(PDD_E_INVALID, "grid needs finite lo < hi");
+    }
+    if ((uint64_t)u->n[0] * u->n[1] * (D == 3 ? (uint64_t)u->n[2] : 1) >= (1ull << 40))
+        return fail(PDD_E_INVALID, "grid too large");
+    HIP_TRY(hipSetDevice(problem->ctx->device));
+    const hipError_t e = pdd::launch_grid_residual(problem->pd, problem->desc.sigma, u, resid,
+                                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(PDD_E_HIP, "grid residual launch: %s", hipGetErrorString(e));
+    return PDD_OK;
+}
+
 extern "C" pdd_status pdd_grid_gradient(pdd_ctx *ctx, const pdd_grid *u, void *const *grad, void *stream)
 {
     if (!ctx || !u || !grad) return fail(PDD_E_INVALID, "NULL argument");

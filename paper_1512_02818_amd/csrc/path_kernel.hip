@@ -1083,7 +1083,94 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 }
 
+// Residual r = f - ((1/2) sigma^2 Lap u + b.grad u + c u) of a gridded u at
+// its points, b, c, f from the problem (FP64), the derivatives of u by
+// second-order differences (central inside; three-point one-sided first and
+// four-point one-sided second derivatives at the ends of each axis).
+template <class S>
+__device__ __forceinline__ double fd_first(const S *__restrict__ u, uint64_t p, uint64_t s, int a, int n, double dx)
+{
+    if (a == 0) return (-3.0 * (double)u[p] + 4.0 * (double)u[p + s] - (double)u[p + 2 * s]) / (2.0 * dx);
+    if (a == n - 1) return (3.0 * (double)u[p] - 4.0 * (double)u[p - s] + (double)u[p - 2 * s]) / (2.0 * dx);
+    return ((double)u[p + s] - (double)u[p - s]) / (2.0 * dx);
+}
+
+template <class S>
+__device__ __forceinline__ double fd_second(const S *__restrict__ u, uint64_t p, uint64_t s, int a, int n, double dx)
+{
+    if (a == 0)
+        return (2.0 * (double)u[p] - 5.0 * (double)u[p + s] + 4.0 * (double)u[p + 2 * s] - (double)u[p + 3 * s]) /
+               (dx * dx);
+    if (a == n - 1)
+        return (2.0 * (double)u[p] - 5.0 * (double)u[p - s] + 4.0 * (double)u[p - 2 * s] - (double)u[p - 3 * s]) /
+               (dx * dx);
+    return ((double)u[p + s] - 2.0 * (double)u[p] + (double)u[p - s]) / (dx * dx);
+}
+
+template <class S, int D>
+__global__ void __launch_bounds__(256) grid_residual_kernel(const DevProblem<double> P, const S *__restrict__ u,
+                                                            int n0, int n1, int n2, double lo0, double lo1,
+                                                            double lo2, double dx0, double dx1, double dx2,
+                                                            double half_s2, S *__restrict__ r)
+{
+    __shared__ double s_cf[kMaxDense];
+    for (int q = threadIdx.x; q < kMaxDense; q += blockDim.x) s_cf[q] = P.fdense[q];
+    __syncthreads();
+    const uint64_t m01 = (uint64_t)n0 * n1;
+    const uint64_t total = m01 * (D == 3 ? (uint64_t)n2 : 1);
+    const int nn[3] = {n0, n1, n2};
+    const double lo[3] = {lo0, lo1, lo2}, dx[3] = {dx0, dx1, dx2};
+    const uint64_t st[3] = {1, (uint64_t)n0, m01};
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < total;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const int idx[3] = {(int)(p % n0), (int)((p / n0) % n1), D == 3 ? (int)(p / m01) : 0};
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = lo[d] + (double)idx[d] * dx[d];
+        double b[D], c, f = 0.0;
+        coefficients<double, D>(P, x, b, c, f, true, s_cf, P.tab);
+        double lap = 0.0, adv = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lap += fd_second<S>(u, p, st[d], idx[d], nn[d], dx[d]);
+            adv += b[d] * fd_first<S>(u, p, st[d], idx[d], nn[d], dx[d]);
+        }
+        r[p] = (S)(f - (half_s2 * lap + adv + c * (double)u[p]));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const pdd_grid *g, void *r, hipStream_t s)
+{
+    const int D = g->dim;
+    const int n2 = D == 3 ? g->n[2] : 1;
+    const uint64_t total = (uint64_t)g->n[0] * g->n[1] * n2;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 16384);
+    double dx[3] = {0, 0, 0};
+    for (int d = 0; d < D; ++d) dx[d] = (g->hi[d] - g->lo[d]) / (g->n[d] - 1);
+    const double h2 = 0.5 * sigma * sigma;
+    if (g->dtype == PDD_DTYPE_F32) {
+        const float *u = static_cast<const float *>(g->data);
+        float *out = static_cast<float *>(r);
+        if (D == 2)
+            hipLaunchKernelGGL((grid_residual_kernel<float, 2>), dim3(blocks), dim3(256), 0, s, P, u, g->n[0], g->n[1],
+                               n2, g->lo[0], g->lo[1], 0.0, dx[0], dx[1], 0.0, h2, out);
+        else
+            hipLaunchKernelGGL((grid_residual_kernel<float, 3>), dim3(blocks), dim3(256), 0, s, P, u, g->n[0], g->n[1],
+                               n2, g->lo[0], g->lo[1], g->lo[2], dx[0], dx[1], dx[2], h2, out);
+    } else {
+        const double *u = static_cast<const double *>(g->data);
+        double *out = static_cast<double *>(r);
+        if (D == 2)
+            hipLaunchKernelGGL((grid_residual_kernel<double, 2>), dim3(blocks), dim3(256), 0, s, P, u, g->n[0],
+                               g->n[1], n2, g->lo[0], g->lo[1], 0.0, dx[0], dx[1], 0.0, h2, out);
+        else
+            hipLaunchKernelGGL((grid_residual_kernel<double, 3>), dim3(blocks), dim3(256), 0, s, P, u, g->n[0],
+                               g->n[1], n2, g->lo[0], g->lo[1], g->lo[2], dx[0], dx[1], dx[2], h2, out);
+    }
+    return hipGetLastError();
+}
 
 template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,

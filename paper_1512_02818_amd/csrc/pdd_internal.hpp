@@ -265,6 +265,9 @@ template <class S, class T, int D>
 hipError_t launch_grid_cells_strided(const S *data, const int32_t *n, T *cells, uint32_t stride, uint32_t off,
                                      hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
+// r = f - ((1/2) sigma^2 Lap u + b.grad u + c u) at the points of grid g (u in
+// g->data, r in g's dtype and layout), by second-order differences.
+hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const pdd_grid *g, void *r, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 // Starting sums of every group node: zero, or the statistics already in the

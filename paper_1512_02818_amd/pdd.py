@@ -178,6 +178,7 @@ SIGNATURES = {
     "pdd_fit_constants": (C.c_int32, [C.c_void_p, C.POINTER(WorkItem), C.POINTER(C.c_double), C.c_int32,
                                       C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]),
     "pdd_grid_gradient": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(C.c_void_p), C.c_void_p]),
+    "pdd_grid_residual": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p]),
     "pdd_last_error": (C.c_char_p, []),
 }
 
@@ -567,6 +568,16 @@ def grid_gradient(ctx: Context, grid: dict, tensor, stream=None):
     _check(lib().pdd_grid_gradient(ctx.handle, C.byref(g), ptrs, _stream_handle(stream)))
     dicts = [{"dim": D, "n": list(grid["n"]), "lo": list(grid["lo"]), "hi": list(grid["hi"])} for _ in range(D)]
     return dicts, outs
+
+
+def grid_residual(problem: Problem, grid: dict, tensor, stream=None):
+    """pdd_grid_residual: (grid dict, device tensor) of r = f - (L + c) u~ for
+    the gridded u~ whose values are in the device tensor `tensor`."""
+    import torch
+    g = grid_struct(grid, tensor)
+    out = torch.empty_like(tensor)
+    _check(lib().pdd_grid_residual(problem.handle, C.byref(g), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return {"dim": int(grid["dim"]), "n": list(grid["n"]), "lo": list(grid["lo"]), "hi": list(grid["hi"])}, out
 
 
 def kernel_times(ctx: Context, cap=4096):

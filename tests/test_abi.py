@@ -33,7 +33,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(built_lib):
     names = declared_functions()
-    assert len(names) == 23, names
+    assert len(names) == 24, names
     for n in names:
         assert hasattr(built_lib, n), n
     assert set(names) == set(pdd.SIGNATURES)
@@ -68,6 +68,7 @@ def test_null_arguments_are_rejected_without_gpu(built_lib):
     assert built_lib.pdd_set_tuning(None, None, None) == -1
     assert built_lib.pdd_glm_fit(None, None, 0, 0, None, None, None) == -1
     assert built_lib.pdd_grid_gradient(None, None, None, None) == -1
+    assert built_lib.pdd_grid_residual(None, None, None, None) == -1
     assert built_lib.pdd_fit_constants(None, None, None, 0, 0, 1.0, None, None) == -1
 
 
