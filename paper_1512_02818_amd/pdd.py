@@ -2,7 +2,8 @@
 
 Every step of the solve runs in the HIP library ``libpdd.so``; PyTorch
 provides device memory (result and record tensors) and the HIP stream. If the
-library is missing, importing the binding raises: there is no CPU fallback.
+library is missing, the first call that needs it raises: there is no CPU
+fallback.
 """
 from __future__ import annotations
 

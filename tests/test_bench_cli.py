@@ -1,10 +1,13 @@
-"""bench.py on the host: more than one GPU is refused with a message (the
-measured path runs on one GPU), and stored HBM byte counts are reported only
-for the kernel sources, precision and launch size they were taken for."""
+"""bench.py and the binding on the host: more than one GPU is refused with a
+message (the measured path runs on one GPU); stored HBM byte counts are
+reported only for the kernel sources, precision and launch size they were
+taken for; without the built library every entry point raises."""
 import json
 import os
 import subprocess
 import sys
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -35,3 +38,18 @@ def test_stored_traffic_is_guarded(tmp_path):
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
         t = json.load(f)
     assert os.path.exists(os.path.join(ROOT, "profiles", t["summary"]))
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library every entry point raises; nothing falls
+    back to a CPU computation."""
+    import numpy as np
+
+    from paper_1512_02818_amd import pdd
+    monkeypatch.setattr(pdd, "LIB_PATH", str(tmp_path / "libpdd.so"))
+    monkeypatch.setattr(pdd, "_lib", None)
+    for call in (lambda: pdd.lib(),
+                 lambda: pdd.glm_fit(np.arange(3.0), np.arange(3.0)),
+                 lambda: pdd.plan_paths(np.zeros(1, dtype=pdd.STATS_DTYPE), 1e-3, 100)):
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            call()
