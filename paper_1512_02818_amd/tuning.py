@@ -9,6 +9,7 @@ pdd_autotune on an item and records the winner. Shapes change only speed,
 never results.
 
     python -m paper_1512_02818_amd.tuning   # tunes the standard workloads, writes the cache
+    python -m paper_1512_02818_amd.tuning --only ito   # only the Ito control variate's items
 """
 from __future__ import annotations
 
@@ -150,6 +151,8 @@ def main():
     from . import workloads as W
     ap = argparse.ArgumentParser(description="tunes the standard workloads, writes the cache")
     ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--only", choices=ESTIMATORS, default=None,
+                    help="tune only the items of this estimator")
     args = ap.parse_args()
     ctx = pdd.Context(0)
     sq = W.big_square_problem(seed=0)
@@ -180,7 +183,17 @@ def main():
         items.append({"problem": probs["ball3"], "nodes": ball3_nodes, "opts": dict(dt=1e-3, precision=prec)})
         items.append(dict(items[2], opts=dict(items[2]["opts"], exit="shift")))
         items.append(dict(items[3], opts=dict(items[3]["opts"], exit="shift")))
+        # the Ito control variate: gradient grids of the same u~ (box / bridge and shifted exit)
+        gg = W.gradient_grids(unit, n=257, seed=1, dtype=dt)
+        gg3 = W.gradient_grids(cube, n=65, seed=1, dtype=dt)
+        for prob, nds, g in ((probs["unit"], W.unit_square_nodes(), gg), (probs["cube"], cube_nodes, gg3)):
+            it = {"problem": prob, "nodes": nds, "opts": dict(dt=1e-3, precision=prec), "grad": g,
+                  "grad_t": [torch.as_tensor(x["data"]).cuda().contiguous() for x in g]}
+            items.append(it)
+            items.append(dict(it, opts=dict(it["opts"], exit="shift")))
         for it in items:
+            if args.only is not None and ESTIMATORS[item_estimator(it)] != args.only:
+                continue
             # full solves of about 4e7 paths (2e6 for the long-path problem) check the winner
             verify = max(1000, int((2e6 if it["problem"] is probs["sq"] else 4e7) / len(it["nodes"])))
             shape = tune(ctx, it, path=args.out, verify_paths=verify)
