@@ -124,6 +124,9 @@ def parse():
     ap.add_argument("--profile-estimator", choices=["correction", "ito"], default="correction",
                     help="with --profile-correction: the correction estimator, or phi + xi with the Ito "
                          "control variate from 257^2 FP32 gradient grids of the same u_prev")
+    ap.add_argument("--profile-paper", type=int, default=0,
+                    help="only run the paper's example PDE (513^2 FP32 tabulated grids, h=1e-3) with this "
+                         "many paths per node three times and print its timing (for profilers)")
     ap.add_argument("--profile-replicas", type=int, default=1,
                     help="with --profile-correction: that many 18-node solves (distinct streams) in one batch")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -496,8 +499,36 @@ def profile_correction(paths, calibrate_mib=0, replicas=1, estimator="correction
     ctx.close()
 
 
+def profile_paper(paths, calibrate_mib=0):
+    """The paper's example PDE alone (every coefficient and g tabulated on
+    513^2 FP32 grids over [0, 2]^2, 18 nodes, h = 1e-3, FP32), three solves
+    with distinct path ranges, for kernel-trace and counter runs."""
+    import numpy as np
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    ctx = pdd.Context(0)
+    prob = pdd.Problem(ctx, W.paper_example_problem(n=513, dtype=np.float32))
+    nodes = W.paper_example_nodes()
+    if calibrate_mib > 0:
+        calibration_copy(calibrate_mib)
+    steps = 0
+    for r in range(3):
+        st = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=paths, path_offset=r * paths,
+                                                precision="fp32", time_kernel=True))
+        steps += int(st["steps_sum"].sum())
+    ms = pdd.kernel_times(ctx)
+    print(json.dumps({"paper_profile": {"paths_per_node": paths, "nodes": len(nodes), "path_steps": steps,
+                                        "kernel_ms": ms, "path_steps_per_s": steps / (sum(ms) / 1e3)}}), flush=True)
+    prob.close()
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.profile_paper > 0:
+        profile_paper(args.profile_paper, args.calibrate_copy_mib)
+        return
     if args.profile_correction > 0:
         profile_correction(args.profile_correction, args.calibrate_copy_mib, args.profile_replicas,
                            args.profile_estimator)
