@@ -358,7 +358,7 @@ def fit_cloud(ctx, m_hat, n_hat=1000, tol=1e-3):
 
 
 def paper_example(ctx):
-    """The paper's own example (Sec. 5, eq. F:PDE_ejemplo: trig-rational b and
+    """The paper's own example (Sec. 6, eq. F:PDE_ejemplo: trig-rational b and
     c, sigma = sqrt(2)) with b, c, f and g tabulated on 513^2 FP32 grids over
     the stand-in box [0, 2]^2, at 18 nodes laid out like the unit square's:
     10^6 paths per node at h = 1e-3 (plain, FP32), and the Ito control variate

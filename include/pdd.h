@@ -287,7 +287,7 @@ pdd_status pdd_solve_to_tolerance(pdd_ctx *ctx, const pdd_work_item *items, int3
                                   void *stream);
 
 /* ------------------------------------------------------------------------
- * Fast fit of nodal constants (appendix H5, Alg. A:Fitting). Host only
+ * Fast fit of nodal constants (Sec. 5, heuristic H5, Alg. A:Fitting). Host only
  * except for the batched solve of pdd_fit_constants.
  * ------------------------------------------------------------------------ */
 enum { PDD_GLM_NORMAL = 0, PDD_GLM_GAMMA = 1 };

@@ -1,4 +1,4 @@
-"""Plain reference of the fast fit of nodal constants (paper, appendix H5 and
+"""Plain reference of the fast fit of nodal constants (paper, Sec. 5 heuristic H5 and
 Alg. A:Fitting).
 
 TEST INFRASTRUCTURE: only the tests, ``__graft_entry__.smoke()`` and the CPU

@@ -1,4 +1,4 @@
-// Fast fit of nodal constants (paper, appendix H5 and Alg. A:Fitting): one
+// Fast fit of nodal constants (paper, Sec. 5 heuristic H5 and Alg. A:Fitting): one
 // batched launch over a cloud of time steps, then per node a normal /
 // identity GLM of the means and a gamma / identity GLM of the variances in
 // x = h^delta (eqs. F:Noisy_model_moment1, F:Noisy_model_moment2). The fits

@@ -257,7 +257,7 @@ PAPER_SIDE = 2.0  # stand-in box [0, 2]^2 for the paper's example (its figure is
 
 
 def paper_example_u(pts) -> np.ndarray:
-    """The exact solution of the paper's example (Sec. 5, eq. F:PDE_ejemplo):
+    """The exact solution of the paper's example (Sec. 6, eq. F:PDE_ejemplo):
     2 cos(2 (y - 2) x) + sin(3 (x - 2) y) + 3.1."""
     pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
     x, y = pts[:, 0], pts[:, 1]

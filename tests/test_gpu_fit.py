@@ -1,4 +1,4 @@
-"""GPU tests of the fast fit of nodal constants (appendix H5, Alg. A:Fitting):
+"""GPU tests of the fast fit of nodal constants (Sec. 5, heuristic H5, Alg. A:Fitting):
 pdd_fit_constants runs the cloud of time steps as one batch on the GPU and
 fits every node on the host.
 

@@ -1,4 +1,4 @@
-"""The paper's own example PDE (Sec. 5, eq. F:PDE_ejemplo) on the GPU: all
+"""The paper's own example PDE (Sec. 6, eq. F:PDE_ejemplo) on the GPU: all
 coefficients, the source and the boundary data tabulated on grids over the
 stand-in box [0, 2]^2, through the C ABI, against the CPU oracle on the same
 streams (FP64 path by path, FP32 within 3 SE), the exact solution kept, the
@@ -36,15 +36,17 @@ def test_paper_example_fp64_per_path(ctx, exit_mode):
 
 
 def test_paper_example_fp32_and_exact_solution(ctx):
-    pd64 = W.paper_example_problem(n=513)
     pd32 = W.paper_example_problem(n=513, dtype=np.float32)
     nodes = W.paper_example_nodes()
     exact = W.paper_example_u(nodes)
     n = 4000
     st, _ = gpu_solve(ctx, pd32, nodes, n, dt=1e-3, precision="fp32")
-    ost, _ = oracle_solve(pd64, nodes, n, dt=1e-3)
-    # FP32 grids (the library keeps an FP32 and an FP64 copy of each) against the FP64 oracle
-    assert np.all(np.abs(st["mean"] - ost["mean"]) <= 3 * ost["stderr"] + 1e-4), (st["mean"] - ost["mean"])
+    # the oracle reads the same FP32-rounded grid values (widened exactly to
+    # FP64) and walks in FP64: the FP32 paths' node means within 3 SE + 1e-5
+    ost, _ = oracle_solve(pd32, nodes, n, dt=1e-3)
+    diff = np.abs(st["mean"] - ost["mean"])
+    assert np.all(diff <= 3 * ost["stderr"] + 1e-5), (st["mean"] - ost["mean"])
+    print(f"paper example fp32: max |mean32 - mean64| {diff.max():.2e}, max SE {ost['stderr'].max():.2e}")
     # many more paths on the GPU: the exact u within 3 SE + the O(h) bias
     big, _ = gpu_solve(ctx, pd32, nodes, 200_000, dt=2.5e-4, precision="fp32", stream_id=1)
     assert np.all(np.abs(big["mean"] - exact) <= 3 * big["stderr"] + 0.01), (big["mean"] - exact, big["stderr"])

@@ -67,14 +67,47 @@ def oracle_solve(pd, nodes, n_paths, grids=None, **opt):
     return O.solve_nodes(pd, nodes, record=True, h=opt["dt"], n_paths=n_paths, **kw)
 
 
-def check_fp64_parity(st, rec, ost, orec, n_paths, cv=False):
+def near_tie(pd, nodes, node, path, oracle_steps, grids=None, **opt):
+    """True when moving x0 of `node` by at most 1e-11 along an axis changes the
+    oracle's exit step of `path`: one of the path's exit decisions sat within
+    rounding of its threshold, so FP64 walks that round differently by an ulp
+    (device vs host transcendentals) may legitimately end at different steps."""
+    from oracle import oracle as O
+    kw = {k: v for k, v in opt.items() if k in ("path_offset", "stream", "exit", "law", "max_steps")}
+    if grids is not None:
+        kw["u_prev"], kw["resid"] = grids
+    nodes = np.asarray(nodes, dtype=np.float64).reshape(len(nodes), -1)
+    for eps in (1e-14, 1e-13, 1e-12, 1e-11):
+        for d in range(nodes.shape[1]):
+            for sgn in (1.0, -1.0):
+                moved = nodes.copy()
+                moved[node, d] += sgn * eps
+                r = O.run_paths(pd, moved, [node], [int(kw.get("path_offset", 0)) + path], h=opt["dt"],
+                                **{k: v for k, v in kw.items() if k != "path_offset"})
+                if int(r["steps"][0]) != int(oracle_steps):
+                    return True
+    return False
+
+
+def check_fp64_parity(st, rec, ost, orec, n_paths, cv=False, tie=None):
+    """FP64 parity bar: >= 99.99 % identical exit steps, every mismatch a near
+    tie (when `tie` = (pd, nodes, grids, opts) is given), matching paths'
+    scores to 1e-11, and on the nodes whose paths all match (at least half of
+    the nodes, and at least one) means to 1e-10, variances to 1e-8 and
+    exit-step sums exactly."""
     steps_g = rec["steps"] & 0x7FFFFFFF
     cap_g = rec["steps"] >> 31
     same = steps_g == orec["steps"].astype(np.uint32)
     assert same.mean() >= 0.9999, f"exit-step agreement {same.mean():.6f}"
     assert np.array_equal(cap_g[same].astype(bool), orec["capped"][same].astype(bool))
+    if tie is not None:
+        pd, nodes, grids, opt = tie
+        for s in np.nonzero(~same)[0]:
+            node, path = divmod(int(s), n_paths)
+            assert near_tie(pd, nodes, node, path, orec["steps"][s], grids=grids, **opt), (node, path)
     n_nodes = len(st)
     per_node = same.reshape(n_nodes, n_paths).all(axis=1)
+    assert per_node.any() and per_node.mean() >= 0.5, per_node
     key = "e" if cv else "phi"
     ok = same
     g = rec[key][ok]
@@ -95,7 +128,8 @@ def test_unit_square_fp64_per_path(ctx, exit_mode):
     n = 10000 if exit_mode == "bridge" else 2000
     st, rec = gpu_solve(ctx, pd, nodes, n, dt=1e-3, precision="fp64", exit=exit_mode)
     ost, orec = oracle_solve(pd, nodes, n, dt=1e-3, exit=exit_mode)
-    agree, nodes_ok = check_fp64_parity(st, rec, ost, orec, n)
+    agree, nodes_ok = check_fp64_parity(st, rec, ost, orec, n,
+                                        tie=(pd, nodes, None, dict(dt=1e-3, exit=exit_mode)))
     print(f"{exit_mode}: exit-step agreement {agree:.6f}, clean nodes {nodes_ok:.3f}")
 
 
@@ -292,7 +326,9 @@ def test_big_square_sampled_paths(ctx):
         slot = ni * n + pj
         same = (rec["steps"][slot] & 0x7FFFFFFF) == orec["steps"].astype(np.uint32)
         if prec == "fp64":
-            assert same.mean() >= 0.99
+            # every sampled path ends at the oracle's step unless it is a near tie
+            for s in np.nonzero(~same)[0]:
+                assert near_tie(pd, nodes, int(ni[s]), int(off + pj[s]), orec["steps"][s], dt=h), (ni[s], pj[s])
             assert np.all(np.abs(rec["phi"][slot][same] - orec["phi"][same])
                           <= 1e-10 * np.maximum(1.0, np.abs(orec["phi"][same])))
         else:

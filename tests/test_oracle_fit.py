@@ -1,4 +1,4 @@
-"""Pins of the oracle's fast fit of nodal constants (appendix H5, Alg. A:Fitting).
+"""Pins of the oracle's fast fit of nodal constants (Sec. 5, heuristic H5, Alg. A:Fitting).
 
 * Normal / identity GLM = ordinary least squares: against numpy's lstsq and
   the textbook standard errors.

@@ -1,4 +1,4 @@
-"""Pins of the oracle on the paper's own example (Sec. 5, eq. F:PDE_ejemplo)
+"""Pins of the oracle on the paper's own example (Sec. 6, eq. F:PDE_ejemplo)
 with every coefficient, the source and the boundary data tabulated, on the
 stand-in box [0, 2]^2 (the paper's domain figure is missing).
 
