@@ -235,6 +235,26 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
 pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                            const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
 
+/* pdd_solve_nodes for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, results and errors as pdd_solve_nodes, and the same statistics
+ * bit for bit whenever the solve's paths fit one launch of this variant
+ * (2^21 paths, or tuning->max_launch_paths); above that its launches cut the
+ * node sums at other places and the statistics agree to rounding.
+ * Limits: one path count for all nodes (n_paths_per_node NULL), at most
+ * PDD_NOALLOC_MAX_NODES nodes, no PDD_TIME_KERNEL (PDD_E_UNSUPPORTED
+ * otherwise). The call allocates nothing, neither device nor pinned memory:
+ * its working memory is a static device array of PDD_NOALLOC_SCRATCH_BYTES
+ * per GPU, held from the library's load until the process ends, and the node
+ * table and problem reach the device as kernel arguments. Calls on one GPU
+ * share that array: two such calls in flight at once on one GPU (other
+ * streams, other contexts) race, and the caller must order them; the
+ * context's other solves use their own memory and do not conflict. */
+#define PDD_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define PDD_NOALLOC_MAX_NODES 32768
+pdd_status pdd_solve_nodes_noalloc(pdd_problem *problem, const double *nodes, int64_t n_nodes,
+                                   const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
+
 /* Correction estimator with u_prev as control variate and the residual
  * r = f - (L + c) u_prev, both on grids (same dim as the problem). */
 pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdd.so")
-SOURCES = ["path_kernel.hip", "reduce_kernel.hip", "pdd_runtime.hip", "pdd_server.hip", "pdd_fit.hip", "grid_kernel.hip"]
+SOURCES = ["path_kernel.hip", "reduce_kernel.hip", "pdd_runtime.hip", "pdd_server.hip", "pdd_fit.hip", "grid_kernel.hip", "pdd_noalloc.hip"]
 HEADERS = ["pdd_internal.hpp", "host_runtime.hpp"]
 
 # Packed FP32 instructions are switched off: hipcc -O3 would otherwise form

@@ -64,6 +64,18 @@ inline int tuning_key(int precision, int dim, int est, bool generic)
 // Whether an item can run in the specialised kernel.
 bool specialised(const HostItem &it);
 
+// Launch shape for a solve: opts->tuning (fields left 0 take the default),
+// else the context's table entry for `key` (tuning_key; < 0: none), else
+// {256, occupancy, 64, 0}; checked.
+pdd_status read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd_tuning &tune);
+// Resident workgroups per CU of kernel `fn` at `block` threads, from the
+// context's table (filled at pdd_init for the plain kernels; `cache`: add a
+// missing entry, which allocates host memory).
+int occupancy(pdd_ctx *ctx, const void *fn, int block, bool cache = true);
+// The allocation-free solve's device scratch on `device` (made current by the
+// caller): looked up once per device; PDD_E_HIP if the lookup fails.
+pdd_status noalloc_attach(int device);
+
 // Validates items, then enqueues them on `s`, grouped by (precision,
 // dimension, estimator); a group of at most kScratchSlots paths without
 // caller records is one launch.

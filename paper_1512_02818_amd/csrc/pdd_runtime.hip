@@ -314,19 +314,18 @@ GridView<T> make_view(const pdd_grid *g, int dim)
     return v;
 }
 
-int occupancy(pdd_ctx *ctx, const void *fn, int block)
+}  // namespace
+
+int pdd::occupancy(pdd_ctx *ctx, const void *fn, int block, bool cache)
 {
     auto key = std::make_tuple(fn, block);
     auto it = ctx->occupancy.find(key);
     if (it != ctx->occupancy.end()) return it->second;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0) != hipSuccess || n < 1) n = 1;
-    ctx->occupancy[key] = n;
+    if (cache) ctx->occupancy[key] = n;
     return n;
 }
-
-
-}  // namespace
 
 bool pdd::specialised(const HostItem &it)
 {
@@ -419,9 +418,11 @@ pdd_status check_tuning(const pdd_tuning &tune)
     return PDD_OK;
 }
 
+}  // namespace
+
 // Launch shape of a group: the caller's (fields left 0 take the default),
 // else the context's table entry for the group's key, else the default.
-pdd_status read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd_tuning &tune)
+pdd_status pdd::read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd_tuning &tune)
 {
     tune = pdd_tuning{256, 0, 64, 0};
     if (!o->tuning && key >= 0) {
@@ -436,6 +437,8 @@ pdd_status read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd
     }
     return check_tuning(tune);
 }
+
+namespace {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -922,6 +925,20 @@ pdd_status pdd_init(pdd_ctx **out, int hip_device)
         delete ctx;
         return fail(PDD_E_HIP, "event creation failed");
     }
+    // the allocation-free solve's scratch on this device, and the occupancy of
+    // every plain path kernel, so that pdd_solve_nodes_noalloc only looks
+    // things up; a failed lookup is reported by that entry point alone (and
+    // cleared here, so that no later launch check mistakes it for its own)
+    if (noalloc_attach(hip_device) != PDD_OK) (void)hipGetLastError();
+    for (int block : {64, 128, 256})
+        for (bool spec : {false, true}) {
+            for (bool one : {false, true}) {
+                occupancy(ctx, path_kernel_symbol<float, 2, kEstPlain>(one, spec), block);
+                occupancy(ctx, path_kernel_symbol<float, 3, kEstPlain>(one, spec), block);
+                occupancy(ctx, path_kernel_symbol<double, 2, kEstPlain>(one, spec), block);
+                occupancy(ctx, path_kernel_symbol<double, 3, kEstPlain>(one, spec), block);
+            }
+        }
     *out = ctx;
     return PDD_OK;
 }

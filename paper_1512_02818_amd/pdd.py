@@ -24,6 +24,7 @@ PLAIN_ALONGSIDE = 1
 TIME_KERNEL = 2
 ACCUMULATE = 4
 MAX_TRIG, MAX_MONO = 16, 8
+NOALLOC_MAX_NODES = 32768  # PDD_NOALLOC_MAX_NODES
 
 
 class TrigTerm(C.Structure):
@@ -153,6 +154,8 @@ SIGNATURES = {
                                                  C.POINTER(C.c_void_p)]),
     "pdd_solve_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
                                     C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
+    "pdd_solve_nodes_noalloc": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
+                                            C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
     "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
                                          C.POINTER(C.c_double), C.c_int64, C.POINTER(SolveOpts),
                                          C.c_void_p, C.c_void_p]),
@@ -418,6 +421,16 @@ def solve_nodes(problem: Problem, nodes, out=None, stream=None, **opt):
     o = make_opts(**opt)
     _check(lib().pdd_solve_nodes(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)), n,
                                  C.byref(o), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def solve_nodes_noalloc(problem: Problem, nodes, out, stream=None, **opt):
+    """pdd_solve_nodes_noalloc: the plain solve without allocation (the
+    statistics tensor `out` is the caller's); asynchronous."""
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
+    o = make_opts(**opt)
+    _check(lib().pdd_solve_nodes_noalloc(problem.handle, nodes.ctypes.data_as(C.POINTER(C.c_double)), len(nodes),
+                                         C.byref(o), C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 
