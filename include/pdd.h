@@ -229,9 +229,15 @@ typedef struct {
 pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *desc,
                                         const pdd_coef_grids *grids, pdd_problem **out);
 
-/* Plain estimator phi at n_nodes nodes (host array, n_nodes x dim). Every
- * node must lie strictly inside Omega. `out` is device memory of n_nodes
- * entries. n_nodes == 0 is a no-op. */
+/* Plain estimator phi at n_nodes nodes (Sec. 2.3, Alg. 1: Euler-Maruyama
+ * paths of eq. F:E_M from each node, score phi = g(X_tau) Y_tau + Z_tau of eq.
+ * F:Dynkin; statistics of Sec. 2.2, eq. F:Statistical_error). `nodes`: host
+ * array, n_nodes x dim, row-major; every node strictly inside Omega. `out`:
+ * device memory of n_nodes entries, written when the stream reaches the end
+ * of the solve. n_nodes == 0 is a no-op. Errors (nothing is enqueued):
+ * PDD_E_INVALID for NULL pointers, a node outside Omega, dt <= 0, bad enums
+ * or limits; PDD_E_UNSUPPORTED for FP32 paths whose trig terms leave the
+ * hardware sine's range; PDD_E_NOMEM / PDD_E_HIP from the device. */
 pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                            const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
 
@@ -255,8 +261,16 @@ pdd_status pdd_solve_nodes(pdd_problem *problem, const double *nodes, int64_t n_
 pdd_status pdd_solve_nodes_noalloc(pdd_problem *problem, const double *nodes, int64_t n_nodes,
                                    const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
 
-/* Correction estimator with u_prev as control variate and the residual
- * r = f - (L + c) u_prev, both on grids (same dim as the problem). */
+/* Correction estimator of the multigrid-like iteration (Sec. 2.3, eqs.
+ * F:Statistics_VR and F:xiControlVariate with gamma = 1, rewritten by Ito's
+ * formula so that no gradient is needed): a previous approximation u_prev is
+ * the control variate; along each path R = sum h Y_k r(X_k) with the residual
+ * r = f - (L + c) u_prev, the score is e = (g - u_prev)(X_tau) Y_tau - R and
+ * the node value u_prev(x0) + mean(e). u_prev and r are grids of the
+ * problem's dim in the path precision's dtype (borrowed until the stream
+ * completes). Arguments, outputs and errors as for pdd_solve_nodes, plus
+ * PDD_E_INVALID for a missing or malformed grid or one that does not cover
+ * Omega, PDD_E_UNSUPPORTED for a grid dtype other than the path precision's. */
 pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,
                                 const pdd_grid *resid, const double *nodes, int64_t n_nodes,
                                 const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
@@ -276,8 +290,13 @@ pdd_status pdd_solve_correction(pdd_problem *problem, const pdd_grid *u_prev,
 pdd_status pdd_solve_ito(pdd_problem *problem, const pdd_grid *grad, const double *nodes, int64_t n_nodes,
                          const pdd_solve_opts *opts, pdd_node_stats *out, void *stream);
 
-/* Several problems in one persistent launch per (dim, precision, estimator)
- * group. Each item's results equal those of its own solve call. */
+/* Many solves at once (the nodal solves of Alg. 1 for several problems, or
+ * the iterates of one): items are grouped by (precision, dim, estimator) and
+ * each group runs as one persistent launch (work items with their own
+ * queues; alike solves merged). Each item's results equal those of its own
+ * pdd_solve_nodes / pdd_solve_correction / pdd_solve_ito call bit for bit.
+ * Errors as for those calls; the first invalid item fails the whole call
+ * before anything is enqueued. */
 pdd_status pdd_solve_batch(pdd_ctx *ctx, const pdd_work_item *items, int32_t n_items,
                            void *stream);
 
@@ -470,14 +489,28 @@ typedef struct {
     int64_t n_nodes;
 } pdd_completion;
 
+/* Latency percentiles count every request that was not shed: a completed
+ * one at its latency, and one that was cancelled or has not finished yet at
+ * its age (submit to cancellation, or to the report), which is only a lower
+ * bound of its latency ("censored"). A percentile is then itself a lower
+ * bound when some censored age is at or below it (p50_censored /
+ * p99_censored = 1); with no censored request it is exact. Nearest-rank
+ * percentiles. */
 typedef struct {
-    uint64_t submitted, shed, admitted, completed, failed, queued, inflight, epochs;
+    uint64_t submitted, shed, admitted, completed;
+    uint64_t failed;                          /* ended with an error other than cancellation */
+    uint64_t queued, inflight, epochs;
     uint64_t nodes_completed, path_steps;
     uint64_t mem_in_use, mem_peak, mem_fixed; /* bytes: admitted requests; their peak; record scratch */
-    double p50_ms, p99_ms, mean_ms;           /* latency of completed requests */
+    double p50_ms, p99_ms;                    /* latency percentiles of every request not shed (above) */
+    double mean_ms;                           /* mean latency of completed requests */
     double wall_s;                            /* first submit to last completion */
     double node_solves_per_s;                 /* nodes_completed / wall_s */
     double epoch_s;                           /* time spent running epochs (enqueue to device done) */
+    uint64_t cancelled;                       /* cancelled by pdd_server_destroy */
+    uint64_t censored;                        /* requests counted at their age (cancelled or unfinished) */
+    int32_t p50_censored, p99_censored;       /* 1: the percentile is a lower bound */
+    double p50_done_ms, p99_done_ms;          /* percentiles of completed requests alone */
 } pdd_server_report;
 
 /* Starts a server on `ctx` (NULL opts = defaults). Errors: bad options, a
@@ -491,7 +524,7 @@ pdd_status pdd_server_submit(pdd_server *server, const pdd_request *req, uint64_
  * their count to `n`, waiting up to wait_ms (0 = no wait) for the first. */
 pdd_status pdd_server_poll(pdd_server *server, pdd_completion *out, int32_t cap, int32_t *n,
                            int32_t wait_ms);
-/* Counters and latency percentiles so far. */
+/* Counters and latency percentiles so far (pdd_server_report). */
 pdd_status pdd_server_report_get(pdd_server *server, pdd_server_report *out);
 /* Stops the server: the running epoch ends, requests still queued or in
  * flight are cancelled (their `out` is not written), device memory is freed.

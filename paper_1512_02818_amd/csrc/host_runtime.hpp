@@ -32,6 +32,7 @@ constexpr double kBridgeSkip = 24.953298500158186;     // 36 ln 2: p < 2^-36 ski
 constexpr uint64_t kDefaultMaxSteps = 1ull << 26;
 constexpr uint64_t kScratchSlots = 1ull << 27;         // record slots per launch
 constexpr uint64_t kMaxLaunchSlots = 1ull << 31;
+constexpr double kHwTrigRevolutions = 256.0;           // input range of the FP32 hardware sine / cosine
 
 struct DeviceBuffer {
     void *ptr = nullptr;
@@ -78,8 +79,10 @@ pdd_status noalloc_attach(int device);
 
 // Validates items, then enqueues them on `s`, grouped by (precision,
 // dimension, estimator); a group of at most kScratchSlots paths without
-// caller records is one launch.
-pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s);
+// caller records is one launch. one_launch: such a group stays one launch
+// whatever the tuning's max_launch_paths says (the serving loop, whose
+// results must not depend on the tuning table).
+pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch = false);
 
 }  // namespace pdd
 
@@ -104,6 +107,10 @@ struct pdd_ctx {
 struct pdd_problem {
     pdd_ctx *ctx = nullptr;
     pdd_problem_desc desc{};
+    // largest |k_d x_d + phase_d| of a trig term over the domain's bounding
+    // box, in revolutions: FP32 paths evaluate sines with the hardware
+    // instruction, whose argument must stay within +-256 revolutions
+    double trig_rev_max = 0.0;
     pdd::DevProblem<float> pf{};
     pdd::DevProblem<double> pd{};
     pdd::DeviceBuffer tab;  // cell layouts of tabulated coefficients (FP32, then FP64)

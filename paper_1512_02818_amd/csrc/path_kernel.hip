@@ -93,7 +93,9 @@ struct Arith;
 template <>
 struct Arith<float> {
     // (w + 1/2) 2^-32 with w rounded to 24 significant bits: within 2^-24
-    // (relative) of the FP64 uniform of the same word, never 0.
+    // (relative) of the FP64 uniform of the same word, in (0, 1]. It is
+    // exactly 1 for the top 128 words (w >= 2^32 - 128, probability 2^-25):
+    // such a bridge draw cannot end a path, and Box-Muller gives r = 0.
     __device__ static __forceinline__ float unif(uint32_t w)
     {
         return fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);

@@ -260,6 +260,21 @@ pdd_status check_desc(const pdd_problem_desc *d)
     return PDD_OK;
 }
 
+// Largest |k_d x_d + phase_d| / (2 pi) of the trig terms over the bounding
+// box of the domain (a corner maximises |k_d x_d|).
+double trig_revolutions(const pdd_problem_desc &d)
+{
+    double mx = 0.0;
+    for (int m = 0; m < d.n_trig; ++m)
+        for (int i = 0; i < d.dim; ++i) {
+            const double lo = d.domain == PDD_DOMAIN_BOX ? d.lo[i] : d.center[i] - d.radius;
+            const double hi = d.domain == PDD_DOMAIN_BOX ? d.hi[i] : d.center[i] + d.radius;
+            const double k = d.trig[m].k[i], ph = d.trig[m].phase[i];
+            mx = std::max(mx, std::max(std::fabs(k * lo + ph), std::fabs(k * hi + ph)));
+        }
+    return mx * 0.15915494309189533577;
+}
+
 bool strictly_inside(const pdd_problem_desc &d, const double *x)
 {
     if (d.domain == PDD_DOMAIN_BOX) {
@@ -353,6 +368,11 @@ pdd_status pdd::validate_item(HostItem &it)
     if (o->exit_mode < PDD_EXIT_BRIDGE || o->exit_mode > PDD_EXIT_NAIVE) return fail(PDD_E_INVALID, "bad exit mode");
     if (o->law != PDD_LAW_GAUSS && o->law != PDD_LAW_RADEMACHER) return fail(PDD_E_INVALID, "bad law");
     if (o->stream_id >= (1u << 28)) return fail(PDD_E_INVALID, "stream_id must be < 2^28");
+    if (o->precision == PDD_FP32 && it.prob->trig_rev_max > kHwTrigRevolutions)
+        return fail(PDD_E_UNSUPPORTED,
+                    "FP32 paths: a trig term's argument reaches %.1f revolutions over the domain, beyond the "
+                    "+-%.0f of the hardware sine (use FP64 paths)",
+                    it.prob->trig_rev_max, kHwTrigRevolutions);
     it.max_steps = o->max_steps ? o->max_steps : kDefaultMaxSteps;
     if (it.max_steps >= (1ull << 31)) return fail(PDD_E_INVALID, "max_steps must be < 2^31");
     if (cv) {
@@ -447,7 +467,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // reductions and statistics.
 template <class T, int D, int EST>
 pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tuning &tune,
-                     bool timed, hipStream_t s)
+                     bool timed, bool one_launch, hipStream_t s)
 {
     const int n_items = (int)items.size();
     // problems used by the group
@@ -516,7 +536,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     kslot[n_k] = total;
 
     uint64_t per_launch = std::min(kScratchSlots, std::max<uint64_t>(total, 1));
-    if (tune.max_launch_paths > 0) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
+    if (tune.max_launch_paths > 0 && !one_launch) per_launch = std::min<uint64_t>(per_launch, tune.max_launch_paths);
     const uint64_t n_launch = total ? (total + per_launch - 1) / per_launch : 0;
 
     // queue counters: one per launch for the single-item kernel, one per item
@@ -852,17 +872,17 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
 
 template <class T, int D>
 pdd_status run_group_est(int est, pdd_ctx *ctx, std::vector<HostItem *> &g, const pdd_tuning &tune, bool timed,
-                         hipStream_t s)
+                         bool one_launch, hipStream_t s)
 {
-    if (est == kEstCorrection) return run_group<T, D, kEstCorrection>(ctx, g, tune, timed, s);
-    if (est == kEstIto) return run_group<T, D, kEstIto>(ctx, g, tune, timed, s);
-    return run_group<T, D, kEstPlain>(ctx, g, tune, timed, s);
+    if (est == kEstCorrection) return run_group<T, D, kEstCorrection>(ctx, g, tune, timed, one_launch, s);
+    if (est == kEstIto) return run_group<T, D, kEstIto>(ctx, g, tune, timed, one_launch, s);
+    return run_group<T, D, kEstPlain>(ctx, g, tune, timed, one_launch, s);
 }
 
 }  // namespace
 
 // Validates items, then runs them grouped by (precision, dim, estimator).
-pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s)
+pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch)
 {
     for (auto &it : items) {
         pdd_status st = validate_item(it);
@@ -888,11 +908,11 @@ pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_
                 const bool generic = !std::all_of(g.begin(), g.end(), [](const HostItem *i) { return specialised(*i); });
                 if ((st = read_tuning(ctx, items[0].o, tuning_key(prec, dim, est, generic), tune))) return st;
                 if (prec == PDD_FP32)
-                    st = dim == 2 ? run_group_est<float, 2>(est, ctx, g, tune, timed, s)
-                                  : run_group_est<float, 3>(est, ctx, g, tune, timed, s);
+                    st = dim == 2 ? run_group_est<float, 2>(est, ctx, g, tune, timed, one_launch, s)
+                                  : run_group_est<float, 3>(est, ctx, g, tune, timed, one_launch, s);
                 else
-                    st = dim == 2 ? run_group_est<double, 2>(est, ctx, g, tune, timed, s)
-                                  : run_group_est<double, 3>(est, ctx, g, tune, timed, s);
+                    st = dim == 2 ? run_group_est<double, 2>(est, ctx, g, tune, timed, one_launch, s)
+                                  : run_group_est<double, 3>(est, ctx, g, tune, timed, one_launch, s);
                 if (st) return st;
                 // the next group reuses the staging buffer and the scratch
                 HIP_TRY(hipEventRecord(ctx->done, s));
@@ -975,6 +995,7 @@ pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_pr
     pdd_problem *p = new pdd_problem();
     p->ctx = ctx;
     p->desc = *desc;
+    p->trig_rev_max = trig_revolutions(*desc);
     if ((st = fill_problem(*desc, p->pf, true)) || (st = fill_problem(*desc, p->pd, false))) {
         delete p;
         return st;
@@ -1042,6 +1063,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
     pdd_problem *p = new pdd_problem();
     p->ctx = ctx;
     p->desc = *desc;
+    p->trig_rev_max = trig_revolutions(*desc);
     if ((st = fill_problem(*desc, p->pf, true)) || (st = fill_problem(*desc, p->pd, false))) {
         delete p;
         return st;

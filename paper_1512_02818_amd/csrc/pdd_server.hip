@@ -15,9 +15,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -84,7 +86,9 @@ struct pdd_server {
     uint64_t next_id = 1;
     // report (under mu)
     pdd_server_report rep{};
-    std::vector<double> latencies;
+    std::vector<double> latencies;         // completed requests
+    std::vector<double> censored;          // cancelled requests: age at cancellation
+    std::map<uint64_t, Clock::time_point> outstanding;  // submitted, not finished: submit time
     bool any_submit = false;
     Clock::time_point first_submit, last_done;
 
@@ -133,12 +137,16 @@ void pdd_server::finish(Request *r, pdd_status status)
         rep.mem_in_use -= r->mem;
         --rep.inflight;
     }
+    outstanding.erase(r->id);
     if (status == PDD_OK) {
         ++rep.completed;
         rep.nodes_completed += (uint64_t)r->req.n_nodes;
         rep.path_steps += c.path_steps;
         latencies.push_back(c.latency_ms);
         last_done = now;
+    } else if (status == PDD_E_BUSY) {  // cancelled: its latency is at least its age
+        ++rep.cancelled;
+        censored.push_back(c.latency_ms);
     } else {
         ++rep.failed;
     }
@@ -163,7 +171,9 @@ void pdd_server::epoch(std::vector<Request *> &batch)
         it.out = r->dev_out;
     }
     const auto t0 = Clock::now();
-    pdd_status st = run_items(ctx, items, stream);
+    // one launch per group whatever the context's tuning table caps: a
+    // request's node sums then never depend on the mix it ran in
+    pdd_status st = run_items(ctx, items, stream, true);
     if (st == PDD_OK && hipStreamSynchronize(stream) != hipSuccess)
         st = fail(PDD_E_HIP, "epoch failed on the device");
     for (Request *r : batch) r->status = st;
@@ -408,6 +418,7 @@ pdd_status pdd_server_submit(pdd_server *sv, const pdd_request *req, uint64_t *i
     }
     r->id = sv->next_id++;
     *id = r->id;
+    sv->outstanding[r->id] = r->t_submit;
     sv->queue.push_back(std::move(r));
     sv->rep.queued = sv->queue.size();
     sv->cv_work.notify_one();
@@ -435,17 +446,35 @@ pdd_status pdd_server_report_get(pdd_server *sv, pdd_server_report *out)
     std::lock_guard<std::mutex> lk(sv->mu);
     pdd_server_report r = sv->rep;
     r.queued = sv->queue.size();
+    // nearest-rank percentile of sorted values
+    auto pct = [](const std::vector<double> &v, double p) {
+        const size_t k = (size_t)std::ceil(p / 100.0 * (double)v.size());
+        return v[std::min(v.size(), std::max<size_t>(k, 1)) - 1];
+    };
     std::vector<double> l = sv->latencies;
-    r.p50_ms = r.p99_ms = r.mean_ms = 0.0;
+    std::sort(l.begin(), l.end());
+    // every request not shed: completed at its latency, cancelled or
+    // unfinished at its age (a lower bound of its latency)
+    std::vector<double> cens = sv->censored;
+    const auto now = Clock::now();
+    for (const auto &kv : sv->outstanding) cens.push_back(ms_between(kv.second, now));
+    std::vector<double> all = l;
+    all.insert(all.end(), cens.begin(), cens.end());
+    std::sort(all.begin(), all.end());
+    r.censored = cens.size();
+    r.p50_ms = r.p99_ms = r.mean_ms = r.p50_done_ms = r.p99_done_ms = 0.0;
+    r.p50_censored = r.p99_censored = 0;
+    if (!all.empty()) {
+        r.p50_ms = pct(all, 50.0);
+        r.p99_ms = pct(all, 99.0);
+        // lower bounds once a censored age sits at or below them
+        const double cmin = cens.empty() ? HUGE_VAL : *std::min_element(cens.begin(), cens.end());
+        r.p50_censored = cmin <= r.p50_ms;
+        r.p99_censored = cmin <= r.p99_ms;
+    }
     if (!l.empty()) {
-        std::sort(l.begin(), l.end());
-        // nearest-rank percentiles
-        auto pct = [&](double p) {
-            size_t k = (size_t)std::ceil(p / 100.0 * (double)l.size());
-            return l[std::min(l.size(), std::max<size_t>(k, 1)) - 1];
-        };
-        r.p50_ms = pct(50.0);
-        r.p99_ms = pct(99.0);
+        r.p50_done_ms = pct(l, 50.0);
+        r.p99_done_ms = pct(l, 99.0);
         double s = 0.0;
         for (double v : l) s += v;
         r.mean_ms = s / (double)l.size();

@@ -141,7 +141,9 @@ class ServerReport(C.Structure):
                                            "queued", "inflight", "epochs", "nodes_completed",
                                            "path_steps", "mem_in_use", "mem_peak", "mem_fixed")] + \
                [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "wall_s", "node_solves_per_s",
-                                          "epoch_s")]
+                                          "epoch_s")] + \
+               [("cancelled", C.c_uint64), ("censored", C.c_uint64), ("p50_censored", C.c_int32),
+                ("p99_censored", C.c_int32), ("p50_done_ms", C.c_double), ("p99_done_ms", C.c_double)]
 
 
 # Every entry point of include/pdd.h with its ctypes signature.
@@ -612,11 +614,12 @@ def autotune(ctx: Context, item: dict):
 
 
 def set_tuning(ctx: Context, precision: str, dim: int, correction, tuning=None, generic=False):
-    """pdd_set_tuning: (block, blocks_per_cu, grab) for the key (correction: 0 / False
+    """pdd_set_tuning: (block, blocks_per_cu, grab[, max_launch_paths]) for the key (correction: 0 / False
     plain, 1 / True correction estimator, 2 Ito control variate; generic: the
     generic rather than the box / bridge / Gaussian kernel), or None to remove it."""
     k = TuningKey(PRECISIONS[precision], int(dim), int(correction), 1 if generic else 0)
-    t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]), 0)
+    t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]),
+                                           int(tuning[3]) if len(tuning) > 3 else 0)
     _check(lib().pdd_set_tuning(ctx.handle, C.byref(k), C.byref(t) if t is not None else None))
 
 

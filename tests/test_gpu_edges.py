@@ -211,3 +211,27 @@ def test_long_node_segments_are_reduced_in_chunks(prob):
                                              precision="fp32", tuning=(256, 0, 64, 100_003)))
     assert np.array_equal(cut["n"], st["n"]) and np.array_equal(cut["steps_sum"], st["steps_sum"])
     assert np.allclose(cut["mean"], st["mean"], rtol=1e-14, atol=1e-15)
+
+
+def test_fp32_trig_range_is_checked(ctx):
+    """FP32 paths evaluate the trig terms with the hardware sine, whose input
+    must stay within +-256 revolutions: a problem whose k x + phase exceeds
+    that over the domain is refused for FP32 paths (PDD_E_UNSUPPORTED) and
+    solved in FP64; one just inside the range runs in both."""
+    base = W.unit_square_problem(seed=0)
+    nodes = W.unit_square_nodes()[:2]
+    # k x over [0, 1]: 2 pi * 300 revolutions at x = 1
+    far = dict(base, trig=[{"amp": 1e-3, "k": [2 * np.pi * 300.0, np.pi], "phase": [0.0, 0.0]}])
+    near = dict(base, trig=[{"amp": 1e-3, "k": [2 * np.pi * 200.0, np.pi], "phase": [0.0, 0.0]}])
+    p = pdd.Problem(ctx, far)
+    with pytest.raises(pdd.PDDError) as e:
+        pdd.solve_nodes(p, nodes, dt=1e-3, n_paths=64, precision="fp32")
+    assert e.value.status == -4 and "revolutions" in str(e.value)
+    st = pdd.stats_to_numpy(pdd.solve_nodes(p, nodes, dt=1e-3, n_paths=64, precision="fp64"))
+    assert np.all(st["n"] == 64)
+    p.close()
+    p = pdd.Problem(ctx, near)
+    for prec in ("fp32", "fp64"):
+        st = pdd.stats_to_numpy(pdd.solve_nodes(p, nodes, dt=1e-3, n_paths=64, precision=prec))
+        assert np.all(st["n"] == 64)
+    p.close()

@@ -129,3 +129,94 @@ def test_invalid_requests(ctx, stream):
     sv.close()
     with pytest.raises(pdd.PDDError):
         pdd.Server(ctx, epoch_paths=1 << 30)
+
+
+def test_served_requests_match_oracle(ctx):
+    """FP64 requests of four kinds (plain and correction estimator, 2D and
+    3D) served together, in many small chunks: for every node the oracle walks
+    paths 0 .. n_i - 1 of the request's RNG stream at its step (n_i = the
+    paths the server planned for that node, Sec. 3.1 eq. F:N_y_h), and the
+    served statistics match it: exit-step sums exactly, node means to 1e-10
+    relative (for the correction estimator u_prev(x0) + mean(e))."""
+    import math
+
+    from oracle import oracle as O
+    from test_gpu_parity import geometry_case
+    sq = W.unit_square_problem(seed=21)
+    box, box_nodes = geometry_case("box3d")
+    g2 = W.correction_grids(sq, n=65, seed=3, dtype=np.float64)[:2]
+    g3 = W.correction_grids(box, n=(9, 13, 11), seed=2, dtype=np.float64)[:2]
+    # standard-error targets: the correction requests' are below what 1,500
+    # paths reach, so their plan is capped at n_max
+    reqs = [(sq, W.unit_square_nodes()[::4], None, 0.03, 11),
+            (sq, W.unit_square_nodes()[1::5], g2, 1e-5, 12),
+            (box, box_nodes, None, 0.01, 13),
+            (box, box_nodes[::-1], g3, 1e-5, 14)]
+    probs = {id(sq): pdd.Problem(ctx, sq), id(box): pdd.Problem(ctx, box)}
+    sv = pdd.Server(ctx, n_pilot=128, n_max=1500, chunk_paths=1 << 10, epoch_paths=1 << 16)
+    ids = []
+    for pd, nodes, grids, se, stream_id in reqs:
+        kw = {}
+        if grids is not None:
+            gu, gr = grids
+            kw = dict(u_prev=gu, u_prev_t=torch.as_tensor(gu["data"]).cuda().contiguous(),
+                      resid=gr, resid_t=torch.as_tensor(gr["data"]).cuda().contiguous())
+        ids.append(sv.submit(probs[id(pd)], nodes, 1e-3, se, precision="fp64", stream_id=stream_id, **kw))
+    assert sv.wait_all(120)
+    rep = sv.report()
+    assert rep["completed"] == 4 and rep["censored"] == 0 and rep["p99_censored"] == 0
+    beyond = 0
+    for rid, (pd, nodes, grids, se, stream_id) in zip(ids, reqs):
+        c = sv.results[rid]
+        assert c["status"] == 0
+        st = c["stats"]
+        beyond += int(np.all(st["n"] > 128))  # planned beyond the pilot: continuation chunks
+        print(f"request {stream_id}: paths per node {st['n'].tolist()}", flush=True)
+        for i, x in enumerate(nodes):
+            n_i = int(st["n"][i])
+            kw = {} if grids is None else dict(u_prev=grids[0], resid=grids[1])
+            rec = O.run_paths(pd, nodes, np.full(n_i, i), np.arange(n_i), h=1e-3, stream=stream_id, **kw)
+            assert int(st["steps_sum"][i]) == int(rec["steps"].astype(np.int64).sum()), (stream_id, i)
+            if grids is None:
+                want = math.fsum(rec["phi"]) / n_i
+            else:
+                want = float(O.interp(grids[0], [x])[0]) + math.fsum(rec["e"]) / n_i
+            assert abs(st["mean"][i] - want) <= 1e-10 * max(1.0, abs(want)), (stream_id, i, st["mean"][i], want)
+    assert beyond == 4
+    sv.close()
+    for p in probs.values():
+        p.close()
+
+
+def test_cancelled_requests_are_censored_in_percentiles(ctx, stream):
+    """Requests still running or queued count in p50 / p99 at their age (a
+    lower bound), and the report says so; cancellations are counted apart
+    from failures."""
+    _, reqs, fx = stream
+    sv = pdd.Server(ctx, **SMALL, max_inflight=1)
+    for r in reqs[:8]:
+        fx.submit(sv, r)
+    rep = sv.report()  # at once: nothing can have finished yet but the first pilot
+    assert rep["censored"] + rep["completed"] == 8
+    assert rep["censored"] >= 1 and rep["p99_censored"] == 1 and rep["p99_ms"] > 0
+    sv.close()
+    assert rep["failed"] == 0
+
+
+def test_tuning_launch_cap_does_not_change_served_results(ctx, stream):
+    """A context tuning entry that caps the paths per launch (max_launch_paths)
+    does not reach the server's epochs: each group of an epoch stays one
+    launch, so a request's statistics are still bitwise those it gets alone."""
+    problems, reqs, fx = stream
+    sub = reqs[:10]
+    keys = [(p, d, e, g) for p in ("fp32", "fp64") for d in (2, 3) for e in (0, 1) for g in (False, True)]
+    for p, d, e, g in keys:
+        pdd.set_tuning(ctx, p, d, e, (256, 0, 64, 3000), generic=g)
+    try:
+        _, done = S.run_stream(ctx, problems, sub, drain_s=120, server_opts=SMALL, fixtures=fx)
+        for r in sub[:3]:
+            alone = _alone(ctx, fx, r, SMALL)
+            assert alone["stats"].tobytes() == done[r["stream_id"]]["stats"].tobytes()
+    finally:
+        for p, d, e, g in keys:
+            pdd.set_tuning(ctx, p, d, e, None, generic=g)
