@@ -4,17 +4,18 @@
 Workload: (1/2) Lap u + b.grad u + c u = f on [0, 4]^2 with b = (0.5 x, -0.3 y),
 c = -(1 + x^2 + y^2), u = sin(pi x) cos(pi y) + x^2 y; 1,792 interface nodes
 of an 8 x 8 partition; h = 1e-4; bridge exit test; FP32 path arithmetic with
-FP64 integrals and sums; 10^6 paths per node in total. One benchmark step is
-one solve call over every node with the next block of `--paths-per-step` paths
-(path_offset = step * paths), so 16 steps of 62,500 paths are the whole job.
+FP64 integrals and sums. One benchmark step is one solve call over every
+node with the next block of `--paths-per-step` paths (path_offset = step *
+paths): 62,500 paths per node per step, 16 steps make 10^6 per node.
 
 Prints one JSON line: path-steps/s over the timed steps (inputs resident on
 the device, timed with HIP events on the solve's stream), the roofline of the
-path kernel (VALU-issue bound; the per-step operation count is STEP_COST
-below), node-solves/s at a fixed RMS error for the correction estimator in
+path kernel (VALU-issue bound; the per-step work is STEP_OPS weighted by
+CLASS_SLOTS below), node-solves/s at a fixed RMS error for the correction estimator in
 FP32 and the plain estimator in FP64, the correction iterates, a batched
-solve, two serving runs (overload and a sustainable load), and the CPU
-oracle timed on a bounded sample of the same workload.
+solve, the serving loop (200 requests/s and a sweep of lower rates), the
+FP64 variant of the workload, and the CPU oracle timed on a bounded sample of
+the same workload (one core, and every core of the host share).
 """
 from __future__ import annotations
 
@@ -31,26 +32,43 @@ sys.path.insert(0, ROOT)
 H = 1e-4
 SEED = 0
 
-# Algorithmic VALU cost of one 2D path step of this workload, in full-rate
-# FP32 lane slots; transcendentals (log2, sqrt, sin, cos, exp2) and 32x32-bit
-# multiplies issue at a quarter of the FP32 rate and count 4, an FP64 add 2.
-# Derived from the operations the step must perform, not from the compiled
-# code.
-STEP_COST = {
-    "philox_half_block": (10 * 2 * 4 + 10 * 2) // 2,  # 10 rounds x (2 wide mul + 2 xor3); 2 steps/block
-    "uniforms": 2 * 2,                                # convert + fma per word
-    "box_muller": 4 * 4 + 5,                          # log2, sqrt, sin, cos; scale, 2 mul
-    "drift_killing": 4 + 3,                           # b = b0 + B x; c = c_a + c_b |x|^2
-    "poly_source": 20,                                # degree-5 Horner form of the polynomial part of f
-    "trig_source": 2 + 4 * 4 + 8,                     # 2 arguments, sin/cos x 2, combination
-    "euler_step": 9 + 2,                              # hY, Z (FP64 add), Y, X
-    "exit_test": 12,                                  # distance to the box, exit, bridge bound
+# Algorithmic VALU work of one 2D path step of this workload (plain
+# estimator, bridge exit, one trig term and the polynomial y - 0.3 x^2 y -
+# x^4 y - x^2 y^3 in f), counted from the operations the step must perform
+# (not from the compiled code), by instruction class.
+STEP_OPS = {
+    # class: count per path-step
+    "single": 10 + 2 + 1 + 1 + 3 + 3,  # Philox 32x32->64 products (10 per half block), 2 word->float
+                                       # conversions, FP64 Z update (convert + add), box distance (3 min),
+                                       # exit / bridge / step-cap compares
+    "xor3": 10,                        # Philox three-way XORs (10 per half block)
+    "fma": 2 + 4 + 3 + 1 + 6 + 1 + 4,  # uniform scaling, b = b0 + B x, c = c_a + c_b |x|^2, f polynomial,
+                                       # f trig term (arguments, combination), Y, X
+    "simple": 3 + 5 + 5 + 2 + 4 + 2,   # Box-Muller scale and products, f polynomial, trig products,
+                                       # h Y and h Y f, four face distances, bridge bound
+    "trans": 8,                        # Box-Muller log2, sqrt, sin, cos; sin, cos of the two trig arguments
 }
-OPS_PER_STEP = sum(STEP_COST.values())
-# FP32 FLOPs of the same step (FMA = 2; transcendentals not counted)
-FLOPS_PER_STEP = 4 + 3 + 8 + 5 + 40 + 16 + 12 + 7
-# 256 CUs x 128 FP32 lanes x 2.4 GHz: the 157.3 TFLOP/s FP32 vector peak / 2
-VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Issue cost of each class in dual-issue slots (one slot = one lane-operation
+# at 128 lane-operations per compute-unit clock), from the sustained issue rate
+# of each class alone measured on gfx950 (profiles/valu_issue_rates_gfx950.md,
+# `bench.py --issue-rates`): 128 / lane-operations per CU clock.
+CLASS_SLOTS = {
+    "single": 128 / 62.6,  # v_mad_u64_u32, v_cvt_f32_u32, v_add_f64, v_max_i32: no dual issue
+    "xor3": 128 / 68.9,    # v_bitop3_b32: pairs with FP32 FMAs, not with itself
+    "fma": 128 / 69.3,     # v_fma_f32 / v_fmac_f32: pairs with v_bitop3_b32, not with itself
+    "simple": 128 / 117.2,  # v_mul_f32, v_add_u32, v_xor_b32, v_mov_b32: dual issue
+    "trans": 128 / 31.5,   # v_exp/log/sin/sqrt_f32: half the single-issue rate
+}
+OPS_PER_STEP = sum(STEP_OPS[k] * CLASS_SLOTS[k] for k in STEP_OPS)
+# FP32 FLOPs of the same step (FMA = 2; simple arithmetic 1; transcendentals,
+# integer work and compares not counted)
+FLOPS_PER_STEP = 2 * STEP_OPS["fma"] + STEP_OPS["simple"] + 3
+# Peak VALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2 instructions
+# per cycle (each SIMD issues up to two VALU instructions per cycle; the
+# SQ_ACTIVE_INST_VALU2 counter counts such cycles) x 2.4 GHz = 78.6 T
+# lane-operations/s, the 157.3 TFLOP/s FP32 vector figure / 2. Measured: a
+# v_mul_f32 stream sustains 117.2 of the 128 lane-operations per CU clock.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -107,6 +125,11 @@ def parse():
                          "as long at 10 requests/s (0 = skip)")
     ap.add_argument("--serve-drain", type=float, default=10.0,
                     help="seconds to wait for completions after the last arrival")
+    ap.add_argument("--serve-sweep", type=int, default=1,
+                    help="1: also serve the same request mix at 0.5, 1, 2, 5 and 20 requests/s (0 = skip)")
+    ap.add_argument("--fp64-paths", type=int, default=4096,
+                    help="paths per node of the FP64 variant of the throughput workload, with the FP32 "
+                         "paths of the same pairs beside it (0 = skip)")
     ap.add_argument("--tuning", default="cache",
                     help="launch shape block,blocks_per_cu,grab of the path kernel, 'cache' (the "
                          "autotuner's cached shape for this GPU, else the default) or 'default'")
@@ -127,23 +150,86 @@ def parse():
     ap.add_argument("--profile-paper", type=int, default=0,
                     help="only run the paper's example PDE (513^2 FP32 tabulated grids, h=1e-3) with this "
                          "many paths per node three times and print its timing (for profilers)")
+    ap.add_argument("--profile-plain64", type=int, default=0,
+                    help="only run the plain FP64 solve of the node-solve measurement (unit square, h=1e-4, "
+                         "--profile-replicas copies of the 18 nodes with distinct streams, this many paths per "
+                         "node) three times and print its timing (for profilers)")
+    ap.add_argument("--profile-batch", type=float, default=0.0,
+                    help="only run the 64-problem batched solve at this path-count scale and print its timing "
+                         "(for profilers)")
     ap.add_argument("--profile-replicas", type=int, default=1,
                     help="with --profile-correction: that many 18-node solves (distinct streams) in one batch")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the VALU issue rate of each instruction class the path kernel "
+                         "uses (libpdd_probe.so) and print them as one JSON line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch measured with rocprofv3 counters")
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_cores() -> int:
+    """Cores this process may use, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_paths(args):
+    """Oracle walk of an explicit list of (node, path) pairs (a worker of the
+    aggregate CPU baseline); returns the path-steps walked."""
+    ni, pj = args
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1512_02818_amd import workloads as W
+    rec = O.run_paths(W.big_square_problem(seed=SEED), W.big_square_nodes(), ni, pj, h=H)
+    return int(np.sum(rec["steps"]))
+
+
 def cpu_baseline(pd, nodes, n_paths):
+    """The oracle on a bounded sample of the workload: paths 0..n_paths-1 of
+    every node on one core, and paths n_paths..5 n_paths-1 on every core of
+    the host share at once (one process per core, disjoint (node, path)
+    pairs)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
     from oracle import oracle as O
     t0 = time.perf_counter()
     _, rec = O.solve_nodes(pd, nodes, record=True, h=H, n_paths=n_paths)
     dt = time.perf_counter() - t0
     steps = int(rec["steps"].sum())
+    procs = host_cores()
+    ni = np.repeat(np.arange(len(nodes), dtype=np.uint32), 4 * n_paths)
+    pj = np.tile(np.arange(n_paths, 5 * n_paths, dtype=np.uint64), len(nodes))
+    order = np.random.default_rng(0).permutation(len(ni))  # spread long and short nodes over the workers
+    jobs = [(ni[c], pj[c]) for c in np.array_split(order, 4 * procs)]
+    t1 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        agg_steps = sum(pool.map(_oracle_paths, jobs))
+    agg_dt = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(nodes)} nodes x paths 0..{n_paths - 1} of the same workload, "
                       f"FP64, single thread: {steps} path-steps in {dt:.1f} s",
-            "host": platform.processor() or platform.machine()}
+            "cpu_model": cpu_model(),
+            "aggregate": {"value": agg_steps / agg_dt, "unit": "path-steps/s", "cores": procs,
+                          "sample": f"{len(nodes)} nodes x paths {n_paths}..{5 * n_paths - 1}, "
+                                    f"{procs} oracle processes on disjoint (node, path) pairs: "
+                                    f"{agg_steps} path-steps in {agg_dt:.1f} s"}}
 
 
 DT_LADDER = (1e-3, 5e-4, 2.5e-4, 1e-4)
@@ -436,6 +522,77 @@ def batch_solve(ctx, scale):
             "median_abs_z_vs_exact": float(np.median(z))}
 
 
+def fp64_variant(ctx, prob, nodes, paths):
+    """The throughput workload with FP64 path arithmetic, and the FP32 paths
+    of the same (node, path) pairs beside it: FP64 path-steps/s, and per node
+    the bias of the FP32 mean against the FP64 mean of the same paths in units
+    of the FP64 standard error (the FP32 path arithmetic of this library
+    against FP64 path arithmetic)."""
+    import numpy as np
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    off = 1 << 30  # a path range no other measurement uses
+    res = {}
+    for prec in ("fp64", "fp32"):
+        pdd.solve_nodes(prob, nodes[:64], dt=H, n_paths=64, path_offset=off, precision=prec)  # warm-up
+        torch.cuda.synchronize()
+        pdd.kernel_times(ctx)
+        st = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=H, n_paths=paths, path_offset=off,
+                                                precision=prec, time_kernel=True))
+        ms = pdd.kernel_times(ctx)
+        res[prec] = (st, float(sum(ms)))
+    s64, ms64 = res["fp64"]
+    s32, ms32 = res["fp32"]
+    bias = s32["mean"] - s64["mean"]
+    z = np.abs(bias) / s64["stderr"]
+    steps64 = int(s64["steps_sum"].sum())
+    return {"workload": f"[0,4]^2, 1,792 nodes x {paths} paths (path offset 2^30), h=1e-4, bridge exit",
+            "fp64_path_steps_per_s": steps64 / (ms64 / 1e3), "fp64_kernel_ms": ms64,
+            "fp32_path_steps_per_s_same_paths": int(s32["steps_sum"].sum()) / (ms32 / 1e3),
+            "fp32_over_fp64": (int(s32["steps_sum"].sum()) / ms32) / (steps64 / ms64),
+            "per_node_bias_fp32_vs_fp64": {
+                "max_abs": float(np.max(np.abs(bias))), "median_abs": float(np.median(np.abs(bias))),
+                "rms": float(np.sqrt(np.mean(bias ** 2))),
+                "max_abs_over_se": float(np.max(z)), "median_abs_over_se": float(np.median(z)),
+                "median_se": float(np.median(s64["stderr"])),
+                "nodes_within_3se_plus_1e-5": int(np.sum(np.abs(bias) <= 3 * s64["stderr"] + 1e-5)),
+                "nodes": int(len(nodes))}}
+
+
+SWEEP_RATES = (0.5, 1.0, 2.0, 5.0, 20.0)
+
+
+def serving_sweep(ctx, drain_s):
+    """The serving loop at offered loads below the 200 requests/s of the main
+    serving run (same request mix, seeded Poisson arrivals, about 12 requests
+    per rate, at least 2 s and at most 12 s of arrivals): completed, cancelled
+    and latency percentiles per rate; the knee is the highest rate at which
+    every request completed within the drain."""
+    from paper_1512_02818_amd import serving
+    from paper_1512_02818_amd import workloads as W
+    out = []
+    for q, rate in enumerate(SWEEP_RATES):
+        dur = min(12.0, max(2.0, 12.0 / rate))
+        problems, reqs = W.serving_stream(seed=20 + q, rate=rate, duration=dur)
+        if not reqs:
+            continue
+        rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=drain_s,
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
+        out.append({"rate_per_s": rate, "arrival_window_s": dur, "offered": len(reqs),
+                    "completed": rep["completed"], "cancelled": rep["cancelled"],
+                    "p50_ms": rep["p50_ms"], "p99_ms": rep["p99_ms"], "p50_censored": rep["p50_censored"],
+                    "p99_censored": rep["p99_censored"], "p99_done_ms": rep["p99_done_ms"],
+                    "node_solves_per_s": rep["node_solves_per_s"], "drain_s": rep["drain_s"]})
+        print(f"serving at {rate:g} requests/s: {rep['completed']} of {len(reqs)} completed, "
+              f"p50 {rep['p50_ms']:.0f} ms, p99 {'>= ' if rep['p99_censored'] else ''}{rep['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+    knee = max([r["rate_per_s"] for r in out if r["cancelled"] == 0 and r["completed"] == r["offered"]],
+               default=None)
+    return {"workload": "the request mix of 'serving' at lower Poisson rates (seeds 20..), drain "
+                        f"{drain_s:g} s", "rates": out, "knee_rate_per_s": knee}
+
+
 def calibration_copy(mib):
     """One plain device copy of `mib` MiB: its HBM byte counters give the
     scale of a profiler's FETCH_SIZE / WRITE_SIZE readings."""
@@ -524,8 +681,95 @@ def profile_paper(paths, calibrate_mib=0):
     ctx.close()
 
 
+def issue_rates(blocks_per_cu=8, target_ms=40.0):
+    """Sustained issue rate of each VALU instruction class of the path kernel
+    on its own (libpdd_probe.so: 8 independent chains per lane, 8 waves per
+    SIMD), in lane-operations per second and per compute-unit clock at the
+    clock the chip ran at (shader-clock counter over the constant wall clock,
+    read by the probe around its loop)."""
+    import ctypes as C
+
+    import torch
+    from paper_1512_02818_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        raise RuntimeError(f"{B.PROBE_LIB} is missing: run `python -m paper_1512_02818_amd.build`")
+    torch.cuda.init()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    L = C.CDLL(B.PROBE_LIB)
+    L.probe_kind_name.restype = C.c_char_p
+    L.probe_issue_rate.argtypes = [C.c_int, C.c_int, C.c_uint32] + [C.POINTER(C.c_double)] * 4
+    rows = []
+    for kind in range(L.probe_kinds()):
+        ms, ops, cyc, wall = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        iters = 64
+        for _ in range(2):  # size the loop to about target_ms
+            rc = L.probe_issue_rate(kind, blocks_per_cu, iters, C.byref(ms), C.byref(ops), C.byref(cyc),
+                                    C.byref(wall))
+            if rc != 0:
+                raise RuntimeError(f"probe {kind} failed with HIP error {rc}")
+            iters = max(64, int(iters * target_ms / max(ms.value, 1e-3)))
+        ghz = cyc.value / wall.value
+        rate = ops.value / (ms.value / 1e3)
+        rows.append({"instruction": L.probe_kind_name(kind).decode(), "ms": ms.value, "lane_ops": ops.value,
+                     "lane_ops_per_s": rate, "clock_ghz": ghz,
+                     "lane_ops_per_cu_clock": rate / (n_cu * ghz * 1e9)})
+        print(f"{rows[-1]['instruction']:>14}: {rate / 1e12:7.2f} T lane-ops/s, "
+              f"{rows[-1]['lane_ops_per_cu_clock']:6.1f} per CU-clock at {ghz:.3f} GHz", file=sys.stderr, flush=True)
+    print(json.dumps({"issue_rates": rows, "n_cu": n_cu, "blocks_per_cu": blocks_per_cu,
+                      "waves_per_simd": blocks_per_cu * 4 // 4}), flush=True)
+
+
+def profile_plain64(paths, replicas, calibrate_mib=0):
+    """The plain FP64 solve of the node-solve measurement alone (unit square,
+    h = 1e-4, `replicas` copies of the 18 nodes with distinct RNG streams in
+    one batch), three times, for kernel-trace and counter runs."""
+    from paper_1512_02818_amd import pdd, tuning
+    from paper_1512_02818_amd import workloads as W
+    ctx = pdd.Context(0)
+    tuning.load(ctx)
+    prob = pdd.Problem(ctx, W.unit_square_problem(seed=SEED))
+    nodes = W.unit_square_nodes()
+    nstat = pdd.STATS_DTYPE.itemsize
+    out = pdd.alloc_stats(replicas * len(nodes))
+    if calibrate_mib > 0:
+        calibration_copy(calibrate_mib)
+    steps = 0
+    for r in range(3):
+        pdd.solve_batch(ctx, [{"problem": prob, "nodes": nodes,
+                               "out": out[q * len(nodes) * nstat:(q + 1) * len(nodes) * nstat],
+                               "opts": dict(dt=1e-4, n_paths=paths, path_offset=r * paths, precision="fp64",
+                                            stream_id=16 + q, time_kernel=q == 0)} for q in range(replicas)])
+        steps += int(pdd.stats_to_numpy(out)["steps_sum"].sum())
+    ms = pdd.kernel_times(ctx)
+    print(json.dumps({"plain64_profile": {"paths_per_node": paths, "nodes": len(nodes), "replicas": replicas,
+                                          "path_steps": steps, "kernel_ms": ms,
+                                          "path_steps_per_s": steps / (sum(ms) / 1e3)}}), flush=True)
+    prob.close()
+    ctx.close()
+
+
+def profile_batch(scale):
+    """The 64-problem batched solve alone at path-count scale `scale`, for
+    kernel-trace and counter runs."""
+    from paper_1512_02818_amd import pdd
+    ctx = pdd.Context(0)
+    b = batch_solve(ctx, scale)
+    b.pop("dims")
+    print(json.dumps({"batch_profile": b}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.issue_rates:
+        issue_rates()
+        return
+    if args.profile_plain64 > 0:
+        profile_plain64(args.profile_plain64, args.profile_replicas, args.calibrate_copy_mib)
+        return
+    if args.profile_batch > 0:
+        profile_batch(args.profile_batch)
+        return
     if args.profile_paper > 0:
         profile_paper(args.profile_paper, args.calibrate_copy_mib)
         return
@@ -547,6 +791,13 @@ def main():
     pd = W.big_square_problem(seed=SEED)
     nodes = W.big_square_nodes()
     P = args.paths_per_step
+    cpu = None
+    if args.cpu_paths > 0:
+        # before anything touches the GPU: the aggregate's worker processes are forked
+        print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(pd, nodes, args.cpu_paths)
+        print(f"oracle: {cpu['value']:.3e} path-steps/s on one core, {cpu['aggregate']['value']:.3e} on "
+              f"{cpu['aggregate']['cores']} cores ({cpu['cpu_model']})", file=sys.stderr, flush=True)
     ctx = pdd.Context(0)
     from paper_1512_02818_amd import tuning
     shape = None
@@ -587,6 +838,7 @@ def main():
     value = total_steps / (elapsed_ms / 1e3)
     avg_kern_s = float(np.mean(kern_ms)) / 1e3
     achieved = OPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12
+    fp32_tflops = FLOPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12
     traffic = stored_traffic(args.traffic_json, args.precision, P)
     exact = W.manufactured_u(pd, nodes)
     z = np.abs(timed[-1]["mean"] - exact) / timed[-1]["stderr"]
@@ -608,19 +860,26 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "[0,4]^2 first-stage nodal solve: 1,792 interface nodes, "
-                               f"{P} paths per node per step (10^6 per node over "
-                               f"{1_000_000 // P} steps), h=1e-4, bridge exit, "
+                               f"{P} paths per node per step (step s walks paths s*{P} .. "
+                               f"(s+1)*{P}-1 of every node, warmup steps first), h=1e-4, bridge exit, "
                                f"{args.precision} paths, fp64 sums",
                    "nodes": int(len(nodes)), "paths_per_step": P, "dt": H, "tuning": args.tuning,
                    "mean_steps_per_path": total_steps / (args.steps * len(nodes) * P)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "Top/s (FP32 VALU lane slots)",
+                     "unit": "T VALU issue slots/s (lane-operations at the dual-issue rate)",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                     "ops_per_step": OPS_PER_STEP,
+                     "slots_per_step": OPS_PER_STEP, "ops_per_step": STEP_OPS,
                      "kernel_ms_per_launch": float(np.mean(kern_ms)),
-                     "fp32_tflops": FLOPS_PER_STEP * float(np.mean(steps_per_launch)) / avg_kern_s / 1e12,
-                     "fp32_peak_tflops": FP32_PEAK_TFLOPS},
+                     "fp32_tflops": fp32_tflops, "fp32_peak_tflops": FP32_PEAK_TFLOPS,
+                     "fp32_flop_frac": fp32_tflops / FP32_PEAK_TFLOPS,
+                     "fp32_flop_frac_target_met": fp32_tflops / FP32_PEAK_TFLOPS >= 0.5},
     }
+    if args.fp64_paths > 0:
+        print("FP64 variant of the throughput workload ...", file=sys.stderr, flush=True)
+        result["fp64_variant"] = fp64_variant(ctx, prob, nodes, args.fp64_paths)
+        fv = result["fp64_variant"]
+        print(f"fp64: {fv['fp64_path_steps_per_s']:.3e} path-steps/s; fp32 vs fp64 per node: max |bias|/SE "
+              f"{fv['per_node_bias_fp32_vs_fp64']['max_abs_over_se']:.3f}", file=sys.stderr, flush=True)
     if args.rms_tol > 0:
         print("node solves at fixed RMS error ...", file=sys.stderr, flush=True)
         result["node_solves_at_rms"] = node_solves_at_rms(ctx, args.rms_tol, args.rms_replicas_plain,
@@ -656,18 +915,13 @@ def main():
                            "(129^2-513^2 or 65^3), FP32, 64 GiB budget; requests still running after "
                            "the drain are cancelled and reported")
         result["serving"] = rep
-        # the same kind of stream at a load one GPU sustains: latency without a backlog
-        problems, reqs = W.serving_stream(seed=6, rate=10.0, duration=2 * args.serve_duration)
-        rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=args.serve_drain,
-                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
-        rep["workload"] = ("the same request mix as 'serving' (seed 6), Poisson 10 requests/s for "
-                           f"{2 * args.serve_duration:g} s")
-        result["serving_light"] = rep
-        print(f"serving at 10 requests/s: {rep['completed']} of {rep['offered_requests']} completed, "
-              f"p50 {rep['p50_ms']:.0f} ms, p99 {rep['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
-    if args.cpu_paths > 0:
-        print("timing the CPU oracle sample ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(pd, nodes, args.cpu_paths)
+        print(f"serving at 200 requests/s: {rep['completed']} of {rep['offered_requests']} completed, "
+              f"p50 {rep['p50_ms']:.0f} ms, p99 {'>= ' if rep['p99_censored'] else ''}{rep['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+        if args.serve_sweep:
+            result["serving_sweep"] = serving_sweep(ctx, args.serve_drain)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
     prob.close()
     ctx.close()

@@ -31,8 +31,29 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+PROBE_LIB = os.path.join(HERE, "libpdd_probe.so")
+PROBE_SOURCES = ["issue_probe.hip"]
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the VALU issue-rate probe (the benchmark's --issue-rates mode)
+    into its own library, libpdd_probe.so."""
+    srcs = [os.path.join(HERE, "csrc", s) for s in PROBE_SOURCES]
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc()] + FLAGS + srcs + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed (probe)")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libpdd.so (always recompiles)."""
+    """Compile every HIP source into libpdd.so (always recompiles), and the
+    issue-rate probe into libpdd_probe.so."""
     srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + FLAGS + srcs + ["-o", tmp]
@@ -48,6 +69,7 @@ def build(verbose: bool = False) -> str:
     if verbose and noise:
         print("\n".join(noise))
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 
