@@ -397,6 +397,43 @@ pdd_status pdd_grid_gradient(pdd_ctx *ctx, const pdd_grid *u, void *const *grad,
  * malformed grid, n_d < 4; PDD_E_HIP on a launch failure. */
 pdd_status pdd_grid_residual(pdd_problem *problem, const pdd_grid *u, void *resid, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Second stage of PDD (Sec. 1; Alg. A:IterPDD, the subdomain-BVP step) on a
+ * 2D box cut into subdomains by axis-parallel interfaces: the nodal values
+ * are interpolated along every interface line and every subdomain is solved,
+ * giving the global approximation u~ = (+)_k v_k on a grid.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n[2];          /* grid points per axis over the problem's box (>= 3): u~'s grid */
+    int32_t n_cuts[2];     /* interfaces x_0 = c (axis 0) and x_1 = c (axis 1) */
+    const double *cuts[2]; /* host: their coordinates; each on an interior grid line */
+    double rbf_eps;        /* shape parameter of the multiquadric sqrt(1 + (eps r)^2), > 0 */
+} pdd_partition;
+
+/* u~ on the n[0] x n[1] grid over the box (device, FP64, x fastest; written
+ * whole). The physical boundary gets the problem's g. Every interface line
+ * gets the multiquadric interpolant R (Def. D:Linear_interpolator; the
+ * paper's experiment, Sec. 6, uses multiquadric RBFs) of the data on it: the
+ * values of the nodes lying on the line and g at the line's two ends on the
+ * boundary (s(t) = sum_m lam_m sqrt(1 + (eps (t - t_m))^2), lam from
+ * s(t_m) = z_m); where an axis-0 and an axis-1 line cross, the mean of the two.
+ * Every subdomain (the grid box between consecutive interfaces) is then solved
+ * for (1/2) sigma^2 Lap v + b.grad v + c v = f with the values on its
+ * boundary, by second-order finite differences on the grid (central second
+ * and first differences, b, c, f of the problem in FP64) and a banded LU
+ * factorisation without pivoting, one workgroup per subdomain. `nodes` (host,
+ * n_nodes x 2) are the interface nodes and `values` (host) their nodal
+ * values; a node may lie on several lines. Synchronous (the interpolation
+ * weights are solved on the host once the boundary values are on the
+ * device); u is complete when the call returns. Errors: PDD_E_INVALID for
+ * NULL pointers, a bad grid or shape parameter, an interface off the grid
+ * lines or given twice, a node off every interface or outside the box, a
+ * singular interpolation system; PDD_E_UNSUPPORTED for a problem that is not
+ * a 2D box or a subdomain whose shorter side has more than 64 interior
+ * points; PDD_E_NOMEM / PDD_E_HIP from the device. */
+pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const double *nodes, const double *values,
+                      int64_t n_nodes, double *u, void *stream);
+
 /* Key of the context's launch-shape table: the path kernel a group of
  * items runs. `generic` selects between the kernel compiled for a box domain
  * with the bridge exit test, Gaussian increments and analytic coefficients

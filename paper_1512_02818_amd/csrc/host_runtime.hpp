@@ -93,6 +93,7 @@ struct pdd_ctx {
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
     bool any_done = false, any_staged = false;
     pdd::DeviceBuffer nodes, starts, acc, counters, rec, partials, gather, cells;
+    pdd::DeviceBuffer stage2;  // second stage: tables, stencils and LU factors
     void *stage = nullptr;
     size_t stage_cap = 0;
     void *readback = nullptr;  // pinned host copy of pilot statistics

@@ -1141,6 +1141,228 @@ __global__ void __launch_bounds__(256) grid_residual_kernel(const DevProblem<dou
     }
 }
 
+// Second stage (the subdomain-BVP step of Alg. A:IterPDD) on a 2D box cut by
+// axis-parallel interfaces. Grid coordinates are lo + span i / (n - 1), as
+// everywhere the grids are sampled.
+__device__ __forceinline__ double stage2_coord(double lo, double span, int n, int i)
+{
+    return lo + span * (double)i / (double)(n - 1);
+}
+
+// g at every point of the box's edges.
+__global__ void __launch_bounds__(256) stage2_boundary_kernel(const DevProblem<double> P, const Stage2Grid g)
+{
+    const int n0 = g.n0, n1 = g.n1;
+    const int total = 2 * n0 + 2 * (n1 - 2);
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        int i, j;
+        if (q < n0) {
+            i = q, j = 0;
+        } else if (q < 2 * n0) {
+            i = q - n0, j = n1 - 1;
+        } else {
+            const int r = q - 2 * n0;
+            i = (r & 1) ? n0 - 1 : 0;
+            j = 1 + (r >> 1);
+        }
+        const double x[2] = {stage2_coord(g.lo0, g.span0, n0, i), stage2_coord(g.lo1, g.span1, n1, j)};
+        g.u[(size_t)j * n0 + i] = boundary_value<double, 2>(P, x, P.tab);
+    }
+}
+
+__device__ __forceinline__ double multiquadric(const double *t, const double *lam, int m, double eps, double x)
+{
+    double acc = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const double e = eps * (x - t[q]);
+        acc += lam[q] * sqrt(1.0 + e * e);
+    }
+    return acc;
+}
+
+// One workgroup row per line (blockIdx.y); the points of the line strictly
+// between the box's edges.
+__global__ void __launch_bounds__(256) stage2_lines_kernel(const Stage2Grid g, const Stage2Line *lines, int32_t n_lines,
+                                                           const double *t, const double *lam)
+{
+    const Stage2Line L = lines[blockIdx.y];
+    const int ne = L.d == 0 ? g.n1 : g.n0;  // points along the line
+    for (int p = 1 + blockIdx.x * blockDim.x + threadIdx.x; p < ne - 1; p += gridDim.x * blockDim.x) {
+        const double tp = L.d == 0 ? stage2_coord(g.lo1, g.span1, g.n1, p) : stage2_coord(g.lo0, g.span0, g.n0, p);
+        // a line of the other axis through this point
+        int cross = -1;
+        for (int q = 0; q < n_lines; ++q)
+            if (lines[q].d != L.d && lines[q].k == p) cross = q;
+        if (cross >= 0 && L.d == 1) continue;  // the crossing axis-0 line writes the point
+        double v = multiquadric(t + L.at, lam + L.at, L.m, L.eps, tp);
+        if (cross >= 0) {
+            const Stage2Line C = lines[cross];
+            const double tc = stage2_coord(g.lo0, g.span0, g.n0, L.k);
+            v = 0.5 * (v + multiquadric(t + C.at, lam + C.at, C.m, C.eps, tc));
+        }
+        const size_t at = L.d == 0 ? (size_t)p * g.n0 + L.k : (size_t)L.k * g.n0 + p;
+        g.u[at] = v;
+    }
+}
+
+// Grid point of unknown r of a subdomain.
+__device__ __forceinline__ void stage2_point(const SubBox &b, uint64_t r, int &i, int &j)
+{
+    const int s = (int)(r / (uint64_t)b.w), f = (int)(r % (uint64_t)b.w);
+    if (b.fast_x) {
+        i = b.i0 + 1 + f;
+        j = b.j0 + 1 + s;
+    } else {
+        i = b.i0 + 1 + s;
+        j = b.j0 + 1 + f;
+    }
+}
+
+// Stencil of every unknown: (1/2) sigma^2 Lap v + b.grad v + c v = f by
+// second-order differences; neighbours on the subdomain's boundary move to
+// the right side with their grid values. Slots: 0 slow-1, 1 fast-1,
+// 2 centre, 3 fast+1, 4 slow+1, 5 right side.
+__global__ void __launch_bounds__(256) stage2_stencil_kernel(const DevProblem<double> P, const Stage2Grid g,
+                                                             const SubBox *boxes, double *stencil)
+{
+    __shared__ double s_cf[kMaxDense];
+    for (int q = threadIdx.x; q < kMaxDense; q += blockDim.x) s_cf[q] = P.fdense[q];
+    __syncthreads();
+    const SubBox b = boxes[blockIdx.y];
+    const uint64_t n = (uint64_t)b.w * (uint64_t)b.L;
+    const double cx = g.half_s2 / (g.dx0 * g.dx0), cy = g.half_s2 / (g.dx1 * g.dx1);
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+        int i, j;
+        stage2_point(b, r, i, j);
+        const double x[2] = {stage2_coord(g.lo0, g.span0, g.n0, i), stage2_coord(g.lo1, g.span1, g.n1, j)};
+        double bb[2], c, f = 0.0;
+        coefficients<double, 2>(P, x, bb, c, f, true, s_cf, P.tab);
+        const double aW = cx - bb[0] / (2.0 * g.dx0), aE = cx + bb[0] / (2.0 * g.dx0);
+        const double aS = cy - bb[1] / (2.0 * g.dx1), aN = cy + bb[1] / (2.0 * g.dx1);
+        double out[6] = {0.0, 0.0, -2.0 * cx - 2.0 * cy + c, 0.0, 0.0, f};
+        // neighbours: west, east, south, north with their band slots
+        const int ni[4] = {i - 1, i + 1, i, i};
+        const int nj[4] = {j, j, j - 1, j + 1};
+        const double a[4] = {aW, aE, aS, aN};
+        const int slot[4] = {b.fast_x ? 1 : 0, b.fast_x ? 3 : 4, b.fast_x ? 0 : 1, b.fast_x ? 4 : 3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool inside = ni[q] > b.i0 && ni[q] < b.i1 && nj[q] > b.j0 && nj[q] < b.j1;
+            if (inside)
+                out[slot[q]] = a[q];
+            else
+                out[5] -= a[q] * g.u[(size_t)nj[q] * g.n0 + ni[q]];
+        }
+        double *o = stencil + (b.first + r) * 6;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = out[q];
+    }
+}
+
+// Entry e (column r - w + e) of unknown r's row of a subdomain's band matrix.
+__device__ __forceinline__ double stage2_entry(const double *st, int w, int e)
+{
+    double v = 0.0;
+    if (e == 0) v += st[0];
+    if (e == w - 1) v += st[1];
+    if (e == w) v += st[2];
+    if (e == w + 1) v += st[3];
+    if (e == 2 * w) v += st[4];
+    return v;
+}
+
+// Banded LU without pivoting (the stencil matrices are diagonally dominant
+// once h is small enough for the drift) of one subdomain per workgroup, the
+// right side eliminated alongside: the rows of the active window (the pivot
+// row and the w rows below it) stay in LDS in a ring of w + 1 slots; a retired
+// pivot row goes to `factor` (w + 1 upper entries and its right side, stride
+// kStage2MaxBand + 2), and the row w + 1 below it takes its slot. Then back
+// substitution by one wave from the last unknown up, U rows staged through
+// LDS in chunks of 64.
+__global__ void __launch_bounds__(256) stage2_lu_kernel(const Stage2Grid g, const SubBox *boxes, const double *stencil,
+                                                        double *factor)
+{
+    constexpr int MW = kStage2MaxBand;
+    constexpr int ROW = 2 * MW + 1;
+    constexpr int FS = MW + 2;  // factor stride
+    constexpr int CH = 64;      // back-substitution chunk
+    __shared__ double A[(MW + 1) * ROW];
+    __shared__ double Brhs[MW + 1];
+    __shared__ double lcol[MW];
+    static_assert((MW + 1) + CH * FS <= (MW + 1) * ROW, "back-substitution buffers fit the window");
+    const SubBox bx = boxes[blockIdx.x];
+    const int w = bx.w, R = w + 1;
+    const uint64_t n = (uint64_t)w * (uint64_t)bx.L;
+    const double *st = stencil + bx.first * 6;
+    double *U = factor + bx.first * FS;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < R * (2 * w + 1); idx += blockDim.x) {
+        const int rr = idx / (2 * w + 1), e = idx % (2 * w + 1);
+        A[rr * ROW + e] = (uint64_t)rr < n ? stage2_entry(st + (size_t)rr * 6, w, e) : 0.0;
+    }
+    for (int rr = tid; rr < R; rr += blockDim.x) Brhs[rr] = (uint64_t)rr < n ? st[(size_t)rr * 6 + 5] : 0.0;
+    for (uint64_t k = 0; k < n; ++k) {
+        __syncthreads();
+        const int sk = (int)(k % R);
+        if (tid < w) {
+            const uint64_t r = k + 1 + tid;
+            double l = 0.0;
+            if (r < n) {
+                const int sr = (int)(r % R);
+                l = A[sr * ROW + (w - 1 - tid)] / A[sk * ROW + w];  // column k of row r: offset k - r + w
+                Brhs[sr] -= l * Brhs[sk];
+            }
+            lcol[tid] = l;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < w * w; idx += blockDim.x) {
+            const int rr = idx / w, cc = idx % w;
+            const uint64_t r = k + 1 + rr, c = k + 1 + cc;
+            if (r < n && c < n)
+                A[(int)(r % R) * ROW + (cc - rr + w)] -= lcol[rr] * A[sk * ROW + (cc + 1 + w)];
+        }
+        __syncthreads();
+        // retire row k (its columns k .. k + w) and load row k + R into its slot
+        const uint64_t nr = k + R;
+        for (int e = tid; e < 2 * w + 1; e += blockDim.x) {
+            if (e >= w) U[k * FS + (e - w)] = A[sk * ROW + e];
+            A[sk * ROW + e] = nr < n ? stage2_entry(st + nr * 6, w, e) : 0.0;
+        }
+        if (tid == 0) {
+            U[k * FS + MW + 1] = Brhs[sk];
+            Brhs[sk] = nr < n ? st[nr * 6 + 5] : 0.0;
+        }
+    }
+    __syncthreads();
+    double *X = A;                // ring of the last w + 1 solved values
+    double *chunk = A + (MW + 1); // U rows of the current chunk
+    const int lane = tid & 63;
+    for (uint64_t hi = n; hi > 0;) {
+        const uint64_t lo = hi > CH ? hi - CH : 0;
+        for (int idx = tid; idx < (int)(hi - lo) * FS; idx += blockDim.x) chunk[idx] = U[lo * FS + idx];
+        __syncthreads();
+        if (tid < 64) {
+            for (uint64_t k = hi; k-- > lo;) {
+                const double *row = chunk + (k - lo) * FS;
+                const uint64_t c = k + 1 + lane;
+                double t = (lane < w && c < n) ? row[lane + 1] * X[c % R] : 0.0;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+                const double x = (row[MW + 1] - t) / row[0];
+                if (lane == 0) {
+                    X[k % R] = x;
+                    int i, j;
+                    stage2_point(bx, k, i, j);
+                    g.u[(size_t)j * g.n0 + i] = x;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const pdd_grid *g, void *r, hipStream_t s)
@@ -1171,6 +1393,36 @@ hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const
             hipLaunchKernelGGL((grid_residual_kernel<double, 3>), dim3(blocks), dim3(256), 0, s, P, u, g->n[0],
                                g->n[1], n2, g->lo[0], g->lo[1], g->lo[2], dx[0], dx[1], dx[2], h2, out);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2_boundary(const DevProblem<double> &P, const Stage2Grid &g, hipStream_t s)
+{
+    const int total = 2 * g.n0 + 2 * (g.n1 - 2);
+    hipLaunchKernelGGL(stage2_boundary_kernel, dim3((total + 255) / 256), dim3(256), 0, s, P, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int32_t n_lines, const double *t,
+                               const double *lam, hipStream_t s)
+{
+    if (n_lines == 0) return hipSuccess;
+    const int len = g.n0 > g.n1 ? g.n0 : g.n1;
+    hipLaunchKernelGGL(stage2_lines_kernel, dim3((len + 255) / 256, n_lines), dim3(256), 0, s, g, lines, n_lines, t,
+                       lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
+                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
+                               hipStream_t s)
+{
+    if (n_boxes == 0) return hipSuccess;
+    hipLaunchKernelGGL(stage2_stencil_kernel, dim3((max_unknowns + 255) / 256, n_boxes), dim3(256), 0, s, P, g,
+                       boxes, stencil);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(256), 0, s, g, boxes, stencil, factor);
     return hipGetLastError();
 }
 

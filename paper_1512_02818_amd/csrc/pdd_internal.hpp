@@ -268,6 +268,48 @@ hipError_t launch_reduce(const ReduceArgs &a, uint32_t n_blocks, hipStream_t s);
 // r = f - ((1/2) sigma^2 Lap u + b.grad u + c u) at the points of grid g (u in
 // g->data, r in g's dtype and layout), by second-order differences.
 hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const pdd_grid *g, void *r, hipStream_t s);
+// Second stage of PDD on a 2D box cut by axis-parallel interfaces (the
+// subdomain-BVP step of Alg. A:IterPDD). u~ lives on a grid of n0 x n1 points
+// over the box (x fastest).
+struct Stage2Grid {
+    double *u;
+    int32_t n0, n1;
+    double lo0, lo1, span0, span1;  // point i of axis d at lo_d + span_d i / (n_d - 1)
+    double dx0, dx1;                 // span_d / (n_d - 1)
+    double half_s2;                  // (1/2) sigma^2
+};
+// One subdomain: the grid box [i0, i1] x [j0, j1] (boundary indices
+// included); its interior unknowns in the order r = s w + f, f running along
+// the box's shorter interior side (fast_x: along x), s along the other;
+// `first`: its first unknown in the stencil / factor tables.
+struct SubBox {
+    int32_t i0, i1, j0, j1;
+    int32_t w, L, fast_x, pad;
+    uint64_t first;
+};
+constexpr int kStage2MaxBand = 64;  // shorter interior side of a subdomain, at most
+// One interface line for the interpolation: axis d (the line is x_d = const at
+// grid index k), m data points at coordinates t[0..m-1] along the other axis
+// with multiquadric weights lam[0..m-1] (at offset `at` in the tables).
+struct Stage2Line {
+    int32_t d, k, m, pad;
+    uint64_t at;
+    double eps;
+};
+// Physical-boundary values g of the grid (every point of the box's edges).
+hipError_t launch_stage2_boundary(const DevProblem<double> &P, const Stage2Grid &g, hipStream_t s);
+// Interface lines: the multiquadric interpolants at the grid points of each
+// line between the box's edges; a point where an axis-0 and an axis-1 line
+// cross takes the mean of the two.
+hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int32_t n_lines, const double *t,
+                               const double *lam, hipStream_t s);
+// Finite-difference stencils of every subdomain's unknowns (6 doubles per
+// unknown: slow-1, fast-1, centre, fast+1, slow+1 coefficients and the right
+// side with the boundary values moved over), then the banded LU solve of each
+// subdomain (one workgroup each) writing the interior values into u.
+hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
+                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
+                               hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 // Starting sums of every group node: zero, or the statistics already in the

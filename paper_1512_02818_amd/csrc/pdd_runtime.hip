@@ -971,7 +971,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
     for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials,
-                            &ctx->gather, &ctx->cells})
+                            &ctx->gather, &ctx->cells, &ctx->stage2})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);
@@ -1457,6 +1457,179 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     if (st) return st;
     ctx->tuned[tuning_key(prec, dim, est, !spec)] = best;
     *out = best;
+    return PDD_OK;
+}
+
+pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const double *nodes, const double *values,
+                      int64_t n_nodes, double *u, void *stream)
+{
+    if (!problem || !part || !u || (n_nodes > 0 && (!nodes || !values)))
+        return fail(PDD_E_INVALID, "NULL argument");
+    if (n_nodes < 0) return fail(PDD_E_INVALID, "n_nodes < 0");
+    const pdd_problem_desc &d = problem->desc;
+    if (d.dim != 2 || d.domain != PDD_DOMAIN_BOX)
+        return fail(PDD_E_UNSUPPORTED, "the second stage takes 2D box domains");
+    if (part->n[0] < 3 || part->n[1] < 3) return fail(PDD_E_INVALID, "the grid needs >= 3 points per axis");
+    if (!(part->rbf_eps > 0.0) || !std::isfinite(part->rbf_eps))
+        return fail(PDD_E_INVALID, "rbf_eps must be finite and > 0");
+    const int n[2] = {part->n[0], part->n[1]};
+    // interfaces: grid indices on each axis
+    std::vector<int> cut_idx[2];
+    std::vector<double> cut_pos[2];
+    for (int a = 0; a < 2; ++a) {
+        if (part->n_cuts[a] < 0 || (part->n_cuts[a] > 0 && !part->cuts[a]))
+            return fail(PDD_E_INVALID, "bad interface list on axis %d", a);
+        for (int q = 0; q < part->n_cuts[a]; ++q) {
+            const double c = part->cuts[a][q];
+            const double t = (c - d.lo[a]) * (double)(n[a] - 1) / (d.hi[a] - d.lo[a]);
+            const double r = std::round(t);
+            if (!std::isfinite(c) || std::fabs(t - r) > 1e-9 || r <= 0.0 || r >= (double)(n[a] - 1))
+                return fail(PDD_E_INVALID, "interface %g on axis %d is not on an interior grid line", c, a);
+            if (std::find(cut_idx[a].begin(), cut_idx[a].end(), (int)r) != cut_idx[a].end())
+                return fail(PDD_E_INVALID, "interface %g on axis %d given twice", c, a);
+            cut_idx[a].push_back((int)r);
+            cut_pos[a].push_back(c);
+        }
+    }
+    // nodes: each on at least one interface line
+    auto on_line = [](double x, double c) { return std::fabs(x - c) <= 1e-9 * std::max(1.0, std::fabs(c)); };
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const double *x = nodes + 2 * i;
+        if (!finite3(x, 2) || !strictly_inside(d, x) || !std::isfinite(values[i]))
+            return fail(PDD_E_INVALID, "node %lld is not strictly inside the domain or its value is not finite",
+                        (long long)i);
+        bool any = false;
+        for (int a = 0; a < 2 && !any; ++a)
+            for (double c : cut_pos[a]) any = any || on_line(x[a], c);
+        if (!any) return fail(PDD_E_INVALID, "node %lld lies on no interface", (long long)i);
+    }
+    // subdomains: the grid boxes between consecutive interfaces
+    std::vector<int> ix = cut_idx[0], iy = cut_idx[1];
+    std::sort(ix.begin(), ix.end());
+    std::sort(iy.begin(), iy.end());
+    ix.insert(ix.begin(), 0);
+    ix.push_back(n[0] - 1);
+    iy.insert(iy.begin(), 0);
+    iy.push_back(n[1] - 1);
+    std::vector<SubBox> boxes;
+    uint64_t unknowns = 0, max_unknowns = 0;
+    for (size_t a = 0; a + 1 < ix.size(); ++a)
+        for (size_t b = 0; b + 1 < iy.size(); ++b) {
+            SubBox bx{};
+            bx.i0 = ix[a], bx.i1 = ix[a + 1], bx.j0 = iy[b], bx.j1 = iy[b + 1];
+            const int mx = bx.i1 - bx.i0 - 1, my = bx.j1 - bx.j0 - 1;
+            if (mx < 1 || my < 1) continue;
+            bx.fast_x = mx <= my;
+            bx.w = bx.fast_x ? mx : my;
+            bx.L = bx.fast_x ? my : mx;
+            if (bx.w > kStage2MaxBand)
+                return fail(PDD_E_UNSUPPORTED, "subdomain of %d x %d interior points: the shorter side must be <= %d",
+                            mx, my, kStage2MaxBand);
+            bx.first = unknowns;
+            unknowns += (uint64_t)mx * my;
+            max_unknowns = std::max<uint64_t>(max_unknowns, (uint64_t)mx * my);
+            boxes.push_back(bx);
+        }
+    pdd_ctx *ctx = problem->ctx;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (ctx->any_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+    Stage2Grid g{};
+    g.u = u;
+    g.n0 = n[0], g.n1 = n[1];
+    g.lo0 = d.lo[0], g.lo1 = d.lo[1];
+    g.span0 = d.hi[0] - d.lo[0], g.span1 = d.hi[1] - d.lo[1];
+    g.dx0 = g.span0 / (n[0] - 1), g.dx1 = g.span1 / (n[1] - 1);
+    g.half_s2 = 0.5 * d.sigma * d.sigma;
+    // physical boundary first: the ends of every interface line carry g
+    HIP_TRY(launch_stage2_boundary(problem->pd, g, s));
+    const size_t grid_bytes = (size_t)n[0] * n[1] * sizeof(double);
+    pdd_status st;
+    if ((st = ensure_stage(ctx, grid_bytes))) return st;
+    double *hg = static_cast<double *>(ctx->stage);
+    HIP_TRY(hipMemcpyAsync(hg, u, grid_bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // multiquadric weights of every line (host: small dense systems)
+    std::vector<Stage2Line> lines;
+    std::vector<double> t_all, lam_all;
+    for (int a = 0; a < 2; ++a)
+        for (size_t q = 0; q < cut_pos[a].size(); ++q) {
+            const int e = 1 - a, k = cut_idx[a][q];
+            std::vector<double> t, z;
+            t.push_back(d.lo[e]);
+            z.push_back(a == 0 ? hg[k] : hg[(size_t)k * n[0]]);
+            for (int64_t i = 0; i < n_nodes; ++i)
+                if (on_line(nodes[2 * i + a], cut_pos[a][q])) {
+                    t.push_back(nodes[2 * i + e]);
+                    z.push_back(values[i]);
+                }
+            t.push_back(d.hi[e]);
+            z.push_back(a == 0 ? hg[(size_t)(n[1] - 1) * n[0] + k] : hg[(size_t)k * n[0] + n[0] - 1]);
+            const int m = (int)t.size();
+            // Phi lam = z by Gaussian elimination with partial pivoting
+            std::vector<double> M((size_t)m * m);
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) {
+                    const double ee = part->rbf_eps * (t[r] - t[c]);
+                    M[(size_t)r * m + c] = std::sqrt(1.0 + ee * ee);
+                }
+            std::vector<double> lam = z;
+            for (int c = 0; c < m; ++c) {
+                int p = c;
+                for (int r = c + 1; r < m; ++r)
+                    if (std::fabs(M[(size_t)r * m + c]) > std::fabs(M[(size_t)p * m + c])) p = r;
+                if (M[(size_t)p * m + c] == 0.0)
+                    return fail(PDD_E_INVALID, "interpolation system of interface %g is singular (repeated nodes?)",
+                                cut_pos[a][q]);
+                if (p != c) {
+                    for (int cc = 0; cc < m; ++cc) std::swap(M[(size_t)p * m + cc], M[(size_t)c * m + cc]);
+                    std::swap(lam[p], lam[c]);
+                }
+                for (int r = c + 1; r < m; ++r) {
+                    const double l = M[(size_t)r * m + c] / M[(size_t)c * m + c];
+                    for (int cc = c; cc < m; ++cc) M[(size_t)r * m + cc] -= l * M[(size_t)c * m + cc];
+                    lam[r] -= l * lam[c];
+                }
+            }
+            for (int r = m - 1; r >= 0; --r) {
+                double acc = lam[r];
+                for (int cc = r + 1; cc < m; ++cc) acc -= M[(size_t)r * m + cc] * lam[cc];
+                lam[r] = acc / M[(size_t)r * m + r];
+            }
+            Stage2Line L{};
+            L.d = a, L.k = k, L.m = m, L.at = t_all.size(), L.eps = part->rbf_eps;
+            lines.push_back(L);
+            t_all.insert(t_all.end(), t.begin(), t.end());
+            lam_all.insert(lam_all.end(), lam.begin(), lam.end());
+        }
+    // device tables: lines | t | lam | boxes | stencils | factors
+    const size_t off_lines = 0;
+    const size_t off_t = align_up(off_lines + lines.size() * sizeof(Stage2Line), 256);
+    const size_t off_lam = align_up(off_t + t_all.size() * sizeof(double), 256);
+    const size_t off_boxes = align_up(off_lam + lam_all.size() * sizeof(double), 256);
+    const size_t table_bytes = align_up(off_boxes + boxes.size() * sizeof(SubBox), 256);
+    const size_t off_stencil = table_bytes;
+    const size_t off_factor = align_up(off_stencil + unknowns * 6 * sizeof(double), 256);
+    const size_t bytes = off_factor + unknowns * (kStage2MaxBand + 2) * sizeof(double);
+    if ((st = ensure(ctx, ctx->stage2, bytes))) return st;
+    if ((st = ensure_stage(ctx, table_bytes))) return st;
+    char *h = static_cast<char *>(ctx->stage);
+    std::memcpy(h + off_lines, lines.data(), lines.size() * sizeof(Stage2Line));
+    std::memcpy(h + off_t, t_all.data(), t_all.size() * sizeof(double));
+    std::memcpy(h + off_lam, lam_all.data(), lam_all.size() * sizeof(double));
+    std::memcpy(h + off_boxes, boxes.data(), boxes.size() * sizeof(SubBox));
+    char *dv = static_cast<char *>(ctx->stage2.ptr);
+    HIP_TRY(hipMemcpyAsync(dv, h, table_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->staged, s));
+    ctx->any_staged = true;
+    HIP_TRY(launch_stage2_lines(g, reinterpret_cast<const Stage2Line *>(dv + off_lines), (int32_t)lines.size(),
+                                reinterpret_cast<const double *>(dv + off_t),
+                                reinterpret_cast<const double *>(dv + off_lam), s));
+    HIP_TRY(launch_stage2_solve(problem->pd, g, reinterpret_cast<const SubBox *>(dv + off_boxes), (int32_t)boxes.size(),
+                                (uint32_t)max_unknowns, reinterpret_cast<double *>(dv + off_stencil),
+                                reinterpret_cast<double *>(dv + off_factor), s));
+    HIP_TRY(hipEventRecord(ctx->done, s));
+    ctx->any_done = true;
     return PDD_OK;
 }
 

@@ -111,6 +111,11 @@ assert CONSTANTS_DTYPE.itemsize == C.sizeof(NodeConstants)
 GLM_FAMILIES = {"normal": 0, "gamma": 1}
 
 
+class Partition(C.Structure):
+    _fields_ = [("n", C.c_int32 * 2), ("n_cuts", C.c_int32 * 2), ("cuts", C.POINTER(C.c_double) * 2),
+                ("rbf_eps", C.c_double)]
+
+
 class TuningKey(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dim", C.c_int32), ("correction", C.c_int32),
                 ("generic", C.c_int32)]
@@ -158,6 +163,8 @@ SIGNATURES = {
                                     C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
     "pdd_solve_nodes_noalloc": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
                                             C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
+    "pdd_stage2": (C.c_int32, [C.c_void_p, C.POINTER(Partition), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.c_int64, C.c_void_p, C.c_void_p]),
     "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
                                          C.POINTER(C.c_double), C.c_int64, C.POINTER(SolveOpts),
                                          C.c_void_p, C.c_void_p]),
@@ -584,6 +591,30 @@ def grid_gradient(ctx: Context, grid: dict, tensor, stream=None):
     _check(lib().pdd_grid_gradient(ctx.handle, C.byref(g), ptrs, _stream_handle(stream)))
     dicts = [{"dim": D, "n": list(grid["n"]), "lo": list(grid["lo"]), "hi": list(grid["hi"])} for _ in range(D)]
     return dicts, outs
+
+
+def stage2(problem: Problem, n, cuts, nodes, values, rbf_eps, out=None, stream=None):
+    """pdd_stage2: u~ on the n[0] x n[1] grid over the problem's box from the
+    nodal values (cuts = [axis-0 interface coordinates, axis-1 ones]); returns
+    the device FP64 tensor of shape (n[1], n[0])."""
+    import torch
+    nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, 2))
+    values = np.ascontiguousarray(np.asarray(values, dtype=np.float64).ravel())
+    if out is None:
+        out = torch.empty((int(n[1]), int(n[0])), dtype=torch.float64, device="cuda")
+    part = Partition()
+    keep = []
+    for a in range(2):
+        part.n[a] = int(n[a])
+        c = np.ascontiguousarray(np.asarray(cuts[a], dtype=np.float64).ravel())
+        keep.append(c)
+        part.n_cuts[a] = len(c)
+        part.cuts[a] = c.ctypes.data_as(C.POINTER(C.c_double))
+    part.rbf_eps = float(rbf_eps)
+    _check(lib().pdd_stage2(problem.handle, C.byref(part), nodes.ctypes.data_as(C.POINTER(C.c_double)),
+                            values.ctypes.data_as(C.POINTER(C.c_double)), len(values), C.c_void_p(out.data_ptr()),
+                            _stream_handle(stream)))
+    return out
 
 
 def grid_residual(problem: Problem, grid: dict, tensor, stream=None):

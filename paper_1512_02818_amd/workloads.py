@@ -318,6 +318,24 @@ def paper_example_nodes():
     return unit_square_nodes() * PAPER_SIDE
 
 
+# --------------------------------------------------------------------------- partitions
+def unit_square_partition(n=257):
+    """The unit square's 4 strips: interfaces x = 1/4, 1/2, 3/4 on an n x n
+    grid (n - 1 divisible by 4), multiquadric shape parameter 3 (about 0.4 /
+    node spacing 1/7)."""
+    return {"n": (n, n), "cuts": [[0.25, 0.5, 0.75], []], "rbf_eps": 3.0}
+
+
+def big_square_partition(n=257, side=4.0, cells=8, per_segment=16):
+    """The [0, side]^2 box cut into cells x cells subdomains: interfaces at
+    the multiples of side / cells on both axes, on an n x n grid; the shape
+    parameter is the inverse node spacing along a line (side / cells /
+    (per_segment + 1))."""
+    step = side / cells
+    cuts = [a * step for a in range(1, cells)]
+    return {"n": (n, n), "cuts": [cuts, cuts], "rbf_eps": (per_segment + 1) / step}
+
+
 # --------------------------------------------------------------------------- grids
 def grid_points(n, lo, hi):
     """Coordinates of an n[0] x n[1] (x n[2]) uniform grid, x fastest, shape
