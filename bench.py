@@ -127,6 +127,8 @@ def parse():
                     help="seconds to wait for completions after the last arrival")
     ap.add_argument("--serve-sweep", type=int, default=1,
                     help="1: also serve the same request mix at 0.5, 1, 2, 5 and 20 requests/s (0 = skip)")
+    ap.add_argument("--iterpdd", default="0.01,0.0025",
+                    help="nodal tolerances a0 of the outer-iteration runs on the unit square ('' = skip)")
     ap.add_argument("--fp64-paths", type=int, default=4096,
                     help="paths per node of the FP64 variant of the throughput workload, with the FP32 "
                          "paths of the same pairs beside it (0 = skip)")
@@ -560,6 +562,28 @@ def fp64_variant(ctx, prob, nodes, paths):
                 "nodes": int(len(nodes))}}
 
 
+def iterpdd_runs(ctx, tols):
+    """The outer iteration (Alg. A:IterPDD) on the unit square's four strips
+    (u~ on a 257^2 grid): per nodal tolerance a0, the schedule, the cost and
+    RMS error of every level, and PlainPDD(a0) beside it."""
+    from paper_1512_02818_amd import iterpdd
+    from paper_1512_02818_amd import workloads as W
+    pd = W.unit_square_problem(seed=SEED)
+    out = []
+    for a0 in tols:
+        rep = iterpdd.run(ctx, pd, W.unit_square_nodes(), W.unit_square_partition(129), a0=a0,
+                          exact=lambda p: W.manufactured_u(pd, p),
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+        rep.pop("constants")
+        out.append(rep)
+        print(f"IterPDD(a0={a0}): {rep['iterpdd_path_steps']:.3e} path-steps vs PlainPDD "
+              f"{rep['plainpdd']['path_steps']:.3e} (x{rep['speedup_path_steps']:.1f}); final RMS error "
+              f"{rep['levels'][-1]['rms_error_nodes']:.2e}", file=sys.stderr, flush=True)
+    return {"workload": "unit square, 18 nodes on the interfaces x = 1/4, 1/2, 3/4, u~ on 129^2 (multiquadric "
+                        "shape 3, FD subdomain solves), q = 2, bridge exit (delta = 1), FP32 paths, Ito control "
+                        "variate from grad(u~) of the previous level", "runs": out}
+
+
 SWEEP_RATES = (0.5, 1.0, 2.0, 5.0, 20.0)
 
 
@@ -893,6 +917,9 @@ def main():
         f = result["fit_constants"]
         print(f"fit: {f['paths']} paths in {f['wall_s']:.3f} s, beta RMS {f['beta_rms']:.3f}, "
               f"dt from beta {f['dt_from_beta']:.2e}", file=sys.stderr, flush=True)
+    if args.iterpdd:
+        print("outer iteration (IterPDD) ...", file=sys.stderr, flush=True)
+        result["iterpdd"] = iterpdd_runs(ctx, [float(v) for v in args.iterpdd.split(",")])
     if args.paper_example:
         print("the paper's example PDE ...", file=sys.stderr, flush=True)
         result["paper_example"] = paper_example(ctx)

@@ -370,6 +370,32 @@ typedef struct {
 pdd_status pdd_fit_constants(pdd_ctx *ctx, const pdd_work_item *item, const double *h, int32_t n_h,
                              uint64_t n_hat, double delta, pdd_node_constants *out, void *stream);
 
+/* Nodal constants of the scheduling algorithm (Alg. A:Scheduling): K the
+ * cost constant of eq. F:Pointwise_cost (4 q^2 E[tau] (2 |beta|)^(1/delta)),
+ * V = V[phi], alpha, beta the fitted variance and bias constants
+ * (pdd_fit_constants), V_psi = V[psi-bar] and rho_psi = rho[phi, psi-bar]
+ * of the auxiliary variate psi-bar of eq. F:Bar_psi. */
+typedef struct {
+    double K, V, alpha, beta, V_psi, rho_psi;
+} pdd_sched_node;
+
+/* Alg. A:Scheduling: from a_0 (the nodal target tolerance), each a_{j+1}
+ * minimises over (a_j, a_max] the sum over nodes of
+ *   K V (kappa (1 - r^2(a) + |alpha r(a) / beta| a_j) + (a_j / a)^(2 + 1/delta)),
+ *   r^2(a) = 1 - V_psi a^2 (1 - rho_psi^2) / (4 V)  (eq. F:Sensitivity_formula,
+ * kept in [0, 1]); minimised on a 512-point log grid, then by golden section
+ * around its best point. The loop stops when the predicted speedup of the
+ * level, (sum K V) / that minimum = cost(PlainPDD(a_j)) / cost(IterPDD(a_j,
+ * a_{j+1})) without the subdomain terms (eqs. F:PlainPDD_cost,
+ * F:IterPDD_cost), falls below s_min (the paper stops at 1.5, Sec. 6; that
+ * level is not taken), when a_j reaches a_max, or after max_levels levels.
+ * Writes a_out[0 .. J] = a_0 < a_1 < ... < a_J (host, max_levels + 1 values),
+ * the levels' predicted speedups to speedup[0 .. J - 1] (nullable) and J to
+ * n_levels. Host only. Errors: NULL pointers, n < 1, a bad constant, or not
+ * 0 < a_0 < a_max, kappa > 0, delta > 0, s_min > 0. */
+pdd_status pdd_schedule(const pdd_sched_node *nodes, int64_t n, double a0, double kappa, double delta, double a_max,
+                        double s_min, int32_t max_levels, double *a_out, double *speedup, int32_t *n_levels);
+
 /* Gradient of a gridded u~ by second-order finite differences (the grad(u~)
  * grids of pdd_solve_ito when only values of u~ on a grid are known, as
  * inside the outer iteration of Sec. 2.3): with dx_d = (hi_d - lo_d) /

@@ -1279,8 +1279,10 @@ __device__ __forceinline__ double stage2_entry(const double *st, int w, int e)
 // kStage2MaxBand + 2), and the row w + 1 below it takes its slot. Then back
 // substitution by one wave from the last unknown up, U rows staged through
 // LDS in chunks of 64.
-__global__ void __launch_bounds__(256) stage2_lu_kernel(const Stage2Grid g, const SubBox *boxes, const double *stencil,
-                                                        double *factor)
+constexpr int kStage2LuThreads = 1024;
+
+__global__ void __launch_bounds__(kStage2LuThreads) stage2_lu_kernel(const Stage2Grid g, const SubBox *boxes,
+                                                                     const double *stencil, double *factor)
 {
     constexpr int MW = kStage2MaxBand;
     constexpr int ROW = 2 * MW + 1;
@@ -1289,6 +1291,7 @@ __global__ void __launch_bounds__(256) stage2_lu_kernel(const Stage2Grid g, cons
     __shared__ double A[(MW + 1) * ROW];
     __shared__ double Brhs[MW + 1];
     __shared__ double lcol[MW];
+    __shared__ double S[CH * 6];  // stencils of the rows that the next CH pivots bring into the window
     static_assert((MW + 1) + CH * FS <= (MW + 1) * ROW, "back-substitution buffers fit the window");
     const SubBox bx = boxes[blockIdx.x];
     const int w = bx.w, R = w + 1;
@@ -1301,37 +1304,73 @@ __global__ void __launch_bounds__(256) stage2_lu_kernel(const Stage2Grid g, cons
         A[rr * ROW + e] = (uint64_t)rr < n ? stage2_entry(st + (size_t)rr * 6, w, e) : 0.0;
     }
     for (int rr = tid; rr < R; rr += blockDim.x) Brhs[rr] = (uint64_t)rr < n ? st[(size_t)rr * 6 + 5] : 0.0;
+    // this thread's (row, column) offsets of the w x w update, the same at
+    // every pivot: pair m is update idx = tid + T m (T threads), row offset
+    // idx / w and column offset idx % w (no division inside the pivot loop)
+    constexpr int T = kStage2LuThreads;
+    constexpr int kPairs = MW * MW / T;
+    static_assert(MW * MW % T == 0, "whole pairs per thread");
+    int prr[kPairs], pcc[kPairs];
+#pragma unroll
+    for (int m = 0; m < kPairs; ++m) {
+        const int idx = tid + T * m;
+        prr[m] = idx < w * w ? idx / w : -1;
+        pcc[m] = idx < w * w ? idx % w : 0;
+    }
+    int sk = 0;  // slot of pivot row k: k mod R
     for (uint64_t k = 0; k < n; ++k) {
         __syncthreads();
-        const int sk = (int)(k % R);
+        if (k % CH == 0) {  // rows k + R .. k + R + CH - 1, entering at pivots k .. k + CH - 1
+            for (int idx = tid; idx < CH * 6; idx += blockDim.x) {
+                const uint64_t q = (k + R) * 6 + idx;
+                S[idx] = q < n * 6 ? st[q] : 0.0;
+            }
+            __syncthreads();
+        }
         if (tid < w) {
             const uint64_t r = k + 1 + tid;
             double l = 0.0;
             if (r < n) {
-                const int sr = (int)(r % R);
+                int sr = sk + 1 + tid;
+                if (sr >= R) sr -= R;
                 l = A[sr * ROW + (w - 1 - tid)] / A[sk * ROW + w];  // column k of row r: offset k - r + w
                 Brhs[sr] -= l * Brhs[sk];
             }
             lcol[tid] = l;
         }
         __syncthreads();
-        for (int idx = tid; idx < w * w; idx += blockDim.x) {
-            const int rr = idx / w, cc = idx % w;
-            const uint64_t r = k + 1 + rr, c = k + 1 + cc;
-            if (r < n && c < n)
-                A[(int)(r % R) * ROW + (cc - rr + w)] -= lcol[rr] * A[sk * ROW + (cc + 1 + w)];
+        const uint64_t left = n - 1 - k;  // unknowns after k: rows and columns k + 1 + o exist for o < left
+        // all reads first, then the stores: each pair writes its own entry, and
+        // the pivot row and multipliers are not written in this phase
+        int at[kPairs];
+        double upd[kPairs];
+#pragma unroll
+        for (int m = 0; m < kPairs; ++m) {
+            const int rr = prr[m], cc = pcc[m];
+            at[m] = -1;
+            if (rr >= 0 && (uint64_t)rr < left && (uint64_t)cc < left) {
+                int sr = sk + 1 + rr;
+                if (sr >= R) sr -= R;
+                at[m] = sr * ROW + (cc - rr + w);
+                upd[m] = A[at[m]] - lcol[rr] * A[sk * ROW + (cc + 1 + w)];
+            }
         }
+#pragma unroll
+        for (int m = 0; m < kPairs; ++m)
+            if (at[m] >= 0) A[at[m]] = upd[m];
         __syncthreads();
         // retire row k (its columns k .. k + w) and load row k + R into its slot
         const uint64_t nr = k + R;
+        const double *sn = S + (k % CH) * 6;  // row nr's stencil
         for (int e = tid; e < 2 * w + 1; e += blockDim.x) {
             if (e >= w) U[k * FS + (e - w)] = A[sk * ROW + e];
-            A[sk * ROW + e] = nr < n ? stage2_entry(st + nr * 6, w, e) : 0.0;
+            A[sk * ROW + e] = nr < n ? stage2_entry(sn, w, e) : 0.0;
         }
         if (tid == 0) {
             U[k * FS + MW + 1] = Brhs[sk];
-            Brhs[sk] = nr < n ? st[nr * 6 + 5] : 0.0;
+            Brhs[sk] = nr < n ? sn[5] : 0.0;
         }
+        if (++sk == R) sk = 0;
     }
     __syncthreads();
     double *X = A;                // ring of the last w + 1 solved values
@@ -1422,7 +1461,7 @@ hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g,
                        boxes, stencil);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(256), 0, s, g, boxes, stencil, factor);
+    hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(kStage2LuThreads), 0, s, g, boxes, stencil, factor);
     return hipGetLastError();
 }
 

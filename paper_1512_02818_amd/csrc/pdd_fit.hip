@@ -94,9 +94,95 @@ pdd_status glm(const double *x, const double *y, int n, int family, double coef[
     return PDD_OK;
 }
 
+// Objective of the scheduling algorithm at a > a_j (Alg. A:Scheduling with
+// the sensitivity formula, eq. F:Sensitivity_formula): sum over nodes of
+// K V (kappa (1 - r^2 + |alpha r / beta| a_j) + (a_j / a)^(2 + 1/delta)),
+// r^2 = 1 - V[psi] a^2 (1 - rho^2[phi, psi]) / (4 V), kept in [0, 1].
+double schedule_objective(const pdd_sched_node *nd, int64_t n, double a, double a_j, double kappa, double delta)
+{
+    const double p = 2.0 + 1.0 / delta;
+    const double tail = std::pow(a_j / a, p);
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double r2 = 1.0 - nd[i].V_psi * a * a * (1.0 - nd[i].rho_psi * nd[i].rho_psi) / (4.0 * nd[i].V);
+        r2 = r2 < 0.0 ? 0.0 : (r2 > 1.0 ? 1.0 : r2);
+        const double r = std::sqrt(r2);
+        acc += nd[i].K * nd[i].V * (kappa * (1.0 - r2 + std::fabs(nd[i].alpha * r / nd[i].beta) * a_j) + tail);
+    }
+    return acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+pdd_status pdd_schedule(const pdd_sched_node *nodes, int64_t n, double a0, double kappa, double delta, double a_max,
+                        double s_min, int32_t max_levels, double *a_out, double *speedup, int32_t *n_levels)
+{
+    if (!nodes || n < 1 || !a_out || !n_levels) return fail(PDD_E_INVALID, "NULL argument or no nodes");
+    if (!(a0 > 0.0) || !(a_max > a0) || !(kappa > 0.0) || !(delta > 0.0) || !(s_min > 0.0) || max_levels < 0 ||
+        !std::isfinite(a_max) || !std::isfinite(kappa))
+        return fail(PDD_E_INVALID, "need 0 < a0 < a_max, kappa > 0, delta > 0, s_min > 0, max_levels >= 0");
+    for (int64_t i = 0; i < n; ++i) {
+        const pdd_sched_node &q = nodes[i];
+        if (!(q.K > 0.0) || !(q.V > 0.0) || !(q.V_psi >= 0.0) || !(std::fabs(q.rho_psi) <= 1.0) || q.beta == 0.0 ||
+            !std::isfinite(q.alpha) || !std::isfinite(q.beta) || !std::isfinite(q.K) || !std::isfinite(q.V_psi))
+            return fail(PDD_E_INVALID, "node %lld: need K > 0, V > 0, V_psi >= 0, |rho| <= 1, beta != 0, finite values",
+                        (long long)i);
+    }
+    const double p = 2.0 + 1.0 / delta;
+    double plain_kv = 0.0;
+    for (int64_t i = 0; i < n; ++i) plain_kv += nodes[i].K * nodes[i].V;
+    a_out[0] = a0;
+    int32_t J = 0;
+    while (J < max_levels) {
+        const double a_j = a_out[J];
+        if (a_j >= a_max) break;
+        // coarse log grid over (a_j, a_max], then golden section around the best point
+        constexpr int kGrid = 512;
+        const double la = std::log(a_j), lb = std::log(a_max);
+        int best = 1;
+        double best_f = HUGE_VAL;
+        for (int k = 1; k <= kGrid; ++k) {
+            const double f = schedule_objective(nodes, n, std::exp(la + (lb - la) * k / kGrid), a_j, kappa, delta);
+            if (f < best_f) {
+                best_f = f;
+                best = k;
+            }
+        }
+        double lo = la + (lb - la) * (best - 1) / kGrid, hi = la + (lb - la) * std::min(best + 1, kGrid) / kGrid;
+        const double gr = 0.6180339887498949;
+        double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+        double f1 = schedule_objective(nodes, n, std::exp(x1), a_j, kappa, delta);
+        double f2 = schedule_objective(nodes, n, std::exp(x2), a_j, kappa, delta);
+        for (int it = 0; it < 200 && hi - lo > 1e-12; ++it) {
+            if (f1 <= f2) {
+                hi = x2, x2 = x1, f2 = f1;
+                x1 = hi - gr * (hi - lo);
+                f1 = schedule_objective(nodes, n, std::exp(x1), a_j, kappa, delta);
+            } else {
+                lo = x1, x1 = x2, f1 = f2;
+                x2 = lo + gr * (hi - lo);
+                f2 = schedule_objective(nodes, n, std::exp(x2), a_j, kappa, delta);
+            }
+        }
+        double a = std::exp(0.5 * (lo + hi));
+        double f = schedule_objective(nodes, n, a, a_j, kappa, delta);
+        if (best_f < f) {  // keep the grid point if the refinement did not improve on it
+            a = std::exp(la + (lb - la) * best / kGrid);
+            f = best_f;
+        }
+        // predicted speedup cost(PlainPDD(a_j)) / cost(IterPDD(a_j, a)) (eqs.
+        // F:PlainPDD_cost, F:IterPDD_cost without the subdomain terms)
+        const double s = plain_kv / f;
+        (void)p;
+        if (s < s_min) break;
+        if (speedup) speedup[J] = s;
+        a_out[++J] = a;
+    }
+    *n_levels = J;
+    return PDD_OK;
+}
 
 pdd_status pdd_glm_fit(const double *x, const double *y, int32_t n, int32_t family, double *coef, double *se,
                        int32_t *iterations)

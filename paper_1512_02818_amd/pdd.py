@@ -116,6 +116,10 @@ class Partition(C.Structure):
                 ("rbf_eps", C.c_double)]
 
 
+class SchedNode(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("K", "V", "alpha", "beta", "V_psi", "rho_psi")]
+
+
 class TuningKey(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dim", C.c_int32), ("correction", C.c_int32),
                 ("generic", C.c_int32)]
@@ -163,6 +167,9 @@ SIGNATURES = {
                                     C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
     "pdd_solve_nodes_noalloc": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int64,
                                             C.POINTER(SolveOpts), C.c_void_p, C.c_void_p]),
+    "pdd_schedule": (C.c_int32, [C.POINTER(SchedNode), C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_int32)]),
     "pdd_stage2": (C.c_int32, [C.c_void_p, C.POINTER(Partition), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.c_int64, C.c_void_p, C.c_void_p]),
     "pdd_solve_correction": (C.c_int32, [C.c_void_p, C.POINTER(Grid), C.POINTER(Grid),
@@ -591,6 +598,22 @@ def grid_gradient(ctx: Context, grid: dict, tensor, stream=None):
     _check(lib().pdd_grid_gradient(ctx.handle, C.byref(g), ptrs, _stream_handle(stream)))
     dicts = [{"dim": D, "n": list(grid["n"]), "lo": list(grid["lo"]), "hi": list(grid["hi"])} for _ in range(D)]
     return dicts, outs
+
+
+def schedule(K, V, alpha, beta, V_psi, rho_psi, a0, kappa, delta=1.0, a_max=1.0, s_min=1.5, max_levels=8):
+    """pdd_schedule (host only): returns (levels a_0 < ... < a_J, predicted
+    speedups of the J levels)."""
+    n = len(K)
+    arr = (SchedNode * n)()
+    for i in range(n):
+        arr[i] = SchedNode(float(K[i]), float(V[i]), float(alpha[i]), float(beta[i]), float(V_psi[i]),
+                           float(rho_psi[i]))
+    a = (C.c_double * (max_levels + 1))()
+    sp = (C.c_double * max(max_levels, 1))()
+    J = C.c_int32()
+    _check(lib().pdd_schedule(arr, n, float(a0), float(kappa), float(delta), float(a_max), float(s_min),
+                              int(max_levels), a, sp, C.byref(J)))
+    return [a[i] for i in range(J.value + 1)], [sp[i] for i in range(J.value)]
 
 
 def stage2(problem: Problem, n, cuts, nodes, values, rbf_eps, out=None, stream=None):

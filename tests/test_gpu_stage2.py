@@ -52,6 +52,14 @@ def test_unit_square_strips(ctx, n):
     U = W.manufactured_u(pd, np.stack([X.ravel(), Y.ravel()], 1)).reshape(n, n)
     assert np.sqrt(np.mean((u0 - U) ** 2)) < 5e-3
     assert np.all(np.isfinite(u))
+    import time
+    prob = pdd.Problem(ctx, pd)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        pdd.stage2(prob, (n, n), [[0.25, 0.5, 0.75], []], nodes, vals, 3.0)
+    torch.cuda.synchronize()
+    print(f"stage2 on {n}^2, 4 strips: {(time.perf_counter() - t0) / 3 * 1e3:.2f} ms per call", flush=True)
+    prob.close()
 
 
 def test_big_square_8x8(ctx):
