@@ -64,6 +64,10 @@ inline int tuning_key(int precision, int dim, int est, bool generic)
 }
 // Whether an item can run in the specialised kernel.
 bool specialised(const HostItem &it);
+// Whether many lanes of a wave are near a face at every step of a walk of
+// this problem at step dt (then the dense form of the bridge test is the
+// faster one).
+bool dense_boundary(const pdd_problem_desc &d, double dt);
 
 // Launch shape for a solve: opts->tuning (fields left 0 take the default),
 // else the context's table entry for `key` (tuning_key; < 0: none), else

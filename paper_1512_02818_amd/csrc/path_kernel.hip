@@ -15,13 +15,39 @@
 // In 2D one block gives the two normals of two consecutive steps (words 0,1
 // then 2,3), so a lane starts a new path only at an even step; in 3D one block
 // per step. The bridge uniform of step s is word s mod 4 of the tag-1 block
-// s/4, drawn only when a face is live and cached for the next steps.
+// s/4; the block is drawn for every walking lane of the wave at the first step
+// of its four-step window at which some lane may have a live face, and cached
+// for the rest of the window (drawn per lane inside the rare branch, it would
+// be drawn up to four times per window, once for each step at which another
+// lane first needs it).
 // Box-Muller (1958) on the VALU: in FP32 with the hardware log2, sqrt, sin
 // and cos (which take revolutions, so 2 pi u needs no multiply).
+#include <type_traits>
+
 #include "pdd_internal.hpp"
 
 namespace pdd {
 namespace {
+
+// Device memory that the kernels reach through pointers held in descriptor
+// tables (grids, node tables, records). The compiler cannot tell such a
+// pointer from an LDS one and would emit flat accesses, which count against
+// the same wait counter as the scalar loads of descriptor fields: every wait
+// for a field would then also wait for an in-flight grid gather. Casting to
+// the global address space gives global loads and stores with their own
+// counter.
+template <class T>
+using Global = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const Global<T> *)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *p, T v)
+{
+    *(Global<T> *)p = v;
+}
 
 constexpr float kLn2f = 0.6931471805599453f;
 constexpr float kLog2ef = 1.4426950408889634f;
@@ -39,15 +65,36 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// The ten round keys of a (wave-uniform) Philox key.
+// The ten round keys of a (wave-uniform) Philox key, in vector registers: the
+// XOR3 takes three vector operands at no extra cost, and keeping twenty
+// uniform values out of the scalar register file leaves it to the problem
+// constants. Used by the FP32 walks, which are bound by instruction issue:
+// recomputing the keys would add scalar instructions to every block.
 struct KeySchedule {
     uint32_t k0[10], k1[10];
 };
 
-// Builds the round keys in vector registers: the XOR3 takes three vector
-// operands at no extra cost, and keeping twenty uniform values out of the
-// scalar register file leaves it to the problem constants (no spills).
-__device__ __forceinline__ KeySchedule key_schedule(uint32_t k0, uint32_t k1)
+// The key as two scalar words, round keys recomputed by scalar adds in every
+// block. Used by the FP64 walks, whose vector registers are the scarce
+// resource: twenty fewer live values remove their spills.
+struct ScalarKey {
+    uint32_t k0, k1;
+};
+
+template <class T>
+using KeysOf = typename std::conditional<sizeof(T) == 8, ScalarKey, KeySchedule>::type;
+
+template <class K>
+__device__ __forceinline__ K key_schedule(uint32_t k0, uint32_t k1);
+
+template <>
+__device__ __forceinline__ ScalarKey key_schedule<ScalarKey>(uint32_t k0, uint32_t k1)
+{
+    return {(uint32_t)__builtin_amdgcn_readfirstlane(k0), (uint32_t)__builtin_amdgcn_readfirstlane(k1)};
+}
+
+template <>
+__device__ __forceinline__ KeySchedule key_schedule<KeySchedule>(uint32_t k0, uint32_t k1)
 {
     KeySchedule ks;
 #pragma unroll
@@ -80,10 +127,36 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
     return {c0, c1, c2, c3};
 }
 
+__device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         const ScalarKey &key)
+{
+    // opaque to the optimiser, so that the round keys are formed here rather
+    // than hoisted out of the walk loop into twenty live registers
+    uint32_t ka = key.k0, kb = key.k1;
+    asm volatile("" : "+s"(ka), "+s"(kb));
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, ka);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, kb);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        ka += 0x9E3779B9u;
+        kb += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
 // Multiply-add with one rounding. The library is built without automatic
 // contraction, so every fused operation is written out and all kernels that
 // walk the same path round identically.
 __device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// x clamped to [lo, hi] (lo <= hi, x not NaN): one median-of-three.
+__device__ __forceinline__ float med3(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double med3(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 __device__ __forceinline__ double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <class T>
@@ -346,9 +419,8 @@ __device__ __forceinline__ void grid_cell(const GridView<T> &g, const T *x, int 
 {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const T top = (T)(g.n[d] - 1);
         T t = (x[d] - g.lo[d]) * g.inv[d];
-        t = t > (T)0 ? (t < top ? t : top) : (T)0;
+        t = med3(t, (T)0, g.top[d]);
         int id = (int)t;
         id = id < g.n[d] - 2 ? id : g.n[d] - 2;
         i[d] = id;
@@ -367,8 +439,8 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
     if (D == 2) {
         const T *r0 = g.data + (size_t)i[1] * nx + i[0];
         const T *r1 = r0 + nx;
-        const T l0 = madd(w[0], r0[1], ((T)1 - w[0]) * r0[0]);
-        const T l1 = madd(w[0], r1[1], ((T)1 - w[0]) * r1[0]);
+        const T l0 = madd(w[0], gload(r0 + 1), ((T)1 - w[0]) * gload(r0));
+        const T l1 = madd(w[0], gload(r1 + 1), ((T)1 - w[0]) * gload(r1));
         return madd(w[1], l1, ((T)1 - w[1]) * l0);
     }
     const int ny = g.n[1];
@@ -379,7 +451,7 @@ __device__ __forceinline__ T interp(const GridView<T> &g, const T *x)
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
             const T *row = g.data + ((size_t)(i[2 % D] + dz) * ny + (i[1] + dy)) * nx + i[0];
-            const T line = madd(w[0], row[1], ((T)1 - w[0]) * row[0]);
+            const T line = madd(w[0], gload(row + 1), ((T)1 - w[0]) * gload(row));
             layer = madd(dy ? w[1] : (T)1 - w[1], line, layer);
         }
         acc = madd(dz ? w[2 % D] : (T)1 - w[2 % D], layer, acc);
@@ -396,7 +468,7 @@ template <class T, int D>
 __device__ __forceinline__ size_t cell_index(const GridView<T> &g, const int *i)
 {
     const size_t mx = (size_t)(g.n[0] - 1);
-    if (D == 2) return (size_t)i[1] * mx + i[0];
+    if (D == 2) return (uint32_t)i[1] * (uint32_t)(g.n[0] - 1) + (uint32_t)i[0];
     return ((size_t)i[2 % D] * (size_t)(g.n[1] - 1) + i[1]) * mx + i[0];
 }
 
@@ -406,7 +478,7 @@ __device__ __forceinline__ T interp_corners(const T *p, const T *w)
 {
     typedef T V4 __attribute__((ext_vector_type(4)));
     if (D == 2) {
-        const V4 c = *reinterpret_cast<const V4 *>(p);
+        const V4 c = gload(reinterpret_cast<const V4 *>(p));
         const T l0 = madd(w[0], c.y, ((T)1 - w[0]) * c.x);
         const T l1 = madd(w[0], c.w, ((T)1 - w[0]) * c.z);
         return madd(w[1], l1, ((T)1 - w[1]) * l0);
@@ -415,7 +487,7 @@ __device__ __forceinline__ T interp_corners(const T *p, const T *w)
     T acc = (T)0;
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz) {
-        const V4 c = cv[dz];
+        const V4 c = gload(cv + dz);
         const T line0 = madd(w[0], c.y, ((T)1 - w[0]) * c.x);
         const T line1 = madd(w[0], c.w, ((T)1 - w[0]) * c.z);
         T layer = madd((T)1 - w[1], line0, (T)0);
@@ -465,9 +537,15 @@ __global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, in
 // Domain, exit test and increment law: read from the problem and item at run
 // time, or fixed at compile time for the common box / bridge / Gaussian case,
 // which removes their branches and frees the registers of the other cases.
+// `dense`: the form of the bridge test for walks in which many lanes of a
+// wave are near a face at every step (short paths, a wide step against the
+// box), where the per-lane branches of the other form would run at nearly
+// every step; both give the same bits.
 struct RuntimeMode {
     template <class T>
     __device__ static __forceinline__ int domain(const DevProblem<T> &P) { return P.domain; }
+    template <class T>
+    __device__ static __forceinline__ bool dense(const ItemCore<T> &a) { return a.dense_bridge != 0; }
     template <class T>
     __device__ static __forceinline__ int exit(const ItemCore<T> &a) { return a.exit_mode; }
     template <class T>
@@ -475,7 +553,8 @@ struct RuntimeMode {
     template <class T>
     __device__ static __forceinline__ uint32_t tab(const DevProblem<T> &P) { return P.tab; }
 };
-struct BoxBridgeGauss {
+template <bool DENSE>
+struct BoxBridgeGaussT {
     template <class T>
     __device__ static constexpr int domain(const DevProblem<T> &) { return kBox; }
     template <class T>
@@ -484,7 +563,11 @@ struct BoxBridgeGauss {
     __device__ static constexpr int law(const ItemCore<T> &) { return kLawGauss; }
     template <class T>
     __device__ static constexpr uint32_t tab(const DevProblem<T> &) { return 0u; }
+    template <class T>
+    __device__ static constexpr bool dense(const ItemCore<T> &) { return DENSE; }
 };
+using BoxBridgeGauss = BoxBridgeGaussT<false>;
+using BoxBridgeGaussDense = BoxBridgeGaussT<true>;
 
 template <class T, int D>
 __device__ __forceinline__ T inner_distance(const DevProblem<T> &P, int domain, const T *x)
@@ -578,7 +661,7 @@ struct Walker {
     __device__ __forceinline__ uint32_t stream(const ItemCore<T> &a) const { return RNG_TABLE ? tag : a.stream_tag; }
     uint32_t bb_blk;
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
-    KeySchedule ks;
+    KeysOf<T> ks;
     const T *cf;          // dense source coefficients of the problem, in LDS
 
     // Starts path r (slot within the item) of item a. Returns false when it
@@ -600,13 +683,13 @@ struct Walker {
             uint32_t lo = 0, hi = a.n_nodes;  // node_start[lo] <= r < node_start[hi]
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (a.node_start[mid] <= r)
+                if (gload(a.node_start + mid) <= r)
                     lo = mid;
                 else
                     hi = mid;
             }
             node = lo;
-            jj = r - a.node_start[lo];
+            jj = r - gload(a.node_start + lo);
         }
         // the path's RNG counter: its node, stream and path index in its own solve
         j = (uint32_t)(a.path_offset + jj);
@@ -614,14 +697,15 @@ struct Walker {
         if (RNG_TABLE) {
             tag = a.stream_tag;
             if (node_rng) {
-                const uint4 v = reinterpret_cast<const uint4 *>(node_rng)[node];
+                typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+                const U4 v = gload(reinterpret_cast<const U4 *>(node_rng) + node);
                 rnode = v.x;
                 tag = v.y;
                 j = v.z + (uint32_t)jj;
             }
         }
 #pragma unroll
-        for (int d = 0; d < D; ++d) X[d] = (T)a.nodes[(size_t)node * D + d];
+        for (int d = 0; d < D; ++d) X[d] = (T)gload(a.nodes + (size_t)node * D + d);
         node = rnode;
         m = inner_distance<T, D>(P, M::domain(P), X);
         Y = (T)1;
@@ -637,14 +721,30 @@ struct Walker {
         return true;
     }
 
-    __device__ __forceinline__ T bridge_uniform(const ItemCore<T> &a, uint32_t s)
+    // Bridge block of step s for every active lane when some lane needs it
+    // and does not hold it (wave-uniform branch).
+    __device__ __forceinline__ void bridge_block(const ItemCore<T> &a, uint32_t s, bool need)
     {
         const uint32_t blk = s >> 2;
-        if (blk != bb_blk) {
+        if (__ballot(need && blk != bb_blk)) {
             const Block4 q = philox(blk, j, node, stream(a) | 1u, ks);
             bw01 = (uint64_t)q.w0 | ((uint64_t)q.w1 << 32);
             bw23 = (uint64_t)q.w2 | ((uint64_t)q.w3 << 32);
             bb_blk = blk;
+        }
+    }
+    // The bridge uniform of step s: from the block bridge_block has drawn
+    // (boundary-dense walks), or drawn here for this lane.
+    __device__ __forceinline__ T bridge_uniform(const ItemCore<T> &a, uint32_t s)
+    {
+        if (!M::dense(a)) {
+            const uint32_t blk = s >> 2;
+            if (blk != bb_blk) {
+                const Block4 q = philox(blk, j, node, stream(a) | 1u, ks);
+                bw01 = (uint64_t)q.w0 | ((uint64_t)q.w1 << 32);
+                bw23 = (uint64_t)q.w2 | ((uint64_t)q.w3 << 32);
+                bb_blk = blk;
+            }
         }
         // word s mod 4, picked with a shift (a select chain becomes a stack array)
         const uint32_t w = (uint32_t)(((s & 2) ? bw23 : bw01) >> ((s & 1) << 5));
@@ -716,10 +816,16 @@ struct Walker {
         // a_f >= m and a'_f >= mn, no face is live unless m mn passes that test.
         const bool out = !shift && !(mn > (T)0);
         const bool maybe = M::exit(a) == kExitBridge && m * mn * a.two_over_s2h <= a.bridge_thresh;
+        if (M::exit(a) == kExitBridge && M::dense(a)) bridge_block(a, s, maybe);
         const bool next_stop = k == a.max_steps || (shift && mn <= a.gm_thresh);
         if (out || maybe || next_stop) {
-            if (out) {
-                project<T, D>(P, M::domain(P), Xn, Xt);
+            if (out) {  // outside (or on) the boundary: the nearest point is the clamp
+                if (M::domain(P) == kBox) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) Xt[d] = med3(Xn[d], P.lo[d], P.hi[d]);
+                } else {
+                    radial<T, D>(P, Xn, Xt);
+                }
                 return false;
             }
             if (maybe && bridge_exit(a, P, Xn, mn, s)) return false;
@@ -745,7 +851,74 @@ struct Walker {
     __device__ __forceinline__ bool bridge_exit(const ItemCore<T> &a, const DevProblem<T> &P,
                                                 const T *Xn, T mn, uint32_t s)
     {
-        if (M::domain(P) == kBox) {
+        if (M::domain(P) == kBox && M::dense(a)) {
+            // Per axis the face with the smaller argument: unless both faces
+            // of the axis are live (a box narrow against the step), it is the
+            // only one that can be, so one exponential per axis gives the
+            // combined probability and the exit face of the face-by-face rule
+            // (live faces combined in face order, the exit face the first of
+            // the largest probabilities), with the same operands and
+            // roundings. Lanes with both faces of an axis live take every face
+            // in turn.
+            T alo[D], ahi[D], ad[D];
+            bool both = false, live[D], up[D];
+            int nlive = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                alo[d] = ((X[d] - P.lo[d]) * (Xn[d] - P.lo[d])) * a.two_over_s2h;
+                ahi[d] = ((P.hi[d] - X[d]) * (P.hi[d] - Xn[d])) * a.two_over_s2h;
+                both = both || (alo[d] <= a.bridge_thresh && ahi[d] <= a.bridge_thresh);
+                up[d] = ahi[d] < alo[d];
+                ad[d] = up[d] ? ahi[d] : alo[d];
+                live[d] = ad[d] <= a.bridge_thresh;
+                nlive += live[d] ? 1 : 0;
+            }
+            // one live axis (the usual case): its face alone
+            T amin = ad[0];
+            int bestf = up[0] ? 1 : 0;
+#pragma unroll
+            for (int d = 1; d < D; ++d) {
+                amin = live[d] ? ad[d] : amin;
+                bestf = live[d] ? 2 * d + (up[d] ? 1 : 0) : bestf;
+            }
+            T Pe = nlive ? Arith<T>::exp_neg(amin) : (T)0;
+            if (nlive > 1) {  // near a corner: the live axes in order
+                T bestp = (T)0;
+                Pe = (T)0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const T p = Arith<T>::exp_neg(ad[d]);
+                    Pe = live[d] ? madd(p, (T)1 - Pe, Pe) : Pe;
+                    const bool better = live[d] && p > bestp;
+                    bestp = better ? p : bestp;
+                    bestf = better ? 2 * d + (up[d] ? 1 : 0) : bestf;
+                }
+            }
+            if (__builtin_expect(__ballot(both) != 0, 0)) {
+                if (both) {  // every live face, in face order
+                    Pe = (T)0;
+                    T bestp = (T)0;
+#pragma unroll
+                    for (int q = 0; q < 2 * D; ++q) {
+                        const T aq = (q & 1) ? ahi[q >> 1] : alo[q >> 1];
+                        const bool live = aq <= a.bridge_thresh;
+                        const T p = Arith<T>::exp_neg(aq);
+                        Pe = live ? madd(p, (T)1 - Pe, Pe) : Pe;
+                        const bool better = live && p > bestp;
+                        bestp = better ? p : bestp;
+                        bestf = better ? q : bestf;
+                    }
+                }
+            }
+            if (bridge_uniform(a, s) < Pe) {
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    Xt[d] = (bestf >> 1) == d ? ((bestf & 1) ? P.hi[d] : P.lo[d]) : Xn[d];
+                return true;
+            }
+            return false;
+        }
+        if (M::domain(P) == kBox) {  // few lanes near a face: per face, one exponential for one live face
             T arg[2 * D];
             T amin = (T)0;
             int fmin = -1, nlive = 0;
@@ -807,16 +980,16 @@ struct Walker {
         const uint64_t r = slot - rec_base;
         if (EST == kEstIto) {  // phi and phi + xi
             const double phi = madd((double)gv, (double)Y, Z);
-            a.rec_phi[r] = phi;
-            a.rec_e[r] = phi + R;
+            gstore(a.rec_phi + r, phi);
+            gstore(a.rec_e + r, phi + R);
         } else if (a.score_plain) {
-            a.rec_phi[r] = madd((double)gv, (double)Y, Z);
+            gstore(a.rec_phi + r, madd((double)gv, (double)Y, Z));
         }
         if (EST == kEstCorrection) {
             const T up = interp<T, D>(a.u_prev, Xt);
-            a.rec_e[r] = madd((double)gv - (double)up, (double)Y, -R);
+            gstore(a.rec_e + r, madd((double)gv - (double)up, (double)Y, -R));
         }
-        a.rec_steps[r] = k | (capped ? kCappedBit : 0u);
+        gstore(a.rec_steps + r, k | (capped ? kCappedBit : 0u));
     }
 };
 
@@ -887,7 +1060,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     __syncthreads();
     Walker<T, D, EST, M, false> w;
     w.cf = s_cf;
-    w.ks = key_schedule(P.key0, P.key1);
+    w.ks = key_schedule<KeysOf<T>>(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     Pool pool;
 
@@ -1049,7 +1222,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                     q.move(items, L, lane, k);
                     if (!q.done && q.cur != prev) {
                         const ItemDesc<T> &it = items[q.cur];
-                        w.ks = key_schedule(probs[it.prob].key0, probs[it.prob].key1);
+                        w.ks = key_schedule<KeysOf<T>>(probs[it.prob].key0, probs[it.prob].key1);
                         if (lane < kMaxDense) my_cf[lane] = probs[it.prob].fdense[lane];
                     }
                 }
@@ -1467,9 +1640,12 @@ hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g,
 
 template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
-                              const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s)
+                              const DevProblem<T> *probs, int grid, int block, int kind, hipStream_t s)
 {
-    if (spec)
+    if (kind == kKernelDense)
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), 0, s, l,
+                           items, probs);
+    else if (kind == kKernelSparse)
         hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
                            items, probs);
     else
@@ -1479,11 +1655,13 @@ hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
 }
 
 template <class T, int D, int EST>
-hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s)
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, int kind, hipStream_t s)
 {
-    static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
     if constexpr (kOneItemKernel<T, D, EST>) {
-        if (spec)
+        static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
+        if (kind == kKernelDense)
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), 0, s, a);
+        else if (kind == kKernelSparse)
             hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
         else
             hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, a);
@@ -1494,14 +1672,16 @@ hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, 
 }
 
 template <class T, int D, int EST>
-const void *path_kernel_symbol(bool one, bool spec)
+const void *path_kernel_symbol(bool one, int kind)
 {
     if constexpr (kOneItemKernel<T, D, EST>)
         if (one)
-            return spec ? reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, BoxBridgeGauss>)
-                        : reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, RuntimeMode>);
-    return spec ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGauss>)
-                : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
+            return kind == kKernelDense    ? reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, BoxBridgeGaussDense>)
+                   : kind == kKernelSparse ? reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, BoxBridgeGauss>)
+                                           : reinterpret_cast<const void *>(&path_kernel_one<T, D, EST, RuntimeMode>);
+    return kind == kKernelDense    ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGaussDense>)
+           : kind == kKernelSparse ? reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, BoxBridgeGauss>)
+                                   : reinterpret_cast<const void *>(&path_kernel_many<T, D, EST, RuntimeMode>);
 }
 
 template <class S, class T, int D>
@@ -1537,9 +1717,9 @@ PDD_GRID_CELLS(double, float, 3)
 
 #define PDD_INSTANTIATE(T, D, EST)                                                              \
     template hipError_t launch_path_kernel<T, D, EST>(const LaunchArgs &, const ItemDesc<T> *, \
-                                                     const DevProblem<T> *, int, int, bool, hipStream_t); \
-    template hipError_t launch_path_kernel_one<T, D, EST>(const OneItemArgs<T> &, int, int, bool, hipStream_t); \
-    template const void *path_kernel_symbol<T, D, EST>(bool, bool);
+                                                     const DevProblem<T> *, int, int, int, hipStream_t); \
+    template hipError_t launch_path_kernel_one<T, D, EST>(const OneItemArgs<T> &, int, int, int, hipStream_t); \
+    template const void *path_kernel_symbol<T, D, EST>(bool, int);
 
 PDD_INSTANTIATE(float, 2, kEstPlain)
 PDD_INSTANTIATE(float, 2, kEstCorrection)

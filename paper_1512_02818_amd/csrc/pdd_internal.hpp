@@ -58,6 +58,7 @@ struct GridView {
     int32_t pad;
     T lo[3];
     T inv[3];  // (n - 1) / (hi - lo)
+    T top[3];  // n - 1
 };
 
 template <class T>
@@ -117,6 +118,8 @@ struct ItemCore {
     uint32_t max_steps;
     uint32_t n_nodes;
     uint32_t rec_launch;        // 1: scratch records, at group slot - launch start
+    int32_t dense_bridge;       // 1: the bridge form for boundary-dense walks (generic kernel)
+    int32_t pad_;
     uint64_t slot_begin;        // first slot of the item in the group's slot space
     uint64_t n_slots;
     uint64_t uniform_n;         // paths per node when node_start is null
@@ -246,16 +249,21 @@ struct OneItemArgs {
 template <class T, int D, int EST>
 constexpr bool kOneItemKernel = sizeof(T) == 4 && D == 2 && EST == kEstPlain;
 
-// Launchers (defined in the .hip files). `spec`: every item of the launch is
-// a box problem with the bridge exit test and Gaussian increments, for which
-// a specialised kernel is compiled. EST: kEstPlain, kEstCorrection or kEstIto.
+// Kernel kinds: generic (domain, exit test, law and tabulation read at run
+// time), or specialised for box problems with the bridge exit test and
+// Gaussian increments, in the bridge form for walks with few lanes near a
+// face (sparse) or with many (dense). All kinds give the same bits.
+constexpr int kKernelGeneric = 0, kKernelSparse = 1, kKernelDense = 2;
+
+// Launchers (defined in the .hip files). EST: kEstPlain, kEstCorrection or
+// kEstIto; kind: one of the kernel kinds.
 template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
-                              const DevProblem<T> *probs, int grid, int block, bool spec, hipStream_t s);
+                              const DevProblem<T> *probs, int grid, int block, int kind, hipStream_t s);
 template <class T, int D, int EST>
-hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, bool spec, hipStream_t s);
+hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, int kind, hipStream_t s);
 template <class T, int D, int EST>
-const void *path_kernel_symbol(bool one, bool spec);
+const void *path_kernel_symbol(bool one, int kind);
 // Fills `cells` (cell_values entries) from the point values of a grid,
 // converted from S to T.
 template <class S, class T, int D>

@@ -140,6 +140,7 @@ pdd_status run_noalloc(pdd_ctx *ctx, const HostItem &it, const pdd_tuning &tune,
     a.two_over_s2h = (T)(2.0 / (d.sigma * d.sigma * o->dt));
     a.gm_thresh = (T)(kGmShift * sig_sqh);
     a.bridge_thresh = (T)kBridgeSkip;
+    a.dense_bridge = dense_boundary(d, o->dt) ? 1 : 0;
     FinalItem fi;
     std::memset(&fi, 0, sizeof fi);
     fi.out = it.out;
@@ -161,8 +162,8 @@ pdd_status run_noalloc(pdd_ctx *ctx, const HostItem &it, const pdd_tuning &tune,
     HIP_TRY(launch_init_acc(acc, n, nitem, d_final, s));
 
     const bool one = kOneItemKernel<T, D, kEstPlain>;
-    const bool spec = specialised(it);
-    const void *fn = path_kernel_symbol<T, D, kEstPlain>(one, spec);
+    const int kind = !specialised(it) ? kKernelGeneric : a.dense_bridge ? kKernelDense : kKernelSparse;
+    const void *fn = path_kernel_symbol<T, D, kEstPlain>(one, kind);
     const int occ = occupancy(ctx, fn, tune.block, false);
     const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
     for (uint64_t b = 0; b < total; b += per_launch) {
@@ -185,9 +186,9 @@ pdd_status run_noalloc(pdd_ctx *ctx, const HostItem &it, const pdd_tuning &tune,
             A.item = a;
             A.prob = P;
             if (A.item.rec_launch) A.item.rec_base = b;
-            HIP_TRY((launch_path_kernel_one<T, D, kEstPlain>(A, grid, tune.block, spec, s)));
+            HIP_TRY((launch_path_kernel_one<T, D, kEstPlain>(A, grid, tune.block, kind, s)));
         } else {
-            HIP_TRY((launch_path_kernel<T, D, kEstPlain>(L, d_item, d_prob, grid, tune.block, spec, s)));
+            HIP_TRY((launch_path_kernel<T, D, kEstPlain>(L, d_item, d_prob, grid, tune.block, kind, s)));
         }
         // per-node sums of the nodes this launch touched
         // (node i holds slots [i N, (i + 1) N); the longest piece of a node in

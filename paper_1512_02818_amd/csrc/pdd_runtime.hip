@@ -325,6 +325,7 @@ GridView<T> make_view(const pdd_grid *g, int dim)
         v.n[i] = i < dim ? g->n[i] : 1;
         v.lo[i] = (T)g->lo[i];
         v.inv[i] = i < dim ? (T)((double)(g->n[i] - 1) / (g->hi[i] - g->lo[i])) : (T)0;
+        v.top[i] = (T)(v.n[i] - 1);
     }
     return v;
 }
@@ -346,6 +347,21 @@ bool pdd::specialised(const HostItem &it)
 {
     return it.prob->desc.domain == PDD_DOMAIN_BOX && it.o->exit_mode == PDD_EXIT_BRIDGE &&
            it.o->law == PDD_LAW_GAUSS && it.prob->pf.tab == 0;
+}
+
+// A face can be live within about 3.5 sigma sqrt(dt) of it (2 a a' / (sigma^2
+// dt) <= 36 ln 2), so the share of lanes in such a band is about 7 sigma
+// sqrt(dt) / width per axis. Above 15 % nearly every lane of a wave meets a
+// live face within a few steps and the dense form wins (the unit square at dt
+// = 1e-3: 0.89, 15 % faster); the [0, 4]^2 box at dt = 1e-4 (0.035) keeps the
+// per-lane form, 1.5 % faster there.
+bool pdd::dense_boundary(const pdd_problem_desc &d, double dt)
+{
+    const double band = 7.0 * d.sigma * std::sqrt(dt);
+    double share = 0.0;
+    for (int i = 0; i < d.dim; ++i)
+        share += band / (d.domain == PDD_DOMAIN_BOX ? d.hi[i] - d.lo[i] : 2.0 * d.radius);
+    return share > 0.15;
 }
 
 pdd_status pdd::validate_item(HostItem &it)
@@ -693,6 +709,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         a.two_over_s2h = (T)(2.0 / (d.sigma * d.sigma * hh));
         a.gm_thresh = (T)(kGmShift * sig_sqh);
         a.bridge_thresh = (T)kBridgeSkip;
+        a.dense_bridge = dense_boundary(d, hh) ? 1 : 0;
         a.u_prev = make_view<T>(it.u_prev, D);
         a.resid = make_view<T>(it.resid, D);
         if (EST == kEstCorrection) a.resid.cells = d_cells + cell_at[3 * (size_t)q];
@@ -760,9 +777,14 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     const int block = tune.block;
     // (the single-item kernel has no per-node RNG table)
     const bool one = n_k == 1 && kOneItemKernel<T, D, EST> && kfirst[1] == 1;
-    // box / bridge / Gaussian / analytic throughout: the specialised kernel
+    // box / bridge / Gaussian / analytic throughout: the specialised kernel,
+    // in the bridge form of the walks that hold most of the group's slots
     const bool spec = std::all_of(items.begin(), items.end(), [](const HostItem *i) { return specialised(*i); });
-    const void *fn = path_kernel_symbol<T, D, EST>(one, spec);
+    uint64_t dense_slots = 0;
+    for (int q = 0; q < n_items; ++q)
+        if (oitems[q].dense_bridge) dense_slots += oitems[q].n_slots;
+    const int kind = !spec ? kKernelGeneric : 2 * dense_slots >= total ? kKernelDense : kKernelSparse;
+    const void *fn = path_kernel_symbol<T, D, EST>(one, kind);
     // more workgroups than fit at once only queue behind the resident ones
     const int occ = occupancy(ctx, fn, block);
     const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
@@ -802,9 +824,9 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
             // the single item starts at slot 0; scratch records of this launch
             // start at slot b
             if (A.item.rec_launch) A.item.rec_base = b;
-            HIP_TRY((launch_path_kernel_one<T, D, EST>(A, grid, block, spec, s)));
+            HIP_TRY((launch_path_kernel_one<T, D, EST>(A, grid, block, kind, s)));
         } else {
-            HIP_TRY((launch_path_kernel<T, D, EST>(L, d_items, d_probs, grid, block, spec, s)));
+            HIP_TRY((launch_path_kernel<T, D, EST>(L, d_items, d_probs, grid, block, kind, s)));
         }
         if (timed && b + per_launch >= total) HIP_TRY(hipEventRecord(ev.second, s));
         // reduction of the nodes this launch touched: one launch for the items
@@ -951,12 +973,12 @@ pdd_status pdd_init(pdd_ctx **out, int hip_device)
     // cleared here, so that no later launch check mistakes it for its own)
     if (noalloc_attach(hip_device) != PDD_OK) (void)hipGetLastError();
     for (int block : {64, 128, 256})
-        for (bool spec : {false, true}) {
+        for (int kind : {kKernelGeneric, kKernelSparse, kKernelDense}) {
             for (bool one : {false, true}) {
-                occupancy(ctx, path_kernel_symbol<float, 2, kEstPlain>(one, spec), block);
-                occupancy(ctx, path_kernel_symbol<float, 3, kEstPlain>(one, spec), block);
-                occupancy(ctx, path_kernel_symbol<double, 2, kEstPlain>(one, spec), block);
-                occupancy(ctx, path_kernel_symbol<double, 3, kEstPlain>(one, spec), block);
+                occupancy(ctx, path_kernel_symbol<float, 2, kEstPlain>(one, kind), block);
+                occupancy(ctx, path_kernel_symbol<float, 3, kEstPlain>(one, kind), block);
+                occupancy(ctx, path_kernel_symbol<double, 2, kEstPlain>(one, kind), block);
+                occupancy(ctx, path_kernel_symbol<double, 3, kEstPlain>(one, kind), block);
             }
         }
     *out = ctx;
@@ -1352,15 +1374,17 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     // the kernel this group launches for a single item, and its occupancy
     const bool spec = item->problem->desc.domain == PDD_DOMAIN_BOX && item->problem->pf.tab == 0 &&
                       item->opts->exit_mode == PDD_EXIT_BRIDGE && item->opts->law == PDD_LAW_GAUSS;
+    const int kind = !spec ? kKernelGeneric
+                     : dense_boundary(item->problem->desc, item->opts->dt) ? kKernelDense : kKernelSparse;
     auto symbol = [&](auto tag) -> const void * {
         using T = decltype(tag);
         if (dim == 2)
-            return est == kEstCorrection ? path_kernel_symbol<T, 2, kEstCorrection>(true, spec)
-                   : est == kEstIto      ? path_kernel_symbol<T, 2, kEstIto>(true, spec)
-                                         : path_kernel_symbol<T, 2, kEstPlain>(true, spec);
-        return est == kEstCorrection ? path_kernel_symbol<T, 3, kEstCorrection>(true, spec)
-               : est == kEstIto      ? path_kernel_symbol<T, 3, kEstIto>(true, spec)
-                                     : path_kernel_symbol<T, 3, kEstPlain>(true, spec);
+            return est == kEstCorrection ? path_kernel_symbol<T, 2, kEstCorrection>(true, kind)
+                   : est == kEstIto      ? path_kernel_symbol<T, 2, kEstIto>(true, kind)
+                                         : path_kernel_symbol<T, 2, kEstPlain>(true, kind);
+        return est == kEstCorrection ? path_kernel_symbol<T, 3, kEstCorrection>(true, kind)
+               : est == kEstIto      ? path_kernel_symbol<T, 3, kEstIto>(true, kind)
+                                     : path_kernel_symbol<T, 3, kEstPlain>(true, kind);
     };
     const void *fn = prec == PDD_FP32 ? symbol(0.0f) : symbol(0.0);
     const int occ256 = occupancy(ctx, fn, 256);
