@@ -310,6 +310,8 @@ template <class T, int D>
 __device__ __forceinline__ size_t cell_index(const GridView<T> &g, const int *i);
 template <class T, int D>
 __device__ __forceinline__ T interp_corners(const T *p, const T *w);
+template <class T>
+__device__ __forceinline__ T interp_corner_values(T c00, T c10, T c01, T c11, const T *w);
 template <class T, int D>
 __device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T *x, const T *b, T c, T &f,
                                                 const T *cf);
@@ -335,10 +337,21 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
 #pragma unroll
     for (int d = 0; d < D; ++d) r2 = madd(x[d], x[d], r2);
     c = madd(P.c_b, r2, P.c_a);
-    if (tab & 64u) {  // every coefficient tabulated, one record per cell
+    if (tab & 64u) {  // every coefficient tabulated, interleaved
         int i[D];
         T w[D];
         grid_cell<T, D>(P.tabv[3], x, i, w);
+        if (D == 2 && (tab & 128u)) {  // by point: the records of the cell's four corners
+            typedef T V4 __attribute__((ext_vector_type(4)));
+            const uint32_t n0 = (uint32_t)P.tabv[3].n[0];
+            const V4 *r0 = reinterpret_cast<const V4 *>(P.tab_fused) + ((uint32_t)i[1] * n0 + (uint32_t)i[0]);
+            const V4 p00 = gload(r0), p10 = gload(r0 + 1), p01 = gload(r0 + n0), p11 = gload(r0 + n0 + 1);
+            b[0] = interp_corner_values<T>(p00.x, p10.x, p01.x, p11.x, w);
+            b[1 % D] = interp_corner_values<T>(p00.y, p10.y, p01.y, p11.y, w);
+            c = interp_corner_values<T>(p00.z, p10.z, p01.z, p11.z, w);
+            if (want_f) f = interp_corner_values<T>(p00.w, p10.w, p01.w, p11.w, w);
+            return;
+        }
         const T *rec = P.tab_fused + cell_index<T, D>(P.tabv[3], i) * (size_t)((D + 2) << D);
 #pragma unroll
         for (int d = 0; d < D; ++d) b[d] = interp_corners<T, D>(rec + (d << D), w);
@@ -472,6 +485,16 @@ __device__ __forceinline__ size_t cell_index(const GridView<T> &g, const int *i)
     return ((size_t)i[2 % D] * (size_t)(g.n[1] - 1) + i[1]) * mx + i[0];
 }
 
+// Bilinear interpolation from the four corner values of a cell ((0,0),
+// (1,0), (0,1), (1,1)), the operations of interp_corners.
+template <class T>
+__device__ __forceinline__ T interp_corner_values(T c00, T c10, T c01, T c11, const T *w)
+{
+    const T l0 = madd(w[0], c10, ((T)1 - w[0]) * c00);
+    const T l1 = madd(w[0], c11, ((T)1 - w[0]) * c01);
+    return madd(w[1], l1, ((T)1 - w[1]) * l0);
+}
+
 // Interpolation from the 2^D corner values of one cell, stored together at p.
 template <class T, int D>
 __device__ __forceinline__ T interp_corners(const T *p, const T *w)
@@ -532,6 +555,17 @@ __global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, in
                 for (int dx = 0; dx < 2; ++dx)
                     out[(dz * 2 + dy) * 2 + dx] = (T)data[((k + dz) * (uint64_t)n1 + (j + dy)) * (uint64_t)n0 + i + dx];
     }
+}
+
+// Point values of a grid converted from S to T into every stride-th slot (a
+// field of interleaved point records): one thread per point.
+template <class S, class T>
+__global__ void grid_points_kernel(const S *__restrict__ data, uint64_t n_points, T *__restrict__ out,
+                                   uint32_t stride, uint32_t off)
+{
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < n_points;
+         p += (uint64_t)gridDim.x * blockDim.x)
+        out[p * stride + off] = (T)data[p];
 }
 
 // Domain, exit test and increment law: read from the problem and item at run
@@ -1701,6 +1735,25 @@ hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStrea
 {
     return launch_grid_cells_strided<S, T, D>(data, n, cells, 1u << D, 0u, s);
 }
+
+template <class S, class T>
+hipError_t launch_grid_points_strided(const S *data, uint64_t n_points, T *out, uint32_t stride, uint32_t off,
+                                      hipStream_t s)
+{
+    if (n_points == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n_points + 255) / 256, 4096);
+    hipLaunchKernelGGL((grid_points_kernel<S, T>), dim3((uint32_t)blocks), dim3(256), 0, s, data, n_points, out,
+                       stride, off);
+    return hipGetLastError();
+}
+template hipError_t launch_grid_points_strided<float, float>(const float *, uint64_t, float *, uint32_t, uint32_t,
+                                                             hipStream_t);
+template hipError_t launch_grid_points_strided<float, double>(const float *, uint64_t, double *, uint32_t,
+                                                              uint32_t, hipStream_t);
+template hipError_t launch_grid_points_strided<double, float>(const double *, uint64_t, float *, uint32_t,
+                                                              uint32_t, hipStream_t);
+template hipError_t launch_grid_points_strided<double, double>(const double *, uint64_t, double *, uint32_t,
+                                                               uint32_t, hipStream_t);
 
 #define PDD_GRID_CELLS(S, T, D) \
     template hipError_t launch_grid_cells<S, T, D>(const S *, const int32_t *, T *, hipStream_t); \

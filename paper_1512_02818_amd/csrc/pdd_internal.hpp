@@ -84,9 +84,10 @@ struct DevProblem {
     int32_t tab_pad;
     GridView<T> tabv[6];
     // bit 6 of tab: b_0 .. b_{dim-1}, c and f are all tabulated on one
-    // geometry and their cell layouts are interleaved: cell r's record at
-    // tab_fused + r (dim + 2) 2^dim holds the 2^dim corners of b_0, ..., c, f
-    // in that order (tabv[q] then keep only the geometry)
+    // geometry and interleaved (tabv[q] then keep only the geometry): cell r's
+    // record at tab_fused + r (dim + 2) 2^dim holds the 2^dim corners of b_0,
+    // ..., c, f in that order; with bit 7 too (2D only), grid point p (x
+    // fastest) has its record at tab_fused + 4 p, the values of b_0, b_1, c, f.
     const T *tab_fused;
 };
 
@@ -269,6 +270,10 @@ const void *path_kernel_symbol(bool one, int kind);
 template <class S, class T, int D>
 hipError_t launch_grid_cells(const S *data, const int32_t *n, T *cells, hipStream_t s);
 // The same into records of `stride` values per cell, at offset `off` in each.
+// out[p stride + off] = data[p] converted from S to T, p < n_points.
+template <class S, class T>
+hipError_t launch_grid_points_strided(const S *data, uint64_t n_points, T *out, uint32_t stride, uint32_t off,
+                                      hipStream_t s);
 template <class S, class T, int D>
 hipError_t launch_grid_cells_strided(const S *data, const int32_t *n, T *cells, uint32_t stride, uint32_t off,
                                      hipStream_t s);

