@@ -141,7 +141,7 @@ def parse():
                     help="time steps of the nodal-constant fit's cloud in [1e-3, 1e-2] (0 = skip)")
     ap.add_argument("--paper-example", type=int, default=1,
                     help="1: solve the paper's example PDE on the stand-in box (0 = skip)")
-    ap.add_argument("--batch-scale", type=float, default=0.1,
+    ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="path-count scale of the 64-problem batched solve (0 = skip)")
     ap.add_argument("--profile-correction", type=int, default=0,
                     help="only run the correction solve (unit square, 257^2 FP32 grids, h=1e-3) with "
