@@ -97,7 +97,12 @@ struct pdd_ctx {
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
     bool any_done = false, any_staged = false;
     pdd::DeviceBuffer nodes, starts, acc, counters, rec, partials, gather, cells;
-    pdd::DeviceBuffer stage2;  // second stage: tables, stencils and LU factors
+    pdd::DeviceBuffer stage2;  // second stage: tables and stencils
+    // LU factors of the last second stage's subdomain matrices, and what they
+    // factor (the operator, the grid, the interfaces): a call with the same
+    // ones only eliminates its right sides
+    pdd::DeviceBuffer stage2_lu;
+    std::vector<double> stage2_key;
     void *stage = nullptr;
     size_t stage_cap = 0;
     void *readback = nullptr;  // pinned host copy of pilot statistics
@@ -119,4 +124,5 @@ struct pdd_problem {
     pdd::DevProblem<float> pf{};
     pdd::DevProblem<double> pd{};
     pdd::DeviceBuffer tab;  // cell layouts of tabulated coefficients (FP32, then FP64)
+    uint64_t serial = 0;    // unique per problem created in the process
 };

@@ -1478,39 +1478,47 @@ __device__ __forceinline__ double stage2_entry(const double *st, int w, int e)
     return v;
 }
 
+// A lane's double, read by every lane (wave-uniform result).
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Banded LU without pivoting (the stencil matrices are diagonally dominant
-// once h is small enough for the drift) of one subdomain per workgroup, the
-// right side eliminated alongside: the rows of the active window (the pivot
-// row and the w rows below it) stay in LDS in a ring of w + 1 slots; a retired
-// pivot row goes to `factor` (w + 1 upper entries and its right side, stride
-// kStage2MaxBand + 2), and the row w + 1 below it takes its slot. Then back
-// substitution by one wave from the last unknown up, U rows staged through
-// LDS in chunks of 64.
+// once h is small enough for the drift) of one subdomain per workgroup: the
+// rows of the active window (the pivot row and the w rows below it) stay in
+// LDS in a ring of w + 1 slots; a retired pivot row goes to `factor` (its w + 1
+// upper entries; stride kStage2MaxBand + 2, the last slot left for the
+// eliminated right side), the multipliers l(k + 1 + t, k) of pivot k to
+// lmul[k w + t], and the row w + 1 below it takes its slot. The factors depend
+// on the operator, the grid and the subdomains only, not on the data on the
+// interfaces, so a context keeps them for the next call with the same ones.
 constexpr int kStage2LuThreads = 1024;
 
-__global__ void __launch_bounds__(kStage2LuThreads) stage2_lu_kernel(const Stage2Grid g, const SubBox *boxes,
-                                                                     const double *stencil, double *factor)
+__global__ void __launch_bounds__(kStage2LuThreads) stage2_lu_kernel(const SubBox *boxes, const double *stencil,
+                                                                     double *factor, double *lmul)
 {
     constexpr int MW = kStage2MaxBand;
     constexpr int ROW = 2 * MW + 1;
     constexpr int FS = MW + 2;  // factor stride
     constexpr int CH = 64;      // back-substitution chunk
     __shared__ double A[(MW + 1) * ROW];
-    __shared__ double Brhs[MW + 1];
     __shared__ double lcol[MW];
     __shared__ double S[CH * 6];  // stencils of the rows that the next CH pivots bring into the window
-    static_assert((MW + 1) + CH * FS <= (MW + 1) * ROW, "back-substitution buffers fit the window");
     const SubBox bx = boxes[blockIdx.x];
     const int w = bx.w, R = w + 1;
     const uint64_t n = (uint64_t)w * (uint64_t)bx.L;
     const double *st = stencil + bx.first * 6;
     double *U = factor + bx.first * FS;
+    double *Lm = lmul + bx.first * MW;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < R * (2 * w + 1); idx += blockDim.x) {
         const int rr = idx / (2 * w + 1), e = idx % (2 * w + 1);
         A[rr * ROW + e] = (uint64_t)rr < n ? stage2_entry(st + (size_t)rr * 6, w, e) : 0.0;
     }
-    for (int rr = tid; rr < R; rr += blockDim.x) Brhs[rr] = (uint64_t)rr < n ? st[(size_t)rr * 6 + 5] : 0.0;
     // this thread's (row, column) offsets of the w x w update, the same at
     // every pivot: pair m is update idx = tid + T m (T threads), row offset
     // idx / w and column offset idx % w (no division inside the pivot loop)
@@ -1541,9 +1549,9 @@ __global__ void __launch_bounds__(kStage2LuThreads) stage2_lu_kernel(const Stage
                 int sr = sk + 1 + tid;
                 if (sr >= R) sr -= R;
                 l = A[sr * ROW + (w - 1 - tid)] / A[sk * ROW + w];  // column k of row r: offset k - r + w
-                Brhs[sr] -= l * Brhs[sk];
             }
             lcol[tid] = l;
+            Lm[k * w + tid] = l;
         }
         __syncthreads();
         const uint64_t left = n - 1 - k;  // unknowns after k: rows and columns k + 1 + o exist for o < left
@@ -1573,38 +1581,150 @@ __global__ void __launch_bounds__(kStage2LuThreads) stage2_lu_kernel(const Stage
             if (e >= w) U[k * FS + (e - w)] = A[sk * ROW + e];
             A[sk * ROW + e] = nr < n ? stage2_entry(sn, w, e) : 0.0;
         }
-        if (tid == 0) {
-            U[k * FS + MW + 1] = Brhs[sk];
-            Brhs[sk] = nr < n ? sn[5] : 0.0;
-        }
         if (++sk == R) sk = 0;
     }
-    __syncthreads();
-    double *X = A;                // ring of the last w + 1 solved values
-    double *chunk = A + (MW + 1); // U rows of the current chunk
-    const int lane = tid & 63;
-    for (uint64_t hi = n; hi > 0;) {
-        const uint64_t lo = hi > CH ? hi - CH : 0;
-        for (int idx = tid; idx < (int)(hi - lo) * FS; idx += blockDim.x) chunk[idx] = U[lo * FS + idx];
-        __syncthreads();
-        if (tid < 64) {
-            for (uint64_t k = hi; k-- > lo;) {
-                const double *row = chunk + (k - lo) * FS;
-                const uint64_t c = k + 1 + lane;
-                double t = (lane < w && c < n) ? row[lane + 1] * X[c % R] : 0.0;
+}
+
+// Forward elimination of the right sides (column 5 of the stencils) with the
+// stored multipliers, then back substitution, one subdomain per workgroup,
+// both in wave 0 with the pending rows in registers: row r's value lives in
+// lane r mod w (n = w L, so the w rows of a window fill the lanes). Forward,
+// pivot k: its value y_k (final) is broadcast from lane k mod w, that lane
+// takes row k + w, and every lane subtracts l(r, k) y_k from its row r in
+// k + 1 .. k + w: the products and differences of eliminating the right side
+// alongside the factorization, in its order. y_k goes to the right-side slot
+// of factor row k. Back, from k = n - 1 down: x_k = (its value) / u(k, k) is
+// broadcast, written to u, its lane takes row k - w's y, and every row j in
+// k - w .. k - 1 subtracts u(j, k) x_k. Multipliers, entering right sides and
+// U rows are staged through LDS in chunks.
+constexpr int kStage2SubstThreads = 256;
+
+// dst[i] = src[i] for i < count (count <= PER x the block's threads): each
+// thread issues its PER global loads before any LDS store, so that they are
+// in flight together rather than one after another.
+template <int PER>
+__device__ __forceinline__ void stage_chunk(double *dst, const double *src, int count, int tid)
+{
+    double t[PER];
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
-                const double x = (row[MW + 1] - t) / row[0];
-                if (lane == 0) {
-                    X[k % R] = x;
-                    int i, j;
-                    stage2_point(bx, k, i, j);
-                    g.u[(size_t)j * g.n0 + i] = x;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
+    for (int u = 0; u < PER; ++u) {
+        const int i = tid + u * kStage2SubstThreads;
+        t[u] = i < count ? gload(src + i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = tid + u * kStage2SubstThreads;
+        if (i < count) dst[i] = t[u];
+    }
+}
+
+__global__ void __launch_bounds__(kStage2SubstThreads) stage2_subst_kernel(const Stage2Grid g, const SubBox *boxes,
+                                                                           const double *stencil, double *factor,
+                                                                           const double *lmul)
+{
+    constexpr int MW = kStage2MaxBand;
+    constexpr int FS = MW + 2;  // factor stride
+    constexpr int CH = 64;      // pivots (rows) per chunk
+    constexpr int PF = 8;       // steps whose operands are read ahead
+    __shared__ double Lc[CH * MW];          // forward: multipliers of the chunk's pivots
+    __shared__ double Bc[CH];               // forward: right sides entering the window
+    __shared__ double Uc[(CH + MW) * FS];   // back: U rows lo - w .. hi - 1
+    const SubBox bx = boxes[blockIdx.x];
+    const int w = bx.w;
+    const uint64_t n = (uint64_t)w * (uint64_t)bx.L;
+    const double *st = stencil + bx.first * 6;
+    double *U = factor + bx.first * FS;
+    const double *Lm = lmul + bx.first * MW;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    double v = tid < 64 && lane < w ? st[(size_t)lane * 6 + 5] : 0.0;  // rows 0 .. w - 1
+    int s = 0;  // lane of pivot k: k mod w
+    for (uint64_t k0 = 0; k0 < n; k0 += CH) {
+        const int m = n - k0 < (uint64_t)CH ? (int)(n - k0) : CH;
+        __syncthreads();
+        stage_chunk<CH * MW / kStage2SubstThreads>(Lc, Lm + k0 * w, m * w, tid);
+        for (int idx = tid; idx < m; idx += blockDim.x) {
+            const uint64_t q = k0 + idx + w;  // the row entering the window at pivot k0 + idx
+            Bc[idx] = q < n ? st[q * 6 + 5] : 0.0;
         }
         __syncthreads();
+        if (tid < 64) {
+            double ybuf = 0.0;  // lane i keeps y of pivot k0 + i
+            for (int i0 = 0; i0 < m; i0 += PF) {
+                // this lane's multipliers and the entering right sides of the
+                // next PF pivots, read ahead of the dependent chain
+                double lv[PF], bv[PF];
+                int su = s;
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    int d = lane - su - 1;  // this lane's row at pivot k0 + i0 + u: k + 1 + d
+                    if (d < 0) d += w;
+                    const bool ok = i0 + u < m && lane < w && k0 + i0 + u + 1 + d < n;
+                    lv[u] = ok ? Lc[(i0 + u) * w + d] : 0.0;
+                    bv[u] = i0 + u < m ? Bc[i0 + u] : 0.0;
+                    if (++su == w) su = 0;
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    if (i0 + u >= m) break;
+                    const double yk = readlane_f64(v, s);
+                    ybuf = lane == i0 + u ? yk : ybuf;
+                    v = lane == s ? bv[u] : v;
+                    const double nv = v - lv[u] * yk;
+                    v = lv[u] != 0.0 ? nv : v;  // rows in pivot k's reach (a zero multiplier changes nothing)
+                    if (++s == w) s = 0;
+                }
+            }
+            if (lane < m) U[(k0 + lane) * FS + MW + 1] = ybuf;
+        }
+    }
+    // back substitution; rows n - w .. n - 1 fill lanes 0 .. w - 1
+    s = w - 1;  // lane of row n - 1
+    for (uint64_t hi = n; hi > 0;) {
+        const uint64_t lo = hi > CH ? hi - CH : 0;
+        const uint64_t base = lo > (uint64_t)w ? lo - w : 0;  // rows base .. hi - 1 staged
+        __syncthreads();
+        stage_chunk<((CH + MW) * FS + kStage2SubstThreads - 1) / kStage2SubstThreads>(Uc, U + base * FS,
+                                                                                      (int)(hi - base) * FS, tid);
+        __syncthreads();
+        if (tid < 64) {
+            if (hi == n) v = lane < w ? Uc[(n - w + lane - base) * FS + MW + 1] : 0.0;
+            const int cnt = (int)(hi - lo);
+            double xbuf = 0.0;  // lane i keeps x of row hi - 1 - i
+            for (int i0 = 0; i0 < cnt; i0 += PF) {
+                // rows hi - 1 - i0 - u: the divisor's reciprocal, this lane's
+                // entry of the row it updates and the right side entering the
+                // window
+                double rv[PF], uv[PF], yv[PF];
+                int su = s;
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const uint64_t k = hi - 1 - (uint64_t)(i0 + u);
+                    const bool in = i0 + u < cnt;
+                    int d = su - 1 - lane;  // this lane's row: k - 1 - d
+                    if (d < 0) d += w;
+                    rv[u] = 1.0 / (in ? Uc[(k - base) * FS] : 1.0);
+                    uv[u] = in && lane < w && k >= (uint64_t)(d + 1) ? Uc[(k - 1 - d - base) * FS + (d + 1)] : 0.0;
+                    yv[u] = in && k >= (uint64_t)w ? Uc[(k - w - base) * FS + MW + 1] : 0.0;
+                    if (--su < 0) su = w - 1;
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    if (i0 + u >= cnt) break;
+                    const double xk = readlane_f64(v, s) * rv[u];
+                    xbuf = lane == i0 + u ? xk : xbuf;
+                    v = lane == s ? yv[u] : v;
+                    const double nv = v - uv[u] * xk;
+                    v = uv[u] != 0.0 ? nv : v;
+                    if (--s < 0) s = w - 1;
+                }
+            }
+            if (lane < cnt) {
+                int i, j;
+                stage2_point(bx, hi - 1 - (uint64_t)lane, i, j);
+                g.u[(size_t)j * g.n0 + i] = xbuf;
+            }
+        }
         hi = lo;
     }
 }
@@ -1661,14 +1781,20 @@ hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int
 
 hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
                                int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
-                               hipStream_t s)
+                               double *lmul, bool factored, hipStream_t s)
 {
     if (n_boxes == 0) return hipSuccess;
     hipLaunchKernelGGL(stage2_stencil_kernel, dim3((max_unknowns + 255) / 256, n_boxes), dim3(256), 0, s, P, g,
                        boxes, stencil);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(kStage2LuThreads), 0, s, g, boxes, stencil, factor);
+    if (!factored) {
+        hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(kStage2LuThreads), 0, s, boxes, stencil, factor,
+                           lmul);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(stage2_subst_kernel, dim3(n_boxes), dim3(kStage2SubstThreads), 0, s, g, boxes, stencil,
+                       factor, lmul);
     return hipGetLastError();
 }
 

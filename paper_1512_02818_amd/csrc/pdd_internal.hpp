@@ -318,11 +318,15 @@ hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int
                                const double *lam, hipStream_t s);
 // Finite-difference stencils of every subdomain's unknowns (6 doubles per
 // unknown: slow-1, fast-1, centre, fast+1, slow+1 coefficients and the right
-// side with the boundary values moved over), then the banded LU solve of each
-// subdomain (one workgroup each) writing the interior values into u.
+// side with the boundary values moved over), then (unless `factored`: factor
+// and lmul already hold the factors of these subdomains' matrices) the banded
+// LU factorization of each subdomain, and the forward elimination and back
+// substitution of its right side (one workgroup each), writing the interior
+// values into u. factor: unknowns x (kStage2MaxBand + 2) doubles; lmul:
+// unknowns x kStage2MaxBand doubles.
 hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
                                int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
-                               hipStream_t s);
+                               double *lmul, bool factored, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 // Starting sums of every group node: zero, or the statistics already in the

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -346,6 +347,12 @@ int pdd::occupancy(pdd_ctx *ctx, const void *fn, int block, bool cache)
 // Largest FP32 cell-record layout of a 2D tabulated problem (about half an
 // XCD's L2); larger grids are interleaved by point.
 constexpr size_t kCellRecordMaxBytes = 8u << 20;
+
+uint64_t next_problem_serial()
+{
+    static std::atomic<uint64_t> next{1};
+    return next.fetch_add(1);
+}
 
 bool pdd::specialised(const HostItem &it)
 {
@@ -997,7 +1004,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
     for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials,
-                            &ctx->gather, &ctx->cells, &ctx->stage2})
+                            &ctx->gather, &ctx->cells, &ctx->stage2, &ctx->stage2_lu})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);
@@ -1019,6 +1026,7 @@ pdd_status pdd_create_problem(pdd_ctx *ctx, const pdd_problem_desc *desc, pdd_pr
     pdd_status st = check_desc(desc);
     if (st) return st;
     pdd_problem *p = new pdd_problem();
+    p->serial = next_problem_serial();
     p->ctx = ctx;
     p->desc = *desc;
     p->trig_rev_max = trig_revolutions(*desc);
@@ -1096,6 +1104,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         tab |= by_point ? 64u | 128u : 64u;
     }
     pdd_problem *p = new pdd_problem();
+    p->serial = next_problem_serial();
     p->ctx = ctx;
     p->desc = *desc;
     p->trig_rev_max = trig_revolutions(*desc);
@@ -1647,16 +1656,32 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
             t_all.insert(t_all.end(), t.begin(), t.end());
             lam_all.insert(lam_all.end(), lam.begin(), lam.end());
         }
-    // device tables: lines | t | lam | boxes | stencils | factors
+    // device tables: lines | t | lam | boxes | stencils
     const size_t off_lines = 0;
     const size_t off_t = align_up(off_lines + lines.size() * sizeof(Stage2Line), 256);
     const size_t off_lam = align_up(off_t + t_all.size() * sizeof(double), 256);
     const size_t off_boxes = align_up(off_lam + lam_all.size() * sizeof(double), 256);
     const size_t table_bytes = align_up(off_boxes + boxes.size() * sizeof(SubBox), 256);
     const size_t off_stencil = table_bytes;
-    const size_t off_factor = align_up(off_stencil + unknowns * 6 * sizeof(double), 256);
-    const size_t bytes = off_factor + unknowns * (kStage2MaxBand + 2) * sizeof(double);
+    const size_t bytes = off_stencil + unknowns * 6 * sizeof(double);
     if ((st = ensure(ctx, ctx->stage2, bytes))) return st;
+    // the subdomain matrices depend on the operator (sigma, b, c), the grid
+    // and the interfaces: factored already when the last call had the same
+    std::vector<double> key = {(double)d.dim, d.lo[0], d.lo[1], d.hi[0], d.hi[1], d.sigma, d.b0[0], d.b0[1],
+                               d.B[0][0], d.B[0][1], d.B[1][0], d.B[1][1], d.c_a, d.c_b,
+                               (problem->pd.tab & 15u) ? (double)problem->serial : -1.0, (double)n[0], (double)n[1]};
+    for (int a = 0; a < 2; ++a) {
+        key.push_back((double)cut_pos[a].size());
+        key.insert(key.end(), cut_pos[a].begin(), cut_pos[a].end());
+    }
+    const size_t lu_bytes = unknowns * (2 * kStage2MaxBand + 2) * sizeof(double);
+    const bool factored = ctx->stage2_key == key && ctx->stage2_lu.ptr && ctx->stage2_lu.cap >= lu_bytes;
+    if (!factored) {
+        ctx->stage2_key.clear();
+        if ((st = ensure(ctx, ctx->stage2_lu, lu_bytes))) return st;
+    }
+    double *d_factor = static_cast<double *>(ctx->stage2_lu.ptr);
+    double *d_lmul = d_factor + unknowns * (kStage2MaxBand + 2);
     if ((st = ensure_stage(ctx, table_bytes))) return st;
     char *h = static_cast<char *>(ctx->stage);
     std::memcpy(h + off_lines, lines.data(), lines.size() * sizeof(Stage2Line));
@@ -1671,8 +1696,9 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
                                 reinterpret_cast<const double *>(dv + off_t),
                                 reinterpret_cast<const double *>(dv + off_lam), s));
     HIP_TRY(launch_stage2_solve(problem->pd, g, reinterpret_cast<const SubBox *>(dv + off_boxes), (int32_t)boxes.size(),
-                                (uint32_t)max_unknowns, reinterpret_cast<double *>(dv + off_stencil),
-                                reinterpret_cast<double *>(dv + off_factor), s));
+                                (uint32_t)max_unknowns, reinterpret_cast<double *>(dv + off_stencil), d_factor, d_lmul,
+                                factored, s));
+    ctx->stage2_key = key;
     HIP_TRY(hipEventRecord(ctx->done, s));
     ctx->any_done = true;
     return PDD_OK;

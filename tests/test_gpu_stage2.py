@@ -98,3 +98,41 @@ def test_stage2_arguments(ctx):
         pdd.stage2(p3, (33, 33), [[0.0], []], np.zeros((0, 2)), np.zeros(0), 3.0)
     assert e.value.status == -4
     p3.close()
+
+
+def test_factor_cache_reuse_and_invalidation(ctx):
+    """A context keeps the LU factors of the last call's subdomain matrices
+    (they depend on the operator, the grid and the interfaces, not on the
+    interface data) and only eliminates the right sides of a call with the
+    same ones. Every call of a sequence that hits and misses the cache gives
+    the bits of the same call in a fresh context, and the hit matches the
+    oracle: new nodal values on the same strips (hit), another drift (miss),
+    other interfaces (miss), back to the first (miss, then hit)."""
+    from oracle import stage2 as S2
+    pd = W.unit_square_problem(seed=0)
+    pd2 = dict(pd, b0=[0.3, -0.2])  # another operator on the same grid
+    nodes = W.unit_square_nodes()
+    rng = np.random.default_rng(3)
+    v1 = W.manufactured_u(pd, nodes) + rng.normal(scale=0.01, size=len(nodes))
+    v2 = W.manufactured_u(pd, nodes) + rng.normal(scale=0.01, size=len(nodes))
+    strips = W.unit_square_partition(129)
+    halves = {"n": (129, 129), "cuts": [[0.5], []], "rbf_eps": 3.0}
+    half_nodes = nodes[np.abs(nodes[:, 0] - 0.5) < 1e-12]
+    half_vals = W.manufactured_u(pd, half_nodes)
+    seq = [(pd, strips, nodes, v1), (pd, strips, nodes, v2), (pd2, strips, nodes, v2),
+           (pd, halves, half_nodes, half_vals), (pd, strips, nodes, v1), (pd, strips, nodes, v2)]
+    probs = {id(pd): pdd.Problem(ctx, pd), id(pd2): pdd.Problem(ctx, pd2)}
+    got = [pdd.stage2(probs[id(p)], part["n"], part["cuts"], x, v, part["rbf_eps"]).cpu().numpy()
+           for p, part, x, v in seq]
+    for p in probs.values():
+        p.close()
+    for (p, part, x, v), u in zip(seq, got):
+        fresh = pdd.Context(0)
+        pr = pdd.Problem(fresh, p)
+        ref = pdd.stage2(pr, part["n"], part["cuts"], x, v, part["rbf_eps"]).cpu().numpy()
+        pr.close()
+        fresh.close()
+        assert u.tobytes() == ref.tobytes()
+    oracle = S2.stage2(pd, strips["n"], strips["cuts"], nodes, v2, strips["rbf_eps"])
+    assert np.max(np.abs(got[1] - oracle) / np.maximum(1.0, np.abs(oracle))) <= 1e-10
+    assert got[0].tobytes() == got[4].tobytes() and got[1].tobytes() == got[5].tobytes()
