@@ -447,7 +447,11 @@ typedef struct {
  * for (1/2) sigma^2 Lap v + b.grad v + c v = f with the values on its
  * boundary, by second-order finite differences on the grid (central second
  * and first differences, b, c, f of the problem in FP64) and a banded LU
- * factorisation without pivoting, one workgroup per subdomain. `nodes` (host,
+ * factorisation without pivoting, one workgroup per subdomain. The factors
+ * depend on the operator (sigma, b, c), the grid and the interfaces only, so
+ * the context keeps those of its last call: a call with the same ones (other
+ * nodal values, another problem with the same analytic operator) only
+ * eliminates and back-substitutes its right sides. `nodes` (host,
  * n_nodes x 2) are the interface nodes and `values` (host) their nodal
  * values; a node may lie on several lines. Synchronous (the interpolation
  * weights are solved on the host once the boundary values are on the
