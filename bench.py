@@ -133,8 +133,8 @@ def parse():
                     help="paths per node of the FP64 variant of the throughput workload, with the FP32 "
                          "paths of the same pairs beside it (0 = skip)")
     ap.add_argument("--tuning", default="cache",
-                    help="launch shape block,blocks_per_cu,grab of the path kernel, 'cache' (the "
-                         "autotuner's cached shape for this GPU, else the default) or 'default'")
+                    help="launch shape block,blocks_per_cu,grab[,refill,bridge] of the path kernel, "
+                         "'cache' (the autotuner's cached shape for this GPU, else the default) or 'default'")
     ap.add_argument("--cv-iterates", type=int, default=1,
                     help="1: report the correction iterates 10^3 -> 10^5 (0 = skip)")
     ap.add_argument("--fit-cloud", type=int, default=100,
@@ -267,34 +267,46 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
     tr = torch.as_tensor(gr["data"]).cuda().contiguous()
     gg = W.gradient_grids(pd, n=257, seed=1, dtype=np.float32)
     gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
+    gu64, gr64, _ = W.correction_grids(pd, n=257, seed=1, dtype=np.float64)
+    tu64 = torch.as_tensor(gu64["data"]).cuda().contiguous()
+    tr64 = torch.as_tensor(gr64["data"]).cuda().contiguous()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     budget = tol / np.sqrt(2.0)
     nstat = pdd.STATS_DTYPE.itemsize
+
+    precision = {"plain": "fp64", "plain32": "fp32", "cv": "fp32", "cv64": "fp64", "ito": "fp32"}
 
     def items_for(kind, dt, replicas, stream0, out):
         its = []
         for r in range(replicas):
             it = {"problem": prob, "nodes": nodes,
                   "out": out[r * len(nodes) * nstat:(r + 1) * len(nodes) * nstat],
-                  "opts": dict(dt=dt, precision="fp64" if kind == "plain" else "fp32",
-                               stream_id=stream0 + r)}
+                  "opts": dict(dt=dt, precision=precision[kind], stream_id=stream0 + r)}
             if kind == "cv":
                 it.update(u_prev=gu, u_prev_t=tu, resid=gr, resid_t=tr)
+            elif kind == "cv64":
+                it.update(u_prev=gu64, u_prev_t=tu64, resid=gr64, resid_t=tr64)
             elif kind == "ito":
                 it.update(grad=gg, grad_t=gt)
             its.append(it)
         return its
 
     res = {}
-    for kind, reps in (("plain", replicas_plain), ("cv", replicas_cv), ("ito", replicas_ito)):
+    # plain FP32 and correction FP64 take the step of their other-precision
+    # twin (the time-step bias is the scheme's; FP32 and FP64 paths of the
+    # [0,4]^2 workload differ by 2e-5 RMS per node), and separate the
+    # node-solve ratio of the correction estimator into its factors
+    twin = {"plain32": "plain", "cv64": "cv"}
+    for kind, reps in (("plain", replicas_plain), ("plain32", replicas_plain), ("cv", replicas_cv),
+                       ("cv64", max(1, replicas_cv // 4)), ("ito", replicas_ito)):
         # dt: the largest rung whose measured RMS bias fits half the budget
         # (the bias estimate removes the sampling variance of the means)
         ladder = []
-        chosen = DT_LADDER[-1]
+        chosen = res[twin[kind]]["dt"] if kind in twin else DT_LADDER[-1]
         cal_reps, cal_paths = (8, 1_000_000) if kind == "plain" else (8, 200_000)
         cal_out = pdd.alloc_stats(cal_reps * len(nodes))
-        for dt in DT_LADDER:
+        for dt in (DT_LADDER if kind not in twin else []):
             its = items_for(kind, dt, cal_reps, 1 << 20, cal_out)
             for it in its:
                 it["opts"]["n_paths"] = cal_paths
@@ -342,8 +354,8 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
                      "rms_error": float(np.sqrt(np.mean(err ** 2))),
                      "dt": chosen, "mean_paths_per_node": float(st["n"].mean()),
                      "path_steps": int(st["steps_sum"].sum()),
-                     "precision": "fp64" if kind == "plain" else "fp32",
-                     "dt_ladder": ladder}
+                     "precision": precision[kind],
+                     "dt_ladder": ladder if kind not in twin else f"the step of {twin[kind]}"}
         if kind == "cv":
             res[kind]["small_pilot"] = small
             print(f"cv with a 128-path pilot: {small['node_solves_per_s']:.3e} node-solves/s, RMS err "
@@ -356,9 +368,18 @@ def node_solves_at_rms(ctx, tol, replicas_plain, replicas_cv, replicas_ito):
             "workload": "unit square, 18 interface nodes per replica, manufactured u; "
                         "CV: u_prev = u + 32-mode Fourier perturbation (amplitude 1e-2) on 257^2, FP32 grids; "
                         "Ito CV: the gradient of the same u_prev on 257^2 FP32 grids",
-            "plain_fp64": res["plain"], "cv_fp32": res["cv"], "ito_cv_fp32": res["ito"],
+            "plain_fp64": res["plain"], "plain_fp32": res["plain32"], "cv_fp32": res["cv"], "cv_fp64": res["cv64"],
+            "ito_cv_fp32": res["ito"],
             "ratio_cv_fp32_over_plain_fp64": res["cv"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"],
-            "ratio_ito_cv_fp32_over_plain_fp64": res["ito"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"]}
+            "ratio_ito_cv_fp32_over_plain_fp64": res["ito"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"],
+            # the correction estimator's ratio in factors: the precision of
+            # the paths (plain FP32 / plain FP64, same dt), the estimator and
+            # its larger step at FP64 (correction FP64 / plain FP64), and
+            # the precision again under the correction estimator
+            "ratio_factors": {
+                "plain_fp32_over_plain_fp64": res["plain32"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"],
+                "cv_fp64_over_plain_fp64": res["cv64"]["node_solves_per_s"] / res["plain"]["node_solves_per_s"],
+                "cv_fp32_over_cv_fp64": res["cv"]["node_solves_per_s"] / res["cv64"]["node_solves_per_s"]}}
 
 
 def cv_iteration(ctx):
@@ -828,7 +849,7 @@ def main():
     if args.tuning == "cache":
         tuning.load(ctx)
     elif args.tuning != "default":
-        shape = tuple(int(v) for v in args.tuning.split(","))
+        shape = tuning.to_fields(args.tuning.split(","))
     prob = pdd.Problem(ctx, pd)
     outs = [pdd.alloc_stats(len(nodes)) for _ in range(args.warmup + args.steps)]
 
@@ -838,7 +859,7 @@ def main():
     def step(s):
         pdd.solve_nodes(prob, nodes, out=outs[s], dt=H, n_paths=P, path_offset=s * P,
                         precision=args.precision, time_kernel=True,
-                        tuning=None if shape is None else shape + (0,))
+                        tuning=shape)
 
     for s in range(args.warmup):
         step(s)

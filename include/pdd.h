@@ -130,15 +130,21 @@ typedef struct {
 
 /* Launch shape of the path kernel. A solve whose opts give no tuning uses the
  * context's entry for its (precision, dim, estimator) group, set by
- * pdd_autotune or pdd_set_tuning, else the default {256, occupancy, 64, 0};
- * fields left 0 in a given tuning take the default. Results never depend on
- * the launch shape. */
+ * pdd_autotune or pdd_set_tuning, else the default {256, occupancy, 64, 0,
+ * 0, 0}; fields left 0 in a given tuning take the default. Results never
+ * depend on the launch shape. */
 typedef struct {
     int32_t block;        /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;/* persistent workgroups per compute unit */
     int32_t grab;         /* paths a wavefront takes from the queue at a time */
     int32_t max_launch_paths; /* cap on paths per path-kernel launch (0 = 2^27; records
                                  given by the caller: no cap) */
+    int32_t refill;       /* walk-loop iterations between refills of the lanes that
+                             ended a path: 1, 2, 4 or 8 (0 = 2 in 2D, 4 in 3D; an
+                             iteration is two steps in 2D, one in 3D) */
+    int32_t bridge;       /* form of the bridge exit test in the box / bridge /
+                             Gaussian kernel: 1 per lane, 2 for the whole wave
+                             (boundary-dense walks), 0 = by the walk's boundary density */
 } pdd_tuning;
 
 typedef struct {

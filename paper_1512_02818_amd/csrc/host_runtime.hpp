@@ -64,6 +64,13 @@ inline int tuning_key(int precision, int dim, int est, bool generic)
 }
 // Whether an item can run in the specialised kernel.
 bool specialised(const HostItem &it);
+// The launch's refill mask: walk-loop iterations between lane refills, less
+// one (the tuning's, else every second iteration in 2D, every fourth in 3D).
+template <int D>
+inline uint32_t refill_mask(const pdd_tuning &t)
+{
+    return (uint32_t)((t.refill ? t.refill : (D == 2 ? 2 : 4)) - 1);
+}
 // Whether many lanes of a wave are near a face at every step of a walk of
 // this problem at step dt (then the dense form of the bridge test is the
 // faster one).

@@ -1027,14 +1027,13 @@ struct Walker {
     }
 };
 
-// Lanes end paths at any step but take new ones only every kRefillPeriod
-// iterations of the walk loop (two steps per iteration in 2D, one in 3D), so
-// every path of a wave starts at a step count that is the same modulo 4
-// across its lanes: the bridge uniforms of four consecutive steps share one
-// Philox block, which the wave then draws at most once per four steps, and
-// the scoring and start of new paths run for several lanes at once.
-template <int D>
-constexpr uint32_t kRefillPeriod = D == 2 ? 2 : 4;
+// Lanes end paths at any step but take new ones only every few iterations of
+// the walk loop (two steps per iteration in 2D, one in 3D; the launch's
+// refill_mask, by default every second iteration in 2D and every fourth in
+// 3D): every path of a wave then starts at a step count that is the same
+// modulo 4 across its lanes, so the bridge uniforms of four consecutive steps
+// share one Philox block, which the wave then draws at most once per four
+// steps, and the scoring and start of new paths run for several lanes at once.
 
 // Item whose slot range holds group slot s (items are sorted, non-empty
 // ranges never overlap). Wave-uniform: a scalar binary search.
@@ -1099,7 +1098,7 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     Pool pool;
 
     for (uint32_t iter = 0;; ++iter) {
-        if ((iter & (kRefillPeriod<D> - 1)) == 0) {  // refill turn (wave-uniform)
+        if ((iter & L.refill_mask) == 0) {  // refill turn (wave-uniform)
             if (st == 2) {
                 w.finish(a, P, a.rec_base);  // set per launch by the host
                 st = 0;
@@ -1230,7 +1229,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     ItemQueue<T> q;
 
     for (uint32_t iter = 0;; ++iter) {
-        if ((iter & (kRefillPeriod<D> - 1)) == 0) {  // refill turn (wave-uniform)
+        if ((iter & L.refill_mask) == 0) {  // refill turn (wave-uniform)
             if (st == 2) {
                 const ItemDesc<T> &it = items[q.cur];
                 // scratch records sit at group slot - launch start (modular arithmetic)

@@ -160,7 +160,7 @@ struct LaunchArgs {
     int32_t grab;
     int32_t item_lo;
     uint32_t n_seg;
-    uint32_t pad;
+    uint32_t refill_mask;  // lanes are refilled at walk-loop iterations i with (i & refill_mask) == 0
     uint32_t *counter;
     const uint32_t *seg;
 };

@@ -162,7 +162,11 @@ pdd_status run_noalloc(pdd_ctx *ctx, const HostItem &it, const pdd_tuning &tune,
     HIP_TRY(launch_init_acc(acc, n, nitem, d_final, s));
 
     const bool one = kOneItemKernel<T, D, kEstPlain>;
-    const int kind = !specialised(it) ? kKernelGeneric : a.dense_bridge ? kKernelDense : kKernelSparse;
+    const int kind = !specialised(it)   ? kKernelGeneric
+                     : tune.bridge == 1 ? kKernelSparse
+                     : tune.bridge == 2 ? kKernelDense
+                     : a.dense_bridge   ? kKernelDense
+                                        : kKernelSparse;
     const void *fn = path_kernel_symbol<T, D, kEstPlain>(one, kind);
     const int occ = occupancy(ctx, fn, tune.block, false);
     const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
@@ -177,6 +181,7 @@ pdd_status run_noalloc(pdd_ctx *ctx, const HostItem &it, const pdd_tuning &tune,
         L.counter = counter;
         L.item_lo = 0;
         L.n_seg = 1;
+        L.refill_mask = refill_mask<D>(tune);
         L.seg = d_seg + (len == per_launch ? 0 : 2);
         const uint64_t blocks_needed = ((len + 63) / 64 * 64 + tune.block - 1) / tune.block;
         const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, blocks_needed));

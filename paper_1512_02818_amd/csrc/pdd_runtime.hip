@@ -462,6 +462,9 @@ pdd_status check_tuning(const pdd_tuning &tune)
     if (tune.grab < 1 || tune.grab > 4096 || tune.blocks_per_cu < 0 || tune.blocks_per_cu > 64 ||
         tune.max_launch_paths < 0)
         return fail(PDD_E_INVALID, "tuning out of range");
+    if (tune.refill != 0 && tune.refill != 1 && tune.refill != 2 && tune.refill != 4 && tune.refill != 8)
+        return fail(PDD_E_INVALID, "tuning.refill must be 0, 1, 2, 4 or 8");
+    if (tune.bridge < 0 || tune.bridge > 2) return fail(PDD_E_INVALID, "tuning.bridge must be 0, 1 or 2");
     return PDD_OK;
 }
 
@@ -471,7 +474,7 @@ pdd_status check_tuning(const pdd_tuning &tune)
 // else the context's table entry for the group's key, else the default.
 pdd_status pdd::read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key, pdd_tuning &tune)
 {
-    tune = pdd_tuning{256, 0, 64, 0};
+    tune = pdd_tuning{256, 0, 64, 0, 0, 0};
     if (!o->tuning && key >= 0) {
         auto f = ctx->tuned.find(key);
         if (f != ctx->tuned.end()) tune = f->second;
@@ -481,6 +484,8 @@ pdd_status pdd::read_tuning(const pdd_ctx *ctx, const pdd_solve_opts *o, int key
         if (o->tuning->blocks_per_cu) tune.blocks_per_cu = o->tuning->blocks_per_cu;
         if (o->tuning->grab) tune.grab = o->tuning->grab;
         tune.max_launch_paths = o->tuning->max_launch_paths;
+        if (o->tuning->refill) tune.refill = o->tuning->refill;
+        if (o->tuning->bridge) tune.bridge = o->tuning->bridge;
     }
     return check_tuning(tune);
 }
@@ -794,7 +799,11 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     uint64_t dense_slots = 0;
     for (int q = 0; q < n_items; ++q)
         if (oitems[q].dense_bridge) dense_slots += oitems[q].n_slots;
-    const int kind = !spec ? kKernelGeneric : 2 * dense_slots >= total ? kKernelDense : kKernelSparse;
+    const int kind = !spec                ? kKernelGeneric
+                     : tune.bridge == 1     ? kKernelSparse
+                     : tune.bridge == 2     ? kKernelDense
+                     : 2 * dense_slots >= total ? kKernelDense
+                                            : kKernelSparse;
     const void *fn = path_kernel_symbol<T, D, EST>(one, kind);
     // more workgroups than fit at once only queue behind the resident ones
     const int occ = occupancy(ctx, fn, block);
@@ -822,6 +831,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         L.counter = static_cast<uint32_t *>(ctx->counters.ptr) + ctr_at[launch];
         L.item_lo = (int32_t)seg_lo[launch];
         L.n_seg = seg_n[launch];
+        L.refill_mask = refill_mask<D>(tune);
         L.seg = reinterpret_cast<const uint32_t *>(dv + off_seg) + 2 * ctr_at[launch];
         const uint64_t waves_needed = (len + 63) / 64;
         const uint64_t blocks_needed = (waves_needed * 64 + block - 1) / block;
@@ -1475,7 +1485,7 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
         return PDD_OK;
     };
     float ms = 0.f;
-    const pdd_tuning dflt{256, occ256, 64, 0};
+    const pdd_tuning dflt{256, occ256, 64, 0, 0, 0};
     st = time_one(dflt, 2 * base_paths, ms);  // warm-up (code load, scratch growth)
     // candidates: every block size and grab at full occupancy, and the
     // default block with fewer workgroups per CU
@@ -1483,30 +1493,51 @@ pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out
     for (int block : {64, 128, 256}) {
         const int occ = occupancy(ctx, fn, block);
         for (int grab : {16, 64, 256})
-            if (!(block == 256 && grab == 64)) cands.push_back(pdd_tuning{block, occ, grab, 0});
+            if (!(block == 256 && grab == 64)) cands.push_back(pdd_tuning{block, occ, grab, 0, 0, 0});
     }
-    if (occ256 * 3 / 4 >= 1 && occ256 * 3 / 4 != occ256) cands.push_back(pdd_tuning{256, occ256 * 3 / 4, 64, 0});
-    if (occ256 / 2 >= 1 && occ256 / 2 != occ256 * 3 / 4) cands.push_back(pdd_tuning{256, occ256 / 2, 64, 0});
+    if (occ256 * 3 / 4 >= 1 && occ256 * 3 / 4 != occ256)
+        cands.push_back(pdd_tuning{256, occ256 * 3 / 4, 64, 0, 0, 0});
+    if (occ256 / 2 >= 1 && occ256 / 2 != occ256 * 3 / 4) cands.push_back(pdd_tuning{256, occ256 / 2, 64, 0, 0, 0});
     pdd_tuning best = dflt;
     float best_ms = 1e30f;
     // the cost of a shape is the marginal time of the second P paths, t(2P) -
     // t(P): it cancels the fixed costs and the exit-time tail, which a whole
     // short run would weigh far more than a real solve does
-    for (size_t c = 0; c < cands.size() && !st; ++c) {
-        float t1 = 1e30f, t2 = 1e30f;
-        for (int rep = 0; rep < 2 && !st; ++rep) {
-            st = time_one(cands[c], base_paths, ms);
-            t1 = std::min(t1, ms);
-            if (!st) st = time_one(cands[c], 2 * base_paths, ms);
-            t2 = std::min(t2, ms);
+    auto sweep = [&](const std::vector<pdd_tuning> &cs, bool first) {
+        for (size_t c = 0; c < cs.size() && !st; ++c) {
+            float t1 = 1e30f, t2 = 1e30f;
+            for (int rep = 0; rep < 2 && !st; ++rep) {
+                st = time_one(cs[c], base_paths, ms);
+                t1 = std::min(t1, ms);
+                if (!st) st = time_one(cs[c], 2 * base_paths, ms);
+                t2 = std::min(t2, ms);
+            }
+            const float m = t2 - t1;
+            // the default stands unless a candidate is more than 2% faster
+            if (!st && ((first && c == 0) || m < 0.98f * best_ms)) {
+                best_ms = m;
+                best = cs[c];
+            }
         }
-        const float m = t2 - t1;
-        // the default stands unless a shape is more than 2% faster
-        if (!st && (c == 0 || m < 0.98f * best_ms)) {
-            best_ms = m;
-            best = cands[c];
+    };
+    sweep(cands, true);
+    // then, with the best shape: the refill period, and in the box / bridge /
+    // Gaussian kernel the form of the bridge test
+    std::vector<pdd_tuning> more;
+    for (int r : {1, 2, 4, 8})
+        if (r != (dim == 2 ? 2 : 4)) {
+            pdd_tuning t = best;
+            t.refill = r;
+            more.push_back(t);
         }
-    }
+    if (spec)
+        for (int b : {1, 2})
+            if (b != (kind == kKernelDense ? 2 : 1)) {
+                pdd_tuning t = best;
+                t.bridge = b;
+                more.push_back(t);
+            }
+    sweep(more, false);
     cleanup();
     if (st) return st;
     ctx->tuned[tuning_key(prec, dim, est, !spec)] = best;

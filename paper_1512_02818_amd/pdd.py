@@ -62,7 +62,18 @@ class CoefGrids(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32),
-                ("max_launch_paths", C.c_int32)]
+                ("max_launch_paths", C.c_int32), ("refill", C.c_int32), ("bridge", C.c_int32)]
+
+
+def as_tuning(tuning) -> Tuning:
+    """A Tuning from a Tuning or from its fields in order (block, blocks_per_cu,
+    grab[, max_launch_paths[, refill[, bridge]]]); fields not given are 0 (the default)."""
+    if isinstance(tuning, Tuning):
+        return tuning
+    v = [int(x) for x in tuning]
+    if not 3 <= len(v) <= 6:
+        raise ValueError(f"a tuning has 3 to 6 fields, got {len(v)}")
+    return Tuning(*(v + [0] * (6 - len(v))))
 
 
 class SolveOpts(C.Structure):
@@ -403,7 +414,7 @@ def make_opts(dt, n_paths=0, n_paths_per_node=None, path_offset=0, stream_id=0,
         o.rec_e = records["e"].data_ptr() if records.get("e") is not None else None
         o.rec_steps = records["steps"].data_ptr()
     if tuning is not None:
-        t = Tuning(*[int(v) for v in tuning]) if not isinstance(tuning, Tuning) else tuning
+        t = as_tuning(tuning)
         keep.append(t)
         o.tuning = C.pointer(t)
     o._keep = keep  # noqa: SLF001 - lifetime of the arrays the struct points to
@@ -659,21 +670,22 @@ def kernel_times(ctx: Context, cap=4096):
 
 
 def autotune(ctx: Context, item: dict):
-    """pdd_autotune on a batch-style item dict; returns (block, blocks_per_cu, grab), which
-    the context also keeps for later solves of the same key."""
+    """pdd_autotune on a batch-style item dict; returns the winner's fields (block,
+    blocks_per_cu, grab, max_launch_paths, refill, bridge), which the context
+    also keeps for later solves of the same key."""
     b = Batch([dict(item, out=item.get("out", alloc_stats(0)))])
     t = Tuning()
     _check(lib().pdd_autotune(ctx.handle, b.arr, C.byref(t)))
-    return (t.block, t.blocks_per_cu, t.grab)
+    return (t.block, t.blocks_per_cu, t.grab, t.max_launch_paths, t.refill, t.bridge)
 
 
 def set_tuning(ctx: Context, precision: str, dim: int, correction, tuning=None, generic=False):
-    """pdd_set_tuning: (block, blocks_per_cu, grab[, max_launch_paths]) for the key (correction: 0 / False
-    plain, 1 / True correction estimator, 2 Ito control variate; generic: the
-    generic rather than the box / bridge / Gaussian kernel), or None to remove it."""
+    """pdd_set_tuning: (block, blocks_per_cu, grab[, max_launch_paths[, refill[, bridge]]])
+    for the key (correction: 0 / False plain, 1 / True correction estimator, 2 Ito
+    control variate; generic: the generic rather than the box / bridge / Gaussian
+    kernel), or None to remove it."""
     k = TuningKey(PRECISIONS[precision], int(dim), int(correction), 1 if generic else 0)
-    t = None if tuning is None else Tuning(int(tuning[0]), int(tuning[1]), int(tuning[2]),
-                                           int(tuning[3]) if len(tuning) > 3 else 0)
+    t = None if tuning is None else as_tuning(tuning)
     _check(lib().pdd_set_tuning(ctx.handle, C.byref(k), C.byref(t) if t is not None else None))
 
 

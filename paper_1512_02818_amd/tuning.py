@@ -2,11 +2,12 @@
 
 A JSON object maps "<arch>/<precision>/D<dim>/<plain|correction|ito>", with
 "/generic" appended for the generic kernel (ball domains, the shifted or
-naive exit test, tabulated coefficients), to [block, blocks_per_cu, grab].
-`load` installs the entries of the running GPU's architecture in a context
-(pdd_set_tuning), so solves without an explicit tuning use them; `tune` runs
-pdd_autotune on an item and records the winner. Shapes change only speed,
-never results.
+naive exit test, tabulated coefficients), to [block, blocks_per_cu, grab,
+refill, bridge] (the pdd_tuning fields; older three-field entries leave the
+last two at the library's default). `load` installs the entries of the
+running GPU's architecture in a context (pdd_set_tuning), so solves without an
+explicit tuning use them; `tune` runs pdd_autotune on an item and records the
+winner. Shapes change only speed, never results.
 
     python -m paper_1512_02818_amd.tuning   # tunes the standard workloads, writes the cache
     python -m paper_1512_02818_amd.tuning --only ito   # only the Ito control variate's items
@@ -62,16 +63,31 @@ def read(path: str = DEFAULT_PATH) -> dict:
         data = json.load(f)
     for k, v in data.items():
         parse_key(k)
-        if len(v) != 3:
+        if len(v) not in (3, 5):
             raise ValueError(f"bad shape for {k}: {v}")
     return data
 
 
-def save_entry(path: str, k: str, shape) -> dict:
-    """Adds or replaces one entry; writes the file atomically."""
+def to_fields(entry) -> tuple:
+    """pdd_tuning fields (block, blocks_per_cu, grab, max_launch_paths, refill,
+    bridge) of a cache entry [block, blocks_per_cu, grab(, refill, bridge)]."""
+    v = [int(x) for x in entry]
+    if len(v) == 3:
+        v += [0, 0]
+    return (v[0], v[1], v[2], 0, v[3], v[4])
+
+
+def to_entry(fields) -> list:
+    """Cache entry of a tuning's fields (max_launch_paths is not cached)."""
+    v = [int(x) for x in fields] + [0] * (6 - len(fields))
+    return [v[0], v[1], v[2], v[4], v[5]]
+
+
+def save_entry(path: str, k: str, fields) -> dict:
+    """Adds or replaces one entry (the tuning's fields); writes the file atomically."""
     parse_key(k)
     data = read(path)
-    data[k] = [int(v) for v in shape]
+    data[k] = to_entry(fields)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(dict(sorted(data.items())), f, indent=1)
@@ -92,21 +108,22 @@ def load(ctx: pdd.Context, path: str = DEFAULT_PATH, arch: str | None = None) ->
     for k, shape in read(path).items():
         a, prec, dim, cv, generic = parse_key(k)
         if a == arch:
-            pdd.set_tuning(ctx, prec, dim, cv, shape, generic=generic)
+            pdd.set_tuning(ctx, prec, dim, cv, to_fields(shape), generic=generic)
             n += 1
     return n
 
 
-DEFAULT_SHAPE = (256, 0, 64)  # the library's default: block 256 at full occupancy, grab 64
+# the library's default: block 256 at full occupancy, grab 64, default refill period and bridge form
+DEFAULT_SHAPE = (256, 0, 64, 0, 0, 0)
 
 
 def whole_launch_ms(ctx: pdd.Context, item: dict, shape, n_paths: int, reps: int = 3) -> float:
     """Median path-kernel time of a full solve of `item` with n_paths per node
-    under `shape` (exit-time tail included)."""
+    under the tuning fields `shape` (exit-time tail included)."""
     import numpy as np
     import torch
     it = dict(item, opts=dict(item["opts"], n_paths=int(n_paths), time_kernel=True,
-                              tuning=tuple(shape) + (0,)))
+                              tuning=tuple(shape[:3]) + (0,) + tuple(shape[4:])))
     ms = []
     for r in range(reps + 1):
         it["opts"]["path_offset"] = r * int(n_paths)
