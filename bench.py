@@ -608,6 +608,41 @@ def iterpdd_runs(ctx, tols):
 SWEEP_RATES = (0.5, 1.0, 2.0, 5.0, 20.0)
 
 
+def serving_pipeline(ctx, depths=(1, 2, 3)):
+    """The serving loop with 1, 2 and 3 epochs in flight on one burst of
+    requests (all arriving within 0.1 s; up to 400 nodes, RMS tolerance 1e-2
+    or 3e-3, 30% with a u_prev grid): time to complete all of them, the time
+    with an epoch in flight, throughput and latency. Results are bitwise the
+    same at every depth (checked here on every request)."""
+    from paper_1512_02818_amd import serving
+    from paper_1512_02818_amd import workloads as W
+    problems, reqs = W.serving_stream(seed=41, rate=1000.0, duration=0.1, node_range=(1, 400),
+                                      tols=(1e-2, 3e-3))
+    fx = serving.Fixtures(ctx, problems, reqs)
+    out, ref = [], None
+    for depth in depths:
+        rep, done = serving.run_stream(ctx, problems, reqs, drain_s=120.0, fixtures=fx,
+                                       server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20,
+                                                        pipeline=depth))
+        same = None
+        if ref is None:
+            ref = done
+        else:
+            same = sorted(done) == sorted(ref) and all(done[k]["stats"].tobytes() == ref[k]["stats"].tobytes()
+                                                       for k in ref)
+        out.append({"pipeline": depth, "completed": rep["completed"], "offered": len(reqs),
+                    "wall_s": rep["wall_s"], "busy_s": rep["busy_s"], "epochs": rep["epochs"],
+                    "path_steps": rep["path_steps"], "path_steps_per_s": rep["path_steps"] / max(rep["wall_s"], 1e-9),
+                    "node_solves_per_s": rep["node_solves_per_s"], "p50_ms": rep["p50_ms"],
+                    "p99_ms": rep["p99_ms"], "bitwise_equal_to_depth_1": same})
+        print(f"serving burst, {depth} epoch(s) in flight: {rep['completed']} of {len(reqs)} in "
+              f"{rep['wall_s']:.2f} s, {out[-1]['path_steps_per_s']:.3e} path-steps/s", file=sys.stderr, flush=True)
+    fx.close()
+    return {"workload": f"burst of {len(reqs)} requests within 0.1 s, 1-400 nodes (log-uniform) on 16 random "
+                        "2D/3D box problems, RMS tolerance in {1e-2, 3e-3}, 30% with a u_prev grid, FP32",
+            "depths": out}
+
+
 def serving_sweep(ctx, drain_s):
     """The serving loop at offered loads below the 200 requests/s of the main
     serving run (same request mix, seeded Poisson arrivals, about 12 requests
@@ -968,6 +1003,7 @@ def main():
               file=sys.stderr, flush=True)
         if args.serve_sweep:
             result["serving_sweep"] = serving_sweep(ctx, args.serve_drain)
+            result["serving_pipeline"] = serving_pipeline(ctx)
     if cpu is not None:
         result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)

@@ -511,17 +511,24 @@ pdd_status pdd_kernel_times(pdd_ctx *ctx, double *ms, int32_t cap, int32_t *n);
  * Serving loop: continuous batching of node-solve requests, each to its own
  * standard error (pilot, plan by pdd_plan_paths, continuation in chunks).
  *
- * A server owns a host thread and a HIP stream and is the only user of its
- * context while it lives. The thread runs epochs: each epoch is one
- * pdd_solve_batch-style launch per (precision, dim, estimator) group over the
- * next chunk of admitted requests (a new request's pilot, or the next slice
- * of its planned paths), pilots first, then the requests with the least
- * remaining work (path-steps estimated from the pilot), up to epoch_paths. Requests submitted while an epoch runs wait in
- * a FIFO queue and are admitted at the next epoch boundary when a slot is
- * free and their device memory fits the budget; their chunks then share the
- * launches with those already in flight. A request's chunks depend only on
- * the request and the server options, and each group of an epoch is a single
- * launch, so its results are bitwise the same alone or in any mix.
+ * A server owns a host thread and is the only user of its context while it
+ * lives. The thread runs epochs: each epoch is one pdd_solve_batch-style
+ * launch per (precision, dim, estimator) group over the next chunk of
+ * admitted requests (a new request's pilot, or the next slice of its planned
+ * paths), pilots first, then the requests with the least remaining work
+ * (path-steps estimated from the pilot), up to epoch_paths. Up to `pipeline`
+ * epochs are in flight at once, each on its own HIP stream with its own
+ * scratch (the first on the server's context, the others on contexts the
+ * server creates on the same device): while one epoch finishes its longest
+ * paths, the next one, over requests not in flight, already fills the idle
+ * compute units, and the host plans finished pilots meanwhile. A request is
+ * in at most one epoch in flight, so its chunks run in order. Requests
+ * submitted while epochs run wait in a FIFO queue and are admitted at the
+ * next epoch boundary when a slot is free and their device memory fits the
+ * budget; their chunks then share the launches with those already admitted.
+ * A request's chunks depend only on the request and the server options, and
+ * each group of an epoch is a single launch, so its results are bitwise the
+ * same alone, in any mix, and at any pipeline depth.
  * ------------------------------------------------------------------------ */
 typedef struct pdd_server pdd_server;
 
@@ -533,6 +540,9 @@ typedef struct {
     uint64_t n_max;         /* paths per node at most (0 = 2^31) */
     uint64_t chunk_paths;   /* paths of one request per epoch, cut per request (0 = 2^22) */
     uint64_t epoch_paths;   /* paths per epoch launch, <= 2^27 (0 = 2^27) */
+    int32_t pipeline;       /* epochs in flight at once, 1 to 4 (0 = 2); each holds a
+                               record scratch of epoch_paths paths */
+    int32_t reserved;       /* 0 */
 } pdd_server_opts;
 
 typedef struct {
@@ -579,15 +589,18 @@ typedef struct {
     double mean_ms;                           /* mean latency of completed requests */
     double wall_s;                            /* first submit to last completion */
     double node_solves_per_s;                 /* nodes_completed / wall_s */
-    double epoch_s;                           /* time spent running epochs (enqueue to device done) */
+    double epoch_s;                           /* enqueue-to-done time summed over epochs (epochs in
+                                                 flight together each count) */
     uint64_t cancelled;                       /* cancelled by pdd_server_destroy */
     uint64_t censored;                        /* requests counted at their age (cancelled or unfinished) */
     int32_t p50_censored, p99_censored;       /* 1: the percentile is a lower bound */
     double p50_done_ms, p99_done_ms;          /* percentiles of completed requests alone */
+    double busy_s;                            /* time with at least one epoch in flight */
 } pdd_server_report;
 
 /* Starts a server on `ctx` (NULL opts = defaults). Errors: bad options, a
- * budget smaller than the record scratch, thread or stream creation. */
+ * budget smaller than the record scratch (pipeline x epoch_paths x 20 bytes),
+ * thread, stream or context creation. */
 pdd_status pdd_server_create(pdd_ctx *ctx, const pdd_server_opts *opts, pdd_server **out);
 /* Validates and queues a request; writes its id. PDD_E_INVALID: bad request;
  * PDD_E_NOMEM: it can never fit the budget; PDD_E_UNSUPPORTED: its pilot
@@ -599,9 +612,9 @@ pdd_status pdd_server_poll(pdd_server *server, pdd_completion *out, int32_t cap,
                            int32_t wait_ms);
 /* Counters and latency percentiles so far (pdd_server_report). */
 pdd_status pdd_server_report_get(pdd_server *server, pdd_server_report *out);
-/* Stops the server: the running epoch ends, requests still queued or in
- * flight are cancelled (their `out` is not written), device memory is freed.
- * NULL is a no-op. */
+/* Stops the server: the epochs in flight end, requests still queued or in
+ * flight are cancelled (their `out` is not written), device memory and the
+ * server's own contexts are freed. NULL is a no-op. */
 void pdd_server_destroy(pdd_server *server);
 
 /* Message of the last failure on this thread ("" if none). */

@@ -92,8 +92,11 @@ pdd_status noalloc_attach(int device);
 // dimension, estimator); a group of at most kScratchSlots paths without
 // caller records is one launch. one_launch: such a group stays one launch
 // whatever the tuning's max_launch_paths says (the serving loop, whose
-// results must not depend on the tuning table).
-pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch = false);
+// results must not depend on the tuning table). The items' problems must
+// belong to `owner` (NULL: ctx itself), a context on ctx's device whose
+// problems ctx's scratch then serves.
+pdd_status run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch = false,
+                     const pdd_ctx *owner = nullptr);
 
 }  // namespace pdd
 

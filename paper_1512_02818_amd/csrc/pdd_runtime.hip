@@ -925,12 +925,14 @@ pdd_status run_group_est(int est, pdd_ctx *ctx, std::vector<HostItem *> &g, cons
 }  // namespace
 
 // Validates items, then runs them grouped by (precision, dim, estimator).
-pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch)
+pdd_status pdd::run_items(pdd_ctx *ctx, std::vector<HostItem> &items, hipStream_t s, bool one_launch,
+                          const pdd_ctx *owner)
 {
+    if (!owner) owner = ctx;
     for (auto &it : items) {
         pdd_status st = validate_item(it);
         if (st) return st;
-        if (it.prob->ctx != ctx) return fail(PDD_E_INVALID, "problem belongs to another context");
+        if (it.prob->ctx != owner) return fail(PDD_E_INVALID, "problem belongs to another context");
     }
     if (items.empty()) return PDD_OK;
     pdd_tuning tune;

@@ -5,12 +5,17 @@
 //
 // One host thread runs epochs. An epoch admits waiting requests (FIFO, while
 // a slot is free and the memory model fits the budget), takes the next chunk
-// of every admitted request as a batch item, enqueues the batch through the
-// same path as pdd_solve_batch, waits for it, and then plans finished pilots
-// and completes finished requests. Because a request's chunk sequence depends
-// only on the request and the server options, and an epoch never exceeds one
-// launch per group, a request gives bitwise the same statistics alone or in
-// any mix.
+// of every admitted request that is not in an epoch in flight as a batch
+// item, and enqueues the batch on a free lane (a stream and the scratch of a
+// context) through the same path as pdd_solve_batch. With up to `pipeline`
+// epochs in flight, the thread waits for the first of them to end (cut short
+// by a new request while a lane is free), then plans its finished pilots and
+// completes its finished requests while the other lanes keep the device
+// busy. Because a
+// request's chunk sequence depends only on the request and the server
+// options, a request is in at most one epoch in flight, and an epoch never
+// exceeds one launch per group, a request gives bitwise the same statistics
+// alone or in any mix, at any pipeline depth.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,9 +63,23 @@ struct Request {
     uint64_t chunk = 0;                 // continuation chunks done
     uint64_t max_target = 0;
     Clock::time_point t_submit, t_admit;
-    // batch item of the current epoch
+    // batch item of its epoch in flight
+    int lane = -1;                      // lane of that epoch, -1 when not in flight
     pdd_solve_opts opts{};
     std::vector<uint64_t> counts;
+};
+
+// An epoch slot: a stream, the scratch of a context, the batch it runs.
+struct Lane {
+    pdd_ctx *ctx = nullptr;
+    bool own_ctx = false;               // created by the server (lane 0 uses the server's)
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Request *> batch;
+    std::vector<HostItem> items;
+    pdd_status st = PDD_OK;             // of the enqueue
+    Clock::time_point t0;
+    bool busy = false;
 };
 
 uint64_t grid_bytes(const pdd_grid &g, int dim)
@@ -75,7 +94,7 @@ uint64_t grid_bytes(const pdd_grid &g, int dim)
 struct pdd_server {
     pdd_ctx *ctx = nullptr;
     pdd_server_opts o{};
-    hipStream_t stream = nullptr;
+    std::vector<Lane> lanes;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -84,6 +103,10 @@ struct pdd_server {
     std::vector<std::unique_ptr<Request>> active; // admitted (worker thread only)
     std::deque<pdd_completion> done;
     uint64_t next_id = 1;
+    // device statistics of finished requests, kept for reuse by size: a
+    // hipFree would wait for every epoch in flight (worker thread only)
+    std::multimap<size_t, void *> spare_out;
+    Clock::time_point busy_since;          // first enqueue since the device was last idle
     // report (under mu)
     pdd_server_report rep{};
     std::vector<double> latencies;         // completed requests
@@ -93,23 +116,62 @@ struct pdd_server {
     Clock::time_point first_submit, last_done;
 
     void run();
-    void epoch(std::vector<Request *> &batch);
-    void finish(Request *r, pdd_status status);
+    void launch(int lane, std::vector<Request *> &batch);
+    void complete(Lane &L, std::vector<pdd_node_stats> &pilot);
+    void finish(Request *r, pdd_status status, hipStream_t s);
+    bool admissible();  // under mu
+    pdd_node_stats *take_out(int64_t n);
+    void give_out(pdd_node_stats *p, int64_t n);
+    void release_lanes();
 };
 
 namespace {
 
-pdd_status copy_stats(pdd_node_stats *dst, const pdd_node_stats *src, int64_t n)
+pdd_status copy_stats(pdd_node_stats *dst, const pdd_node_stats *src, int64_t n, hipStream_t s)
 {
-    HIP_TRY(hipMemcpy(dst, src, (size_t)n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(dst, src, (size_t)n * sizeof(pdd_node_stats), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return PDD_OK;
+}
+
+size_t out_bytes(int64_t n)
+{
+    size_t b = 4096;
+    while (b < (size_t)n * sizeof(pdd_node_stats)) b *= 2;
+    return b;
 }
 
 }  // namespace
 
-// Completes a request: statistics to the caller (on success), memory back to
-// the budget, a completion record. Called by the worker without the lock.
-void pdd_server::finish(Request *r, pdd_status status)
+pdd_node_stats *pdd_server::take_out(int64_t n)
+{
+    const size_t b = out_bytes(n);
+    auto f = spare_out.find(b);
+    if (f != spare_out.end()) {
+        void *p = f->second;
+        spare_out.erase(f);
+        return static_cast<pdd_node_stats *>(p);
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) return nullptr;
+    return static_cast<pdd_node_stats *>(p);
+}
+
+void pdd_server::give_out(pdd_node_stats *p, int64_t n)
+{
+    if (p) spare_out.emplace(out_bytes(n), p);
+}
+
+bool pdd_server::admissible()
+{
+    return !queue.empty() && (int64_t)active.size() < o.max_inflight &&
+           rep.mem_in_use + rep.mem_fixed + queue.front()->mem <= o.memory_budget;
+}
+
+// Completes a request: statistics to the caller (on success, copied on
+// stream s), memory back to the budget, a completion record. Called by the
+// worker without the lock.
+void pdd_server::finish(Request *r, pdd_status status, hipStream_t s)
 {
     pdd_completion c{};
     c.id = r->id;
@@ -117,7 +179,7 @@ void pdd_server::finish(Request *r, pdd_status status)
     c.n_nodes = r->req.n_nodes;
     if (status == PDD_OK && r->dev_out) {
         std::vector<pdd_node_stats> st(r->req.n_nodes);
-        status = copy_stats(st.data(), r->dev_out, r->req.n_nodes);
+        status = copy_stats(st.data(), r->dev_out, r->req.n_nodes, s);
         if (status == PDD_OK) {
             std::memcpy(r->req.out, st.data(), st.size() * sizeof(pdd_node_stats));
             for (auto &x : st) {
@@ -126,7 +188,7 @@ void pdd_server::finish(Request *r, pdd_status status)
             }
         }
     }
-    if (r->dev_out) (void)hipFree(r->dev_out);
+    give_out(r->dev_out, r->req.n_nodes);
     r->dev_out = nullptr;
     const auto now = Clock::now();
     c.status = status;
@@ -154,14 +216,16 @@ void pdd_server::finish(Request *r, pdd_status status)
     cv_done.notify_all();
 }
 
-// One epoch over the admitted requests in `batch` (each contributes its
-// next chunk). Runs on the worker thread.
-void pdd_server::epoch(std::vector<Request *> &batch)
+// Enqueues an epoch over `batch` (each request contributes its next chunk) on
+// a free lane. Runs on the worker thread.
+void pdd_server::launch(int lane, std::vector<Request *> &batch)
 {
-    std::vector<HostItem> items(batch.size());
+    Lane &L = lanes[lane];
+    L.batch = batch;
+    L.items.assign(batch.size(), HostItem{});
     for (size_t q = 0; q < batch.size(); ++q) {
         Request *r = batch[q];
-        HostItem &it = items[q];
+        HostItem &it = L.items[q];
         it.prob = r->req.problem;
         it.u_prev = r->cv ? &r->u_prev : nullptr;
         it.resid = r->cv ? &r->resid : nullptr;
@@ -169,33 +233,95 @@ void pdd_server::epoch(std::vector<Request *> &batch)
         it.n_nodes = r->req.n_nodes;
         it.o = &r->opts;
         it.out = r->dev_out;
+        r->lane = lane;
     }
-    const auto t0 = Clock::now();
+    bool idle = true;
+    for (const Lane &x : lanes) idle &= !x.busy;
+    L.t0 = Clock::now();
+    if (idle) busy_since = L.t0;
     // one launch per group whatever the context's tuning table caps: a
     // request's node sums then never depend on the mix it ran in
-    pdd_status st = run_items(ctx, items, stream, true);
-    if (st == PDD_OK && hipStreamSynchronize(stream) != hipSuccess)
-        st = fail(PDD_E_HIP, "epoch failed on the device");
-    for (Request *r : batch) r->status = st;
-    const double sec = ms_between(t0, Clock::now()) / 1e3;
-    std::lock_guard<std::mutex> lk(mu);
-    ++rep.epochs;
-    rep.epoch_s += sec;
+    L.st = run_items(L.ctx, L.items, L.stream, true, ctx);
+    // recorded even after a failed enqueue, so that completion waits for
+    // whatever did reach the stream
+    if (hipEventRecord(L.done, L.stream) != hipSuccess && L.st == PDD_OK)
+        L.st = fail(PDD_E_HIP, "could not record the end of an epoch");
+    L.busy = true;
+}
+
+// Waits for the epoch on lane L, then plans its finished pilots and completes
+// its finished requests. Runs on the worker thread.
+void pdd_server::complete(Lane &L, std::vector<pdd_node_stats> &pilot)
+{
+    pdd_status st = L.st;
+    if (hipEventSynchronize(L.done) != hipSuccess && st == PDD_OK) st = fail(PDD_E_HIP, "epoch failed on the device");
+    const auto now = Clock::now();
+    L.busy = false;
+    bool idle = true;
+    for (const Lane &x : lanes) idle &= !x.busy;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        ++rep.epochs;
+        rep.epoch_s += ms_between(L.t0, now) / 1e3;
+        if (idle) rep.busy_s += ms_between(busy_since, now) / 1e3;
+    }
+    for (Request *r : L.batch) {
+        r->lane = -1;
+        r->status = st;
+    }
+    for (Request *r : L.batch) {
+        bool end = st != PDD_OK;
+        pdd_status why = st;
+        if (!end && r->phase == Phase::Pilot) {
+            const int64_t n = r->req.n_nodes;
+            pilot.resize(n);
+            why = copy_stats(pilot.data(), r->dev_out, n, L.stream);
+            r->target.resize(n);
+            r->nu.resize(n);
+            for (int64_t i = 0; i < n; ++i) r->nu[i] = pilot[i].mean_steps;
+            if (why == PDD_OK) why = pdd_plan_paths(pilot.data(), n, r->req.target_se, o.n_max, r->target.data());
+            if (why != PDD_OK) {
+                end = true;
+            } else {
+                r->phase = Phase::Planned;
+                r->max_target = *std::max_element(r->target.begin(), r->target.end());
+                r->per_node_chunk = std::max<uint64_t>(1, o.chunk_paths / (uint64_t)n);
+                r->chunk = 0;
+                end = r->max_target <= o.n_pilot;
+            }
+        } else if (!end) {
+            ++r->chunk;
+            end = o.n_pilot + r->chunk * r->per_node_chunk >= r->max_target;
+        }
+        if (end) {
+            finish(r, why, L.stream);
+            for (auto &up : active)
+                if (up.get() == r) up.reset();
+        }
+    }
+    active.erase(std::remove(active.begin(), active.end(), nullptr), active.end());
+    L.batch.clear();
+    L.items.clear();
 }
 
 void pdd_server::run()
 {
     (void)hipSetDevice(ctx->device);
     std::vector<pdd_node_stats> pilot;
+    std::deque<int> fifo;  // lanes in flight, oldest first
+    auto free_lane = [&] {
+        for (size_t i = 0; i < lanes.size(); ++i)
+            if (!lanes[i].busy) return (int)i;
+        return -1;
+    };
     for (;;) {
         // admission at the epoch boundary
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (active.empty() && queue.empty() && !stopping)
+            if (fifo.empty() && active.empty() && queue.empty() && !stopping)
                 cv_work.wait(lk, [&] { return stopping || !queue.empty(); });
             if (stopping) break;
-            while (!queue.empty() && (int64_t)active.size() < o.max_inflight &&
-                   rep.mem_in_use + rep.mem_fixed + queue.front()->mem <= o.memory_budget) {
+            while (admissible()) {
                 std::unique_ptr<Request> r = std::move(queue.front());
                 queue.pop_front();
                 r->phase = Phase::Pilot;
@@ -210,111 +336,110 @@ void pdd_server::run()
         }
         // device statistics of newly admitted requests
         for (auto &r : active) {
-            if (r->dev_out || r->phase != Phase::Pilot) continue;
-            if (hipMalloc(&r->dev_out, (size_t)r->req.n_nodes * sizeof(pdd_node_stats)) != hipSuccess) {
-                r->dev_out = nullptr;
+            if (r->dev_out || r->phase != Phase::Pilot || r->status != PDD_OK) continue;
+            r->dev_out = take_out(r->req.n_nodes);
+            if (!r->dev_out)
                 r->status = fail(PDD_E_NOMEM, "device statistics of request %llu", (unsigned long long)r->id);
-            }
         }
-        // the epoch: the next chunk of admitted requests within epoch_paths,
-        // pilots first, then the least remaining work (the order decides only
-        // when a chunk runs, never what it computes)
-        std::vector<Request *> order;
-        for (auto &up : active) {
-            Request *r = up.get();
-            if (r->phase == Phase::Planned) {
-                const uint64_t off = o.n_pilot + r->chunk * r->per_node_chunk;
-                double w = 0.0;
-                for (size_t i = 0; i < r->target.size(); ++i)
-                    if (r->target[i] > off) w += (double)(r->target[i] - off) * r->nu[i];
-                r->remaining = w;
-            }
-            order.push_back(r);
-        }
-        std::stable_sort(order.begin(), order.end(), [](const Request *a, const Request *b) {
-            const bool pa = a->phase == Phase::Pilot, pb = b->phase == Phase::Pilot;
-            if (pa != pb) return pa;
-            if (!pa && a->remaining != b->remaining) return a->remaining < b->remaining;
-            return a->id < b->id;
-        });
-        std::vector<Request *> batch;
-        uint64_t total = 0;
-        for (Request *r : order) {
-            if (r->status != PDD_OK) continue;  // failed allocation
-            const uint64_t n = (uint64_t)r->req.n_nodes;
-            pdd_solve_opts &op = r->opts;
-            std::memset(&op, 0, sizeof op);
-            op.dt = r->req.dt;
-            op.stream_id = r->req.stream_id;
-            op.precision = r->req.precision;
-            op.exit_mode = r->req.exit_mode;
-            op.law = PDD_LAW_GAUSS;
-            uint64_t size;
-            if (r->phase == Phase::Pilot) {
-                op.n_paths = o.n_pilot;
-                size = n * o.n_pilot;
-            } else {
-                const uint64_t off = o.n_pilot + r->chunk * r->per_node_chunk;
-                r->counts.resize(n);
-                size = 0;
-                for (uint64_t i = 0; i < n; ++i) {
-                    const uint64_t t = r->target[i];
-                    r->counts[i] = t > off ? std::min(t - off, r->per_node_chunk) : 0;
-                    size += r->counts[i];
-                }
-                op.n_paths_per_node = r->counts.data();
-                op.path_offset = off;
-                op.flags = PDD_ACCUMULATE;
-            }
-            if (!batch.empty() && total + size > o.epoch_paths) continue;
-            total += size;
-            batch.push_back(r);
-        }
-        // failed allocations end here
+        // failed allocations end here (such a request was never in flight)
         for (auto &up : active)
-            if (up->status != PDD_OK) {
-                finish(up.get(), up->status);
+            if (up->status != PDD_OK && up->lane < 0) {
+                finish(up.get(), up->status, nullptr);
                 up.reset();
             }
         active.erase(std::remove(active.begin(), active.end(), nullptr), active.end());
-        if (batch.empty()) continue;
-        epoch(batch);
-        // plan finished pilots, complete finished requests
-        for (Request *r : batch) {
-            const pdd_status st = r->status;
-            bool end = st != PDD_OK;
-            pdd_status why = st;
-            if (!end && r->phase == Phase::Pilot) {
-                const int64_t n = r->req.n_nodes;
-                pilot.resize(n);
-                why = copy_stats(pilot.data(), r->dev_out, n);
-                r->target.resize(n);
-                r->nu.resize(n);
-                for (int64_t i = 0; i < n; ++i) r->nu[i] = pilot[i].mean_steps;
-                if (why == PDD_OK) why = pdd_plan_paths(pilot.data(), n, r->req.target_se, o.n_max, r->target.data());
-                if (why != PDD_OK) {
-                    end = true;
-                } else {
-                    r->phase = Phase::Planned;
-                    r->max_target = *std::max_element(r->target.begin(), r->target.end());
-                    r->per_node_chunk = std::max<uint64_t>(1, o.chunk_paths / (uint64_t)n);
-                    r->chunk = 0;
-                    end = r->max_target <= o.n_pilot;
+        // the next epoch on a free lane: the next chunk of the requests not in
+        // flight within epoch_paths, pilots first, then the least remaining
+        // work (the order decides only when a chunk runs, never what it computes)
+        const int lane = free_lane();
+        bool left = false;  // requests not in flight that this epoch leaves out
+        if (lane >= 0) {
+            std::vector<Request *> order;
+            for (auto &up : active) {
+                Request *r = up.get();
+                if (r->lane >= 0) continue;
+                if (r->phase == Phase::Planned) {
+                    const uint64_t off = o.n_pilot + r->chunk * r->per_node_chunk;
+                    double w = 0.0;
+                    for (size_t i = 0; i < r->target.size(); ++i)
+                        if (r->target[i] > off) w += (double)(r->target[i] - off) * r->nu[i];
+                    r->remaining = w;
                 }
-            } else if (!end) {
-                ++r->chunk;
-                end = o.n_pilot + r->chunk * r->per_node_chunk >= r->max_target;
+                order.push_back(r);
             }
-            if (end) {
-                finish(r, why);
-                for (auto &up : active)
-                    if (up.get() == r) up.reset();
+            std::stable_sort(order.begin(), order.end(), [](const Request *a, const Request *b) {
+                const bool pa = a->phase == Phase::Pilot, pb = b->phase == Phase::Pilot;
+                if (pa != pb) return pa;
+                if (!pa && a->remaining != b->remaining) return a->remaining < b->remaining;
+                return a->id < b->id;
+            });
+            std::vector<Request *> batch;
+            uint64_t total = 0;
+            for (Request *r : order) {
+                const uint64_t n = (uint64_t)r->req.n_nodes;
+                pdd_solve_opts &op = r->opts;
+                std::memset(&op, 0, sizeof op);
+                op.dt = r->req.dt;
+                op.stream_id = r->req.stream_id;
+                op.precision = r->req.precision;
+                op.exit_mode = r->req.exit_mode;
+                op.law = PDD_LAW_GAUSS;
+                uint64_t size;
+                if (r->phase == Phase::Pilot) {
+                    op.n_paths = o.n_pilot;
+                    size = n * o.n_pilot;
+                } else {
+                    const uint64_t off = o.n_pilot + r->chunk * r->per_node_chunk;
+                    r->counts.resize(n);
+                    size = 0;
+                    for (uint64_t i = 0; i < n; ++i) {
+                        const uint64_t t = r->target[i];
+                        r->counts[i] = t > off ? std::min(t - off, r->per_node_chunk) : 0;
+                        size += r->counts[i];
+                    }
+                    op.n_paths_per_node = r->counts.data();
+                    op.path_offset = off;
+                    op.flags = PDD_ACCUMULATE;
+                }
+                if (!batch.empty() && total + size > o.epoch_paths) {
+                    left = true;
+                    continue;
+                }
+                total += size;
+                batch.push_back(r);
+            }
+            if (!batch.empty()) {
+                launch(lane, batch);
+                fifo.push_back(lane);
             }
         }
-        active.erase(std::remove(active.begin(), active.end(), nullptr), active.end());
+        if (fifo.empty()) continue;
+        // what did not fit goes to the next free lane first
+        const bool lane_free = free_lane() >= 0;
+        if (left && lane_free) continue;
+        // the first epoch in launch order that has ended; with a lane free, a
+        // new request cuts the wait short
+        int ready = -1;
+        for (;;) {
+            for (size_t k = 0; k < fifo.size() && ready < 0; ++k)
+                if (hipEventQuery(lanes[fifo[k]].done) != hipErrorNotReady) ready = (int)k;
+            if (ready >= 0) break;
+            std::unique_lock<std::mutex> lk(mu);
+            if (stopping || (lane_free && admissible())) break;
+            cv_work.wait_for(lk, std::chrono::microseconds(200));
+        }
+        if (ready < 0) continue;
+        const int li = fifo[ready];
+        fifo.erase(fifo.begin() + ready);
+        complete(lanes[li], pilot);
     }
-    // cancelled: in flight, then queued
-    for (auto &up : active) finish(up.get(), PDD_E_BUSY);
+    // stopping: the epochs in flight end, then every request is cancelled
+    for (int i : fifo) {
+        (void)hipEventSynchronize(lanes[i].done);
+        lanes[i].busy = false;
+        for (Request *r : lanes[i].batch) r->lane = -1;
+    }
+    for (auto &up : active) finish(up.get(), PDD_E_BUSY, nullptr);
     active.clear();
     std::deque<std::unique_ptr<Request>> rest;
     {
@@ -322,7 +447,23 @@ void pdd_server::run()
         rest.swap(queue);
         rep.queued = 0;
     }
-    for (auto &up : rest) finish(up.get(), PDD_E_BUSY);
+    for (auto &up : rest) finish(up.get(), PDD_E_BUSY, nullptr);
+}
+
+// Streams, events and contexts of the lanes, and the spare statistics
+// buffers (after the worker has ended).
+void pdd_server::release_lanes()
+{
+    for (Lane &L : lanes) {
+        if (L.done) (void)hipEventSynchronize(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.own_ctx) pdd_shutdown(L.ctx);
+    }
+    lanes.clear();
+    (void)hipSetDevice(ctx->device);
+    for (auto &kv : spare_out) (void)hipFree(kv.second);
+    spare_out.clear();
 }
 
 extern "C" {
@@ -339,23 +480,42 @@ pdd_status pdd_server_create(pdd_ctx *ctx, const pdd_server_opts *opts, pdd_serv
     if (!o.n_max) o.n_max = 1ull << 31;
     if (!o.chunk_paths) o.chunk_paths = 1ull << 22;
     if (!o.epoch_paths) o.epoch_paths = kScratchSlots;
+    if (!o.pipeline) o.pipeline = 2;
     if (o.max_inflight < 0 || o.max_queued < 0 || o.n_pilot < 2 || o.n_max < o.n_pilot ||
-        o.n_max > (1ull << 32) || o.epoch_paths > kScratchSlots || o.chunk_paths > o.epoch_paths)
+        o.n_max > (1ull << 32) || o.epoch_paths > kScratchSlots || o.chunk_paths > o.epoch_paths ||
+        o.pipeline < 1 || o.pipeline > 4 || o.reserved != 0)
         return fail(PDD_E_INVALID, "bad server options");
     auto sv = std::make_unique<pdd_server>();
     sv->ctx = ctx;
     sv->o = o;
-    // record scratch of a full epoch: phi, e (FP64) and the exit step per path
-    sv->rep.mem_fixed = o.epoch_paths * (8 + 8 + 4);
+    // record scratch of a full epoch per lane: phi, e (FP64) and the exit step per path
+    sv->rep.mem_fixed = (uint64_t)o.pipeline * o.epoch_paths * (8 + 8 + 4);
     if (sv->rep.mem_fixed >= o.memory_budget)
         return fail(PDD_E_INVALID, "memory budget below the record scratch (%llu bytes)",
                     (unsigned long long)sv->rep.mem_fixed);
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking));
+    sv->lanes.resize(o.pipeline);
+    for (int i = 0; i < o.pipeline; ++i) {
+        Lane &L = sv->lanes[i];
+        pdd_status st = PDD_OK;
+        if (i == 0) {
+            L.ctx = ctx;
+        } else if ((st = pdd_init(&L.ctx, ctx->device)) == PDD_OK) {
+            L.own_ctx = true;
+            L.ctx->tuned = ctx->tuned;  // the launch shapes of the server's context
+        }
+        if (st == PDD_OK && (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+                             hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess))
+            st = fail(PDD_E_HIP, "could not create the streams of the server");
+        if (st != PDD_OK) {
+            sv->release_lanes();
+            return st;
+        }
+    }
     try {
         sv->worker = std::thread([s = sv.get()] { s->run(); });
     } catch (...) {
-        (void)hipStreamDestroy(sv->stream);
+        sv->release_lanes();
         return fail(PDD_E_INTERNAL, "could not start the server thread");
     }
     *out = sv.release();
@@ -494,7 +654,7 @@ void pdd_server_destroy(pdd_server *sv)
     }
     sv->cv_work.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
-    (void)hipStreamDestroy(sv->stream);
+    sv->release_lanes();
     delete sv;
 }
 

@@ -139,7 +139,7 @@ class TuningKey(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("memory_budget", C.c_uint64), ("max_inflight", C.c_int32), ("max_queued", C.c_int32),
                 ("n_pilot", C.c_uint64), ("n_max", C.c_uint64), ("chunk_paths", C.c_uint64),
-                ("epoch_paths", C.c_uint64)]
+                ("epoch_paths", C.c_uint64), ("pipeline", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -163,7 +163,8 @@ class ServerReport(C.Structure):
                [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "wall_s", "node_solves_per_s",
                                           "epoch_s")] + \
                [("cancelled", C.c_uint64), ("censored", C.c_uint64), ("p50_censored", C.c_int32),
-                ("p99_censored", C.c_int32), ("p50_done_ms", C.c_double), ("p99_done_ms", C.c_double)]
+                ("p99_censored", C.c_int32), ("p50_done_ms", C.c_double), ("p99_done_ms", C.c_double),
+                ("busy_s", C.c_double)]
 
 
 # Every entry point of include/pdd.h with its ctypes signature.
@@ -695,10 +696,10 @@ class Server:
     request completes."""
 
     def __init__(self, ctx: Context, memory_budget=0, max_inflight=0, max_queued=0, n_pilot=0,
-                 n_max=0, chunk_paths=0, epoch_paths=0):
+                 n_max=0, chunk_paths=0, epoch_paths=0, pipeline=0):
         self.ctx = ctx
         o = ServerOpts(int(memory_budget), int(max_inflight), int(max_queued), int(n_pilot),
-                       int(n_max), int(chunk_paths), int(epoch_paths))
+                       int(n_max), int(chunk_paths), int(epoch_paths), int(pipeline), 0)
         h = C.c_void_p()
         _check(lib().pdd_server_create(ctx.handle, C.byref(o), C.byref(h)))
         self.handle = h

@@ -103,13 +103,15 @@ def main(argv=None):
     ap.add_argument("--tols", default="1e-2,3e-3,1e-3")
     ap.add_argument("--epoch-paths", type=int, default=1 << 24)
     ap.add_argument("--chunk-paths", type=int, default=1 << 20)
+    ap.add_argument("--pipeline", type=int, default=0, help="epochs in flight at once (0 = the library's 2)")
     args = ap.parse_args(argv)
     problems, reqs = W.serving_stream(seed=args.seed, rate=args.rate, duration=args.duration,
                                       cv_frac=args.cv_frac,
                                       tols=tuple(float(t) for t in args.tols.split(",")))
     ctx = pdd.Context(0)
     rep, _ = run_stream(ctx, problems, reqs, drain_s=args.drain,
-                        server_opts=dict(epoch_paths=args.epoch_paths, chunk_paths=args.chunk_paths),
+                        server_opts=dict(epoch_paths=args.epoch_paths, chunk_paths=args.chunk_paths,
+                                         pipeline=args.pipeline),
                         log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(rep), flush=True)
     ctx.close()

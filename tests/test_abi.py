@@ -77,19 +77,20 @@ STRUCTS = {
                                            "trig", "mono", "fx", "gx", "seed"]),
     "pdd_grid": (pdd.Grid, ["dtype", "n", "lo", "hi", "data"]),
     "pdd_coef_grids": (pdd.CoefGrids, ["b", "c", "f", "g"]),
-    "pdd_tuning": (pdd.Tuning, ["block", "grab"]),
+    "pdd_tuning": (pdd.Tuning, ["block", "grab", "max_launch_paths", "refill", "bridge"]),
     "pdd_solve_opts": (pdd.SolveOpts, ["dt", "n_paths_per_node", "path_offset", "stream_id",
                                        "max_steps", "flags", "rec_phi", "rec_steps", "tuning"]),
     "pdd_node_stats": (pdd.NodeStats, ["mean", "stderr_", "vr_opt", "sums"]),
     "pdd_work_item": (pdd.WorkItem, ["nodes", "n_nodes", "opts", "resid", "out", "grad"]),
     "pdd_tuning_key": (pdd.TuningKey, ["precision", "dim", "correction", "generic"]),
     "pdd_node_constants": (pdd.NodeConstants, ["E_phi", "se_beta", "alpha", "E_tau", "se_E_tau", "iterations"]),
-    "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths"]),
+    "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths", "pipeline",
+                                         "reserved"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",
                                   "user_tag"]),
     "pdd_completion": (pdd.Completion, ["status", "queued_ms", "latency_ms", "path_steps", "n_nodes"]),
     "pdd_server_report": (pdd.ServerReport, ["shed", "mem_fixed", "p50_ms", "wall_s",
-                                             "node_solves_per_s", "epoch_s"]),
+                                             "node_solves_per_s", "epoch_s", "p99_done_ms", "busy_s"]),
 }
 
 

@@ -1,7 +1,8 @@
 """Serving loop through the C ABI: continuous batching of requests to a
 standard error. A request's statistics are bitwise the same alone and in a
 mix of other requests; admission keeps the memory model within the budget;
-a full queue sheds; results agree with pdd_solve_to_tolerance."""
+a full queue sheds; results agree with pdd_solve_to_tolerance and with the
+oracle, and do not depend on how many epochs are in flight at once."""
 import numpy as np
 import pytest
 
@@ -80,7 +81,7 @@ def test_matches_solve_to_tolerance(ctx, stream):
 def test_admission_respects_memory_budget(ctx, stream):
     problems, reqs, fx = stream
     sub = reqs[:12]
-    fixed = SMALL["epoch_paths"] * 20
+    fixed = 2 * SMALL["epoch_paths"] * 20  # a record scratch per epoch in flight (two by default)
     # room for about two requests' device state at a time
     per = [len(r["nodes"]) * (184 + 112 + 8 * 3 + 16) +
            (2 * 4 * r["grid_n"] ** problems[r["problem"]]["dim"] if r["cv"] else 0) for r in sub]
@@ -129,6 +130,35 @@ def test_invalid_requests(ctx, stream):
     sv.close()
     with pytest.raises(pdd.PDDError):
         pdd.Server(ctx, epoch_paths=1 << 30)
+    for depth in (-1, 5):
+        with pytest.raises(pdd.PDDError):
+            pdd.Server(ctx, **SMALL, pipeline=depth)
+
+
+def test_pipeline_depth_does_not_change_results(ctx, stream):
+    """One, two and four epochs in flight: every request's statistics are
+    bitwise the same (a request is in one epoch in flight at a time, so its
+    chunks run in order, each a single launch per group), the record scratch
+    grows with the depth, and the time with an epoch in flight is within the
+    wall time."""
+    problems, reqs, fx = stream
+    sub = reqs[:16]
+    ref = None
+    for depth in (1, 2, 4):
+        rep, done = S.run_stream(ctx, problems, sub, drain_s=120, fixtures=fx,
+                                 server_opts=dict(SMALL, pipeline=depth))
+        assert rep["completed"] == len(sub) and rep["failed"] == 0 and rep["cancelled"] == 0
+        assert rep["mem_fixed"] == depth * SMALL["epoch_paths"] * 20
+        assert 0 < rep["busy_s"] <= rep["wall_s"] + 0.05 and rep["epochs"] >= 3
+        print(f"depth {depth}: {rep['epochs']} epochs, wall {rep['wall_s']:.3f} s, busy {rep['busy_s']:.3f} s",
+              flush=True)
+        if ref is None:
+            ref = done
+            continue
+        assert sorted(done) == sorted(ref)
+        for k in ref:
+            assert done[k]["stats"].tobytes() == ref[k]["stats"].tobytes(), (depth, k)
+            assert done[k]["path_steps"] == ref[k]["path_steps"]
 
 
 def test_served_requests_match_oracle(ctx):
