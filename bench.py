@@ -622,7 +622,7 @@ def serving_pipeline(ctx, depths=(1, 2, 3)):
     out, ref = [], None
     for depth in depths:
         rep, done = serving.run_stream(ctx, problems, reqs, drain_s=120.0, fixtures=fx,
-                                       server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20,
+                                       server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 22,
                                                         pipeline=depth))
         same = None
         if ref is None:
@@ -631,7 +631,7 @@ def serving_pipeline(ctx, depths=(1, 2, 3)):
             same = sorted(done) == sorted(ref) and all(done[k]["stats"].tobytes() == ref[k]["stats"].tobytes()
                                                        for k in ref)
         out.append({"pipeline": depth, "completed": rep["completed"], "offered": len(reqs),
-                    "wall_s": rep["wall_s"], "busy_s": rep["busy_s"], "epochs": rep["epochs"],
+                    "wall_s": rep["wall_s"], "busy_s": rep["busy_s"], "epochs": rep["epochs"], "paths_run": rep["paths_run"],
                     "path_steps": rep["path_steps"], "path_steps_per_s": rep["path_steps"] / max(rep["wall_s"], 1e-9),
                     "node_solves_per_s": rep["node_solves_per_s"], "p50_ms": rep["p50_ms"],
                     "p99_ms": rep["p99_ms"], "bitwise_equal_to_depth_1": same})
@@ -658,7 +658,7 @@ def serving_sweep(ctx, drain_s):
         if not reqs:
             continue
         rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=drain_s,
-                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 22))
         out.append({"rate_per_s": rate, "arrival_window_s": dur, "offered": len(reqs),
                     "completed": rep["completed"], "cancelled": rep["cancelled"],
                     "p50_ms": rep["p50_ms"], "p99_ms": rep["p99_ms"], "p50_censored": rep["p50_censored"],
@@ -992,7 +992,7 @@ def main():
         from paper_1512_02818_amd import serving
         problems, reqs = W.serving_stream(seed=5, rate=200.0, duration=args.serve_duration)
         rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=args.serve_drain,
-                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 20))
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 22))
         rep["workload"] = ("Poisson 200 requests/s of 1-2,000 nodes (log-uniform) on 16 random 2D/3D "
                            "box problems, RMS tolerance in {1e-2, 3e-3, 1e-3}, 30% with a u_prev grid "
                            "(129^2-513^2 or 65^3), FP32, 64 GiB budget; requests still running after "

@@ -596,6 +596,7 @@ typedef struct {
     int32_t p50_censored, p99_censored;       /* 1: the percentile is a lower bound */
     double p50_done_ms, p99_done_ms;          /* percentiles of completed requests alone */
     double busy_s;                            /* time with at least one epoch in flight */
+    uint64_t paths_run;                       /* paths enqueued in epochs (cancelled requests' too) */
 } pdd_server_report;
 
 /* Starts a server on `ctx` (NULL opts = defaults). Errors: bad options, a

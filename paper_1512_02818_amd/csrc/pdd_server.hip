@@ -106,9 +106,10 @@ struct pdd_server {
     // device statistics of finished requests, kept for reuse by size: a
     // hipFree would wait for every epoch in flight (worker thread only)
     std::multimap<size_t, void *> spare_out;
-    Clock::time_point busy_since;          // first enqueue since the device was last idle
     // report (under mu)
     pdd_server_report rep{};
+    bool busy_open = false;                // an epoch is in flight, since busy_since
+    Clock::time_point busy_since;
     std::vector<double> latencies;         // completed requests
     std::vector<double> censored;          // cancelled requests: age at cancellation
     std::map<uint64_t, Clock::time_point> outstanding;  // submitted, not finished: submit time
@@ -116,7 +117,7 @@ struct pdd_server {
     Clock::time_point first_submit, last_done;
 
     void run();
-    void launch(int lane, std::vector<Request *> &batch);
+    void launch(int lane, std::vector<Request *> &batch, uint64_t paths);
     void complete(Lane &L, std::vector<pdd_node_stats> &pilot);
     void finish(Request *r, pdd_status status, hipStream_t s);
     bool admissible();  // under mu
@@ -218,7 +219,7 @@ void pdd_server::finish(Request *r, pdd_status status, hipStream_t s)
 
 // Enqueues an epoch over `batch` (each request contributes its next chunk) on
 // a free lane. Runs on the worker thread.
-void pdd_server::launch(int lane, std::vector<Request *> &batch)
+void pdd_server::launch(int lane, std::vector<Request *> &batch, uint64_t paths)
 {
     Lane &L = lanes[lane];
     L.batch = batch;
@@ -235,10 +236,15 @@ void pdd_server::launch(int lane, std::vector<Request *> &batch)
         it.out = r->dev_out;
         r->lane = lane;
     }
-    bool idle = true;
-    for (const Lane &x : lanes) idle &= !x.busy;
     L.t0 = Clock::now();
-    if (idle) busy_since = L.t0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        rep.paths_run += paths;
+        if (!busy_open) {
+            busy_open = true;
+            busy_since = L.t0;
+        }
+    }
     // one launch per group whatever the context's tuning table caps: a
     // request's node sums then never depend on the mix it ran in
     L.st = run_items(L.ctx, L.items, L.stream, true, ctx);
@@ -263,7 +269,10 @@ void pdd_server::complete(Lane &L, std::vector<pdd_node_stats> &pilot)
         std::lock_guard<std::mutex> lk(mu);
         ++rep.epochs;
         rep.epoch_s += ms_between(L.t0, now) / 1e3;
-        if (idle) rep.busy_s += ms_between(busy_since, now) / 1e3;
+        if (idle && busy_open) {
+            rep.busy_s += ms_between(busy_since, now) / 1e3;
+            busy_open = false;
+        }
     }
     for (Request *r : L.batch) {
         r->lane = -1;
@@ -409,7 +418,7 @@ void pdd_server::run()
                 batch.push_back(r);
             }
             if (!batch.empty()) {
-                launch(lane, batch);
+                launch(lane, batch, total);
                 fifo.push_back(lane);
             }
         }
@@ -438,6 +447,11 @@ void pdd_server::run()
         (void)hipEventSynchronize(lanes[i].done);
         lanes[i].busy = false;
         for (Request *r : lanes[i].batch) r->lane = -1;
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (busy_open) rep.busy_s += ms_between(busy_since, Clock::now()) / 1e3;
+        busy_open = false;
     }
     for (auto &up : active) finish(up.get(), PDD_E_BUSY, nullptr);
     active.clear();
@@ -622,6 +636,7 @@ pdd_status pdd_server_report_get(pdd_server *sv, pdd_server_report *out)
     all.insert(all.end(), cens.begin(), cens.end());
     std::sort(all.begin(), all.end());
     r.censored = cens.size();
+    if (sv->busy_open) r.busy_s += ms_between(sv->busy_since, now) / 1e3;
     r.p50_ms = r.p99_ms = r.mean_ms = r.p50_done_ms = r.p99_done_ms = 0.0;
     r.p50_censored = r.p99_censored = 0;
     if (!all.empty()) {

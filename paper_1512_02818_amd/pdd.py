@@ -164,7 +164,7 @@ class ServerReport(C.Structure):
                                           "epoch_s")] + \
                [("cancelled", C.c_uint64), ("censored", C.c_uint64), ("p50_censored", C.c_int32),
                 ("p99_censored", C.c_int32), ("p50_done_ms", C.c_double), ("p99_done_ms", C.c_double),
-                ("busy_s", C.c_double)]
+                ("busy_s", C.c_double), ("paths_run", C.c_uint64)]
 
 
 # Every entry point of include/pdd.h with its ctypes signature.

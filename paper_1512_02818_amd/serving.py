@@ -102,7 +102,7 @@ def main(argv=None):
     ap.add_argument("--cv-frac", type=float, default=0.3)
     ap.add_argument("--tols", default="1e-2,3e-3,1e-3")
     ap.add_argument("--epoch-paths", type=int, default=1 << 24)
-    ap.add_argument("--chunk-paths", type=int, default=1 << 20)
+    ap.add_argument("--chunk-paths", type=int, default=1 << 22)
     ap.add_argument("--pipeline", type=int, default=0, help="epochs in flight at once (0 = the library's 2)")
     args = ap.parse_args(argv)
     problems, reqs = W.serving_stream(seed=args.seed, rate=args.rate, duration=args.duration,

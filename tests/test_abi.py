@@ -90,7 +90,8 @@ STRUCTS = {
                                   "user_tag"]),
     "pdd_completion": (pdd.Completion, ["status", "queued_ms", "latency_ms", "path_steps", "n_nodes"]),
     "pdd_server_report": (pdd.ServerReport, ["shed", "mem_fixed", "p50_ms", "wall_s",
-                                             "node_solves_per_s", "epoch_s", "p99_done_ms", "busy_s"]),
+                                             "node_solves_per_s", "epoch_s", "p99_done_ms", "busy_s",
+                                             "paths_run"]),
 }
 
 

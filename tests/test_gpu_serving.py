@@ -143,7 +143,7 @@ def test_pipeline_depth_does_not_change_results(ctx, stream):
     wall time."""
     problems, reqs, fx = stream
     sub = reqs[:16]
-    ref = None
+    ref = ref_paths = None
     for depth in (1, 2, 4):
         rep, done = S.run_stream(ctx, problems, sub, drain_s=120, fixtures=fx,
                                  server_opts=dict(SMALL, pipeline=depth))
@@ -153,8 +153,10 @@ def test_pipeline_depth_does_not_change_results(ctx, stream):
         print(f"depth {depth}: {rep['epochs']} epochs, wall {rep['wall_s']:.3f} s, busy {rep['busy_s']:.3f} s",
               flush=True)
         if ref is None:
-            ref = done
+            ref, ref_paths = done, rep["paths_run"]
+            assert ref_paths >= sum(int(c["paths"]) for c in done.values())
             continue
+        assert rep["paths_run"] == ref_paths  # the same chunks, whatever the depth
         assert sorted(done) == sorted(ref)
         for k in ref:
             assert done[k]["stats"].tobytes() == ref[k]["stats"].tobytes(), (depth, k)
