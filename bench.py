@@ -608,6 +608,44 @@ def iterpdd_runs(ctx, tols):
 SWEEP_RATES = (0.5, 1.0, 2.0, 5.0, 20.0)
 
 
+LIGHT_RATES = (10.0, 25.0, 50.0, 100.0)
+
+
+def serving_sweep_light(ctx, duration=4.0, drain_s=20.0):
+    """The serving loop on a lighter mix whose requests one GPU can keep up
+    with (up to 400 nodes, RMS tolerance 1e-2 or 3e-3, 30 % with a u_prev
+    grid), at Poisson rates of 10 to 100 requests/s for `duration` seconds
+    each: completions, latency, the lag (last arrival to last completion) and
+    the fraction of the run with an epoch in flight. The knee is the highest
+    rate up to which every rate completed all its requests with the device
+    busy less than 95 % of the time (above it the backlog grows: the device
+    never idles and the lag rises)."""
+    from paper_1512_02818_amd import serving
+    from paper_1512_02818_amd import workloads as W
+    out = []
+    for q, rate in enumerate(LIGHT_RATES):
+        problems, reqs = W.serving_stream(seed=60 + q, rate=rate, duration=duration, node_range=(1, 400),
+                                          tols=(1e-2, 3e-3))
+        rep, _ = serving.run_stream(ctx, problems, reqs, drain_s=drain_s,
+                                    server_opts=dict(epoch_paths=1 << 24, chunk_paths=1 << 22))
+        out.append({"rate_per_s": rate, "offered": len(reqs), "completed": rep["completed"],
+                    "cancelled": rep["cancelled"], "lag_s": rep["drain_s"], "p50_ms": rep["p50_ms"],
+                    "p99_ms": rep["p99_ms"], "p99_censored": rep["p99_censored"],
+                    "node_solves_per_s": rep["node_solves_per_s"], "busy_s": rep["busy_s"],
+                    "wall_s": rep["wall_s"], "busy_frac": rep["busy_s"] / max(rep["wall_s"], 1e-9)})
+        print(f"light serving at {rate:g} requests/s: {rep['completed']} of {len(reqs)} completed, lag "
+              f"{rep['drain_s']:.2f} s, p50 {rep['p50_ms']:.0f} ms, p99 {rep['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+    knee = None
+    for r in out:
+        if r["cancelled"] or r["completed"] != r["offered"] or r["busy_frac"] >= 0.95:
+            break
+        knee = r["rate_per_s"]
+    return {"workload": f"Poisson arrivals for {duration:g} s per rate, 1-400 nodes (log-uniform) on 16 random "
+                        "2D/3D box problems, RMS tolerance in {1e-2, 3e-3}, 30% with a u_prev grid, FP32, "
+                        f"drain up to {drain_s:g} s", "rates": out, "knee_rate_per_s": knee}
+
+
 def serving_pipeline(ctx, depths=(1, 2, 3)):
     """The serving loop with 1, 2 and 3 epochs in flight on one burst of
     requests (all arriving within 0.1 s; up to 400 nodes, RMS tolerance 1e-2
@@ -647,8 +685,8 @@ def serving_sweep(ctx, drain_s):
     """The serving loop at offered loads below the 200 requests/s of the main
     serving run (same request mix, seeded Poisson arrivals, about 12 requests
     per rate, at least 2 s and at most 12 s of arrivals): completed, cancelled
-    and latency percentiles per rate; the knee is the highest rate at which
-    every request completed within the drain."""
+    and latency percentiles per rate; the knee is the highest rate up to which
+    every rate of the sweep completed all its requests within the drain."""
     from paper_1512_02818_amd import serving
     from paper_1512_02818_amd import workloads as W
     out = []
@@ -667,8 +705,12 @@ def serving_sweep(ctx, drain_s):
         print(f"serving at {rate:g} requests/s: {rep['completed']} of {len(reqs)} completed, "
               f"p50 {rep['p50_ms']:.0f} ms, p99 {'>= ' if rep['p99_censored'] else ''}{rep['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-    knee = max([r["rate_per_s"] for r in out if r["cancelled"] == 0 and r["completed"] == r["offered"]],
-               default=None)
+    # the knee: the highest rate up to which every rate of the sweep completed all its requests
+    knee = None
+    for r in sorted(out, key=lambda r: r["rate_per_s"]):
+        if r["cancelled"] or r["completed"] != r["offered"]:
+            break
+        knee = r["rate_per_s"]
     return {"workload": "the request mix of 'serving' at lower Poisson rates (seeds 20..), drain "
                         f"{drain_s:g} s", "rates": out, "knee_rate_per_s": knee}
 
@@ -1003,6 +1045,7 @@ def main():
               file=sys.stderr, flush=True)
         if args.serve_sweep:
             result["serving_sweep"] = serving_sweep(ctx, args.serve_drain)
+            result["serving_sweep_light"] = serving_sweep_light(ctx)
             result["serving_pipeline"] = serving_pipeline(ctx)
     if cpu is not None:
         result["cpu_baseline"] = cpu
