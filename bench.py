@@ -585,7 +585,7 @@ def fp64_variant(ctx, prob, nodes, paths):
 
 def iterpdd_runs(ctx, tols):
     """The outer iteration (Alg. A:IterPDD) on the unit square's four strips
-    (u~ on a 257^2 grid): per nodal tolerance a0, the schedule, the cost and
+    (u~ on a 129^2 grid): per nodal tolerance a0, the schedule, the cost and
     RMS error of every level, and PlainPDD(a0) beside it."""
     from paper_1512_02818_amd import iterpdd
     from paper_1512_02818_amd import workloads as W

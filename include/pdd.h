@@ -455,9 +455,15 @@ typedef struct {
  * and first differences, b, c, f of the problem in FP64) and a banded LU
  * factorisation without pivoting, one workgroup per subdomain. The factors
  * depend on the operator (sigma, b, c), the grid and the interfaces only, so
- * the context keeps those of its last call: a call with the same ones (other
- * nodal values, another problem with the same analytic operator) only
- * eliminates and back-substitutes its right sides. `nodes` (host,
+ * the context keeps those of its last call. Since a subdomain's solution is
+ * affine in its boundary values, the context also keeps, per subdomain, its
+ * solution for f with zero boundary values and its response to a unit value
+ * at each row next to the boundary (computed from the factors; at most 2 GiB
+ * in all, else every call substitutes): a call with the same operator, grid,
+ * interfaces and problem (another set of nodal values) then only adds up
+ * those columns, weighted by its boundary values, in a fixed order. The
+ * result equals the direct solve to rounding (the same in a fresh context
+ * and in a kept one, bit for bit). `nodes` (host,
  * n_nodes x 2) are the interface nodes and `values` (host) their nodal
  * values; a node may lie on several lines. Synchronous (the interpolation
  * weights are solved on the host once the boundary values are on the

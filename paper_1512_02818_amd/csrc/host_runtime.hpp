@@ -113,6 +113,10 @@ struct pdd_ctx {
     // ones only eliminates its right sides
     pdd::DeviceBuffer stage2_lu;
     std::vector<double> stage2_key;
+    // the subdomains' response columns to their boundary values (and to f),
+    // kept with their key: the factors' key and the problem's serial number
+    pdd::DeviceBuffer stage2_resp;
+    std::vector<double> stage2_resp_key;
     void *stage = nullptr;
     size_t stage_cap = 0;
     void *readback = nullptr;  // pinned host copy of pilot statistics

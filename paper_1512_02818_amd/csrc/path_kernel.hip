@@ -1427,9 +1427,10 @@ __device__ __forceinline__ void stage2_point(const SubBox &b, uint64_t r, int &i
 // Stencil of every unknown: (1/2) sigma^2 Lap v + b.grad v + c v = f by
 // second-order differences; neighbours on the subdomain's boundary move to
 // the right side with their grid values. Slots: 0 slow-1, 1 fast-1,
-// 2 centre, 3 fast+1, 4 slow+1, 5 right side.
+// 2 centre, 3 fast+1, 4 slow+1, 5 right side; aux: f, and the boundary
+// neighbours' part of the right side (the same products, summed from zero).
 __global__ void __launch_bounds__(256) stage2_stencil_kernel(const DevProblem<double> P, const Stage2Grid g,
-                                                             const SubBox *boxes, double *stencil)
+                                                             const SubBox *boxes, double *stencil, double *aux)
 {
     __shared__ double s_cf[kMaxDense];
     for (int q = threadIdx.x; q < kMaxDense; q += blockDim.x) s_cf[q] = P.fdense[q];
@@ -1446,6 +1447,7 @@ __global__ void __launch_bounds__(256) stage2_stencil_kernel(const DevProblem<do
         const double aW = cx - bb[0] / (2.0 * g.dx0), aE = cx + bb[0] / (2.0 * g.dx0);
         const double aS = cy - bb[1] / (2.0 * g.dx1), aN = cy + bb[1] / (2.0 * g.dx1);
         double out[6] = {0.0, 0.0, -2.0 * cx - 2.0 * cy + c, 0.0, 0.0, f};
+        double yb = 0.0;
         // neighbours: west, east, south, north with their band slots
         const int ni[4] = {i - 1, i + 1, i, i};
         const int nj[4] = {j, j, j - 1, j + 1};
@@ -1454,14 +1456,19 @@ __global__ void __launch_bounds__(256) stage2_stencil_kernel(const DevProblem<do
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const bool inside = ni[q] > b.i0 && ni[q] < b.i1 && nj[q] > b.j0 && nj[q] < b.j1;
-            if (inside)
+            if (inside) {
                 out[slot[q]] = a[q];
-            else
-                out[5] -= a[q] * g.u[(size_t)nj[q] * g.n0 + ni[q]];
+            } else {
+                const double t = a[q] * g.u[(size_t)nj[q] * g.n0 + ni[q]];
+                out[5] -= t;
+                yb -= t;
+            }
         }
         double *o = stencil + (b.first + r) * 6;
 #pragma unroll
         for (int q = 0; q < 6; ++q) o[q] = out[q];
+        aux[(b.first + r) * 2] = f;
+        aux[(b.first + r) * 2 + 1] = yb;
     }
 }
 
@@ -1728,6 +1735,149 @@ __global__ void __launch_bounds__(kStage2SubstThreads) stage2_subst_kernel(const
     }
 }
 
+// Response columns of the subdomains (one workgroup per subdomain and four
+// columns, a wave per column): the solution for a unit right side at each
+// row next to the box's boundary, and for the source f with zero boundary
+// values, by the substitution of stage2_subst_kernel with the stored factors
+// (the chunks of multipliers and U rows staged once for the four waves). The
+// forward pass leaves y in the column, the backward pass overwrites it with
+// the solution.
+constexpr int kStage2RespWaves = kStage2SubstThreads / 64;
+__global__ void __launch_bounds__(kStage2SubstThreads) stage2_resp_kernel(const SubBox *boxes, const double *aux,
+                                                                          const double *factor, const double *lmul,
+                                                                          const Stage2Resp *tab, const uint32_t *rb,
+                                                                          double *resp)
+{
+    constexpr int MW = kStage2MaxBand;
+    constexpr int FS = MW + 2;
+    constexpr int CH = 64;
+    constexpr int PF = 8;
+    constexpr int NW = kStage2RespWaves;
+    __shared__ double Lc[CH * MW];
+    __shared__ double Bc[NW][CH];
+    __shared__ double Uc[(CH + MW) * FS];
+    __shared__ double Yc[NW][CH + MW];
+    const SubBox bx = boxes[blockIdx.x];
+    const Stage2Resp rt = tab[blockIdx.x];
+    const int w = bx.w;
+    const uint64_t n = (uint64_t)w * (uint64_t)bx.L;
+    const double *U = factor + bx.first * FS;
+    const double *Lm = lmul + bx.first * MW;
+    const double *fa = aux + bx.first * 2;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int col = (int)blockIdx.y * NW + wv;
+    const bool act = col <= rt.nb;
+    const bool src = col == rt.nb;  // the source column
+    const uint64_t rc = act && !src ? rb[rt.rb_at + col] : ~0ull;
+    double *out = resp + rt.out_at + (uint64_t)(act ? col : 0) * n;
+    auto rhs = [&](uint64_t q) { return src ? fa[q * 2] : (q == rc ? 1.0 : 0.0); };
+    double v = act && lane < w ? rhs((uint64_t)lane) : 0.0;
+    int s = 0;
+    for (uint64_t k0 = 0; k0 < n; k0 += CH) {
+        const int m = n - k0 < (uint64_t)CH ? (int)(n - k0) : CH;
+        __syncthreads();
+        stage_chunk<CH * MW / kStage2SubstThreads>(Lc, Lm + k0 * w, m * w, tid);
+        for (int idx = lane; idx < m; idx += 64) {
+            const uint64_t q = k0 + idx + w;
+            Bc[wv][idx] = act && q < n ? rhs(q) : 0.0;
+        }
+        __syncthreads();
+        if (act) {
+            double ybuf = 0.0;
+            for (int i0 = 0; i0 < m; i0 += PF) {
+                double lv[PF], bv[PF];
+                int su = s;
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    int d = lane - su - 1;
+                    if (d < 0) d += w;
+                    const bool ok = i0 + u < m && lane < w && k0 + i0 + u + 1 + d < n;
+                    lv[u] = ok ? Lc[(i0 + u) * w + d] : 0.0;
+                    bv[u] = i0 + u < m ? Bc[wv][i0 + u] : 0.0;
+                    if (++su == w) su = 0;
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    if (i0 + u >= m) break;
+                    const double yk = readlane_f64(v, s);
+                    ybuf = lane == i0 + u ? yk : ybuf;
+                    v = lane == s ? bv[u] : v;
+                    const double nv = v - lv[u] * yk;
+                    v = lv[u] != 0.0 ? nv : v;
+                    if (++s == w) s = 0;
+                }
+            }
+            if (lane < m) out[k0 + lane] = ybuf;
+        }
+    }
+    s = w - 1;
+    for (uint64_t hi = n; hi > 0;) {
+        const uint64_t lo = hi > CH ? hi - CH : 0;
+        const uint64_t base = lo > (uint64_t)w ? lo - w : 0;
+        __syncthreads();
+        stage_chunk<((CH + MW) * FS + kStage2SubstThreads - 1) / kStage2SubstThreads>(Uc, U + base * FS,
+                                                                                      (int)(hi - base) * FS, tid);
+        for (int idx = lane; idx < (int)(hi - base); idx += 64) Yc[wv][idx] = act ? gload(out + base + idx) : 0.0;
+        __syncthreads();
+        if (act) {
+            if (hi == n) v = lane < w ? Yc[wv][n - w + lane - base] : 0.0;
+            const int cnt = (int)(hi - lo);
+            double xbuf = 0.0;
+            for (int i0 = 0; i0 < cnt; i0 += PF) {
+                double rv[PF], uv[PF], yv[PF];
+                int su = s;
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const uint64_t k = hi - 1 - (uint64_t)(i0 + u);
+                    const bool in = i0 + u < cnt;
+                    int d = su - 1 - lane;
+                    if (d < 0) d += w;
+                    rv[u] = 1.0 / (in ? Uc[(k - base) * FS] : 1.0);
+                    uv[u] = in && lane < w && k >= (uint64_t)(d + 1) ? Uc[(k - 1 - d - base) * FS + (d + 1)] : 0.0;
+                    yv[u] = in && k >= (uint64_t)w ? Yc[wv][k - w - base] : 0.0;
+                    if (--su < 0) su = w - 1;
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    if (i0 + u >= cnt) break;
+                    const double xk = readlane_f64(v, s) * rv[u];
+                    xbuf = lane == i0 + u ? xk : xbuf;
+                    v = lane == s ? yv[u] : v;
+                    const double nv = v - uv[u] * xk;
+                    v = uv[u] != 0.0 ? nv : v;
+                    if (--s < 0) s = w - 1;
+                }
+            }
+            if (lane < cnt) out[hi - 1 - lane] = xbuf;
+        }
+        hi = lo;
+    }
+}
+
+// Interior values from the response columns: u = (f's column) + sum over the
+// rows next to the boundary of (that row's column) x (its boundary part of
+// the right side), in row order; one thread per unknown.
+__global__ void __launch_bounds__(256) stage2_apply_kernel(const Stage2Grid g, const SubBox *boxes, const double *aux,
+                                                           const Stage2Resp *tab, const uint32_t *rb,
+                                                           const double *resp)
+{
+    __shared__ double yb[kStage2MaxBoundaryRows];
+    const SubBox bx = boxes[blockIdx.y];
+    const Stage2Resp rt = tab[blockIdx.y];
+    const uint64_t n = (uint64_t)bx.w * (uint64_t)bx.L;
+    for (int c = threadIdx.x; c < rt.nb; c += blockDim.x) yb[c] = aux[(bx.first + rb[rt.rb_at + c]) * 2 + 1];
+    __syncthreads();
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+        const double *col = resp + rt.out_at + r;
+        double acc = col[(uint64_t)rt.nb * n];
+        for (int c = 0; c < rt.nb; ++c) acc = fma(col[(uint64_t)c * n], yb[c], acc);
+        int i, j;
+        stage2_point(bx, r, i, j);
+        g.u[(size_t)j * g.n0 + i] = acc;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_grid_residual(const DevProblem<double> &P, double sigma, const pdd_grid *g, void *r, hipStream_t s)
@@ -1779,21 +1929,33 @@ hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int
 }
 
 hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
-                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
-                               double *lmul, bool factored, hipStream_t s)
+                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *aux, double *factor,
+                               double *lmul, const Stage2Plan &plan, hipStream_t s)
 {
     if (n_boxes == 0) return hipSuccess;
     hipLaunchKernelGGL(stage2_stencil_kernel, dim3((max_unknowns + 255) / 256, n_boxes), dim3(256), 0, s, P, g,
-                       boxes, stencil);
+                       boxes, stencil, aux);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (!factored) {
+    if (!plan.factored) {
         hipLaunchKernelGGL(stage2_lu_kernel, dim3(n_boxes), dim3(kStage2LuThreads), 0, s, boxes, stencil, factor,
                            lmul);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(stage2_subst_kernel, dim3(n_boxes), dim3(kStage2SubstThreads), 0, s, g, boxes, stencil,
-                       factor, lmul);
+    if (!plan.resp) {
+        hipLaunchKernelGGL(stage2_subst_kernel, dim3(n_boxes), dim3(kStage2SubstThreads), 0, s, g, boxes, stencil,
+                           factor, lmul);
+        return hipGetLastError();
+    }
+    if (!plan.resp_ready) {
+        const uint32_t groups = (uint32_t)(plan.max_cols + kStage2RespWaves - 1) / kStage2RespWaves;
+        hipLaunchKernelGGL(stage2_resp_kernel, dim3(n_boxes, groups), dim3(kStage2SubstThreads), 0, s, boxes, aux,
+                           factor, lmul, plan.resp_tab, plan.rb, plan.resp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((max_unknowns + 255) / 256, 1024);
+    hipLaunchKernelGGL(stage2_apply_kernel, dim3(blocks, n_boxes), dim3(256), 0, s, g, boxes, aux, plan.resp_tab,
+                       plan.rb, plan.resp);
     return hipGetLastError();
 }
 

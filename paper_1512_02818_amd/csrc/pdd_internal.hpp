@@ -316,17 +316,41 @@ hipError_t launch_stage2_boundary(const DevProblem<double> &P, const Stage2Grid 
 // cross takes the mean of the two.
 hipError_t launch_stage2_lines(const Stage2Grid &g, const Stage2Line *lines, int32_t n_lines, const double *t,
                                const double *lam, hipStream_t s);
+// Response of a subdomain's interior to its boundary values: the rows next
+// to the box's boundary (nb of them, at rb[rb_at ..]) and, at out_at in the
+// response buffer, nb + 1 columns of n values (column q < nb: the solution
+// for a unit right side at row rb[rb_at + q]; column nb: the solution for the
+// source f with zero boundary values).
+struct Stage2Resp {
+    uint64_t rb_at, out_at;
+    int32_t nb, pad;
+};
+constexpr int kStage2MaxBoundaryRows = 4096;
+// What launch_stage2_solve is to do after the stencils: factor (unless
+// `factored`), then either substitute the right side (resp == nullptr) or,
+// with the response columns (computed first unless `resp_ready`), add up
+// f's column and the boundary values' columns.
+struct Stage2Plan {
+    bool factored;
+    const Stage2Resp *resp_tab;  // device, one per subdomain, or null
+    const uint32_t *rb;          // device rows next to the boundary
+    double *resp;                // device response columns
+    int32_t max_cols;            // largest nb + 1
+    bool resp_ready;
+};
 // Finite-difference stencils of every subdomain's unknowns (6 doubles per
 // unknown: slow-1, fast-1, centre, fast+1, slow+1 coefficients and the right
-// side with the boundary values moved over), then (unless `factored`: factor
-// and lmul already hold the factors of these subdomains' matrices) the banded
-// LU factorization of each subdomain, and the forward elimination and back
-// substitution of its right side (one workgroup each), writing the interior
-// values into u. factor: unknowns x (kStage2MaxBand + 2) doubles; lmul:
-// unknowns x kStage2MaxBand doubles.
+// side with the boundary values moved over; in aux, 2 doubles per unknown:
+// the source f alone and the boundary values' part of the right side), then
+// (unless plan.factored: factor and lmul already hold the factors of these
+// subdomains' matrices) the banded LU factorization of each subdomain, and
+// the interior values written into u: by forward elimination and back
+// substitution of the right side (one workgroup each), or from the response
+// columns. factor: unknowns x (kStage2MaxBand + 2) doubles; lmul: unknowns x
+// kStage2MaxBand doubles.
 hipError_t launch_stage2_solve(const DevProblem<double> &P, const Stage2Grid &g, const SubBox *boxes,
-                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *factor,
-                               double *lmul, bool factored, hipStream_t s);
+                               int32_t n_boxes, uint32_t max_unknowns, double *stencil, double *aux, double *factor,
+                               double *lmul, const Stage2Plan &plan, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_zero(void *ptr, uint64_t bytes, hipStream_t s);
 // Starting sums of every group node: zero, or the statistics already in the

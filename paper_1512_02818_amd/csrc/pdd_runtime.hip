@@ -1016,7 +1016,7 @@ void pdd_shutdown(pdd_ctx *ctx)
     if (ctx->any_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->any_staged) (void)hipEventSynchronize(ctx->staged);
     for (DeviceBuffer *b : {&ctx->nodes, &ctx->starts, &ctx->acc, &ctx->counters, &ctx->rec, &ctx->partials,
-                            &ctx->gather, &ctx->cells, &ctx->stage2, &ctx->stage2_lu})
+                            &ctx->gather, &ctx->cells, &ctx->stage2, &ctx->stage2_lu, &ctx->stage2_resp})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->readback) (void)hipHostFree(ctx->readback);
@@ -1689,14 +1689,41 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
             t_all.insert(t_all.end(), t.begin(), t.end());
             lam_all.insert(lam_all.end(), lam.begin(), lam.end());
         }
-    // device tables: lines | t | lam | boxes | stencils
+    // the rows of every subdomain next to its boundary, and the layout of its
+    // response columns (nb + 1 columns of its unknowns)
+    std::vector<Stage2Resp> resp_tab(boxes.size());
+    std::vector<uint32_t> rb;
+    uint64_t resp_values = 0;
+    int32_t max_cols = 0;
+    bool use_resp = true;
+    for (size_t q = 0; q < boxes.size(); ++q) {
+        const SubBox &bx = boxes[q];
+        const uint64_t nq = (uint64_t)bx.w * bx.L;
+        resp_tab[q].rb_at = rb.size();
+        for (uint64_t r = 0; r < nq; ++r) {
+            const int sl = (int)(r / bx.w), f = (int)(r % bx.w);
+            const int i = bx.i0 + 1 + (bx.fast_x ? f : sl), j = bx.j0 + 1 + (bx.fast_x ? sl : f);
+            if (i - 1 == bx.i0 || i + 1 == bx.i1 || j - 1 == bx.j0 || j + 1 == bx.j1) rb.push_back((uint32_t)r);
+        }
+        resp_tab[q].nb = (int32_t)(rb.size() - resp_tab[q].rb_at);
+        resp_tab[q].out_at = resp_values;
+        resp_values += (uint64_t)(resp_tab[q].nb + 1) * nq;
+        max_cols = std::max(max_cols, resp_tab[q].nb + 1);
+        use_resp = use_resp && resp_tab[q].nb <= kStage2MaxBoundaryRows;
+    }
+    // response columns up to 2 GiB; beyond, every call substitutes
+    use_resp = use_resp && resp_values * sizeof(double) <= (2ull << 30);
+    // device tables: lines | t | lam | boxes | response layout | boundary rows | stencils | aux
     const size_t off_lines = 0;
     const size_t off_t = align_up(off_lines + lines.size() * sizeof(Stage2Line), 256);
     const size_t off_lam = align_up(off_t + t_all.size() * sizeof(double), 256);
     const size_t off_boxes = align_up(off_lam + lam_all.size() * sizeof(double), 256);
-    const size_t table_bytes = align_up(off_boxes + boxes.size() * sizeof(SubBox), 256);
+    const size_t off_resp = align_up(off_boxes + boxes.size() * sizeof(SubBox), 256);
+    const size_t off_rb = align_up(off_resp + resp_tab.size() * sizeof(Stage2Resp), 256);
+    const size_t table_bytes = align_up(off_rb + rb.size() * sizeof(uint32_t), 256);
     const size_t off_stencil = table_bytes;
-    const size_t bytes = off_stencil + unknowns * 6 * sizeof(double);
+    const size_t off_aux = align_up(off_stencil + unknowns * 6 * sizeof(double), 256);
+    const size_t bytes = off_aux + unknowns * 2 * sizeof(double);
     if ((st = ensure(ctx, ctx->stage2, bytes))) return st;
     // the subdomain matrices depend on the operator (sigma, b, c), the grid
     // and the interfaces: factored already when the last call had the same
@@ -1715,12 +1742,28 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
     }
     double *d_factor = static_cast<double *>(ctx->stage2_lu.ptr);
     double *d_lmul = d_factor + unknowns * (kStage2MaxBand + 2);
+    // the response columns depend on the factors and on f: the factors' key
+    // and the problem
+    std::vector<double> resp_key = key;
+    resp_key.push_back((double)problem->serial);
+    const size_t resp_bytes = resp_values * sizeof(double);
+    bool resp_ready = false;
+    if (use_resp) {
+        resp_ready = factored && ctx->stage2_resp_key == resp_key && ctx->stage2_resp.ptr &&
+                     ctx->stage2_resp.cap >= resp_bytes;
+        if (!resp_ready) {
+            ctx->stage2_resp_key.clear();
+            if ((st = ensure(ctx, ctx->stage2_resp, resp_bytes))) return st;
+        }
+    }
     if ((st = ensure_stage(ctx, table_bytes))) return st;
     char *h = static_cast<char *>(ctx->stage);
     std::memcpy(h + off_lines, lines.data(), lines.size() * sizeof(Stage2Line));
     std::memcpy(h + off_t, t_all.data(), t_all.size() * sizeof(double));
     std::memcpy(h + off_lam, lam_all.data(), lam_all.size() * sizeof(double));
     std::memcpy(h + off_boxes, boxes.data(), boxes.size() * sizeof(SubBox));
+    std::memcpy(h + off_resp, resp_tab.data(), resp_tab.size() * sizeof(Stage2Resp));
+    std::memcpy(h + off_rb, rb.data(), rb.size() * sizeof(uint32_t));
     char *dv = static_cast<char *>(ctx->stage2.ptr);
     HIP_TRY(hipMemcpyAsync(dv, h, table_bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->staged, s));
@@ -1728,10 +1771,20 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
     HIP_TRY(launch_stage2_lines(g, reinterpret_cast<const Stage2Line *>(dv + off_lines), (int32_t)lines.size(),
                                 reinterpret_cast<const double *>(dv + off_t),
                                 reinterpret_cast<const double *>(dv + off_lam), s));
+    Stage2Plan plan{};
+    plan.factored = factored;
+    if (use_resp) {
+        plan.resp_tab = reinterpret_cast<const Stage2Resp *>(dv + off_resp);
+        plan.rb = reinterpret_cast<const uint32_t *>(dv + off_rb);
+        plan.resp = static_cast<double *>(ctx->stage2_resp.ptr);
+        plan.max_cols = max_cols;
+        plan.resp_ready = resp_ready;
+    }
     HIP_TRY(launch_stage2_solve(problem->pd, g, reinterpret_cast<const SubBox *>(dv + off_boxes), (int32_t)boxes.size(),
-                                (uint32_t)max_unknowns, reinterpret_cast<double *>(dv + off_stencil), d_factor, d_lmul,
-                                factored, s));
+                                (uint32_t)max_unknowns, reinterpret_cast<double *>(dv + off_stencil),
+                                reinterpret_cast<double *>(dv + off_aux), d_factor, d_lmul, plan, s));
     ctx->stage2_key = key;
+    if (use_resp) ctx->stage2_resp_key = resp_key;
     HIP_TRY(hipEventRecord(ctx->done, s));
     ctx->any_done = true;
     return PDD_OK;

@@ -103,11 +103,13 @@ def test_stage2_arguments(ctx):
 def test_factor_cache_reuse_and_invalidation(ctx):
     """A context keeps the LU factors of the last call's subdomain matrices
     (they depend on the operator, the grid and the interfaces, not on the
-    interface data) and only eliminates the right sides of a call with the
-    same ones. Every call of a sequence that hits and misses the cache gives
-    the bits of the same call in a fresh context, and the hit matches the
-    oracle: new nodal values on the same strips (hit), another drift (miss),
-    other interfaces (miss), back to the first (miss, then hit)."""
+    interface data) and each subdomain's response columns (its solution for
+    f and for a unit value at each row next to its boundary), so a call with
+    the same operator, grid, interfaces and problem only adds up columns.
+    Every call of a sequence that hits and misses the cache gives the bits of
+    the same call in a fresh context, and the hit matches the oracle: new
+    nodal values on the same strips (hit), another drift (miss), other
+    interfaces (miss), back to the first (miss, then hit)."""
     from oracle import stage2 as S2
     pd = W.unit_square_problem(seed=0)
     pd2 = dict(pd, b0=[0.3, -0.2])  # another operator on the same grid
