@@ -112,16 +112,18 @@ def level_solve(ctx, prob, nodes, a, beta, q, delta, grads=None, n_pilot=128, n_
     tensors) the Ito control variate. One pdd_solve_to_tolerance over the
     nodes as separate items. Returns (stats per node, h per node)."""
     h = np.clip((a / (2.0 * np.abs(beta))) ** (1.0 / delta), *h_bounds)
+    # one statistics buffer for all the nodes (one copy back, not one per node)
+    out = pdd.alloc_stats(len(nodes))
+    sz = pdd.STATS_DTYPE.itemsize
     items = []
     for i, x in enumerate(nodes):
-        it = {"problem": prob, "nodes": x[None, :],
+        it = {"problem": prob, "nodes": x[None, :], "out": out[i * sz:(i + 1) * sz],
               "opts": dict(dt=float(h[i]), precision="fp32", stream_id=stream0 + i)}
         if grads is not None:
             it["grad"], it["grad_t"] = grads
         items.append(it)
-    outs = pdd.solve_to_tolerance(ctx, items, a / (2.0 * q), n_pilot, n_max)
-    st = np.concatenate([pdd.stats_to_numpy(o) for o in outs])
-    return st, h
+    pdd.solve_to_tolerance(ctx, items, a / (2.0 * q), n_pilot, n_max)
+    return pdd.stats_to_numpy(out), h
 
 
 def run(ctx, pd, nodes, part, a0, q=2.0, delta=1.0, a_max=1.0, exact=None, schedule=None, fit_cloud=(100, 1000),
