@@ -156,6 +156,8 @@ def parse():
                     help="only run the plain FP64 solve of the node-solve measurement (unit square, h=1e-4, "
                          "--profile-replicas copies of the 18 nodes with distinct streams, this many paths per "
                          "node) three times and print its timing (for profilers)")
+    ap.add_argument("--profile-stage2", type=int, default=0,
+                    help="run only the second stage on the unit square's strips on this n^2 grid, for profiling")
     ap.add_argument("--profile-batch", type=float, default=0.0,
                     help="only run the 64-problem batched solve at this path-count scale and print its timing "
                          "(for profilers)")
@@ -870,6 +872,36 @@ def profile_plain64(paths, replicas, calibrate_mib=0):
     ctx.close()
 
 
+def profile_stage2(n):
+    """The second stage alone, for kernel-trace runs: the unit square's four
+    strips on an n^2 grid, four problems with the same operator (so the LU
+    factors are kept across them while each needs its own response columns),
+    two calls each with the exact nodal values; wall time of every call."""
+    import time
+
+    import torch
+
+    from paper_1512_02818_amd import pdd
+    from paper_1512_02818_amd import workloads as W
+    ctx = pdd.Context(0)
+    pd = W.unit_square_problem(seed=SEED)
+    part = W.unit_square_partition(n)
+    nodes = W.unit_square_nodes()
+    vals = W.manufactured_u(pd, nodes)
+    ms = []
+    for k in range(4):
+        prob = pdd.Problem(ctx, pd)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pdd.stage2(prob, part["n"], part["cuts"], nodes, vals, part["rbf_eps"])
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t) * 1e3)
+        prob.close()
+    print(json.dumps({"stage2_profile": {"grid": n, "call_ms": ms}}), flush=True)
+    ctx.close()
+
+
 def profile_batch(scale):
     """The 64-problem batched solve alone at path-count scale `scale`, for
     kernel-trace and counter runs."""
@@ -888,6 +920,9 @@ def main():
         return
     if args.profile_plain64 > 0:
         profile_plain64(args.profile_plain64, args.profile_replicas, args.calibrate_copy_mib)
+        return
+    if args.profile_stage2 > 0:
+        profile_stage2(args.profile_stage2)
         return
     if args.profile_batch > 0:
         profile_batch(args.profile_batch)
