@@ -463,7 +463,8 @@ typedef struct {
  * interfaces and problem (another set of nodal values) then only adds up
  * those columns, weighted by its boundary values, in a fixed order. The
  * result equals the direct solve to rounding (the same in a fresh context
- * and in a kept one, bit for bit). `nodes` (host,
+ * and in a kept one, bit for bit); PDD_STAGE2_SUBSTITUTE=1 in the
+ * environment makes every call substitute instead. `nodes` (host,
  * n_nodes x 2) are the interface nodes and `values` (host) their nodal
  * values; a node may lie on several lines. Synchronous (the interpolation
  * weights are solved on the host once the boundary values are on the

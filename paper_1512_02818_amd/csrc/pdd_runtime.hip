@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -1711,8 +1712,12 @@ pdd_status pdd_stage2(pdd_problem *problem, const pdd_partition *part, const dou
         max_cols = std::max(max_cols, resp_tab[q].nb + 1);
         use_resp = use_resp && resp_tab[q].nb <= kStage2MaxBoundaryRows;
     }
-    // response columns up to 2 GiB; beyond, every call substitutes
-    use_resp = use_resp && resp_values * sizeof(double) <= (2ull << 30);
+    // response columns up to 2 GiB; beyond, every call substitutes (as every
+    // call does with PDD_STAGE2_SUBSTITUTE=1 in the environment, which the
+    // tests use to check the two ways against each other)
+    const char *force_subst = std::getenv("PDD_STAGE2_SUBSTITUTE");
+    use_resp = use_resp && resp_values * sizeof(double) <= (2ull << 30) &&
+               !(force_subst && force_subst[0] == '1');
     // device tables: lines | t | lam | boxes | response layout | boundary rows | stencils | aux
     const size_t off_lines = 0;
     const size_t off_t = align_up(off_lines + lines.size() * sizeof(Stage2Line), 256);

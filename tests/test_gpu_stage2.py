@@ -138,3 +138,31 @@ def test_factor_cache_reuse_and_invalidation(ctx):
     oracle = S2.stage2(pd, strips["n"], strips["cuts"], nodes, v2, strips["rbf_eps"])
     assert np.max(np.abs(got[1] - oracle) / np.maximum(1.0, np.abs(oracle))) <= 1e-10
     assert got[0].tobytes() == got[4].tobytes() and got[1].tobytes() == got[5].tobytes()
+
+
+def test_substitution_and_response_columns_agree(ctx, monkeypatch):
+    """The two ways of solving the subdomains, substituting each call's right
+    side with the kept factors (forced here; the library falls back to it
+    when the response columns would exceed 2 GiB) and adding up the kept
+    response columns, agree to rounding and both match the oracle."""
+    from oracle import stage2 as S2
+    pd = W.unit_square_problem(seed=0)
+    nodes = W.unit_square_nodes()
+    vals = W.manufactured_u(pd, nodes) + np.random.default_rng(5).normal(scale=0.01, size=len(nodes))
+    part = W.unit_square_partition(129)
+    got = {}
+    for way in ("0", "1"):
+        monkeypatch.setenv("PDD_STAGE2_SUBSTITUTE", way)
+        fresh = pdd.Context(0)
+        pr = pdd.Problem(fresh, pd)
+        got[way] = [pdd.stage2(pr, part["n"], part["cuts"], nodes, vals, part["rbf_eps"]).cpu().numpy()
+                    for _ in range(2)]  # the second call reuses what the first kept
+        pr.close()
+        fresh.close()
+    monkeypatch.delenv("PDD_STAGE2_SUBSTITUTE")
+    oracle = S2.stage2(pd, part["n"], part["cuts"], nodes, vals, part["rbf_eps"])
+    scale = np.maximum(1.0, np.abs(oracle))
+    for way in ("0", "1"):
+        assert got[way][0].tobytes() == got[way][1].tobytes()
+        assert np.max(np.abs(got[way][0] - oracle) / scale) <= 1e-10
+    assert np.max(np.abs(got["0"][0] - got["1"][0]) / scale) <= 1e-12
