@@ -341,11 +341,11 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
         int i[D];
         T w[D];
         grid_cell<T, D>(P.tabv[3], x, i, w);
-        if (D == 2 && (tab & 128u)) {  // by point: the records of the cell's four corners
+        if (D == 2 && (tab & 128u)) {  // pair records of the cell's two lower corners: all four
             typedef T V4 __attribute__((ext_vector_type(4)));
             const uint32_t n0 = (uint32_t)P.tabv[3].n[0];
-            const V4 *r0 = reinterpret_cast<const V4 *>(P.tab_fused) + ((uint32_t)i[1] * n0 + (uint32_t)i[0]);
-            const V4 p00 = gload(r0), p10 = gload(r0 + 1), p01 = gload(r0 + n0), p11 = gload(r0 + n0 + 1);
+            const V4 *r0 = reinterpret_cast<const V4 *>(P.tab_fused) + 2u * ((uint32_t)i[1] * n0 + (uint32_t)i[0]);
+            const V4 p00 = gload(r0), p01 = gload(r0 + 1), p10 = gload(r0 + 2), p11 = gload(r0 + 3);
             b[0] = interp_corner_values<T>(p00.x, p10.x, p01.x, p11.x, w);
             b[1 % D] = interp_corner_values<T>(p00.y, p10.y, p01.y, p11.y, w);
             c = interp_corner_values<T>(p00.z, p10.z, p01.z, p11.z, w);
@@ -558,7 +558,7 @@ __global__ void grid_cells_kernel(const S *__restrict__ data, int n0, int n1, in
 }
 
 // Point values of a grid converted from S to T into every stride-th slot (a
-// field of interleaved point records): one thread per point.
+// field of interleaved records): one thread per point.
 template <class S, class T>
 __global__ void grid_points_kernel(const S *__restrict__ data, uint64_t n_points, T *__restrict__ out,
                                    uint32_t stride, uint32_t off)

@@ -87,7 +87,8 @@ struct DevProblem {
     // geometry and interleaved (tabv[q] then keep only the geometry): cell r's
     // record at tab_fused + r (dim + 2) 2^dim holds the 2^dim corners of b_0,
     // ..., c, f in that order; with bit 7 too (2D only), grid point p (x
-    // fastest) has its record at tab_fused + 4 p, the values of b_0, b_1, c, f.
+    // fastest, rows 0 .. n1 - 2) has its record at tab_fused + 8 p: the values
+    // of b_0, b_1, c, f at p, then at p + n0 (the point above).
     const T *tab_fused;
 };
 

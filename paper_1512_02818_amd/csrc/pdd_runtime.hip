@@ -346,7 +346,7 @@ int pdd::occupancy(pdd_ctx *ctx, const void *fn, int block, bool cache)
 }
 
 // Largest FP32 cell-record layout of a 2D tabulated problem (about half an
-// XCD's L2); larger grids are interleaved by point.
+// XCD's L2); larger grids are interleaved by pairs of points.
 constexpr size_t kCellRecordMaxBytes = 8u << 20;
 
 uint64_t next_problem_serial()
@@ -1083,12 +1083,14 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
     // b_0 .. b_{D-1}, c and f all given on one geometry: interleaved (slot 6),
     // so a step reads all of them at once, in one record of the (D + 2) values'
     // 2^D corners per cell (one 64-byte read per step in 2D FP32). A 2D grid
-    // whose cell records would outgrow an XCD's 4 MB L2 takes one record of
-    // the four values per grid point instead (a quarter of the bytes; a step
-    // reads two adjacent points in two rows, 2 x 32 bytes): at 513^2 the cell
-    // records (16.8 MB) hit L2 55 % of the time and the launch waits on the
-    // memory fabric, the point records (4.2 MB) hit 99 % and it waits on L2
-    // requests, 7.5 % sooner.
+    // whose cell records would outgrow an XCD's 4 MB L2 takes, per grid point,
+    // one record of the four values at the point and at the point above it
+    // instead (half the bytes; a cell's four corners are the records of two
+    // adjacent points, 64 contiguous bytes, mostly one L2 request): at 513^2
+    // the cell records (16.8 MB) hit L2 55 % of the time and the launch waits
+    // on the memory fabric; records of single points (4.2 MB; a step then
+    // reads two rows, about 2.2 L2 requests) were 7.5 % faster, these pair
+    // records (8.4 MB) 6 % faster again.
     auto in_record = [&](int q) { return q < D || q == 3 || q == 4; };
     bool fused = g[3] != nullptr;  // the geometry is compared with c's grid
     for (int q = 0; q < 5; ++q)
@@ -1099,7 +1101,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
         }
     const bool by_point =
         fused && D == 2 && (size_t)(g[3]->n[0] - 1) * (size_t)(g[3]->n[1] - 1) * 16 * sizeof(float) > kCellRecordMaxBytes;
-    const uint32_t rec_vals = by_point ? 4u : (uint32_t)((D + 2) << D);
+    const uint32_t rec_vals = by_point ? 8u : (uint32_t)((D + 2) << D);
     size_t off32[7] = {}, off64[7] = {}, n32 = 0, n64 = 0;
     for (int q = 0; q < 6; ++q)
         if ((tab & (1u << q)) && !(fused && in_record(q))) {
@@ -1109,7 +1111,7 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
             n64 += align_up(cell_values<double>(g[q]->n, D), 64);
         }
     if (fused) {
-        const size_t recs = by_point ? (size_t)g[3]->n[0] * g[3]->n[1] : cell_values<float>(g[3]->n, D) >> D;
+        const size_t recs = by_point ? (size_t)g[3]->n[0] * (g[3]->n[1] - 1) : cell_values<float>(g[3]->n, D) >> D;
         off32[6] = n32;
         n32 += align_up(recs * rec_vals, 64);
         off64[6] = n64;
@@ -1149,14 +1151,22 @@ pdd_status pdd_create_problem_tabulated(pdd_ctx *ctx, const pdd_problem_desc *de
             float *d32 = c32 + (rec ? off32[6] : off32[q]);
             double *d64 = c64 + (rec ? off64[6] : off64[q]);
             hipError_t e1, e2;
-            if (rec && by_point) {  // field k of the point records
-                const uint64_t np = (uint64_t)gq->n[0] * gq->n[1];
-                e1 = gq->dtype == PDD_DTYPE_F32
-                         ? launch_grid_points_strided<float, float>(static_cast<const float *>(gq->data), np, d32, 4u, k, nullptr)
-                         : launch_grid_points_strided<double, float>(static_cast<const double *>(gq->data), np, d32, 4u, k, nullptr);
-                e2 = gq->dtype == PDD_DTYPE_F32
-                         ? launch_grid_points_strided<float, double>(static_cast<const float *>(gq->data), np, d64, 4u, k, nullptr)
-                         : launch_grid_points_strided<double, double>(static_cast<const double *>(gq->data), np, d64, 4u, k, nullptr);
+            if (rec && by_point) {  // field k of the pair records: point p, then p + n0
+                const uint64_t np = (uint64_t)gq->n[0] * (gq->n[1] - 1);
+                const uint64_t n0 = (uint64_t)gq->n[0];
+                if (gq->dtype == PDD_DTYPE_F32) {
+                    const float *src = static_cast<const float *>(gq->data);
+                    e1 = launch_grid_points_strided<float, float>(src, np, d32, 8u, k, nullptr);
+                    if (e1 == hipSuccess) e1 = launch_grid_points_strided<float, float>(src + n0, np, d32, 8u, 4u + k, nullptr);
+                    e2 = launch_grid_points_strided<float, double>(src, np, d64, 8u, k, nullptr);
+                    if (e2 == hipSuccess) e2 = launch_grid_points_strided<float, double>(src + n0, np, d64, 8u, 4u + k, nullptr);
+                } else {
+                    const double *src = static_cast<const double *>(gq->data);
+                    e1 = launch_grid_points_strided<double, float>(src, np, d32, 8u, k, nullptr);
+                    if (e1 == hipSuccess) e1 = launch_grid_points_strided<double, float>(src + n0, np, d32, 8u, 4u + k, nullptr);
+                    e2 = launch_grid_points_strided<double, double>(src, np, d64, 8u, k, nullptr);
+                    if (e2 == hipSuccess) e2 = launch_grid_points_strided<double, double>(src + n0, np, d64, 8u, 4u + k, nullptr);
+                }
             } else if (gq->dtype == PDD_DTYPE_F32) {
                 const float *src = static_cast<const float *>(gq->data);
                 e1 = D == 2 ? launch_grid_cells_strided<float, float, 2>(src, gq->n, d32, stride, off, nullptr)
