@@ -810,13 +810,16 @@ struct Walker {
         if constexpr (EST == kEstIto) {
             // eq. F:xiControlVariate, left-point rule: -Y sigma grad(u~)(X_k)
             // . sqrt(h) N_k, with this step's normals; the gradient grids
-            // share one geometry, so the cell is found once
+            // share one geometry, so the cell is found once, and their cell
+            // layouts are interleaved, so its corners of every component are
+            // one record (32 bytes in 2D FP32: one L2 request, not two)
             int gi[D];
             T gw[D];
             grid_cell<T, D>(a.grad[0], X, gi, gw);
+            const T *rec = a.grad[0].cells + cell_index<T, D>(a.grad[0], gi) * (size_t)(D << D);
             T gn = (T)0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) gn = madd(interp_cell_at<T, D>(a.grad[d], gi, gw), n[d], gn);
+            for (int d = 0; d < D; ++d) gn = madd(interp_corners<T, D>(rec + (d << D), gw), n[d], gn);
             R -= (double)((Y * a.sig_sqh) * gn);
         }
         Y = madd(hY, c, Y);

@@ -141,7 +141,9 @@ struct ItemCore {
 // solve it belongs to, when several solves that walk alike are merged into
 // this item; null: node, stream_tag, path_offset of the core. The
 // single-item kernel takes the core alone. Ito items read the components of
-// grad(u~) from grad[0 .. dim - 1] (one grid geometry, cell layout).
+// grad(u~) from grad[0 .. dim - 1] (one grid geometry; the components'
+// cell layouts interleaved at grad[0].cells: cell r's record of dim x 2^dim
+// values at r dim 2^dim, component c's corners at offset c 2^dim).
 template <class T>
 struct ItemDesc : ItemCore<T> {
     const uint32_t *node_rng;

@@ -621,24 +621,30 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     // of a correction item, the gradient components of an Ito item (grid c of
     // item q at cell_at[3 q + c]); one copy per distinct grid, rebuilt per
     // solve since the caller may change a grid's values between solves
+    // (an Ito item's D components are interleaved: one record of D x 2^D
+    // values per cell, component c at offset c 2^D, keyed by its first grid)
     std::vector<const pdd_grid *> cell_grid;
     std::vector<size_t> cell_off, cell_at(3 * (size_t)n_items, 0);
     if (HAS_E) {
         size_t used = 0;
-        for (int q = 0; q < n_items; ++q)
-            for (int c = 0; c < (EST == kEstIto ? D : 1); ++c) {
-                const pdd_grid *g = EST == kEstIto ? &items[q]->grad[c] : items[q]->resid;
-                size_t k = 0;
-                while (k < cell_grid.size() &&
-                       !(cell_grid[k]->data == g->data && std::equal(g->n, g->n + D, cell_grid[k]->n)))
-                    ++k;
-                if (k == cell_grid.size()) {
-                    cell_grid.push_back(g);
-                    cell_off.push_back(used);
-                    used += align_up(cell_values<T>(g->n, D), 64);
-                }
-                cell_at[3 * (size_t)q + c] = cell_off[k];
+        for (int q = 0; q < n_items; ++q) {
+            const pdd_grid *g = EST == kEstIto ? &items[q]->grad[0] : items[q]->resid;
+            auto same = [&](const pdd_grid *o) {
+                if (!std::equal(g->n, g->n + D, o->n)) return false;
+                if (EST != kEstIto) return o->data == g->data;
+                for (int c = 0; c < D; ++c)
+                    if ((&items[q]->grad[0])[c].data != o[c].data) return false;
+                return true;
+            };
+            size_t k = 0;
+            while (k < cell_grid.size() && !same(cell_grid[k])) ++k;
+            if (k == cell_grid.size()) {
+                cell_grid.push_back(g);
+                cell_off.push_back(used);
+                used += align_up(cell_values<T>(g->n, D) * (EST == kEstIto ? D : 1), 64);
             }
+            cell_at[3 * (size_t)q] = cell_off[k];
+        }
         if ((st = ensure(ctx, ctx->cells, used * sizeof(T)))) return st;
     }
     T *d_cells = static_cast<T *>(ctx->cells.ptr);
@@ -733,7 +739,7 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
         if (EST == kEstIto)
             for (int c = 0; c < D; ++c) {
                 a.grad[c] = make_view<T>(&it.grad[c], D);
-                a.grad[c].cells = d_cells + cell_at[3 * (size_t)q + c];
+                a.grad[c].cells = d_cells + cell_at[3 * (size_t)q];
             }
     }
     h_gstart[n_nodes_all] = total;
@@ -787,9 +793,17 @@ pdd_status run_group(pdd_ctx *ctx, std::vector<HostItem *> &items, const pdd_tun
     // zero sums, or the earlier paths' sums of accumulating items
     HIP_TRY(launch_init_acc(d_acc, (uint32_t)n_nodes_all, d_nitem, d_fitems, s));
     HIP_TRY(launch_zero(ctx->counters.ptr, ctr_bytes, s));
-    for (size_t k = 0; k < cell_grid.size(); ++k)
-        HIP_TRY((launch_grid_cells<T, T, D>(static_cast<const T *>(cell_grid[k]->data), cell_grid[k]->n,
-                                         d_cells + cell_off[k], s)));
+    for (size_t k = 0; k < cell_grid.size(); ++k) {
+        if (EST == kEstIto) {
+            for (int c = 0; c < D; ++c)
+                HIP_TRY((launch_grid_cells_strided<T, T, D>(static_cast<const T *>(cell_grid[k][c].data),
+                                                             cell_grid[k]->n, d_cells + cell_off[k],
+                                                             (uint32_t)(D << D), (uint32_t)(c << D), s)));
+        } else {
+            HIP_TRY((launch_grid_cells<T, T, D>(static_cast<const T *>(cell_grid[k]->data), cell_grid[k]->n,
+                                             d_cells + cell_off[k], s)));
+        }
+    }
 
     const int block = tune.block;
     // (the single-item kernel has no per-node RNG table)
