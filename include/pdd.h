@@ -567,6 +567,10 @@ typedef struct {
     pdd_node_stats *out;         /* host, n_nodes entries; final statistics, written before
                                     the completion is reported */
     uint64_t user_tag;           /* returned in the completion */
+    const pdd_grid *grad;        /* NULL, or the problem's dim gradient grids of u~ (one
+                                    geometry): the Ito control variate, as pdd_solve_ito;
+                                    not with u_prev / resid (structs copied, data borrowed
+                                    until completion) */
 } pdd_request;
 
 typedef struct {

@@ -51,7 +51,8 @@ struct Request {
     pdd_request req{};
     std::vector<double> nodes;          // copy of the caller's nodes
     pdd_grid u_prev{}, resid{};         // copies of the grid structs
-    bool cv = false;
+    pdd_grid grad[3]{};                 // gradient grids of an Ito request (copies)
+    bool cv = false, ito = false;
     uint64_t mem = 0;                   // memory model of the request
     Phase phase = Phase::Queued;
     pdd_status status = PDD_OK;         // of its last allocation or epoch
@@ -230,6 +231,7 @@ void pdd_server::launch(int lane, std::vector<Request *> &batch, uint64_t paths)
         it.prob = r->req.problem;
         it.u_prev = r->cv ? &r->u_prev : nullptr;
         it.resid = r->cv ? &r->resid : nullptr;
+        it.grad = r->ito ? r->grad : nullptr;
         it.nodes = r->nodes.data();
         it.n_nodes = r->req.n_nodes;
         it.o = &r->opts;
@@ -552,6 +554,10 @@ pdd_status pdd_server_submit(pdd_server *sv, const pdd_request *req, uint64_t *i
     r->cv = req->u_prev || req->resid;
     if (req->u_prev) r->u_prev = *req->u_prev;
     if (req->resid) r->resid = *req->resid;
+    r->ito = req->grad != nullptr;
+    if (r->ito && r->cv) return fail(PDD_E_INVALID, "a request takes the correction grids or the gradient grids, not both");
+    if (r->ito)
+        for (int c = 0; c < dim; ++c) r->grad[c] = req->grad[c];
     // the same checks as a solve of the pilot (nodes inside, grids, options)
     pdd_solve_opts op{};
     op.dt = req->dt;
@@ -563,6 +569,7 @@ pdd_status pdd_server_submit(pdd_server *sv, const pdd_request *req, uint64_t *i
     it.prob = req->problem;
     it.u_prev = req->u_prev ? &r->u_prev : nullptr;
     it.resid = req->resid ? &r->resid : nullptr;
+    it.grad = r->ito ? r->grad : nullptr;
     it.nodes = r->nodes.data();
     it.n_nodes = req->n_nodes;
     it.o = &op;
@@ -575,6 +582,7 @@ pdd_status pdd_server_submit(pdd_server *sv, const pdd_request *req, uint64_t *i
     // memory model: device statistics + the solve's per-node tables + grids
     r->mem = n * (sizeof(pdd_node_stats) + sizeof(NodeAcc) + dim * sizeof(double) + 2 * sizeof(uint64_t));
     if (r->cv) r->mem += grid_bytes(r->u_prev, dim) + grid_bytes(r->resid, dim);
+    if (r->ito) r->mem += (uint64_t)dim * grid_bytes(r->grad[0], dim);
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
     ++sv->rep.submitted;

@@ -147,7 +147,7 @@ class Request(C.Structure):
                 ("dt", C.c_double), ("target_se", C.c_double), ("precision", C.c_int32),
                 ("exit_mode", C.c_int32), ("stream_id", C.c_uint32), ("reserved", C.c_int32),
                 ("u_prev", C.POINTER(Grid)), ("resid", C.POINTER(Grid)), ("out", C.c_void_p),
-                ("user_tag", C.c_uint64)]
+                ("user_tag", C.c_uint64), ("grad", C.POINTER(Grid))]
 
 
 class Completion(C.Structure):
@@ -707,7 +707,8 @@ class Server:
         self.results = {}  # id -> (Completion fields, stats array)
 
     def submit(self, problem: Problem, nodes, dt, target_se, precision="fp32", exit="bridge",
-               stream_id=0, u_prev=None, u_prev_t=None, resid=None, resid_t=None, tag=0):
+               stream_id=0, u_prev=None, u_prev_t=None, resid=None, resid_t=None, tag=0, grad=None,
+               grad_t=None):
         nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(-1, problem.dim))
         out = np.zeros(len(nodes), dtype=STATS_DTYPE)
         r = Request()
@@ -725,6 +726,10 @@ class Server:
             keep += [gu, gr, u_prev_t, resid_t]
             r.u_prev = C.pointer(gu)
             r.resid = C.pointer(gr)
+        if grad is not None:
+            ga = grid_array(grad, grad_t)
+            keep += [ga, grad_t]
+            r.grad = C.cast(ga, C.POINTER(Grid))
         r.out = out.ctypes.data
         r.user_tag = int(tag)
         rid = C.c_uint64()

@@ -87,7 +87,7 @@ STRUCTS = {
     "pdd_server_opts": (pdd.ServerOpts, ["memory_budget", "max_queued", "n_pilot", "epoch_paths", "pipeline",
                                          "reserved"]),
     "pdd_request": (pdd.Request, ["n_nodes", "target_se", "stream_id", "u_prev", "resid", "out",
-                                  "user_tag"]),
+                                  "user_tag", "grad"]),
     "pdd_completion": (pdd.Completion, ["status", "queued_ms", "latency_ms", "path_steps", "n_nodes"]),
     "pdd_server_report": (pdd.ServerReport, ["shed", "mem_fixed", "p50_ms", "wall_s",
                                              "node_solves_per_s", "epoch_s", "p99_done_ms", "busy_s",

@@ -252,3 +252,54 @@ def test_tuning_launch_cap_does_not_change_served_results(ctx, stream):
     finally:
         for p, d, e, g in keys:
             pdd.set_tuning(ctx, p, d, e, None, generic=g)
+
+
+def test_served_ito_request_matches_oracle(ctx):
+    """An FP64 request with the Ito control variate (the gradient grids of a
+    u~, eq. F:xiControlVariate), served beside a plain request in small
+    chunks: for every node the oracle walks paths 0 .. n_i - 1 of the
+    request's stream and the served statistics match it (exit-step sums
+    exactly, node means mean(phi + xi) to 1e-10 relative); served alone, the
+    request gives the same bits."""
+    import math
+
+    from oracle import oracle as O
+    sq = W.unit_square_problem(seed=22)
+    grad = W.gradient_grids(sq, n=65, seed=3, dtype=np.float64)
+    grad_t = [torch.as_tensor(g["data"]).cuda().contiguous() for g in grad]
+    prob = pdd.Problem(ctx, sq)
+    nodes = W.unit_square_nodes()[::3]
+    opts = dict(n_pilot=128, n_max=3000, chunk_paths=1 << 10, epoch_paths=1 << 16)
+
+    def serve(with_plain):
+        sv = pdd.Server(ctx, **opts)
+        rid = sv.submit(prob, nodes, 1e-3, 2e-4, precision="fp64", stream_id=31, grad=grad, grad_t=grad_t)
+        if with_plain:
+            sv.submit(prob, W.unit_square_nodes()[1::4], 1e-3, 0.02, precision="fp64", stream_id=32)
+        assert sv.wait_all(120)
+        c = sv.results[rid]
+        rep = sv.report()
+        sv.close()
+        assert c["status"] == 0 and rep["failed"] == 0
+        return c
+
+    mixed = serve(True)
+    alone = serve(False)
+    assert mixed["stats"].tobytes() == alone["stats"].tobytes()
+    st = mixed["stats"]
+    assert np.all(st["n"] > 128)  # planned beyond the pilot: continuation chunks
+    for i in range(len(nodes)):
+        n_i = int(st["n"][i])
+        rec = O.run_paths(sq, nodes, np.full(n_i, i), np.arange(n_i), h=1e-3, stream=31, grad=grad)
+        assert int(st["steps_sum"][i]) == int(rec["steps"].astype(np.int64).sum()), i
+        want = math.fsum(rec["e"]) / n_i
+        assert abs(st["mean"][i] - want) <= 1e-10 * max(1.0, abs(want)), (i, st["mean"][i], want)
+    # a request cannot carry both kinds of grids
+    sv = pdd.Server(ctx, **opts)
+    gu, gr, _ = W.correction_grids(sq, n=65, seed=2, dtype=np.float64)
+    with pytest.raises(pdd.PDDError):
+        sv.submit(prob, nodes, 1e-3, 1e-3, precision="fp64", grad=grad, grad_t=grad_t,
+                  u_prev=gu, u_prev_t=torch.as_tensor(gu["data"]).cuda().contiguous(),
+                  resid=gr, resid_t=torch.as_tensor(gr["data"]).cuda().contiguous())
+    sv.close()
+    prob.close()
