@@ -610,6 +610,21 @@ def iterpdd_runs(ctx, tols):
 SWEEP_RATES = (0.5, 1.0, 2.0, 5.0, 20.0)
 
 
+def knee_rate(rates, busy_limit=None):
+    """The highest rate up to which every rate of a sweep (dicts with
+    rate_per_s, offered, completed, cancelled and, with busy_limit, busy_frac)
+    completed all its requests (and kept the device busy less than busy_limit
+    of the time); None if the lowest rate already fails."""
+    knee = None
+    for r in sorted(rates, key=lambda r: r["rate_per_s"]):
+        if r["cancelled"] or r["completed"] != r["offered"]:
+            break
+        if busy_limit is not None and r["busy_frac"] >= busy_limit:
+            break
+        knee = r["rate_per_s"]
+    return knee
+
+
 LIGHT_RATES = (10.0, 25.0, 50.0, 100.0)
 
 
@@ -638,11 +653,7 @@ def serving_sweep_light(ctx, duration=4.0, drain_s=20.0):
         print(f"light serving at {rate:g} requests/s: {rep['completed']} of {len(reqs)} completed, lag "
               f"{rep['drain_s']:.2f} s, p50 {rep['p50_ms']:.0f} ms, p99 {rep['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-    knee = None
-    for r in out:
-        if r["cancelled"] or r["completed"] != r["offered"] or r["busy_frac"] >= 0.95:
-            break
-        knee = r["rate_per_s"]
+    knee = knee_rate(out, busy_limit=0.95)
     return {"workload": f"Poisson arrivals for {duration:g} s per rate, 1-400 nodes (log-uniform) on 16 random "
                         "2D/3D box problems, RMS tolerance in {1e-2, 3e-3}, 30% with a u_prev grid, FP32, "
                         f"drain up to {drain_s:g} s", "rates": out, "knee_rate_per_s": knee}
@@ -707,14 +718,8 @@ def serving_sweep(ctx, drain_s):
         print(f"serving at {rate:g} requests/s: {rep['completed']} of {len(reqs)} completed, "
               f"p50 {rep['p50_ms']:.0f} ms, p99 {'>= ' if rep['p99_censored'] else ''}{rep['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-    # the knee: the highest rate up to which every rate of the sweep completed all its requests
-    knee = None
-    for r in sorted(out, key=lambda r: r["rate_per_s"]):
-        if r["cancelled"] or r["completed"] != r["offered"]:
-            break
-        knee = r["rate_per_s"]
     return {"workload": "the request mix of 'serving' at lower Poisson rates (seeds 20..), drain "
-                        f"{drain_s:g} s", "rates": out, "knee_rate_per_s": knee}
+                        f"{drain_s:g} s", "rates": out, "knee_rate_per_s": knee_rate(out)}
 
 
 def calibration_copy(mib):

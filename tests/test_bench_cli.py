@@ -53,3 +53,21 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
                  lambda: pdd.plan_paths(np.zeros(1, dtype=pdd.STATS_DTYPE), 1e-3, 100)):
         with pytest.raises(RuntimeError, match="no CPU fallback"):
             call()
+
+
+def test_serving_knee():
+    """The knee of a rate sweep: the highest rate up to which every rate
+    completed everything (and, with a busy limit, left the device idle part
+    of the time); unordered input is sorted by rate first."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def r(rate, offered, completed, busy=0.5):
+        return {"rate_per_s": rate, "offered": offered, "completed": completed,
+                "cancelled": offered - completed, "busy_frac": busy}
+    sweep = [r(5.0, 10, 10), r(0.5, 6, 6), r(1.0, 8, 7), r(2.0, 9, 9)]
+    assert bench.knee_rate(sweep) == 0.5  # 1 request/s lost one: the higher rates do not count
+    assert bench.knee_rate([r(1.0, 3, 2)]) is None
+    light = [r(10.0, 46, 46, 0.32), r(25.0, 109, 109, 0.84), r(50.0, 191, 191, 0.94), r(100.0, 413, 413, 1.0)]
+    assert bench.knee_rate(light, busy_limit=0.95) == 50.0
+    assert bench.knee_rate(light) == 100.0
