@@ -69,6 +69,41 @@ def test_ragged_counts_match_oracle_paths(prob):
             assert st["steps_sum"][i] == int((rec["steps"][seg].view(np.uint32) & 0x7FFFFFFF).sum())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_last_path_indices_and_streams_match_oracle(ctx, prob, prec):
+    """The highest valid counters: paths 2^32 - 128 .. 2^32 - 1 under the
+    stream ids 2^28 - 1 and 2^28 - 2, solved alone and as two merged items of
+    one batch (the per-node RNG table), path for path against the oracle; the
+    merged records are bitwise those of the solo solves."""
+    from oracle import oracle as O
+    nodes = W.unit_square_nodes()[:3]
+    n = 64
+    cases = [((1 << 28) - 1, (1 << 32) - n), ((1 << 28) - 2, (1 << 32) - 2 * n)]
+    solo = []
+    for stream, off in cases:
+        _, rec = run(prob, nodes, 3 * n, dt=1e-3, n_paths=n, path_offset=off, stream_id=stream, precision=prec)
+        solo.append(rec)
+        orec = O.run_paths(prob.pd, nodes, np.repeat(np.arange(3), n), np.tile(np.arange(n, dtype=np.uint64) + off, 3),
+                           h=1e-3, stream=stream)
+        steps = rec["steps"].view(np.uint32) & 0x7FFFFFFF
+        same = steps == orec["steps"]
+        if prec == "fp64":
+            assert (~same).sum() <= 1, np.nonzero(~same)
+            assert np.allclose(rec["phi"][same], orec["phi"][same], rtol=1e-11, atol=1e-12)
+        else:
+            assert same.mean() >= 0.95, same.mean()
+            scale = np.maximum(1.0, np.abs(orec["phi"][same]))
+            assert np.max(np.abs(rec["phi"][same] - orec["phi"][same]) / scale) < 2e-3
+    recs = [pdd.alloc_records(3 * n) for _ in cases]
+    pdd.solve_batch(ctx, [{"problem": prob, "nodes": nodes,
+                           "opts": dict(dt=1e-3, n_paths=n, path_offset=off, stream_id=stream, precision=prec,
+                                        records=r)} for (stream, off), r in zip(cases, recs)])
+    torch.cuda.synchronize()
+    for r, ref in zip(recs, solo):
+        assert r["phi"].cpu().numpy()[:3 * n].tobytes() == ref["phi"].tobytes()
+        assert r["steps"].cpu().numpy()[:3 * n].tobytes() == ref["steps"].tobytes()
+
+
 def test_step_cap(prob):
     nodes = W.unit_square_nodes()[:3]
     st, rec = run(prob, nodes, 3 * 500, dt=1e-3, n_paths=500, max_steps=9, precision="fp64")
