@@ -494,13 +494,17 @@ typedef struct {
  * resident lane in all, its dt, precision, exit test, law, stream and grids;
  * its path counts, records and tuning are ignored) under the launch shapes
  * block {64, 128, 256} x grab {16, 64, 256} at full occupancy, and block 256
- * with 3/4 and 1/2 of the occupancy, twice each after a warm-up. A shape's
- * cost is the time of the larger sample minus that of the smaller, which
- * leaves out fixed costs and the exit-time tail. The default
- * {256, occupancy, 64} is kept unless a shape is more than 2% faster. The
- * winner is written to `out` (host) and stored in the context's table for
- * the item's key. Synchronous; uses the context like a solve. Errors as for
- * the solve. */
+ * with 3/4 and 1/2 of the occupancy, twice each after a warm-up; then, with
+ * the best shape, the refill periods {1, 2, 4, 8} and, in the box / bridge /
+ * Gaussian kernel, both forms of the bridge test. A candidate's cost is the
+ * time of the larger sample minus that of the smaller, which leaves out fixed
+ * costs and the exit-time tail. The default {256, occupancy, 64} (and the
+ * default period and form) is kept unless a candidate is more than 2% faster.
+ * The winner is written to `out` (host) and stored in the context's table
+ * for the item's key. The tuner takes a work item rather than a problem and
+ * options alone because the item also holds what the estimator reads (the
+ * u_prev and residual grids, or the gradient grids) and the nodes to sample.
+ * Synchronous; uses the context like a solve. Errors as for the solve. */
 pdd_status pdd_autotune(pdd_ctx *ctx, const pdd_work_item *item, pdd_tuning *out);
 
 /* Sets (t non-NULL) or removes (t NULL) the context's table entry for `key`,
