@@ -680,6 +680,44 @@ __device__ __forceinline__ void project(const DevProblem<T> &P, int domain, cons
 // State of the path a lane is walking.
 // RNG_TABLE: items may be merged solves with a per-node RNG table (batch
 // kernel); the single-item kernel takes the stream tag from its item.
+// Score of an ended path, written as its record r: phi = g(X_tau) Y + Z
+// (plain), e = (g - u_prev)(X_tau) Y - R (correction), phi and phi + xi (Ito),
+// and the exit step word.
+template <class T, int D, int EST, class M>
+__device__ __forceinline__ void score_path(const ItemCore<T> &a, const DevProblem<T> &P, const T *Xt, T Y, double Z,
+                                           double R, uint32_t word, uint64_t r)
+{
+    const T gv = boundary_value<T, D>(P, Xt, M::tab(P));
+    if (EST == kEstIto) {  // phi and phi + xi
+        const double phi = madd((double)gv, (double)Y, Z);
+        gstore(a.rec_phi + r, phi);
+        gstore(a.rec_e + r, phi + R);
+    } else if (a.score_plain) {
+        gstore(a.rec_phi + r, madd((double)gv, (double)Y, Z));
+    }
+    if (EST == kEstCorrection) {
+        const T up = interp<T, D>(a.u_prev, Xt);
+        gstore(a.rec_e + r, madd((double)gv - (double)up, (double)Y, -R));
+    }
+    gstore(a.rec_steps + r, word);
+}
+
+// Ended paths of a batch-kernel wave waiting to be scored: a ring in the
+// wave's LDS (dynamic shared memory, one ring per wave).
+template <class T, int D>
+struct EndedPath {
+    T Xt[D];
+    T Y;
+    uint32_t word;  // exit step | capped bit
+    double Z, R;
+    uint64_t r;     // record index
+};
+constexpr uint32_t kEndRing = 128;  // holds a batch of 64 and the up to 64 ended at one turn
+template <class T, int D>
+struct EndRing {
+    EndedPath<T, D> e[kEndRing];
+};
+
 template <class T, int D, int EST, class M, bool RNG_TABLE>
 struct Walker {
     T X[D], Xt[D];
@@ -1013,20 +1051,19 @@ struct Walker {
     __device__ __forceinline__ void finish(const ItemCore<T> &a, const DevProblem<T> &P,
                                            uint64_t rec_base)
     {
-        const T gv = boundary_value<T, D>(P, Xt, M::tab(P));
-        const uint64_t r = slot - rec_base;
-        if (EST == kEstIto) {  // phi and phi + xi
-            const double phi = madd((double)gv, (double)Y, Z);
-            gstore(a.rec_phi + r, phi);
-            gstore(a.rec_e + r, phi + R);
-        } else if (a.score_plain) {
-            gstore(a.rec_phi + r, madd((double)gv, (double)Y, Z));
-        }
-        if (EST == kEstCorrection) {
-            const T up = interp<T, D>(a.u_prev, Xt);
-            gstore(a.rec_e + r, madd((double)gv - (double)up, (double)Y, -R));
-        }
-        gstore(a.rec_steps + r, k | (capped ? kCappedBit : 0u));
+        score_path<T, D, EST, M>(a, P, Xt, Y, Z, R, k | (capped ? kCappedBit : 0u), slot - rec_base);
+    }
+
+    // What scoring the ended path needs, for scoring later (batch kernel).
+    __device__ __forceinline__ void stash(EndedPath<T, D> &e, uint64_t rec_base) const
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) e.Xt[d] = Xt[d];
+        e.Y = Y;
+        e.word = k | (capped ? kCappedBit : 0u);
+        e.Z = Z;
+        e.R = R;
+        e.r = slot - rec_base;
     }
 };
 
@@ -1216,30 +1253,63 @@ struct ItemQueue {
 // LDS slot (written when it changes item; a wave's LDS accesses complete in
 // order, so no barrier is needed).
 // FP64 walks are asked to fit three waves per SIMD (168 registers; the few
-// spilled values live outside the step loop), which is faster than two.
+// spilled values live outside the step loop), which is faster than two, and
+// the FP32 2D box / bridge / Gaussian correction walks five (96 registers:
+// one 8-byte value is reloaded at refill turns).
 template <class T, int D, int EST, class M>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1, 8)))
+constexpr int kManyMinWaves = sizeof(T) == 8 ? 3
+                              : (D == 2 && EST == kEstCorrection && !std::is_same<M, RuntimeMode>::value) ? 5
+                                                                                                          : 1;
+template <class T, int D, int EST, class M>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kManyMinWaves<T, D, EST, M>, 8)))
     path_kernel_many(const LaunchArgs L, const ItemDesc<T> *__restrict__ items,
                      const DevProblem<T> *__restrict__ probs)
 {
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[256 / 64][kMaxDense];
+    extern __shared__ uint64_t s_ring[];  // dynamic: one EndRing per wave
     T *my_cf = s_cf[threadIdx.x >> 6];
+    EndRing<T, D> *ring = reinterpret_cast<EndRing<T, D> *>(s_ring) + (threadIdx.x >> 6);
     Walker<T, D, EST, M, true> w;
     w.cf = my_cf;
     int st = 0;
     ItemQueue<T> q;
+    // Ended paths are scored 64 at a time, one per lane, from the wave's ring
+    // (ring_head, ring_count: wave-uniform): scored as each lane ends, the
+    // scoring would run for the whole wave at nearly every refill turn of
+    // short walks for the two or three lanes that ended. Every ended path of
+    // an item is scored before the wave leaves it.
+    uint32_t ring_head = 0, ring_count = 0;
 
     for (uint32_t iter = 0;; ++iter) {
         if ((iter & L.refill_mask) == 0) {  // refill turn (wave-uniform)
-            if (st == 2) {
-                const ItemDesc<T> &it = items[q.cur];
-                // scratch records sit at group slot - launch start (modular arithmetic)
-                w.finish(it, probs[it.prob], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
-                st = 0;
+            const uint64_t ended = __ballot(st == 2);
+            if (ended) {
+                if (st == 2) {
+                    const ItemDesc<T> &it = items[q.cur];
+                    const uint32_t at = (ring_head + ring_count + (uint32_t)__popcll(ended & below)) & (kEndRing - 1);
+                    // scratch records sit at group slot - launch start (modular arithmetic)
+                    w.stash(ring->e[at], it.rec_launch ? L.slot_begin - it.slot_begin : it.rec_base);
+                    st = 0;
+                }
+                ring_count += (uint32_t)__popcll(ended);
             }
             const uint64_t idle = __ballot(st == 0);
+            const bool leaving = idle == ~0ull && q.next == q.end;  // the wave may move or stop at this turn
+            while (ring_count >= 64u || (leaving && ring_count)) {
+                const uint32_t n = min(ring_count, 64u);
+                if ((uint32_t)lane < n) {
+                    const ItemDesc<T> &it = items[q.cur];
+                    const EndedPath<T, D> &e = ring->e[(ring_head + (uint32_t)lane) & (kEndRing - 1)];
+                    T Xt[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) Xt[d] = e.Xt[d];
+                    score_path<T, D, EST, M>(it, probs[it.prob], Xt, e.Y, e.Z, e.R, e.word, e.r);
+                }
+                ring_head = (ring_head + n) & (kEndRing - 1);
+                ring_count -= n;
+            }
             if (idle && q.next == q.end && !q.done) {
                 if (!q.dry) q.take(L, lane);
                 if (q.dry && idle == ~0ull) {
@@ -1966,14 +2036,15 @@ template <class T, int D, int EST>
 hipError_t launch_path_kernel(const LaunchArgs &l, const ItemDesc<T> *items,
                               const DevProblem<T> *probs, int grid, int block, int kind, hipStream_t s)
 {
+    const size_t lds = (size_t)(block / 64) * sizeof(EndRing<T, D>);
     if (kind == kKernelDense)
-        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), 0, s, l,
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), lds, s, l,
                            items, probs);
     else if (kind == kKernelSparse)
-        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, l,
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), lds, s, l,
                            items, probs);
     else
-        hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, l, items,
+        hipLaunchKernelGGL((path_kernel_many<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), lds, s, l, items,
                            probs);
     return hipGetLastError();
 }
