@@ -1114,6 +1114,14 @@ struct Pool {
     }
 };
 
+// The single-item kernel scores ended paths from the wave's ring, as the
+// batch kernel does, in its dense bridge form (boundary-dense, short walks)
+// and its generic form; in the sparse form, for long walks whose lanes seldom
+// end at the same turn, each path is scored as it ends (the ring's
+// bookkeeping cost the [0,4]^2 launch 2.7 %).
+template <class M>
+constexpr bool kRingScoreOne = !std::is_same<M, BoxBridgeGaussT<false>>::value;
+
 // One item, passed by value (FP32 2D plain solves). The source polynomial's
 // coefficients are staged through LDS once per workgroup: read from there,
 // they stay in vector registers for the whole loop (about 96 registers, five
@@ -1129,21 +1137,49 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[kMaxDense];
+    extern __shared__ uint64_t s_ring1[];  // dynamic: one EndRing per wave (ring-scoring kernels)
     for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
     __syncthreads();
+    EndRing<T, D> *ring = reinterpret_cast<EndRing<T, D> *>(s_ring1) + (threadIdx.x >> 6);
     Walker<T, D, EST, M, false> w;
     w.cf = s_cf;
     w.ks = key_schedule<KeysOf<T>>(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     Pool pool;
+    uint32_t ring_head = 0, ring_count = 0;
 
     for (uint32_t iter = 0;; ++iter) {
         if ((iter & L.refill_mask) == 0) {  // refill turn (wave-uniform)
-            if (st == 2) {
-                w.finish(a, P, a.rec_base);  // set per launch by the host
+            if constexpr (kRingScoreOne<M>) {
+                const uint64_t ended = __ballot(st == 2);
+                if (ended) {
+                    if (st == 2) {
+                        const uint32_t at = (ring_head + ring_count + (uint32_t)__popcll(ended & below)) & (kEndRing - 1);
+                        w.stash(ring->e[at], a.rec_base);  // set per launch by the host
+                        st = 0;
+                    }
+                    ring_count += (uint32_t)__popcll(ended);
+                }
+            } else if (st == 2) {
+                w.finish(a, P, a.rec_base);
                 st = 0;
             }
             const uint64_t idle = __ballot(st == 0);
+            if constexpr (kRingScoreOne<M>) {
+                const bool leaving = idle == ~0ull && pool.next == pool.end;  // the wave may stop at this turn
+                while (ring_count >= 64u || (leaving && ring_count)) {
+                    const uint32_t n = min(ring_count, 64u);
+                    if ((uint32_t)lane < n) {
+                        const EndedPath<T, D> &e = ring->e[(ring_head + (uint32_t)lane) & (kEndRing - 1)];
+                        T Xt[D];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) Xt[d] = e.Xt[d];
+                        score_path<T, D, EST, M>(a, P, Xt, e.Y, e.Z, e.R, e.word, e.r);
+                    }
+                    ring_head = (ring_head + n) & (kEndRing - 1);
+                    ring_count -= n;
+                }
+            }
             if (idle) {
                 pool.refill(L, lane);
                 const uint32_t avail = pool.end - pool.next;
@@ -2054,12 +2090,13 @@ hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, 
 {
     if constexpr (kOneItemKernel<T, D, EST>) {
         static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
+        const size_t lds = (size_t)(block / 64) * sizeof(EndRing<T, D>);  // the ring-scoring forms
         if (kind == kKernelDense)
-            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), lds, s, a);
         else if (kind == kKernelSparse)
             hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), lds, s, a);
         return hipGetLastError();
     } else {
         return hipErrorInvalidDeviceFunction;
