@@ -322,9 +322,54 @@ __device__ __forceinline__ void analytic_source(const DevProblem<T> &P, const T 
 // The dense coefficients of F come from `cf` (a copy of P.fdense in LDS).
 // Tabulated coefficients (bit q of `tab`: tabv[q] replaces b_0, b_1, b_2, c,
 // f) are interpolated instead; the analytic f always uses the analytic b, c.
+template <class T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
+
+// The four 16-byte chunks of the pair records that hold a cell's corners
+// (p00, p01, p10, p11 at rec[0..3]). Each lane of a quad whose four lanes are
+// all active loads chunk m = lane & 3 of every quad member's record, so that a
+// load instruction touches 16 cache lines rather than 64 (one per lane: the
+// gather of divergent 64-byte records is what bounds these walks), and the
+// wave's LDS block `tr` (4 x 64 chunks) hands each lane its own four chunks
+// back. Lanes of other quads load their record themselves. The values are
+// those of the direct loads, bit for bit.
+template <class T>
+__device__ __forceinline__ void pair_chunks(const Vec4<T> *base, uint32_t rec, Vec4<T> *tr, Vec4<T> &p00,
+                                            Vec4<T> &p01, Vec4<T> &p10, Vec4<T> &p11)
+{
+    const int lane = __lane_id();
+    const uint64_t act = __builtin_amdgcn_read_exec();
+    if (tr != nullptr && ((act >> (lane & ~3)) & 0xfull) == 0xfull) {
+        const uint32_t m = (uint32_t)lane & 3u;
+        // record offset of quad lane k (quad_perm k,k,k,k), chunk m of it
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)rec, 0x00, 0xf, 0xf, false);
+        const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)rec, 0x55, 0xf, 0xf, false);
+        const uint32_t r2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)rec, 0xaa, 0xf, 0xf, false);
+        const uint32_t r3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)rec, 0xff, 0xf, 0xf, false);
+        const Vec4<T> v0 = gload(base + r0 + m), v1 = gload(base + r1 + m), v2 = gload(base + r2 + m),
+                      v3 = gload(base + r3 + m);
+        tr[0 * 64 + lane] = v0;
+        tr[1 * 64 + lane] = v1;
+        tr[2 * 64 + lane] = v2;
+        tr[3 * 64 + lane] = v3;
+        // chunk m of quad lane k sits at tr[k * 64 + quad + m]
+        const Vec4<T> *mine = tr + (lane & 3) * 64 + (lane & ~3);
+        p00 = mine[0];
+        p01 = mine[1];
+        p10 = mine[2];
+        p11 = mine[3];
+    } else {
+        p00 = gload(base + rec);
+        p01 = gload(base + rec + 1);
+        p10 = gload(base + rec + 2);
+        p11 = gload(base + rec + 3);
+    }
+}
+
 template <class T, int D>
 __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x, T *b, T &c,
-                                             T &f, bool want_f, const T *cf, uint32_t tab)
+                                             T &f, bool want_f, const T *cf, uint32_t tab,
+                                             Vec4<T> *tr = nullptr)
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -342,10 +387,10 @@ __device__ __forceinline__ void coefficients(const DevProblem<T> &P, const T *x,
         T w[D];
         grid_cell<T, D>(P.tabv[3], x, i, w);
         if (D == 2 && (tab & 128u)) {  // pair records of the cell's two lower corners: all four
-            typedef T V4 __attribute__((ext_vector_type(4)));
             const uint32_t n0 = (uint32_t)P.tabv[3].n[0];
-            const V4 *r0 = reinterpret_cast<const V4 *>(P.tab_fused) + 2u * ((uint32_t)i[1] * n0 + (uint32_t)i[0]);
-            const V4 p00 = gload(r0), p01 = gload(r0 + 1), p10 = gload(r0 + 2), p11 = gload(r0 + 3);
+            Vec4<T> p00, p01, p10, p11;
+            pair_chunks<T>(reinterpret_cast<const Vec4<T> *>(P.tab_fused), 2u * ((uint32_t)i[1] * n0 + (uint32_t)i[0]),
+                           tr, p00, p01, p10, p11);
             b[0] = interp_corner_values<T>(p00.x, p10.x, p01.x, p11.x, w);
             b[1 % D] = interp_corner_values<T>(p00.y, p10.y, p01.y, p11.y, w);
             c = interp_corner_values<T>(p00.z, p10.z, p01.z, p11.z, w);
@@ -735,6 +780,7 @@ struct Walker {
     uint64_t bw01, bw23;  // cached bridge block, words (0,1) and (2,3)
     KeysOf<T> ks;
     const T *cf;          // dense source coefficients of the problem, in LDS
+    Vec4<T> *tr;          // the wave's LDS block for gathering pair records (single-item kernel)
 
     // Starts path r (slot within the item) of item a. Returns false when it
     // ends before any step (a node inside the shift band of the shifted test).
@@ -841,7 +887,8 @@ struct Walker {
             if (D == 3) n[2 % D] = (wc >> 31) ? (T)1 : (T)-1;
         }
         T b[D], c, f = (T)0;
-        coefficients<T, D>(P, X, b, c, f, EST == kEstIto || a.score_plain != 0, cf, M::tab(P));
+        coefficients<T, D>(P, X, b, c, f, EST == kEstIto || a.score_plain != 0, cf, M::tab(P),
+                           RNG_TABLE ? nullptr : tr);
         const T hY = a.h * Y;
         if (EST == kEstIto || a.score_plain) Z -= (double)(hY * f);
         if (EST == kEstCorrection) R += (double)(hY * interp_cells<T, D>(a.resid, X));
@@ -1122,6 +1169,15 @@ struct Pool {
 template <class M>
 constexpr bool kRingScoreOne = !std::is_same<M, BoxBridgeGaussT<false>>::value;
 
+// Dynamic LDS of a wave of the single-item kernel: the ring of ended paths,
+// and in the generic form (the one that walks tabulated problems) the block
+// for gathering pair records.
+template <class T, int D, class M>
+struct OneWaveLds {
+    EndRing<T, D> ring;
+    Vec4<T> tr[std::is_same<M, RuntimeMode>::value ? 4 * 64 : 1];
+};
+
 // One item, passed by value (FP32 2D plain solves). The source polynomial's
 // coefficients are staged through LDS once per workgroup: read from there,
 // they stay in vector registers for the whole loop (about 96 registers, five
@@ -1137,12 +1193,14 @@ __global__ void __launch_bounds__(256) path_kernel_one(const OneItemArgs<T> A)
     const int lane = __lane_id();
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     __shared__ T s_cf[kMaxDense];
-    extern __shared__ uint64_t s_ring1[];  // dynamic: one EndRing per wave (ring-scoring kernels)
+    extern __shared__ __attribute__((aligned(16))) uint64_t s_one[];  // dynamic: OneWaveLds per wave (ring-scoring forms)
     for (uint32_t i = threadIdx.x; i < (uint32_t)kMaxDense; i += blockDim.x) s_cf[i] = P.fdense[i];
     __syncthreads();
-    EndRing<T, D> *ring = reinterpret_cast<EndRing<T, D> *>(s_ring1) + (threadIdx.x >> 6);
+    OneWaveLds<T, D, M> *wl = reinterpret_cast<OneWaveLds<T, D, M> *>(s_one) + (threadIdx.x >> 6);
+    EndRing<T, D> *ring = &wl->ring;
     Walker<T, D, EST, M, false> w;
     w.cf = s_cf;
+    w.tr = std::is_same<M, RuntimeMode>::value ? wl->tr : nullptr;
     w.ks = key_schedule<KeysOf<T>>(P.key0, P.key1);
     int st = 0;  // 0 idle, 1 walking, 2 ended (to be scored)
     Pool pool;
@@ -1309,6 +1367,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kManyM
     EndRing<T, D> *ring = reinterpret_cast<EndRing<T, D> *>(s_ring) + (threadIdx.x >> 6);
     Walker<T, D, EST, M, true> w;
     w.cf = my_cf;
+    w.tr = nullptr;
     int st = 0;
     ItemQueue<T> q;
     // Ended paths are scored 64 at a time, one per lane, from the wave's ring
@@ -2090,13 +2149,15 @@ hipError_t launch_path_kernel_one(const OneItemArgs<T> &a, int grid, int block, 
 {
     if constexpr (kOneItemKernel<T, D, EST>) {
         static_assert(sizeof(OneItemArgs<T>) <= 4096, "kernel arguments exceed 4 KiB");
-        const size_t lds = (size_t)(block / 64) * sizeof(EndRing<T, D>);  // the ring-scoring forms
+        const size_t waves = (size_t)(block / 64);
         if (kind == kKernelDense)
-            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block), lds, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGaussDense>), dim3(grid), dim3(block),
+                               waves * sizeof(OneWaveLds<T, D, BoxBridgeGaussDense>), s, a);
         else if (kind == kKernelSparse)
             hipLaunchKernelGGL((path_kernel_one<T, D, EST, BoxBridgeGauss>), dim3(grid), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block), lds, s, a);
+            hipLaunchKernelGGL((path_kernel_one<T, D, EST, RuntimeMode>), dim3(grid), dim3(block),
+                               waves * sizeof(OneWaveLds<T, D, RuntimeMode>), s, a);
         return hipGetLastError();
     } else {
         return hipErrorInvalidDeviceFunction;
