@@ -270,3 +270,39 @@ def test_fp32_trig_range_is_checked(ctx):
         st = pdd.stats_to_numpy(pdd.solve_nodes(p, nodes, dt=1e-3, n_paths=64, precision=prec))
         assert np.all(st["n"] == 64)
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_paths_ending_before_their_first_step(prob, prec):
+    """Nodes inside the shifted test's band (distance <= 0.5826 sigma sqrt(h)
+    from the boundary, Alg. 1) end every path before its first step, so whole
+    waves end 64 paths at one refill turn (a full batch of ended paths waiting
+    to be scored at once) while waves on the other nodes walk. Exit steps and
+    scores match the oracle path by path (FP64: scores to 1e-11; FP32: the
+    in-band scores are g at the projected point, within FP32 rounding), and
+    the records are bitwise the same at refill periods 1 and 8."""
+    from oracle import oracle as O
+    h = 1e-3
+    band = 0.5826 * math.sqrt(h)  # sigma = 1
+    nodes = np.array([[0.4 * band, 0.5], [0.3, 0.4], [0.5, 1.0 - 0.7 * band], [0.2 * band, 0.3 * band]])
+    n = 640
+    recs = []
+    for refill in (1, 8):
+        st, rec = run(prob, nodes, len(nodes) * n, dt=h, n_paths=n, precision=prec, exit="shift",
+                      tuning=(256, 0, 64, 0, refill, 0))
+        assert list(st["n"]) == [n] * len(nodes)
+        recs.append(rec)
+    assert recs[0]["phi"].tobytes() == recs[1]["phi"].tobytes()
+    assert recs[0]["steps"].tobytes() == recs[1]["steps"].tobytes()
+    ost, orec = O.solve_nodes(prob.pd, nodes, record=True, h=h, n_paths=n, exit="shift")
+    steps = recs[0]["steps"].view(np.uint32) & 0x7FFFFFFF
+    in_band = np.repeat([True, False, True, True], n)
+    assert np.all(steps[in_band] == 0) and np.all(orec["steps"][in_band] == 0)
+    same = steps == orec["steps"].astype(np.uint32)
+    if prec == "fp64":
+        assert same.mean() >= 0.9999, same.mean()
+    phi, ophi = recs[0]["phi"], orec["phi"]
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    ok = same if prec == "fp64" else in_band
+    assert np.all(np.abs(phi[ok] - ophi[ok]) <= tol * np.maximum(1.0, np.abs(ophi[ok]))), \
+        np.max(np.abs(phi[ok] - ophi[ok]))
