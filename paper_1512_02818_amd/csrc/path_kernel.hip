@@ -747,8 +747,9 @@ __device__ __forceinline__ void score_path(const ItemCore<T> &a, const DevProble
     gstore(a.rec_steps + r, word);
 }
 
-// Ended paths of a batch-kernel wave waiting to be scored: a ring in the
-// wave's LDS (dynamic shared memory, one ring per wave).
+// Ended paths of a wave waiting to be scored (batch kernel; dense-bridge and
+// generic forms of the single-item kernel): a ring in the wave's LDS (dynamic
+// shared memory, one ring per wave).
 template <class T, int D>
 struct EndedPath {
     T Xt[D];
@@ -1101,7 +1102,7 @@ struct Walker {
         score_path<T, D, EST, M>(a, P, Xt, Y, Z, R, k | (capped ? kCappedBit : 0u), slot - rec_base);
     }
 
-    // What scoring the ended path needs, for scoring later (batch kernel).
+    // What scoring the ended path needs, for scoring later from the ring.
     __device__ __forceinline__ void stash(EndedPath<T, D> &e, uint64_t rec_base) const
     {
 #pragma unroll
