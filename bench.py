@@ -485,20 +485,26 @@ def paper_example(ctx):
     prob = pdd.Problem(ctx, pd)
     pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=1000, precision="fp32")  # warm-up
     torch.cuda.synchronize()
-    pdd.kernel_times(ctx)
-    t0 = time.perf_counter()
-    st = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=1_000_000, precision="fp32",
-                                            stream_id=1, time_kernel=True))
-    wall = time.perf_counter() - t0
-    kern = pdd.kernel_times(ctx)
-    steps = int(st["steps_sum"].sum())
+    # three solves of disjoint paths (path offsets 0, 10^6, 2 x 10^6): the rate
+    # is their total; the accuracy figures are those of the first
+    kern, steps, wall, st = [], 0, 0.0, None
+    for q in range(3):
+        pdd.kernel_times(ctx)
+        t0 = time.perf_counter()
+        sq = pdd.stats_to_numpy(pdd.solve_nodes(prob, nodes, dt=1e-3, n_paths=1_000_000, precision="fp32",
+                                                stream_id=1, path_offset=q * 1_000_000, time_kernel=True))
+        wall += time.perf_counter() - t0
+        kern += pdd.kernel_times(ctx)
+        steps += int(sq["steps_sum"].sum())
+        st = sq if st is None else st
     gg = W.paper_example_gradient_grids(n=257, dtype=np.float32)
     gt = [torch.as_tensor(g["data"]).cuda().contiguous() for g in gg]
     si = pdd.stats_to_numpy(pdd.solve_ito(prob, gg, gt, nodes, dt=2.5e-4, n_paths=100_000, precision="fp32",
                                           stream_id=2))
     prob.close()
     return {"workload": "paper's example PDE (trig-rational b, c; sigma = sqrt(2)) on [0,2]^2, b, c, f, g on "
-                        "513^2 FP32 grids, 18 nodes, 10^6 paths per node, h = 1e-3, FP32, bridge exit",
+                        "513^2 FP32 grids, 18 nodes, 10^6 paths per node, h = 1e-3, FP32, bridge exit; three "
+                        "solves of disjoint paths timed, accuracy from the first",
             "wall_s": wall, "path_kernel_ms": [float(k) for k in kern], "path_steps": steps,
             "path_steps_per_s": steps / (sum(kern) / 1e3), "mean_steps_per_path": float(st["mean_steps"].mean()),
             "rms_error": float(np.sqrt(np.mean((st["mean"] - exact) ** 2))),
