@@ -136,12 +136,19 @@ def whole_launch_ms(ctx: pdd.Context, item: dict, shape, n_paths: int, reps: int
     return float(np.median(ms))
 
 
+REFILL_PERIODS = (1, 2, 4, 8)
+
+
 def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: str | None = None,
          verify_paths: int = 0):
     """pdd_autotune on `item` (batch-style dict); records the winner under its key.
     With verify_paths, the winner must also beat the default by 2 % on a full
     solve with that many paths per node (its sampled timing leaves the tail
-    out), else the default is recorded."""
+    out), else the default is kept; then, with that shape, each refill period
+    is timed on full solves too and one more than 2 % faster taken: the period
+    trades lanes idle until the next refill turn against the turns' start and
+    scoring code, a balance that the exit-time tail, absent from the samples,
+    decides."""
     shape = pdd.autotune(ctx, item)
     if verify_paths:
         prob = item["problem"]
@@ -149,8 +156,18 @@ def tune(ctx: pdd.Context, item: dict, path: str | None = DEFAULT_PATH, arch: st
         t_tuned = whole_launch_ms(ctx, item, shape, verify_paths)
         t_default = whole_launch_ms(ctx, item, DEFAULT_SHAPE, verify_paths)
         if not t_tuned < 0.98 * t_default:
-            shape = DEFAULT_SHAPE
+            shape, t_tuned = DEFAULT_SHAPE, t_default
+        for r in REFILL_PERIODS:
+            cand = tuple(shape[:4]) + (r,) + tuple(shape[5:])
+            if cand == tuple(shape):
+                continue
+            t = whole_launch_ms(ctx, item, cand, verify_paths)
+            if t < 0.98 * t_tuned:
+                shape, t_tuned = cand, t
+        if tuple(shape) == DEFAULT_SHAPE:
             pdd.set_tuning(ctx, prec, prob.dim, item_estimator(item), None, generic=generic_item(item))
+        else:
+            pdd.set_tuning(ctx, prec, prob.dim, item_estimator(item), tuple(shape), generic=generic_item(item))
     if path:
         prob = item["problem"]
         prec = item["opts"].get("precision", "fp32")
